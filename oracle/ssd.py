@@ -1,0 +1,438 @@
+"""The sliding-mesh SD residual, the dynamic mortars and SSP-RK3 (Sec. 3).
+
+State layout at the interface: Q[v, j, i, e], the 4 conservative variables
+at solution point (X_i, X_j) of element e.  The state is the physical Q at
+the SPs; since |J| of a rigidly rotating or fixed cell does not change in
+time, dQ~/dt = |J| dQ/dt and residual() returns dQ/dt.
+
+Per residual evaluation (Sec. 3.1, Sec. 3.2):
+  1. Q at the FPs by Lagrange interpolation along each line (eq. Qt).
+  2. Transformed fluxes F~ = |J| J^-1 (F, G) at interior FPs
+     (eq. transform_relation) with the ALE grid-velocity terms (Sec. 2.2).
+  3. Common normal fluxes at element-boundary FPs: Rusanov on conforming
+     and periodic faces, boundary fluxes on walls and far field, and the
+     curved dynamic mortar on the sliding interface (eqs. xz, prjQ2, prjF2).
+  4. With viscosity, BR1-style common solution and common gradient
+     (Sec. 3.1 refers the viscous details elsewhere; Sec. 3.2 gives the
+     mortar steps for them).
+  5. dQ~/dt = -(dF~/dxi + dG~/deta) at the SPs from the degree-N flux
+     polynomials (eqs. Ft, Gt).
+"""
+import numpy as np
+
+from workloads.meshes import (FACE_CORNERS, FACE_INTERIOR, FACE_PERIODIC, FACE_SLIDING,
+                              FACE_WALL_ISOTHERMAL, FACE_WALL_SLIP, FACE_FARFIELD)
+from .basis import Operators
+from .geometry import Geometry
+from . import physics as ph
+
+FACE_EXTERNAL = 100   # face of a sub-mesh whose neighbour lies outside it
+
+
+def _wrap_pi(a):
+    return (a + np.pi) % (2 * np.pi) - np.pi
+
+
+class Interface:
+    """The two rings of faces on the circular sliding interface (Sec. 3.2).
+
+    Inner cells are the left (L) side, outer cells the right (R) side; faces
+    on each side are sorted counter-clockwise.  Each face gets a canonical
+    coordinate that increases counter-clockwise (its own parameter, or the
+    reverse when `flip`), so face j of a side spans the angles
+    phi0 + theta_side + [j, j+1] * Delta, Delta = 2 pi / K.
+    """
+
+    def __init__(self, mesh, ops):
+        self.ops = ops
+        self.c = np.asarray(mesh["center"], dtype=float)
+        self.R = float(mesh["radius"])
+        xy = mesh["xy"]
+        e, f = np.nonzero(mesh["face_kind"] == FACE_SLIDING)
+        st = xy[e, FACE_CORNERS[f, 0]] - self.c
+        en = xy[e, FACE_CORNERS[f, 1]] - self.c
+        a0 = np.arctan2(st[:, 1], st[:, 0])
+        a1 = np.arctan2(en[:, 1], en[:, 0])
+        d = _wrap_pi(a1 - a0)
+        flip = d < 0
+        start = np.where(flip, a1, a0) % (2 * np.pi)
+        cen = xy[e][:, [0, 3, 6, 9]].mean(axis=1) - self.c
+        inner = np.hypot(cen[:, 0], cen[:, 1]) < self.R
+        sides = []
+        for sel in (inner, ~inner):
+            order = np.argsort(start[sel])
+            sides.append(dict(e=e[sel][order], f=f[sel][order], flip=flip[sel][order],
+                              start=start[sel][order], zone=mesh["zone"][e[sel][order]]))
+        self.L, self.Rt = sides
+        K = len(self.L["e"])
+        if K == 0 or len(self.Rt["e"]) != K:
+            raise ValueError("sliding interface needs the same number of faces on both sides")
+        self.K = K
+        self.delta = 2 * np.pi / K
+        for s in sides:
+            steps = _wrap_pi(np.diff(np.concatenate([s["start"], s["start"][:1] + 2 * np.pi])))
+            if np.max(np.abs(steps - self.delta)) > 1e-9:
+                raise ValueError("sliding interface faces are not uniform")
+            if len(set(s["zone"].tolist())) != 1:
+                raise ValueError("one side of the interface spans two zones")
+        self.rotL = int(self.L["zone"][0]) == 1
+        self.rotR = int(self.Rt["zone"][0]) == 1
+
+    def placement(self, theta):
+        """(m, delta_frac, thL, thR): L face j overlaps R faces j+m and j+m+1;
+        its first (1 - delta_frac) lies on R face j+m."""
+        thL = theta if self.rotL else 0.0
+        thR = theta if self.rotR else 0.0
+        a = (self.L["start"][0] + thL) - (self.Rt["start"][0] + thR)
+        x = a / self.delta
+        fl = np.floor(x)
+        dlt = x - fl
+        m = int(fl) % self.K
+        if dlt >= 1.0:
+            dlt, m = 0.0, (m + 1) % self.K
+        return m, float(dlt), thL, thR
+
+    def operators(self, dlt):
+        """(o, s) of the two mortars seen from an L face and from an R face,
+        with their forward and backward projections (eqs. prjQ2, prjF2)."""
+        ops = self.ops
+        osL = [(0.0, 1.0 - dlt), (1.0 - dlt, dlt)]
+        osR = [(dlt, 1.0 - dlt), (0.0, dlt)]
+        PfL = [ops.forward(o, s) for o, s in osL]
+        PbL = [ops.backward(o, s) for o, s in osL]
+        PfR = [ops.forward(o, s) for o, s in osR]
+        PbR = [ops.backward(o, s) for o, s in osR]
+        return osL, PfL, PbL, PfR, PbR
+
+    def canon(self, side, arr):
+        """Face data (4, E, 4, N) -> canonical ring data (4, K, N)."""
+        d = arr[:, side["e"], side["f"], :]
+        return np.where(side["flip"][None, :, None], d[:, :, ::-1], d)
+
+    def scatter(self, side, ring, out, sign):
+        """Canonical ring data (4, K, N) -> element faces of `out`."""
+        d = np.where(side["flip"][None, :, None], ring[:, :, ::-1], ring)
+        out[:, side["e"], side["f"], :] = sign * d
+
+    def mortar_angles(self, theta_side_L, osL):
+        """Angles of the mortar SPs, (2, K, N), from the L faces."""
+        j = np.arange(self.K)[:, None]
+        X = self.ops.X[None, :]
+        return [self.L["start"][0] + theta_side_L + self.delta * (j + o + s * X) for o, s in osL]
+
+    def face_angles(self, side, theta_side):
+        j = np.arange(self.K)[:, None]
+        return side["start"][0] + theta_side + self.delta * (j + self.ops.X[None, :])
+
+    def to_mortars(self, qL, qR, m, PfL, PfR):
+        """Project canonical L and R face data onto the 2K mortars."""
+        K = self.K
+        r1 = (np.arange(K) + m) % K
+        r2 = (np.arange(K) + m + 1) % K
+        out = []
+        for k, rr in ((0, r1), (1, r2)):
+            aL = np.einsum("ab,vjb->vja", PfL[k], qL)
+            aR = np.einsum("ab,vjb->vja", PfR[k], qR[:, rr, :])
+            out.append((aL, aR))
+        return out
+
+    def to_faces(self, mort, m, PbL, PbR):
+        """Back-project per-mortar data (2 x (4, K, N)) to L and R faces."""
+        K = self.K
+        FL = (np.einsum("ab,vjb->vja", PbL[0], mort[0])
+              + np.einsum("ab,vjb->vja", PbL[1], mort[1]))
+        r = np.arange(K)
+        FR = (np.einsum("ab,vjb->vja", PbR[0], mort[0][:, (r - m) % K, :])
+              + np.einsum("ab,vjb->vja", PbR[1], mort[1][:, (r - m - 1) % K, :]))
+        return FL, FR
+
+
+class SSD:
+    """FP64 residual of the SSD method on one mesh (Sec. 3)."""
+
+    def __init__(self, mesh, case, N):
+        self.mesh = mesh
+        self.case = case
+        self.N = N
+        self.ops = Operators(N)
+        self.geo = Geometry(mesh, self.ops)
+        self.E = len(mesh["zone"])
+        self.kind = np.asarray(mesh["face_kind"])
+        self.nbr = np.asarray(mesh["nbr"])
+        self.nbf = np.asarray(mesh["nbr_face"])
+        xy = mesh["xy"]
+        ends = xy[:, FACE_CORNERS]                          # (E,4,2,2)
+        tang = ends[:, :, 1] - ends[:, :, 0]
+        has = self.nbr >= 0
+        nb = np.where(has, self.nbr, 0)
+        nf = np.where(has, self.nbf, 0)
+        self.rev = has & (np.einsum("efc,efc->ef", tang, tang[nb, nf]) < 0)
+        self.iface = Interface(mesh, self.ops) if np.any(self.kind == FACE_SLIDING) else None
+        self.zone1 = np.asarray(mesh["zone"]) == 1
+
+    # ------------------------------------------------------------------
+    def _neighbor(self, T):
+        """Neighbour traces (.., E, 4, N) aligned with each face's parameter."""
+        nb = np.where(self.nbr >= 0, self.nbr, np.arange(self.E)[:, None])
+        nf = np.where(self.nbr >= 0, self.nbf, np.arange(4)[None, :])
+        Tn = T[..., nb, nf, :]
+        return np.where(self.rev[..., :, :, None], Tn[..., ::-1], Tn)
+
+    @staticmethod
+    def _faces(axi, aeta, N):
+        """Face values (.., E, 4, N) from xi-FP (.., E, N, N+1) and eta-FP
+        (.., E, N+1, N) arrays, in each face's own parameter order."""
+        return np.stack([aeta[..., 0, :], axi[..., :, N], aeta[..., N, :], axi[..., :, 0]], axis=-2)
+
+    def residual(self, Q, theta, omega, diag=False):
+        """dQ/dt at the SPs for state Q[v, j, i, e] with zone 1 at angle
+        theta turning at rate omega."""
+        ops, N, E = self.ops, self.N, self.E
+        cs = self.case
+        gam = cs["gamma"]
+        visc = cs["mu"] > 0.0
+        q = np.moveaxis(np.asarray(Q, dtype=float), 3, 1)            # (4,E,N,N) [v,e,j,i]
+        g = self.geo.at(theta)
+        cx, cy = self.geo.center
+        rot = self.zone1
+
+        qxi = np.einsum("ki,veji->vejk", ops.I, q)                  # (4,E,N,N+1)
+        qeta = np.einsum("kj,veji->veki", ops.I, q)                 # (4,E,N+1,N)
+
+        def gridvel(d):
+            m = rot.reshape((-1,) + (1,) * (d["x"].ndim - 1))
+            ug = np.where(m, -omega * (d["y"] - cy), 0.0)
+            vg = np.where(m, omega * (d["x"] - cx), 0.0)
+            return ug, vg
+
+        gx, ge = g["fxi"], g["feta"]
+        ugx, vgx = gridvel(gx)
+        uge, vge = gridvel(ge)
+        # scaled contravariant normals of the FP lines: (y_eta, -x_eta), (-y_xi, x_xi)
+        nxi = (gx["y_eta"], -gx["x_eta"])
+        neta = (-ge["y_xi"], ge["x_xi"])
+        vgn_xi = ugx * nxi[0] + vgx * nxi[1]
+        vgn_eta = uge * neta[0] + vge * neta[1]
+        Ft = ph.normal_inviscid_flux(qxi, nxi[0], nxi[1], vgn_xi, gam)     # (4,E,N,N+1)
+        Gt = ph.normal_inviscid_flux(qeta, neta[0], neta[1], vgn_eta, gam)  # (4,E,N+1,N)
+
+        # ---- faces: traces, outward scaled normals, grid velocity --------
+        T = self._faces(qxi, qeta, N)                                    # (4,E,4,N)
+        sgn = np.array([-1.0, 1.0, 1.0, -1.0])[None, :, None]
+        fnx = self._faces(nxi[0], neta[0], N) * sgn
+        fny = self._faces(nxi[1], neta[1], N) * sgn
+        fug = self._faces(ugx, uge, N)
+        fvg = self._faces(vgx, vge, N)
+        fvgn = fug * fnx + fvg * fny
+        Tn = self._neighbor(T)
+        kind = self.kind[:, :, None]
+        inter = (kind == FACE_INTERIOR) | (kind == FACE_PERIODIC)
+        wall = (kind == FACE_WALL_ISOTHERMAL) | (kind == FACE_WALL_SLIP)
+        far = kind == FACE_FARFIELD
+        ext = kind == FACE_EXTERNAL
+        Qinf = ph.conservative(*cs["farfield"], gam)[:, None, None, None] * np.ones_like(T)
+
+        fs = np.zeros_like(T)
+        rus = ph.rusanov(T, Tn, fnx, fny, fvgn, gam)
+        fs = np.where(inter, rus, fs)
+        _, _, _, pT = ph.primitives(T, gam)
+        zero = np.zeros_like(pT)
+        fwall = np.stack([zero, pT * fnx, pT * fny, pT * fvgn])
+        fs = np.where(wall, fwall, fs)
+        fs = np.where(far, ph.rusanov(T, Qinf, fnx, fny, fvgn, gam), fs)
+        fs = np.where(ext, ph.normal_inviscid_flux(T, fnx, fny, fvgn, gam), fs)
+
+        itf = self.iface
+        if itf is not None:
+            m, dlt, thL, thR = itf.placement(theta)
+            osL, PfL, PbL, PfR, PbR = itf.operators(dlt)
+            TL, TR = itf.canon(itf.L, T), itf.canon(itf.Rt, T)
+            proj = itf.to_mortars(TL, TR, m, PfL, PfR)
+            ang = itf.mortar_angles(thL, osL)
+            scale = itf.R * itf.delta
+            fm = []
+            for (aL, aR), phi in zip(proj, ang):
+                nx, ny = np.cos(phi) * scale, np.sin(phi) * scale
+                fm.append(ph.rusanov(aL, aR, nx, ny, 0.0, gam))
+            FL, FR = itf.to_faces(fm, m, PbL, PbR)
+            itf.scatter(itf.L, FL, fs, 1.0)
+            itf.scatter(itf.Rt, FR, fs, -1.0)
+
+        if visc:
+            fv, Ftv, Gtv = self._viscous(q, qxi, qeta, T, Tn, g, fnx, fny, fug, fvg,
+                                         nxi, neta, theta)
+            fs = fs + fv
+            Ft = Ft + Ftv
+            Gt = Gt + Gtv
+
+        # common fluxes at the element-boundary FPs (sign: outward -> F~, G~)
+        Ft[..., 0] = -fs[:, :, 3, :]
+        Ft[..., N] = fs[:, :, 1, :]
+        Gt[:, :, 0, :] = -fs[:, :, 0, :]
+        Gt[:, :, N, :] = fs[:, :, 2, :]
+
+        dF = np.einsum("ik,vejk->veji", ops.D, Ft)
+        dG = np.einsum("jk,veki->veji", ops.D, Gt)
+        R = -(dF + dG) / self.geo.detJ[None]
+        Rapi = np.moveaxis(R, 1, 3)
+        if not diag:
+            return Rapi
+        absD = np.abs(ops.D)
+        scale = (np.einsum("ik,vejk->veji", absD, np.abs(Ft))
+                 + np.einsum("jk,veki->veji", absD, np.abs(Gt))) / np.abs(self.geo.detJ[None])
+        return Rapi, dict(flux_scale=np.moveaxis(scale, 1, 3), face_flux=fs)
+
+    # ------------------------------------------------------------------
+    def _viscous(self, q, qxi, qeta, T, Tn, g, fnx, fny, fug, fvg, nxi, neta, theta):
+        """Viscous parts (BR1 reading): face common viscous flux (outward,
+        per unit face parameter) and interior transformed viscous fluxes."""
+        ops, N = self.ops, self.N
+        cs = self.case
+        gam, Rg, mu, Pr = cs["gamma"], cs["gas_R"], cs["mu"], cs["prandtl"]
+        kind = self.kind[:, :, None]
+        inter = (kind == FACE_INTERIOR) | (kind == FACE_PERIODIC)
+        iso = kind == FACE_WALL_ISOTHERMAL
+        slip = kind == FACE_WALL_SLIP
+        far = kind == FACE_FARFIELD
+
+        # common solution at the faces
+        rho, u, v, p = ph.primitives(T, gam)
+        Qc = T.copy()
+        Qc = np.where(inter, 0.5 * (T + Tn), Qc)
+        rb = p / (Rg * cs["T_wall"])
+        Qiso = ph.conservative(rb, fug, fvg, p, gam)
+        Qc = np.where(iso, Qiso, Qc)
+        mag = np.sqrt(fnx * fnx + fny * fny)
+        nhx, nhy = fnx / mag, fny / mag
+        urel = (u - fug) * nhx + (v - fvg) * nhy
+        Qslip = ph.conservative(rho, u - urel * nhx, v - urel * nhy, p, gam)
+        Qc = np.where(slip, Qslip, Qc)
+        Qinf = ph.conservative(*cs["farfield"], gam)[:, None, None, None] * np.ones_like(T)
+        Qc = np.where(far, Qinf, Qc)
+
+        itf = self.iface
+        if itf is not None:
+            m, dlt, thL, thR = itf.placement(theta)
+            osL, PfL, PbL, PfR, PbR = itf.operators(dlt)
+            TL, TR = itf.canon(itf.L, T), itf.canon(itf.Rt, T)
+            proj = itf.to_mortars(TL, TR, m, PfL, PfR)
+            avg = [0.5 * (aL + aR) for aL, aR in proj]
+            QcL, QcR = itf.to_faces(avg, m, PbL, PbR)
+            itf.scatter(itf.L, QcL, Qc, 1.0)
+            itf.scatter(itf.Rt, QcR, Qc, 1.0)
+
+        # gradients at the SPs from FP values with common boundary values
+        qxs = qxi.copy()
+        qxs[..., 0] = Qc[:, :, 3, :]
+        qxs[..., N] = Qc[:, :, 1, :]
+        qes = qeta.copy()
+        qes[:, :, 0, :] = Qc[:, :, 0, :]
+        qes[:, :, N, :] = Qc[:, :, 2, :]
+        Qxi = np.einsum("ik,vejk->veji", ops.D, qxs)
+        Qeta = np.einsum("jk,veki->veji", ops.D, qes)
+        sp = g["sp"]
+        J = self.geo.detJ[None]
+        Qx = (sp["y_eta"][None] * Qxi - sp["y_xi"][None] * Qeta) / J
+        Qy = (-sp["x_eta"][None] * Qxi + sp["x_xi"][None] * Qeta) / J
+
+        # gradients at the FPs
+        gx_xi = np.einsum("ki,veji->vejk", ops.I, Qx)
+        gy_xi = np.einsum("ki,veji->vejk", ops.I, Qy)
+        gx_eta = np.einsum("kj,veji->veki", ops.I, Qx)
+        gy_eta = np.einsum("kj,veji->veki", ops.I, Qy)
+        GX = self._faces(gx_xi, gx_eta, N)
+        GY = self._faces(gy_xi, gy_eta, N)
+        GXn, GYn = self._neighbor(GX), self._neighbor(GY)
+        GXc = np.where(inter, 0.5 * (GX + GXn), GX)
+        GYc = np.where(inter, 0.5 * (GY + GYn), GY)
+
+        Fv, Gv = ph.viscous_flux(Qc, GXc, GYc, gam, Rg, mu, Pr)
+        fv = Fv * fnx + Gv * fny
+        fv = np.where(slip, 0.0, fv)
+
+        if itf is not None:
+            scale = itf.R * itf.delta
+
+            def side_flux(side, th):
+                phi = itf.face_angles(side, th)
+                nx, ny = np.cos(phi) * scale, np.sin(phi) * scale
+                Fs, Gs = ph.viscous_flux(itf.canon(side, Qc), itf.canon(side, GX),
+                                         itf.canon(side, GY), gam, Rg, mu, Pr)
+                return Fs * nx + Gs * ny
+
+            vL = side_flux(itf.L, thL)
+            vR = side_flux(itf.Rt, thR)
+            proj = itf.to_mortars(vL, vR, m, PfL, PfR)
+            avg = [0.5 * (aL + aR) for aL, aR in proj]
+            FvL, FvR = itf.to_faces(avg, m, PbL, PbR)
+            itf.scatter(itf.L, FvL, fv, 1.0)
+            itf.scatter(itf.Rt, FvR, fv, -1.0)
+
+        Fx, Gx = ph.viscous_flux(qxi, gx_xi, gy_xi, gam, Rg, mu, Pr)
+        Fe, Ge = ph.viscous_flux(qeta, gx_eta, gy_eta, gam, Rg, mu, Pr)
+        Ftv = Fx * nxi[0] + Gx * nxi[1]
+        Gtv = Fe * neta[0] + Ge * neta[1]
+        return fv, Ftv, Gtv
+
+    # ------------------------------------------------------------------
+    def theta(self, t):
+        return self.case["theta0"] + self.case["omega"] * t
+
+    def ssprk3_step(self, Q, t, dt):
+        """Three-stage SSP Runge-Kutta step (Shu-Osher form); the rotor angle
+        and the mortars follow the stage times t, t+dt, t+dt/2."""
+        w = self.case["omega"]
+        Q1 = Q + dt * self.residual(Q, self.theta(t), w)
+        Q2 = 0.75 * Q + 0.25 * (Q1 + dt * self.residual(Q1, self.theta(t + dt), w))
+        return Q / 3.0 + 2.0 / 3.0 * (Q2 + dt * self.residual(Q2, self.theta(t + 0.5 * dt), w))
+
+    def run(self, Q, t0, dt, nsteps):
+        Q = np.array(Q, dtype=float)
+        t = t0
+        for _ in range(nsteps):
+            Q = self.ssprk3_step(Q, t, dt)
+            t += dt
+        return Q
+
+    # ------------------------------------------------------------------
+    def sp_coords(self, theta=0.0):
+        """Physical coordinates of the SPs at angle theta, each (N, N, E)."""
+        sp = self.geo.at(theta)["sp"]
+        return np.moveaxis(sp["x"], 0, 2), np.moveaxis(sp["y"], 0, 2)
+
+    def integrate(self, Q):
+        """sum_e sum_ij w_i w_j |J|_ij Q_ij for each variable (4,)."""
+        w = self.ops.w
+        W = (w[:, None] * w[None, :])[:, :, None] * np.moveaxis(self.geo.detJ, 0, 2)
+        return np.einsum("vjie,jie->v", np.asarray(Q), W)
+
+
+def submesh(mesh, elems, depth=2):
+    """Sub-mesh around `elems` for sampled evaluation.
+
+    Holds `elems`, every cell with a sliding face, and `depth` layers of
+    neighbours around both.  Faces whose neighbour is left out become
+    FACE_EXTERNAL; residuals are exact for cells at least `depth` faces away
+    from such faces.  Returns (sub_mesh, global indices of its cells).
+    """
+    E = len(mesh["zone"])
+    keep = np.zeros(E, bool)
+    keep[np.asarray(elems)] = True
+    keep[np.any(mesh["face_kind"] == FACE_SLIDING, axis=1)] = True
+    for _ in range(depth):
+        nb = mesh["nbr"][keep]
+        keep[nb[nb >= 0]] = True
+    idx = np.nonzero(keep)[0]
+    remap = np.full(E, -1, np.int64)
+    remap[idx] = np.arange(len(idx))
+    nb = mesh["nbr"][idx]
+    newnb = np.where(nb >= 0, remap[np.maximum(nb, 0)], -1)
+    kind = mesh["face_kind"][idx].copy()
+    lost = (nb >= 0) & (newnb < 0)
+    kind[lost] = FACE_EXTERNAL
+    sub = dict(mesh)
+    sub.update(xy=mesh["xy"][idx], geom=mesh["geom"][idx], zone=mesh["zone"][idx],
+               nbr=newnb.astype(np.int32),
+               nbr_face=np.where(newnb >= 0, mesh["nbr_face"][idx], -1).astype(np.int32),
+               face_kind=kind)
+    return sub, idx

@@ -1,0 +1,320 @@
+"""Pins of the oracle's residual, mortar and time stepping (Sec. 3, Sec. 4).
+
+- free-stream preservation on fixed, distorted and rotating cells;
+- conservation across the sliding interface (Sec. 3.2; Kopriva's mortar
+  argument): the integral of dQ/dt vanishes on a periodic domain;
+- invariance under relabelling of element corners (orientation bookkeeping)
+  and covariance under a rigid rotation of the whole problem;
+- the mortar at zero offset reduces to a pointwise Rusanov flux across the
+  matching faces; continuity of the residual as the offset wraps;
+- truncation error of the exact vortex and Taylor-Couette solutions decays
+  with refinement; the vortex converges at the paper's orders (Table 1,
+  Table 2, tests/golden/paper_tables.json);
+- SSP-RK3 is third order.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import physics as ph
+from oracle.exact import Couette, vortex_state
+from oracle.ssd import SSD, submesh
+from workloads import cases as C
+from workloads import meshes as M
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")
+
+
+def _wl2(s, e):
+    w = s.ops.w
+    W = (w[:, None] * w[None, :])[:, :, None] * np.moveaxis(s.geo.detJ, 0, 2)
+    return np.array([np.sqrt((W * e[v] ** 2).sum() / W.sum()) for v in range(4)])
+
+
+# ---------------------------------------------------------------- free stream
+@pytest.mark.parametrize("N", [2, 3, 4, 5])
+def test_freestream_fixed_box(N):
+    case = C.vortex_case()
+    mesh = M.box_mesh(6, 5, distort=0.2)
+    s = SSD(mesh, case, N)
+    R = s.residual(C.uniform_state(case, N, s.E, v=0.2), 0.0, 0.0)
+    assert np.abs(R).max() < 1e-11
+    if N >= 3:   # cubic cells: metrics of degree 3 <= N
+        mesh = M.box_mesh(6, 5, distort=0.2, curved=0.08)
+        s = SSD(mesh, case, N)
+        R = s.residual(C.uniform_state(case, N, s.E, v=0.2), 0.0, 0.0)
+        assert np.abs(R).max() < 1e-11
+
+
+@pytest.mark.parametrize("N", [2, 3, 4])
+def test_freestream_rotating_box(N):
+    """A whole rotating zone of bilinear cells (2 p_g <= N)."""
+    case = C.vortex_case()
+    mesh = M.box_mesh(6, 5, distort=0.2, zone=1)
+    s = SSD(mesh, case, N)
+    R = s.residual(C.uniform_state(case, N, s.E, v=-0.3), 0.4, 1.3)
+    assert np.abs(R).max() < 1e-11
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_freestream_sliding_mesh(N):
+    """Exact in every cell away from the interface; at interface cells the
+    exact-circle mortar differs from the cells' cubic faces by a geometric
+    error that shrinks with refinement."""
+    case = C.vortex_case(omega=0.5)
+    errs = []
+    for f in (1, 4):
+        mesh = M.vortex_mesh(f)
+        s = SSD(mesh, case, N)
+        R = s.residual(C.uniform_state(case, N, s.E), 0.17, 0.5)
+        em = np.abs(R).max(axis=(0, 1, 2))
+        sl = np.any(mesh["face_kind"] == M.FACE_SLIDING, axis=1)
+        assert em[~sl].max() < 1e-11
+        errs.append(em[sl].max())
+    assert errs[1] < 0.3 * errs[0]
+
+
+# ---------------------------------------------------------------- conservation
+def _vortex_setup(N, f=1, omega=0.5, theta0=0.0):
+    case = C.vortex_case(omega=omega, theta0=theta0)
+    s = SSD(M.vortex_mesh(f), case, N)
+    x, y = s.sp_coords(theta0)
+    return case, s, vortex_state(x, y, 0.0, case)
+
+
+@pytest.mark.parametrize("N", [2, 3, 4])
+@pytest.mark.parametrize("theta", [0.0, 0.05, 0.1963495408, 0.31, -0.77])
+def test_conservation_across_interface(N, theta):
+    case, s, Q = _vortex_setup(N)
+    R = s.residual(Q, theta, 0.5)
+    tot = s.integrate(R)
+    scale = s.integrate(np.abs(R))
+    assert np.all(np.abs(tot) <= 1e-12 * scale)
+
+
+def test_conservation_over_rk_steps():
+    case, s, Q = _vortex_setup(3, omega=0.5, theta0=2 * np.pi / 32 - 0.02)
+    m0 = s.integrate(Q)
+    Q = s.run(Q, 0.0, 2e-2, 5)           # delta wraps within these steps
+    assert np.allclose(s.integrate(Q), m0, rtol=0, atol=1e-13 * np.abs(m0).max())
+
+
+# ---------------------------------------------------------- orientation, frame
+def _relabel_state(Q, shifts):
+    """State on the relabelled mesh.  One quarter-turn relabelling gives old
+    coordinates xi = 1 - eta', eta = xi'; it is applied `shift` times."""
+    out = Q.copy()
+    for e, k in enumerate(shifts):
+        a = Q[:, :, :, e]
+        for _ in range(k % 4):
+            # new[j', i'] = old[i', N-1-j']  (old xi = 1 - eta', old eta = xi')
+            a = np.transpose(a, (0, 2, 1))[:, ::-1, :]
+        out[:, :, :, e] = a
+    return out
+
+
+@pytest.mark.parametrize("meshname", ["vortex", "couette"])
+def test_relabel_invariance(meshname):
+    rng = np.random.default_rng(3)
+    if meshname == "vortex":
+        case, s, Q = _vortex_setup(3, omega=0.5)
+        mesh = M.vortex_mesh(1)
+    else:
+        case = C.couette_case()
+        mesh = M.couette_mesh(4, 16, phi_offset=0.4 * 2 * np.pi / 16)
+        s = SSD(mesh, case, 3)
+        x, y = s.sp_coords(0.0)
+        Q = Couette(case).state(x, y)
+        Q[0] *= 1 + 0.01 * np.sin(3 * x) * np.cos(2 * y)
+    shifts = rng.integers(0, 4, s.E)
+    m2 = M.relabel(mesh, shifts)
+    s2 = SSD(m2, case, 3)
+    Q2 = _relabel_state(Q, shifts)
+    for th in (0.0, 0.123):
+        R = s.residual(Q, th, case["omega"])
+        R2 = s2.residual(Q2, th, case["omega"])
+        assert np.allclose(_relabel_state(R, shifts), R2, rtol=0, atol=1e-10 * np.abs(R).max())
+
+
+def test_rotation_covariance():
+    case, s, Q = _vortex_setup(3, omega=0.7)
+    a = 0.37
+    mesh2 = M.rotate_mesh(M.vortex_mesh(1), a)
+    s2 = SSD(mesh2, case, 3)
+    ca, sa = np.cos(a), np.sin(a)
+
+    def rot(A):
+        B = A.copy()
+        B[1], B[2] = ca * A[1] - sa * A[2], sa * A[1] + ca * A[2]
+        return B
+    R = s.residual(Q, 0.21, 0.7)
+    R2 = s2.residual(rot(Q), 0.21, 0.7)
+    assert np.allclose(rot(R), R2, rtol=0, atol=1e-10 * np.abs(R).max())
+
+
+# ------------------------------------------------------------- mortar special
+def test_mortar_zero_offset_is_pointwise_rusanov():
+    case, s, Q = _vortex_setup(3, omega=0.5)
+    itf = s.iface
+    m, dlt, thL, thR = itf.placement(0.0)
+    assert dlt == 0.0 or dlt > 1 - 1e-12 or dlt < 1e-12
+    _, diag = s.residual(Q, 0.0, 0.5, diag=True)
+    fs = diag["face_flux"]
+    # traces: re-interpolate each side's face values directly
+    q = np.moveaxis(Q, 3, 1)
+    I = s.ops.I
+    qxi = np.einsum("ki,veji->vejk", I, q)
+    qeta = np.einsum("kj,veji->veki", I, q)
+    T = s._faces(qxi, qeta, s.N)
+    TL, TR = itf.canon(itf.L, T), itf.canon(itf.Rt, T)
+    if dlt > 0.5:
+        m = (m + 1) % itf.K
+    TRm = TR[:, (np.arange(itf.K) + m) % itf.K]
+    phi = itf.face_angles(itf.L, thL)
+    sc = itf.R * itf.delta
+    f = ph.rusanov(TL, TRm, np.cos(phi) * sc, np.sin(phi) * sc, 0.0, case["gamma"])
+    got = itf.canon(itf.L, fs)
+    assert np.allclose(got, f, rtol=0, atol=1e-11)
+
+
+def test_residual_continuous_across_wrap():
+    case, s, Q = _vortex_setup(3, omega=0.5)
+    D = s.iface.delta
+    R1 = s.residual(Q, D * (1 - 1e-9), 0.5)
+    R2 = s.residual(Q, D * (1 + 1e-9), 0.5)
+    m1 = s.iface.placement(D * (1 - 1e-9))[0]
+    m2 = s.iface.placement(D * (1 + 1e-9))[0]
+    assert m1 != m2
+    assert np.abs(R1 - R2).max() < 1e-6 * np.abs(R1).max()
+
+
+# ------------------------------------------------------------ truncation error
+@pytest.mark.parametrize("N,min_order", [(3, 1.4), (4, 2.2)])
+def test_vortex_truncation_error_decays(N, min_order):
+    case = C.vortex_case(omega=1.0)
+    errs = []
+    for f in (1, 2):
+        s = SSD(M.vortex_mesh(f), case, N)
+        t, h = 0.3, 1e-5
+
+        def qat(tt):
+            x, y = s.sp_coords(s.theta(tt))
+            return vortex_state(x, y, tt, case)
+        dQ = (qat(t + h) - qat(t - h)) / (2 * h)     # d/dt following the SPs
+        R = s.residual(qat(t), s.theta(t), case["omega"])
+        errs.append(_wl2(s, R - dQ))
+    order = np.log2(errs[0] / errs[1])
+    assert np.all(order > min_order), order
+    assert np.all(errs[1] < 3e-3)
+
+
+@pytest.mark.parametrize("N,min_order", [(2, 0.6), (3, 2.0), (4, 2.2)])
+def test_couette_truncation_error_decays(N, min_order):
+    """Exact steady compressible Couette state (viscous path, isothermal
+    walls, viscous mortar at a non-zero offset)."""
+    case = C.couette_case()
+    ex = Couette(case)
+    errs = []
+    for nr in (4, 8):
+        mesh = M.couette_mesh(nr, 4 * nr, phi_offset=0.3 * 2 * np.pi / (4 * nr))
+        s = SSD(mesh, case, N)
+        th, h = 0.2, 1e-5
+
+        def qat(tt):
+            x, y = s.sp_coords(tt)
+            return ex.state(x, y)
+        dQ = (qat(th + h) - qat(th - h)) / (2 * h)
+        R = s.residual(qat(th), th, case["omega"])
+        errs.append(_wl2(s, R - dQ))
+    order = np.log2(errs[0] / errs[1])
+    assert np.all(order > min_order), order
+
+
+def test_couette_mass_conservation():
+    case = C.couette_case()
+    mesh = M.couette_mesh(4, 16, phi_offset=0.27)
+    s = SSD(mesh, case, 3)
+    x, y = s.sp_coords(0.0)
+    Q = Couette(case).state(x, y)
+    Q[0] *= 1 + 0.02 * np.sin(2 * x + y)
+    R = s.residual(Q, 0.31, 1.0)
+    tot = s.integrate(R)
+    assert abs(tot[0]) < 1e-12 * s.integrate(np.abs(R))[0]
+
+
+# ------------------------------------------------------------------ time order
+def test_ssprk3_third_order():
+    class Lin(SSD):
+        def __init__(self, lam):
+            self.lam = lam
+            self.case = dict(theta0=0.0, omega=0.0)
+
+        def residual(self, Q, theta, omega, diag=False):
+            return self.lam * Q
+    lam = -1.3
+    s = Lin(lam)
+    errs = []
+    for n in (10, 20, 40):
+        Q = np.array([1.0])
+        Q = s.run(Q, 0.0, 1.0 / n, n)
+        errs.append(abs(Q[0] - np.exp(lam)))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(orders - 3.0) < 0.15), orders
+
+
+# ---------------------------------------------------------------- convergence
+def _vortex_errors(N, fs, T, dt0):
+    case = C.vortex_case(omega=1.0)
+    out = []
+    for f in fs:
+        s = SSD(M.vortex_mesh(f), case, N)
+        x, y = s.sp_coords(0.0)
+        Q = vortex_state(x, y, 0.0, case)
+        n = int(round(T / (dt0 / f)))
+        Q = s.run(Q, 0.0, T / n, n)
+        xT, yT = s.sp_coords(s.theta(T))
+        e = Q[0] - vortex_state(xT, yT, T, case)[0]
+        w = s.ops.w
+        W = (w[:, None] * w[None, :])[:, :, None] * np.moveaxis(s.geo.detJ, 0, 2)
+        out.append(((W * np.abs(e)).sum() / W.sum(), np.sqrt((W * e * e).sum() / W.sum())))
+    return np.array(out)
+
+
+def _paper_orders(table):
+    with open(GOLD) as fh:
+        g = json.load(fh)[table]
+    return np.array([[r["L1_order"], r["L2_order"]] for r in g["rows"] if r["L1_order"] is not None])
+
+
+@pytest.mark.parametrize("N,table,T,dt0,slack", [(3, "table1_vortex_N3", 0.2, 0.01, 0.75),
+                                                  (4, "table2_vortex_N4", 0.2, 0.004, 1.1)])
+def test_vortex_convergence_two_levels(N, table, T, dt0, slack):
+    """Density error order on 384 -> 1536 cells against Table 1 / Table 2."""
+    e = _vortex_errors(N, (1, 2), T, dt0)
+    order = np.log2(e[0] / e[1])
+    paper = _paper_orders(table).min(axis=0)
+    assert np.all(order > paper - slack), (order, paper)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("N,table,dt0", [(3, "table1_vortex_N3", 0.01), (4, "table2_vortex_N4", 0.004)])
+def test_vortex_convergence_three_levels(N, table, dt0):
+    e = _vortex_errors(N, (1, 2, 4), 0.5, dt0)
+    order = np.log2(e[1] / e[2])
+    paper = _paper_orders(table).min(axis=0)
+    assert np.all(order > paper - 0.4), (order, paper)
+
+
+# ---------------------------------------------------------------- sub-meshes
+def test_submesh_matches_full_residual():
+    case, s, Q = _vortex_setup(3, omega=0.5)
+    R = s.residual(Q, 0.08, 0.5)
+    mesh = M.vortex_mesh(1)
+    pick = np.array([0, 17, 100, 250, 300, 383])
+    sub, idx = submesh(mesh, pick, depth=1)
+    s2 = SSD(sub, case, 3)
+    R2 = s2.residual(Q[..., idx], 0.08, 0.5)
+    loc = np.searchsorted(idx, pick)
+    assert np.allclose(R2[..., loc], R[..., pick], rtol=0, atol=1e-12)
