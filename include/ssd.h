@@ -1,0 +1,204 @@
+/*
+ * ssd.h -- C ABI of the sliding-mesh spectral difference (SSD) library.
+ *
+ * The library evaluates the per-stage residual of the 2-D compressible
+ * Euler / Navier-Stokes equations on quadrilateral meshes whose rotating
+ * and stationary zones meet at a circular sliding interface, and advances
+ * it with an explicit SSP Runge-Kutta method, on one AMD Instinct GPU
+ * (Zhang & Liang, arXiv:1503.02198).
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns ssd_status: 0 on success, a negative code on
+ *    failure.  No C++ exception crosses the ABI.  After a failure
+ *    ssd_last_error() returns a message for the calling thread.
+ *  - A failing call has no side effect on the mesh handle.
+ *  - Device arrays (q, r, work) are caller-owned device pointers of 32-bit
+ *    floats; the library never frees or retains them beyond the call.
+ *  - State layout: q[v][j][i][e], v = 0..3 the conservative variables
+ *    rho, rho u, rho v, E (Sec. 2.1, eq. Q) at solution point (X_i, X_j) of
+ *    element e; element index fastest.  state_len = 4 N^2 n_elem floats.
+ *    The state holds the physical Q at the solution points; since the
+ *    Jacobian of a fixed or rigidly rotating cell does not change in time,
+ *    d(|J| Q)/dt = |J| dQ/dt and the residual is returned as dQ/dt.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls that enqueue work return before it completes.
+ *  - One handle is used by one host thread and one stream at a time.
+ */
+#ifndef SSD_H
+#define SSD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ssd_mesh ssd_mesh;
+
+typedef enum {
+  SSD_OK = 0,
+  SSD_ERR_INVALID_ARG = -1, /* null pointer, out-of-range size or value   */
+  SSD_ERR_MESH = -2,        /* the mesh description is inconsistent        */
+  SSD_ERR_STATE = -3,       /* call out of order (e.g. stale mortars)      */
+  SSD_ERR_DEVICE = -4,      /* a HIP runtime call failed                   */
+  SSD_ERR_NOMEM = -5,       /* device or host allocation failed            */
+  SSD_ERR_NUMERIC = -6      /* a stage produced rho <= 0, p <= 0 or NaN    */
+} ssd_status;
+
+/* Face tags of ssd_mesh_desc.face_kind. */
+enum {
+  SSD_FACE_INTERIOR = 0,        /* conforming neighbour, Rusanov flux (Sec. 3.1)   */
+  SSD_FACE_PERIODIC = 1,        /* conforming neighbour across a periodic cut      */
+  SSD_FACE_SLIDING = 2,         /* on the circular rotor/stator interface (Sec. 3.2) */
+  SSD_FACE_WALL_ISOTHERMAL = 3, /* no-slip wall at T_wall moving with its zone      */
+  SSD_FACE_WALL_SLIP = 4,       /* impermeable slip wall moving with its zone       */
+  SSD_FACE_FARFIELD = 5         /* Rusanov flux against the far-field state         */
+};
+
+/* Element maps of ssd_mesh_desc.elem_geom (Sec. 3.1: 4-node linear cells,
+ * 12-node cubic cells along curved boundaries). */
+enum { SSD_GEOM_LINEAR = 0, SSD_GEOM_CUBIC = 1 };
+
+/* Time integrators. SSP-RK3 in Shu-Osher form, stage times t, t+dt, t+dt/2. */
+typedef enum { SSD_RK3_SSP = 0 } ssd_rk;
+
+/*
+ * Mesh and case description.  All arrays are host memory, read during
+ * ssd_create_mesh and copied; the caller may free them afterwards.
+ *
+ *  N          solution points per direction = order of accuracy, 2..6
+ *             (Sec. 3.1: N Chebyshev-Gauss SPs, N+1 FPs per direction).
+ *  elem_xy    [n_elem][12][2] node coordinates, counter-clockwise around
+ *             the reference square [0,1]^2: (0,0) (1/3,0) (2/3,0) (1,0)
+ *             (1,1/3) (1,2/3) (1,1) (2/3,1) (1/3,1) (0,1) (0,2/3) (0,1/3).
+ *             Linear cells use only nodes 0, 3, 6, 9.
+ *  elem_geom  [n_elem] SSD_GEOM_LINEAR (bilinear) or SSD_GEOM_CUBIC
+ *             (12-node cubic serendipity).
+ *  elem_zone  [n_elem] 0 stationary, 1 rotating about rot_center.
+ *  nbr_elem, nbr_face, face_kind   [n_elem][4] for the local faces
+ *             0: eta=0, 1: xi=1, 2: eta=1, 3: xi=0.  INTERIOR and PERIODIC
+ *             faces name their neighbour element and its local face; other
+ *             kinds set nbr_elem = -1.
+ *  rot_center, iface_radius   centre of rotation and radius of the sliding
+ *             circle (ignored without SLIDING faces).
+ *  omega, theta0   rotation rate of zone 1 and its angle at t = 0; the
+ *             rotor angle used by ssd_rk_step is theta0 + omega t.
+ *  gamma, gas_R, mu, prandtl   gas properties; mu = 0 selects the Euler
+ *             equations (Sec. 2.1), constant mu otherwise.
+ *  T_wall     temperature of isothermal walls.
+ *  farfield   rho, u, v, p of far-field faces.
+ */
+typedef struct {
+  int32_t N;
+  int32_t n_elem;
+  const double *elem_xy;
+  const int32_t *elem_geom;
+  const int32_t *elem_zone;
+  const int32_t *nbr_elem;
+  const int32_t *nbr_face;
+  const int32_t *face_kind;
+  double rot_center[2];
+  double iface_radius;
+  double omega;
+  double theta0;
+  double gamma;
+  double gas_R;
+  double mu;
+  double prandtl;
+  double T_wall;
+  double farfield[4];
+} ssd_mesh_desc;
+
+typedef struct {
+  int32_t N;          /* solution points per direction                  */
+  int32_t n_elem;     /* elements                                       */
+  int32_t K;          /* faces per side of the sliding interface (0: none) */
+  int32_t n_cubic;    /* cubic elements                                 */
+  int32_t viscous;    /* 1 when mu > 0                                  */
+  int32_t device;     /* HIP device the handle lives on                 */
+  int64_t state_len;  /* floats in one state array: 4 N^2 n_elem        */
+  int64_t work_len;   /* floats ssd_rk_step needs in `work`: 2 state_len */
+} ssd_info;
+
+/*
+ * Validates the description, builds FP64 geometry and operator tables and
+ * uploads them to `device`.  Fails with SSD_ERR_MESH when a neighbour link is
+ * not mutual, a face tag is unknown, |J| <= 0 at a solution or flux point,
+ * the two sides of the sliding interface hold different numbers of faces,
+ * or their faces are not uniform arcs of the circle (Sec. 3.2 assumes
+ * uniformly meshed interface faces).  *out receives the handle.
+ */
+ssd_status ssd_create_mesh(const ssd_mesh_desc *desc, int device, ssd_mesh **out);
+
+/* Frees every device and host resource of the handle (synchronises). */
+ssd_status ssd_destroy_mesh(ssd_mesh *m);
+
+/* Sizes of the handle; synchronous, no device work. */
+ssd_status ssd_query(const ssd_mesh *m, ssd_info *info);
+
+/*
+ * Sets the rotor angle theta and rate omega used by the next
+ * ssd_mortar_rebuild and ssd_residual (Sec. 2.2: grid velocity
+ * omega x r, coordinates rotated analytically).  Marks the mortars stale.
+ */
+ssd_status ssd_set_rotation(ssd_mesh *m, double theta, double omega);
+
+/*
+ * Rebuilds the sliding-interface connectivity and projection matrices for
+ * the current angle on the device in FP64 (Sec. 3.2: each face meets two
+ * mortars whose offset o and scale s follow the rotor, eq. xz; the
+ * face-to-mortar matrices M^-1 S and mortar-to-face matrices s M^-1 S^T of
+ * eqs. prjQ2 and prjF2).  Enqueued on `stream`; a no-op without an
+ * interface.
+ */
+ssd_status ssd_mortar_rebuild(ssd_mesh *m, void *stream);
+
+/*
+ * r = dQ/dt for state q at the current angle and rate: interpolation to
+ * the flux points (eq. Qt), transformed fluxes (eq. transform_relation)
+ * with the ALE terms, common fluxes on conforming, boundary and sliding
+ * faces (Sec. 3.1, Sec. 3.2), and the flux-polynomial derivative (eqs. Ft,
+ * Gt).  q and r: device float arrays of state_len, must not overlap.
+ * SSD_ERR_STATE if the mortars are stale (ssd_set_rotation without a later
+ * ssd_mortar_rebuild).
+ */
+ssd_status ssd_residual(ssd_mesh *m, const float *q, float *r, void *stream);
+
+/*
+ * One SSP-RK3 step from t to t + dt in place on q (device, state_len
+ * floats), using `work` (device, work_len floats) as scratch.  Before each
+ * stage it sets the angle theta0 + omega t_stage and rebuilds the mortars
+ * (Sec. 3.2: the connectivity is updated at every Runge-Kutta stage).
+ * SSD_ERR_INVALID_ARG for dt <= 0 or a non-finite t; work must not
+ * overlap q.
+ */
+ssd_status ssd_rk_step(ssd_mesh *m, float *q, float *work, double t, double dt, ssd_rk scheme,
+                       void *stream);
+
+/*
+ * Synchronises `stream` and reports SSD_ERR_NUMERIC if any stage since the
+ * last check produced a non-finite value, rho <= 0 or p <= 0; clears the
+ * flag.
+ */
+ssd_status ssd_check(ssd_mesh *m, void *stream);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char *ssd_last_error(void);
+
+/*
+ * Kernel timing.  While enabled, every kernel launch of the handle is
+ * bracketed by HIP events on its stream.  ssd_timing_read synchronises and
+ * returns the summed milliseconds and the launch count of one kernel class
+ * (SSD_KERNEL_*) since the last reset; ssd_timing_reset clears them.
+ */
+enum { SSD_KERNEL_STAGE = 0, SSD_KERNEL_TRACES = 1, SSD_KERNEL_MORTAR = 2, SSD_KERNEL_REBUILD = 3,
+       SSD_KERNEL_GRAD = 4, SSD_KERNEL_COUNT = 5 };
+ssd_status ssd_timing_enable(ssd_mesh *m, int enable);
+ssd_status ssd_timing_reset(ssd_mesh *m);
+ssd_status ssd_timing_read(ssd_mesh *m, int kernel, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSD_H */

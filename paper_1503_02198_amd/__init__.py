@@ -1,0 +1,6 @@
+"""MI355X-native sliding-mesh spectral difference (SSD) solver.
+
+The compute path is the HIP library libssd.so (C ABI in include/ssd.h);
+`paper_1503_02198_amd.ssd` is its ctypes binding.
+"""
+from .ssd import Mesh, SSDError, lib  # noqa: F401

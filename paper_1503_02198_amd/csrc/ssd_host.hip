@@ -1,0 +1,886 @@
+// Host side of the SSD library: the C ABI of include/ssd.h, mesh ingest and
+// validation, FP64 operator and geometry tables, device buffers, and the
+// per-stage launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ssd_internal.h"
+
+using namespace ssd;
+
+namespace {
+
+thread_local std::string g_err;
+
+ssd_status fail(ssd_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+#define SSD_HIP(call, what)                                                                   \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail(e_ == hipErrorOutOfMemory ? SSD_ERR_NOMEM : SSD_ERR_DEVICE,                  \
+                  std::string(what) + ": " + hipGetErrorString(e_));                           \
+  } while (0)
+
+// Keeps the caller's current device across a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+constexpr double PI = 3.14159265358979323846;
+const int FACE_CORNERS[4][2] = {{0, 3}, {3, 6}, {9, 6}, {0, 9}};
+
+// ---------------------------------------------------------------------------
+// 1-D operators (Sec. 3.1)
+// ---------------------------------------------------------------------------
+void symmetrize(std::vector<double> &x) {
+  const int n = int(x.size());
+  for (int s = 0; s < n / 2; ++s) {
+    const double a = 0.5 * (x[s] + 1.0 - x[n - 1 - s]);
+    x[s] = a;
+    x[n - 1 - s] = 1.0 - a;
+  }
+  if (n % 2) x[n / 2] = 0.5;
+}
+
+// Chebyshev-Gauss points mapped to [0,1].
+std::vector<double> solution_points(int N) {
+  std::vector<double> X(N);
+  for (int s = 0; s < N; ++s) X[s] = 0.5 * (1.0 - std::cos((2.0 * s + 1.0) * PI / (2.0 * N)));
+  symmetrize(X);
+  return X;
+}
+
+// Gauss-Legendre nodes (ascending) and weights on [-1,1] by Newton's method
+// on the three-term recurrence.
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) {
+        p1 = z;
+        p0 = 1.0;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) {
+        p1 = z;
+        p0 = 1.0;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+    }
+    x[n - 1 - i] = z;
+    w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// End points plus the Legendre-Gauss points of order N-1, on [0,1].
+std::vector<double> flux_points(int N) {
+  std::vector<double> Xf(N + 1);
+  Xf[0] = 0.0;
+  Xf[N] = 1.0;
+  if (N >= 2) {
+    std::vector<double> g, w;
+    gauss_legendre(N - 1, g, w);
+    std::vector<double> in(N - 1);
+    for (int i = 0; i < N - 1; ++i) in[i] = 0.5 * (g[i] + 1.0);
+    symmetrize(in);
+    for (int i = 0; i < N - 1; ++i) Xf[i + 1] = in[i];
+  }
+  return Xf;
+}
+
+std::vector<double> bary_weights(const std::vector<double> &x) {
+  const int n = int(x.size());
+  std::vector<double> b(n, 1.0);
+  for (int i = 0; i < n; ++i)
+    for (int t = 0; t < n; ++t)
+      if (t != i) b[i] /= (x[i] - x[t]);
+  return b;
+}
+
+// Cardinal basis values at x (barycentric form, exact at the nodes).
+std::vector<double> cardinal(const std::vector<double> &x, const std::vector<double> &bw, double at) {
+  const int n = int(x.size());
+  std::vector<double> out(n, 0.0);
+  for (int i = 0; i < n; ++i)
+    if (at == x[i]) {
+      out[i] = 1.0;
+      return out;
+    }
+  double den = 0.0;
+  for (int i = 0; i < n; ++i) den += bw[i] / (at - x[i]);
+  for (int i = 0; i < n; ++i) out[i] = (bw[i] / (at - x[i])) / den;
+  return out;
+}
+
+// Derivatives of the cardinal basis at a point that is not a node:
+// l_k'(x) = l_k(x) sum_{m != k} 1 / (x - x_m).
+std::vector<double> cardinal_deriv(const std::vector<double> &x, const std::vector<double> &bw,
+                                   double at) {
+  const int n = int(x.size());
+  std::vector<double> v = cardinal(x, bw, at), out(n);
+  for (int k = 0; k < n; ++k) {
+    double s = 0.0;
+    for (int m = 0; m < n; ++m)
+      if (m != k) s += 1.0 / (at - x[m]);
+    out[k] = v[k] * s;
+  }
+  return out;
+}
+
+bool invert(int n, std::vector<double> a, std::vector<double> &inv) {
+  inv.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i) inv[i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(a[r * n + c]) > std::fabs(a[p * n + c])) p = r;
+    if (std::fabs(a[p * n + c]) < 1e-300) return false;
+    for (int k = 0; k < n; ++k) {
+      std::swap(a[c * n + k], a[p * n + k]);
+      std::swap(inv[c * n + k], inv[p * n + k]);
+    }
+    const double d = a[c * n + c];
+    for (int k = 0; k < n; ++k) {
+      a[c * n + k] /= d;
+      inv[c * n + k] /= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = a[r * n + c];
+      for (int k = 0; k < n; ++k) {
+        a[r * n + k] -= f * a[c * n + k];
+        inv[r * n + k] -= f * inv[c * n + k];
+      }
+    }
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// element maps (Sec. 2.3, Sec. 3.1)
+// ---------------------------------------------------------------------------
+// Reference coordinates of the 12 perimeter nodes.
+const double NODE_XI[12] = {0, 1. / 3, 2. / 3, 1, 1, 1, 1, 2. / 3, 1. / 3, 0, 0, 0};
+const double NODE_ETA[12] = {0, 0, 0, 0, 1. / 3, 2. / 3, 1, 1, 1, 1, 2. / 3, 1. / 3};
+
+// Cubic serendipity shape functions on [0,1]^2 (closed form on [-1,1]^2 with
+// s = 2 xi - 1, t = 2 eta - 1) and their xi, eta derivatives.
+void serendipity(double xi, double eta, double Nf[12], double Nx[12], double Ny[12]) {
+  const double s = 2.0 * xi - 1.0, t = 2.0 * eta - 1.0;
+  for (int a = 0; a < 12; ++a) {
+    const double si = 2.0 * NODE_XI[a] - 1.0, ti = 2.0 * NODE_ETA[a] - 1.0;
+    double n, ds, dt;
+    if (std::fabs(std::fabs(si) - 1.0) < 1e-12 && std::fabs(std::fabs(ti) - 1.0) < 1e-12) {
+      const double A = 1.0 + s * si, B = 1.0 + t * ti, Cc = 9.0 * (s * s + t * t) - 10.0;
+      n = A * B * Cc / 32.0;
+      ds = (si * B * Cc + A * B * 18.0 * s) / 32.0;
+      dt = (A * ti * Cc + A * B * 18.0 * t) / 32.0;
+    } else if (std::fabs(std::fabs(ti) - 1.0) < 1e-12) {   // node on an eta = const edge
+      const double B = 1.0 + t * ti, P = 1.0 - s * s, Q = 1.0 + 9.0 * s * si;
+      n = 9.0 / 32.0 * B * P * Q;
+      ds = 9.0 / 32.0 * B * (-2.0 * s * Q + P * 9.0 * si);
+      dt = 9.0 / 32.0 * ti * P * Q;
+    } else {                                               // node on a xi = const edge
+      const double A = 1.0 + s * si, P = 1.0 - t * t, Q = 1.0 + 9.0 * t * ti;
+      n = 9.0 / 32.0 * A * P * Q;
+      dt = 9.0 / 32.0 * A * (-2.0 * t * Q + P * 9.0 * ti);
+      ds = 9.0 / 32.0 * si * P * Q;
+    }
+    Nf[a] = n;
+    Nx[a] = 2.0 * ds;
+    Ny[a] = 2.0 * dt;
+  }
+}
+
+struct MapVal {
+  double x, y, xx, xe, yx, ye;   // position and d/dxi, d/deta
+};
+
+MapVal map_at(const double *xy, int geom, double xi, double eta) {
+  MapVal r{};
+  if (geom == SSD_GEOM_CUBIC) {
+    double Nf[12], Nx[12], Ny[12];
+    serendipity(xi, eta, Nf, Nx, Ny);
+    for (int a = 0; a < 12; ++a) {
+      r.x += Nf[a] * xy[2 * a];
+      r.y += Nf[a] * xy[2 * a + 1];
+      r.xx += Nx[a] * xy[2 * a];
+      r.yx += Nx[a] * xy[2 * a + 1];
+      r.xe += Ny[a] * xy[2 * a];
+      r.ye += Ny[a] * xy[2 * a + 1];
+    }
+  } else {
+    const int c[4] = {0, 3, 6, 9};
+    const double w[4] = {(1 - xi) * (1 - eta), xi * (1 - eta), xi * eta, (1 - xi) * eta};
+    const double wx[4] = {-(1 - eta), (1 - eta), eta, -eta};
+    const double we[4] = {-(1 - xi), -xi, xi, (1 - xi)};
+    for (int a = 0; a < 4; ++a) {
+      const double px = xy[2 * c[a]], py = xy[2 * c[a] + 1];
+      r.x += w[a] * px;
+      r.y += w[a] * py;
+      r.xx += wx[a] * px;
+      r.yx += wx[a] * py;
+      r.xe += we[a] * px;
+      r.ye += we[a] * py;
+    }
+  }
+  return r;
+}
+
+double wrap_pi(double a) {
+  a = std::fmod(a + PI, 2.0 * PI);
+  if (a < 0) a += 2.0 * PI;
+  return a - PI;
+}
+
+struct RingFace {
+  int e, f, flip;
+  double start;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// the handle
+// ---------------------------------------------------------------------------
+struct ssd_mesh {
+  int device = 0;
+  int N = 0, E = 0, K = 0, C = 0;
+  bool viscous = false;
+  OpTables T{};
+  MortarTables MT{};
+  DevMesh D{};
+  double theta0 = 0.0, omega0 = 0.0;   // motion used by ssd_rk_step
+  double theta = 0.0, omega = 0.0;     // angle/rate for ssd_residual
+  bool mortar_fresh = false;
+  std::vector<void *> allocs;
+  float *tr[2] = {nullptr, nullptr};
+  float *mflux = nullptr;
+  MortarState *ms = nullptr;
+  int *flag = nullptr;
+  bool timing = false;
+  struct Timer {
+    std::vector<hipEvent_t> ev;   // start/stop pairs
+    size_t used = 0;
+  } timers[SSD_KERNEL_COUNT];
+};
+
+namespace {
+
+template <class T>
+hipError_t dev_alloc(ssd_mesh *m, T **p, size_t count) {
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+  if (e == hipSuccess) {
+    m->allocs.push_back(q);
+    *p = static_cast<T *>(q);
+  }
+  return e;
+}
+
+void free_all(ssd_mesh *m) {
+  for (void *p : m->allocs) (void)hipFree(p);
+  m->allocs.clear();
+  for (auto &t : m->timers) {
+    for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
+    t.ev.clear();
+    t.used = 0;
+  }
+}
+
+// Brackets one kernel launch with events when timing is on.
+struct LaunchTimer {
+  ssd_mesh *m;
+  int kind;
+  hipStream_t s;
+  hipEvent_t stop = nullptr;
+  LaunchTimer(ssd_mesh *m_, int k, hipStream_t s_) : m(m_), kind(k), s(s_) {
+    if (!m->timing) return;
+    auto &t = m->timers[kind];
+    if (t.used + 2 > t.ev.size()) {
+      for (int i = 0; i < 2; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        t.ev.push_back(e);
+      }
+    }
+    (void)hipEventRecord(t.ev[t.used], s);
+    stop = t.ev[t.used + 1];
+    t.used += 2;
+  }
+  ~LaunchTimer() {
+    if (stop) (void)hipEventRecord(stop, s);
+  }
+};
+
+bool finite_all(const double *v, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+  const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
+  const int N = d->N, E = d->n_elem;
+  m->N = N;
+  m->E = E;
+  m->viscous = d->mu > 0.0;
+  const double cx = d->rot_center[0], cy = d->rot_center[1];
+
+  // ---- operator tables
+  const std::vector<double> X = solution_points(N), Xf = flux_points(N);
+  const std::vector<double> bX = bary_weights(X), bF = bary_weights(Xf);
+  std::memset(&m->T, 0, sizeof(m->T));
+  for (int k = 0; k <= N; ++k) {
+    const std::vector<double> h = cardinal(X, bX, Xf[k]);
+    for (int i = 0; i < N; ++i) m->T.I[k][i] = float(h[i]);
+    m->T.Xf[k] = Xf[k];
+  }
+  for (int i = 0; i < N; ++i) {
+    const std::vector<double> dl = cardinal_deriv(Xf, bF, X[i]);
+    for (int k = 0; k <= N; ++k) m->T.D[i][k] = float(dl[k]);
+    m->T.X[i] = X[i];
+  }
+  // mortar tables: Gauss-Legendre on [0,1], mass matrix and its inverse
+  {
+    std::vector<double> g, w;
+    gauss_legendre(N, g, w);
+    std::memset(&m->MT, 0, sizeof(m->MT));
+    std::vector<double> Mm(N * N, 0.0), Mi;
+    for (int q = 0; q < N; ++q) {
+      m->MT.zq[q] = 0.5 * (g[q] + 1.0);
+      m->MT.wq[q] = 0.5 * w[q];
+      const std::vector<double> h = cardinal(X, bX, m->MT.zq[q]);
+      for (int i = 0; i < N; ++i) m->MT.hq[q][i] = h[i];
+      for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) Mm[i * N + j] += m->MT.wq[q] * h[i] * h[j];
+    }
+    if (!invert(N, Mm, Mi)) return fail(SSD_ERR_MESH, "singular mortar mass matrix");
+    for (int i = 0; i < N; ++i) {
+      m->MT.X[i] = X[i];
+      m->MT.bw[i] = bX[i];
+      for (int j = 0; j < N; ++j) m->MT.Minv[i][j] = Mi[i * N + j];
+    }
+  }
+
+  // ---- elements: flags, geometry checks, cubic tables
+  std::vector<int> eflag(E);
+  std::vector<double> corners(8L * E);
+  std::vector<int> cslot(E, -1);
+  int C = 0;
+  for (int e = 0; e < E; ++e) {
+    const int g = d->elem_geom[e], z = d->elem_zone[e];
+    if (g != SSD_GEOM_LINEAR && g != SSD_GEOM_CUBIC)
+      return fail(SSD_ERR_MESH, "element " + std::to_string(e) + ": unknown geometry kind");
+    if (z != 0 && z != 1)
+      return fail(SSD_ERR_MESH, "element " + std::to_string(e) + ": zone must be 0 or 1");
+    if (!finite_all(d->elem_xy + 24L * e, 24))
+      return fail(SSD_ERR_MESH, "element " + std::to_string(e) + ": non-finite coordinates");
+    if (g == SSD_GEOM_CUBIC) cslot[e] = C++;
+    eflag[e] = (g == SSD_GEOM_CUBIC ? EF_CUBIC : 0) | (z == 1 ? EF_ROT : 0) |
+               (g == SSD_GEOM_CUBIC ? (cslot[e] << 8) : 0);
+    const int cn[4] = {0, 3, 6, 9};
+    for (int a = 0; a < 4; ++a) {
+      corners[(2 * a) * long(E) + e] = d->elem_xy[24L * e + 2 * cn[a]] - cx;
+      corners[(2 * a + 1) * long(E) + e] = d->elem_xy[24L * e + 2 * cn[a] + 1] - cy;
+    }
+  }
+  if (C >= (1 << 23)) return fail(SSD_ERR_MESH, "too many cubic elements");
+  m->C = C;
+  // |J| > 0 at every solution and flux point
+  for (int e = 0; e < E; ++e) {
+    const double *xy = d->elem_xy + 24L * e;
+    const int g = d->elem_geom[e];
+    auto check = [&](double xi, double eta) {
+      const MapVal v = map_at(xy, g, xi, eta);
+      return v.xx * v.ye - v.xe * v.yx > 0.0;
+    };
+    for (int j = 0; j < N; ++j)
+      for (int i = 0; i < N; ++i)
+        if (!check(X[i], X[j]))
+          return fail(SSD_ERR_MESH, "element " + std::to_string(e) + ": |J| <= 0 at a solution point");
+    for (int j = 0; j < N; ++j)
+      for (int k = 0; k <= N; ++k)
+        if (!check(Xf[k], X[j]) || !check(X[j], Xf[k]))
+          return fail(SSD_ERR_MESH, "element " + std::to_string(e) + ": |J| <= 0 at a flux point");
+  }
+  std::vector<double> cmet(cubic_len(N, C));
+  for (int e = 0; e < E; ++e) {
+    const int c = cslot[e];
+    if (c < 0) continue;
+    const double *xy = d->elem_xy + 24L * e;
+    for (int j = 0; j < N; ++j)
+      for (int k = 0; k <= N; ++k) {
+        const MapVal v = map_at(xy, SSD_GEOM_CUBIC, Xf[k], X[j]);
+        cmet[cubic_xi_index(N, C, 0, j, k, c)] = v.xe;
+        cmet[cubic_xi_index(N, C, 1, j, k, c)] = v.ye;
+        cmet[cubic_xi_index(N, C, 2, j, k, c)] = v.x - cx;
+        cmet[cubic_xi_index(N, C, 3, j, k, c)] = v.y - cy;
+        const MapVal u = map_at(xy, SSD_GEOM_CUBIC, X[j], Xf[k]);   // (X_i = X[j], Xf_k)
+        cmet[cubic_eta_index(N, C, 0, k, j, c)] = u.xx;
+        cmet[cubic_eta_index(N, C, 1, k, j, c)] = u.yx;
+        cmet[cubic_eta_index(N, C, 2, k, j, c)] = u.x - cx;
+        cmet[cubic_eta_index(N, C, 3, k, j, c)] = u.y - cy;
+      }
+    for (int j = 0; j < N; ++j)
+      for (int i = 0; i < N; ++i) {
+        const MapVal v = map_at(xy, SSD_GEOM_CUBIC, X[i], X[j]);
+        cmet[cubic_sp_index(N, C, 0, j, i, c)] = v.xx * v.ye - v.xe * v.yx;
+        cmet[cubic_sp_index(N, C, 1, j, i, c)] = v.xx;
+        cmet[cubic_sp_index(N, C, 2, j, i, c)] = v.xe;
+        cmet[cubic_sp_index(N, C, 3, j, i, c)] = v.yx;
+        cmet[cubic_sp_index(N, C, 4, j, i, c)] = v.ye;
+      }
+  }
+
+  // ---- faces
+  std::vector<uint32_t> face(4L * E);
+  std::vector<RingFace> L, R;
+  bool need_wall = false, need_far = false;
+  const double Rs = d->iface_radius;
+  auto corner = [&](int e, int n, double &x, double &y) {
+    x = d->elem_xy[24L * e + 2 * n];
+    y = d->elem_xy[24L * e + 2 * n + 1];
+  };
+  for (int e = 0; e < E; ++e)
+    for (int f = 0; f < 4; ++f) {
+      const int kind = d->face_kind[4L * e + f];
+      const int nb = d->nbr_elem[4L * e + f], nf = d->nbr_face[4L * e + f];
+      const std::string where = "element " + std::to_string(e) + " face " + std::to_string(f);
+      double ax, ay, bx, by;
+      corner(e, FACE_CORNERS[f][0], ax, ay);
+      corner(e, FACE_CORNERS[f][1], bx, by);
+      if (kind == SSD_FACE_INTERIOR || kind == SSD_FACE_PERIODIC) {
+        if (nb < 0 || nb >= E || nf < 0 || nf > 3)
+          return fail(SSD_ERR_MESH, where + ": neighbour out of range");
+        if (d->nbr_elem[4L * nb + nf] != e || d->nbr_face[4L * nb + nf] != f ||
+            d->face_kind[4L * nb + nf] != kind)
+          return fail(SSD_ERR_MESH, where + ": neighbour link is not mutual");
+        double cx2, cy2, dx2, dy2;
+        corner(nb, FACE_CORNERS[nf][0], cx2, cy2);
+        corner(nb, FACE_CORNERS[nf][1], dx2, dy2);
+        const double tx = bx - ax, ty = by - ay, ux = dx2 - cx2, uy = dy2 - cy2;
+        const double len = std::hypot(tx, ty), len2 = std::hypot(ux, uy);
+        if (std::fabs(len - len2) > 1e-8 * std::max(len, len2))
+          return fail(SSD_ERR_MESH, where + ": neighbouring faces differ in length");
+        const int rev = (tx * ux + ty * uy) < 0.0;
+        if (kind == SSD_FACE_INTERIOR) {
+          // the two faces must share their end points
+          const double e1 = rev ? std::hypot(ax - dx2, ay - dy2) + std::hypot(bx - cx2, by - cy2)
+                                : std::hypot(ax - cx2, ay - cy2) + std::hypot(bx - dx2, by - dy2);
+          if (e1 > 1e-8 * len) return fail(SSD_ERR_MESH, where + ": neighbouring faces do not meet");
+        }
+        face[long(f) * E + e] = pack_face(kind, nb, nf, rev);
+      } else if (kind == SSD_FACE_SLIDING) {
+        if (!(Rs > 0.0)) return fail(SSD_ERR_MESH, where + ": sliding face but iface_radius <= 0");
+        const double ra = std::hypot(ax - cx, ay - cy), rb = std::hypot(bx - cx, by - cy);
+        if (std::fabs(ra - Rs) > 1e-8 * Rs || std::fabs(rb - Rs) > 1e-8 * Rs)
+          return fail(SSD_ERR_MESH, where + ": sliding face is not on the interface circle");
+        const double a0 = std::atan2(ay - cy, ax - cx), a1 = std::atan2(by - cy, bx - cx);
+        const double dd = wrap_pi(a1 - a0);
+        RingFace rf;
+        rf.e = e;
+        rf.f = f;
+        rf.flip = dd < 0.0;
+        double st = rf.flip ? a1 : a0;
+        st = std::fmod(st, 2.0 * PI);
+        if (st < 0) st += 2.0 * PI;
+        rf.start = st;
+        double gx = 0, gy = 0;
+        for (int a : {0, 3, 6, 9}) {
+          double px, py;
+          corner(e, a, px, py);
+          gx += 0.25 * px;
+          gy += 0.25 * py;
+        }
+        (std::hypot(gx - cx, gy - cy) < Rs ? L : R).push_back(rf);
+        face[long(f) * E + e] = pack_face(kind, 0, 0, 0);
+      } else if (kind == SSD_FACE_WALL_ISOTHERMAL || kind == SSD_FACE_WALL_SLIP) {
+        need_wall |= kind == SSD_FACE_WALL_ISOTHERMAL;
+        face[long(f) * E + e] = pack_face(kind, 0, 0, 0);
+      } else if (kind == SSD_FACE_FARFIELD) {
+        need_far = true;
+        face[long(f) * E + e] = pack_face(kind, 0, 0, 0);
+      } else {
+        return fail(SSD_ERR_MESH, where + ": unknown face kind");
+      }
+    }
+  if (need_wall && !(d->T_wall > 0.0)) return fail(SSD_ERR_MESH, "isothermal walls need T_wall > 0");
+  if (need_far && !(d->farfield[0] > 0.0 && d->farfield[3] > 0.0))
+    return fail(SSD_ERR_MESH, "far-field faces need rho > 0 and p > 0");
+
+  // ---- sliding interface rings (Sec. 3.2: uniform faces, K per side)
+  if (!L.empty() || !R.empty()) {
+    if (L.size() != R.size())
+      return fail(SSD_ERR_MESH, "sliding interface: " + std::to_string(L.size()) + " inner vs " +
+                                    std::to_string(R.size()) + " outer faces");
+    const int K = int(L.size());
+    const double dphi = 2.0 * PI / K;
+    for (auto *side : {&L, &R}) {
+      std::sort(side->begin(), side->end(),
+                [](const RingFace &a, const RingFace &b) { return a.start < b.start; });
+      const int z0 = d->elem_zone[(*side)[0].e];
+      for (int j = 0; j < K; ++j) {
+        const RingFace &rf = (*side)[j];
+        const double nxt = (j + 1 < K) ? (*side)[j + 1].start : (*side)[0].start + 2.0 * PI;
+        if (std::fabs(nxt - rf.start - dphi) > 1e-8 * dphi)
+          return fail(SSD_ERR_MESH, "sliding interface faces are not uniform");
+        double ax, ay, bx, by;
+        corner(rf.e, FACE_CORNERS[rf.f][0], ax, ay);
+        corner(rf.e, FACE_CORNERS[rf.f][1], bx, by);
+        const double span = std::fabs(wrap_pi(std::atan2(by - cy, bx - cx) - std::atan2(ay - cy, ax - cx)));
+        if (std::fabs(span - dphi) > 1e-8 * dphi)
+          return fail(SSD_ERR_MESH, "sliding interface face spans the wrong angle");
+        if (d->elem_zone[rf.e] != z0)
+          return fail(SSD_ERR_MESH, "one side of the sliding interface spans two zones");
+      }
+    }
+    if (d->elem_zone[L[0].e] == d->elem_zone[R[0].e])
+      return fail(SSD_ERR_MESH, "both sides of the sliding interface are in the same zone");
+    m->K = K;
+    std::vector<int> re(2 * K), rfv(2 * K), rfl(2 * K);
+    for (int j = 0; j < K; ++j) {
+      re[j] = L[j].e;
+      rfv[j] = L[j].f;
+      rfl[j] = L[j].flip;
+      re[K + j] = R[j].e;
+      rfv[K + j] = R[j].f;
+      rfl[K + j] = R[j].flip;
+      face[long(L[j].f) * E + L[j].e] = pack_face(SSD_FACE_SLIDING, j, 0, 0);
+      face[long(R[j].f) * E + R[j].e] = pack_face(SSD_FACE_SLIDING, K + j, 0, 0);
+    }
+    m->D.phi0L = L[0].start;
+    m->D.phi0R = R[0].start;
+    m->D.dphi = dphi;
+    m->D.Rs = Rs;
+    m->D.rotL = d->elem_zone[L[0].e] == 1;
+    m->D.rotR = d->elem_zone[R[0].e] == 1;
+    int *dre, *drf, *drl;
+    SSD_HIP(dev_alloc(m, &dre, 2 * K), "alloc ring");
+    SSD_HIP(dev_alloc(m, &drf, 2 * K), "alloc ring");
+    SSD_HIP(dev_alloc(m, &drl, 2 * K), "alloc ring");
+    SSD_HIP(hipMemcpy(dre, re.data(), 2 * K * sizeof(int), hipMemcpyHostToDevice), "upload ring");
+    SSD_HIP(hipMemcpy(drf, rfv.data(), 2 * K * sizeof(int), hipMemcpyHostToDevice), "upload ring");
+    SSD_HIP(hipMemcpy(drl, rfl.data(), 2 * K * sizeof(int), hipMemcpyHostToDevice), "upload ring");
+    m->D.ring_e = dre;
+    m->D.ring_f = drf;
+    m->D.ring_flip = drl;
+    SSD_HIP(dev_alloc(m, &m->mflux, 2L * K * 4 * N), "alloc mortar flux");
+    SSD_HIP(dev_alloc(m, &m->ms, 1), "alloc mortar state");
+    SSD_HIP(hipMemset(m->ms, 0, sizeof(MortarState)), "clear mortar state");
+  }
+
+  // ---- upload
+  double *dcorn, *dcmet;
+  int *deflag;
+  uint32_t *dface;
+  SSD_HIP(dev_alloc(m, &dcorn, 8L * E), "alloc corners");
+  SSD_HIP(dev_alloc(m, &deflag, E), "alloc flags");
+  SSD_HIP(dev_alloc(m, &dface, 4L * E), "alloc faces");
+  SSD_HIP(dev_alloc(m, &dcmet, cmet.size()), "alloc cubic metrics");
+  SSD_HIP(hipMemcpy(dcorn, corners.data(), corners.size() * sizeof(double), hipMemcpyHostToDevice),
+          "upload corners");
+  SSD_HIP(hipMemcpy(deflag, eflag.data(), E * sizeof(int), hipMemcpyHostToDevice), "upload flags");
+  SSD_HIP(hipMemcpy(dface, face.data(), face.size() * sizeof(uint32_t), hipMemcpyHostToDevice),
+          "upload faces");
+  if (!cmet.empty())
+    SSD_HIP(hipMemcpy(dcmet, cmet.data(), cmet.size() * sizeof(double), hipMemcpyHostToDevice),
+            "upload cubic metrics");
+  for (int b = 0; b < 2; ++b) SSD_HIP(dev_alloc(m, &m->tr[b], 16L * N * E), "alloc traces");
+  SSD_HIP(dev_alloc(m, &m->flag, 1), "alloc flag");
+  SSD_HIP(hipMemset(m->flag, 0, sizeof(int)), "clear flag");
+
+  DevMesh &D = m->D;
+  D.E = E;
+  D.K = m->K;
+  D.C = C;
+  D.N = N;
+  D.corners = dcorn;
+  D.eflag = deflag;
+  D.face = dface;
+  D.cmet = dcmet;
+  D.flag = m->flag;
+  D.gamma = float(d->gamma);
+  D.gas_R = float(d->gas_R);
+  D.mu = float(d->mu);
+  D.prandtl = float(d->prandtl);
+  D.T_wall = float(d->T_wall);
+  const double r0 = d->farfield[0], u0 = d->farfield[1], v0 = d->farfield[2], p0 = d->farfield[3];
+  D.qinf[0] = float(r0);
+  D.qinf[1] = float(r0 * u0);
+  D.qinf[2] = float(r0 * v0);
+  D.qinf[3] = float(p0 / (d->gamma - 1.0) + 0.5 * r0 * (u0 * u0 + v0 * v0));
+
+  m->theta0 = d->theta0;
+  m->omega0 = d->omega;
+  m->theta = d->theta0;
+  m->omega = d->omega;
+  m->mortar_fresh = m->K == 0;
+  return SSD_OK;
+}
+
+ssd_status check_handle(const ssd_mesh *m) {
+  if (!m) return fail(SSD_ERR_INVALID_ARG, "null mesh handle");
+  return SSD_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *ssd_last_error(void) { return g_err.c_str(); }
+
+ssd_status ssd_create_mesh(const ssd_mesh_desc *d, int device, ssd_mesh **out) {
+  if (!d || !out) return fail(SSD_ERR_INVALID_ARG, "null descriptor or output pointer");
+  *out = nullptr;
+  if (d->N < 2 || d->N > NMAX) return fail(SSD_ERR_INVALID_ARG, "N must be in 2..6");
+  if (d->n_elem <= 0 || d->n_elem >= MAX_ELEMS)
+    return fail(SSD_ERR_INVALID_ARG, "n_elem out of range");
+  if (!d->elem_xy || !d->elem_geom || !d->elem_zone || !d->nbr_elem || !d->nbr_face || !d->face_kind)
+    return fail(SSD_ERR_INVALID_ARG, "null mesh array");
+  const double sc[] = {d->rot_center[0], d->rot_center[1], d->iface_radius, d->omega, d->theta0,
+                       d->gamma, d->gas_R, d->mu, d->prandtl, d->T_wall, d->farfield[0],
+                       d->farfield[1], d->farfield[2], d->farfield[3]};
+  if (!finite_all(sc, 14)) return fail(SSD_ERR_INVALID_ARG, "non-finite scalar in descriptor");
+  if (!(d->gamma > 1.0) || !(d->gas_R > 0.0) || d->mu < 0.0)
+    return fail(SSD_ERR_INVALID_ARG, "need gamma > 1, gas_R > 0, mu >= 0");
+  if (d->mu > 0.0 && !(d->prandtl > 0.0)) return fail(SSD_ERR_INVALID_ARG, "need prandtl > 0");
+  if (d->mu > 0.0) return fail(SSD_ERR_INVALID_ARG, "viscous meshes are not supported yet");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return fail(SSD_ERR_DEVICE, "no HIP device");
+  if (device < 0 || device >= ndev) return fail(SSD_ERR_INVALID_ARG, "device out of range");
+  DeviceGuard guard(device);
+  if (!guard.ok) return fail(SSD_ERR_DEVICE, "hipSetDevice failed");
+  ssd_mesh *m = new (std::nothrow) ssd_mesh();
+  if (!m) return fail(SSD_ERR_NOMEM, "host allocation failed");
+  m->device = device;
+  ssd_status st;
+  try {
+    st = build(m, d);
+  } catch (const std::bad_alloc &) {
+    st = fail(SSD_ERR_NOMEM, "host allocation failed");
+  }
+  if (st != SSD_OK) {
+    free_all(m);
+    delete m;
+    return st;
+  }
+  *out = m;
+  return SSD_OK;
+}
+
+ssd_status ssd_destroy_mesh(ssd_mesh *m) {
+  if (!m) return SSD_OK;
+  DeviceGuard guard(m->device);
+  (void)hipDeviceSynchronize();
+  free_all(m);
+  delete m;
+  return SSD_OK;
+}
+
+ssd_status ssd_query(const ssd_mesh *m, ssd_info *info) {
+  if (ssd_status s = check_handle(m)) return s;
+  if (!info) return fail(SSD_ERR_INVALID_ARG, "null info pointer");
+  info->N = m->N;
+  info->n_elem = m->E;
+  info->K = m->K;
+  info->n_cubic = m->C;
+  info->viscous = m->viscous;
+  info->device = m->device;
+  info->state_len = 4L * m->N * m->N * m->E;
+  info->work_len = 2 * info->state_len;
+  return SSD_OK;
+}
+
+ssd_status ssd_set_rotation(ssd_mesh *m, double theta, double omega) {
+  if (ssd_status s = check_handle(m)) return s;
+  if (!std::isfinite(theta) || !std::isfinite(omega))
+    return fail(SSD_ERR_INVALID_ARG, "non-finite theta or omega");
+  m->theta = theta;
+  m->omega = omega;
+  m->mortar_fresh = m->K == 0;
+  return SSD_OK;
+}
+
+ssd_status ssd_mortar_rebuild(ssd_mesh *m, void *stream) {
+  if (ssd_status s = check_handle(m)) return s;
+  if (m->K == 0) {
+    m->mortar_fresh = true;
+    return SSD_OK;
+  }
+  DeviceGuard guard(m->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  {
+    LaunchTimer lt(m, SSD_KERNEL_REBUILD, st);
+    SSD_HIP(launch_rebuild(m->D, m->MT, m->theta, m->ms, st), "mortar rebuild launch");
+  }
+  m->mortar_fresh = true;
+  return SSD_OK;
+}
+
+ssd_status ssd_residual(ssd_mesh *m, const float *q, float *r, void *stream) {
+  if (ssd_status s = check_handle(m)) return s;
+  if (!q || !r) return fail(SSD_ERR_INVALID_ARG, "null state pointer");
+  const size_t bytes = sizeof(float) * 4L * m->N * m->N * m->E;
+  if (overlap(q, bytes, r, bytes)) return fail(SSD_ERR_INVALID_ARG, "q and r overlap");
+  if (!m->mortar_fresh)
+    return fail(SSD_ERR_STATE, "mortars are stale: call ssd_mortar_rebuild after ssd_set_rotation");
+  DeviceGuard guard(m->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  {
+    LaunchTimer lt(m, SSD_KERNEL_TRACES, st);
+    SSD_HIP(launch_traces(m->D, m->T, q, m->tr[0], st), "trace launch");
+  }
+  if (m->K) {
+    LaunchTimer lt(m, SSD_KERNEL_MORTAR, st);
+    SSD_HIP(launch_mortar(m->D, m->T, m->ms, m->tr[0], m->mflux, st), "mortar launch");
+  }
+  Rotation rot{std::cos(m->theta), std::sin(m->theta), m->omega};
+  {
+    LaunchTimer lt(m, SSD_KERNEL_STAGE, st);
+    SSD_HIP(launch_stage(m->D, m->T, rot, q, nullptr, r, m->tr[0], nullptr, m->mflux, 0.f, 1.f,
+                         0.f, false, st),
+            "residual launch");
+  }
+  return SSD_OK;
+}
+
+ssd_status ssd_rk_step(ssd_mesh *m, float *q, float *work, double t, double dt, ssd_rk scheme,
+                       void *stream) {
+  if (ssd_status s = check_handle(m)) return s;
+  if (!q || !work) return fail(SSD_ERR_INVALID_ARG, "null state or work pointer");
+  if (!std::isfinite(t) || !std::isfinite(dt) || !(dt > 0.0))
+    return fail(SSD_ERR_INVALID_ARG, "need finite t and dt > 0");
+  if (scheme != SSD_RK3_SSP) return fail(SSD_ERR_INVALID_ARG, "unknown Runge-Kutta scheme");
+  const long len = 4L * m->N * m->N * m->E;
+  if (overlap(q, len * sizeof(float), work, 2 * len * sizeof(float)))
+    return fail(SSD_ERR_INVALID_ARG, "q and work overlap");
+  DeviceGuard guard(m->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // Shu-Osher SSP-RK3: stage s gives a_s Q^n + b_s (Q_s + dt R(Q_s, t + c_s dt))
+  const float A[3] = {0.0f, 0.75f, 1.0f / 3.0f};
+  const float B[3] = {1.0f, 0.25f, 2.0f / 3.0f};
+  const double Cs[3] = {0.0, 1.0, 0.5};
+  float *w1 = work, *w2 = work + len;
+  const float *in[3] = {q, w1, w2};
+  float *outp[3] = {w1, w2, q};
+  {
+    LaunchTimer lt(m, SSD_KERNEL_TRACES, st);
+    SSD_HIP(launch_traces(m->D, m->T, q, m->tr[0], st), "trace launch");
+  }
+  double th = m->theta0;
+  for (int s = 0; s < 3; ++s) {
+    th = m->theta0 + m->omega0 * (t + Cs[s] * dt);
+    if (m->K) {
+      {
+        LaunchTimer lt(m, SSD_KERNEL_REBUILD, st);
+        SSD_HIP(launch_rebuild(m->D, m->MT, th, m->ms, st), "mortar rebuild launch");
+      }
+      LaunchTimer lt(m, SSD_KERNEL_MORTAR, st);
+      SSD_HIP(launch_mortar(m->D, m->T, m->ms, m->tr[s & 1], m->mflux, st), "mortar launch");
+    }
+    Rotation rot{std::cos(th), std::sin(th), m->omega0};
+    LaunchTimer lt(m, SSD_KERNEL_STAGE, st);
+    SSD_HIP(launch_stage(m->D, m->T, rot, in[s], s ? q : nullptr, outp[s], m->tr[s & 1],
+                         m->tr[(s + 1) & 1], m->mflux, A[s], B[s], float(dt), true, st),
+            "stage launch");
+  }
+  m->theta = m->theta0 + m->omega0 * (t + dt);
+  m->omega = m->omega0;
+  m->mortar_fresh = m->K == 0;
+  return SSD_OK;
+}
+
+ssd_status ssd_check(ssd_mesh *m, void *stream) {
+  if (ssd_status s = check_handle(m)) return s;
+  DeviceGuard guard(m->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SSD_HIP(hipStreamSynchronize(st), "stream synchronize");
+  int flag = 0;
+  SSD_HIP(hipMemcpy(&flag, m->flag, sizeof(int), hipMemcpyDeviceToHost), "read flag");
+  if (flag) {
+    SSD_HIP(hipMemset(m->flag, 0, sizeof(int)), "clear flag");
+    return fail(SSD_ERR_NUMERIC, "a stage produced a non-finite value, rho <= 0 or p <= 0");
+  }
+  return SSD_OK;
+}
+
+ssd_status ssd_timing_enable(ssd_mesh *m, int enable) {
+  if (ssd_status s = check_handle(m)) return s;
+  m->timing = enable != 0;
+  return SSD_OK;
+}
+
+ssd_status ssd_timing_reset(ssd_mesh *m) {
+  if (ssd_status s = check_handle(m)) return s;
+  DeviceGuard guard(m->device);
+  SSD_HIP(hipDeviceSynchronize(), "synchronize");
+  for (auto &t : m->timers) t.used = 0;
+  return SSD_OK;
+}
+
+ssd_status ssd_timing_read(ssd_mesh *m, int kernel, double *total_ms, int64_t *launches) {
+  if (ssd_status s = check_handle(m)) return s;
+  if (kernel < 0 || kernel >= SSD_KERNEL_COUNT || !total_ms || !launches)
+    return fail(SSD_ERR_INVALID_ARG, "bad kernel class or null output");
+  DeviceGuard guard(m->device);
+  SSD_HIP(hipDeviceSynchronize(), "synchronize");
+  auto &t = m->timers[kernel];
+  double sum = 0.0;
+  for (size_t i = 0; i + 1 < t.used; i += 2) {
+    float ms = 0.f;
+    SSD_HIP(hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1]), "event elapsed");
+    sum += ms;
+  }
+  *total_ms = sum;
+  *launches = int64_t(t.used / 2);
+  return SSD_OK;
+}
+
+}  // extern "C"

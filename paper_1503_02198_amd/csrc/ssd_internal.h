@@ -1,0 +1,119 @@
+// Internal data structures shared by the host side and the kernels of the
+// SSD library.  Nothing here is part of the public ABI (include/ssd.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ssd.h"
+
+namespace ssd {
+
+constexpr int NMAX = 6;
+
+// Packed per-face word, one per (local face, element):
+//   bits  0..25  neighbour element (INTERIOR/PERIODIC) or interface slot (SLIDING)
+//   bits 26..27  neighbour's local face
+//   bit  28      the neighbour's face parameter runs opposite to ours
+//   bits 29..31  SSD_FACE_* kind
+__host__ __device__ inline uint32_t pack_face(int kind, int idx, int nf, int rev) {
+  return (uint32_t(kind) << 29) | (uint32_t(rev & 1) << 28) | (uint32_t(nf & 3) << 26) |
+         (uint32_t(idx) & 0x3FFFFFFu);
+}
+__host__ __device__ inline int face_kind_of(uint32_t w) { return int(w >> 29); }
+__host__ __device__ inline int face_idx_of(uint32_t w) { return int(w & 0x3FFFFFFu); }
+__host__ __device__ inline int face_nf_of(uint32_t w) { return int((w >> 26) & 3u); }
+__host__ __device__ inline int face_rev_of(uint32_t w) { return int((w >> 28) & 1u); }
+constexpr int MAX_ELEMS = 1 << 26;
+
+// Element flag word: bit 0 cubic map, bit 1 rotating zone, bits 8.. cubic slot.
+constexpr int EF_CUBIC = 1;
+constexpr int EF_ROT = 2;
+
+// 1-D operator tables in FP32 for the kernels (interpolation and
+// derivative of eqs. Qt, Ft, Gt), the point sets in FP64 for the metrics.
+struct OpTables {
+  float I[NMAX + 1][NMAX];   // I[k][i] = h_i(Xf_k)
+  float D[NMAX][NMAX + 1];   // D[i][k] = l'_k(X_i)
+  double X[NMAX];            // solution points
+  double Xf[NMAX + 1];       // flux points
+};
+
+// Tables for the device-side mortar rebuild (FP64).
+struct MortarTables {
+  double X[NMAX];            // solution points (mortar and face share them)
+  double bw[NMAX];           // barycentric weights of X
+  double zq[NMAX];           // N-point Gauss-Legendre nodes on [0,1]
+  double wq[NMAX];           // and weights
+  double hq[NMAX][NMAX];     // hq[q][i] = h_i(zq[q])
+  double Minv[NMAX][NMAX];   // inverse mortar mass matrix (eq. mortarM)
+};
+
+// Mortar placement and projections for the current angle, written by the
+// rebuild kernel.  Index k: 0 L-side mortar 1, 1 L-side mortar 2,
+// 2 R-side mortar 1, 3 R-side mortar 2.
+struct MortarState {
+  int m;
+  int valid;
+  double delta;
+  double thL, thR;
+  double o[4], s[4];
+  double Pf[4][NMAX][NMAX];   // M^-1 A(o,s)          (eq. prjQ2)
+  double Pb[4][NMAX][NMAX];   // s M^-1 A(o,s)^T      (eq. prjF2)
+};
+
+// Everything the kernels need about one mesh (passed by value).
+struct DevMesh {
+  int E;           // elements
+  int K;           // faces per interface side (0: no interface)
+  int C;           // cubic elements
+  int N;
+  const double *corners;   // [8][E]: corners 0,3,6,9 (x, y), relative to rot centre
+  const int *eflag;        // [E]
+  const uint32_t *face;    // [4][E]
+  const double *cmet;      // cubic-cell metrics, see cubic_index()
+  const int *ring_e;       // [2K] L slots 0..K-1, R slots K..2K-1 (CCW order)
+  const int *ring_f;       // [2K]
+  const int *ring_flip;    // [2K]
+  int *flag;               // numeric-failure flag
+  float gamma, gas_R, mu, prandtl, T_wall;
+  float qinf[4];
+  double phi0L, phi0R, dphi, Rs;
+  int rotL, rotR;
+};
+
+// Layout of the cubic-cell metric array (FP64, body frame, positions
+// relative to the rotation centre), cubic slot fastest:
+//   xi-FPs  (j, k), quantities 0 x_eta, 1 y_eta, 2 x, 3 y
+//   eta-FPs (k, i), quantities 0 x_xi, 1 y_xi, 2 x, 3 y
+//   SPs     (j, i), quantities 0 |J|, 1 x_xi, 2 x_eta, 3 y_xi, 4 y_eta
+__host__ __device__ inline long cubic_xi_index(int N, int C, int q, int j, int k, int c) {
+  return ((long(q) * N + j) * (N + 1) + k) * C + c;
+}
+__host__ __device__ inline long cubic_eta_index(int N, int C, int q, int k, int i, int c) {
+  return 4L * N * (N + 1) * C + ((long(q) * (N + 1) + k) * N + i) * C + c;
+}
+__host__ __device__ inline long cubic_sp_index(int N, int C, int q, int j, int i, int c) {
+  return 8L * N * (N + 1) * C + ((long(q) * N + j) * N + i) * C + c;
+}
+__host__ __device__ inline long cubic_len(int N, int C) {
+  return (8L * N * (N + 1) + 5L * N * N) * C;
+}
+
+// Per-call rotation of zone 1 (cos, sin of theta, and omega).
+struct Rotation {
+  double ct, st, omega;
+};
+
+// Kernel launchers (defined in ssd_kernels.hip).
+hipError_t launch_traces(const DevMesh &M, const OpTables &T, const float *q, float *tr,
+                         hipStream_t s);
+hipError_t launch_rebuild(const DevMesh &M, const MortarTables &MT, double theta, MortarState *ms,
+                          hipStream_t s);
+hipError_t launch_mortar(const DevMesh &M, const OpTables &T, const MortarState *ms,
+                         const float *tr, float *mflux, hipStream_t s);
+hipError_t launch_stage(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
+                        const float *qn, float *out, const float *trin, float *trout,
+                        const float *mflux, float a, float b, float dt, bool rk, hipStream_t s);
+
+}  // namespace ssd

@@ -1,0 +1,204 @@
+"""ctypes binding of libssd.so (include/ssd.h).
+
+Argument marshalling only: every step of the residual and the time step
+runs in the library's HIP kernels.  Device arrays are torch float32 CUDA
+(HIP) tensors; streams are torch streams.  The binding fails loudly when
+the library is not built; there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libssd.so")
+
+SSD_OK = 0
+STATUS = {0: "SSD_OK", -1: "SSD_ERR_INVALID_ARG", -2: "SSD_ERR_MESH", -3: "SSD_ERR_STATE",
+          -4: "SSD_ERR_DEVICE", -5: "SSD_ERR_NOMEM", -6: "SSD_ERR_NUMERIC"}
+KERNELS = {"stage": 0, "traces": 1, "mortar": 2, "rebuild": 3, "grad": 4}
+EXPORTS = ["ssd_create_mesh", "ssd_destroy_mesh", "ssd_query", "ssd_set_rotation",
+           "ssd_mortar_rebuild", "ssd_residual", "ssd_rk_step", "ssd_check", "ssd_last_error",
+           "ssd_timing_enable", "ssd_timing_reset", "ssd_timing_read"]
+
+
+class SSDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("n_elem", ctypes.c_int32),
+                ("elem_xy", ctypes.POINTER(ctypes.c_double)),
+                ("elem_geom", ctypes.POINTER(ctypes.c_int32)),
+                ("elem_zone", ctypes.POINTER(ctypes.c_int32)),
+                ("nbr_elem", ctypes.POINTER(ctypes.c_int32)),
+                ("nbr_face", ctypes.POINTER(ctypes.c_int32)),
+                ("face_kind", ctypes.POINTER(ctypes.c_int32)),
+                ("rot_center", ctypes.c_double * 2), ("iface_radius", ctypes.c_double),
+                ("omega", ctypes.c_double), ("theta0", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("gas_R", ctypes.c_double), ("mu", ctypes.c_double),
+                ("prandtl", ctypes.c_double), ("T_wall", ctypes.c_double),
+                ("farfield", ctypes.c_double * 4)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("n_elem", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("n_cubic", ctypes.c_int32), ("viscous", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("state_len", ctypes.c_int64),
+                ("work_len", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libssd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1503_02198_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        sig = {
+            "ssd_create_mesh": (i32, [ctypes.POINTER(MeshDesc), ctypes.c_int, ctypes.POINTER(vp)]),
+            "ssd_destroy_mesh": (i32, [vp]),
+            "ssd_query": (i32, [vp, ctypes.POINTER(Info)]),
+            "ssd_set_rotation": (i32, [vp, dbl, dbl]),
+            "ssd_mortar_rebuild": (i32, [vp, vp]),
+            "ssd_residual": (i32, [vp, vp, vp, vp]),
+            "ssd_rk_step": (i32, [vp, vp, vp, dbl, dbl, ctypes.c_int, vp]),
+            "ssd_check": (i32, [vp, vp]),
+            "ssd_last_error": (ctypes.c_char_p, []),
+            "ssd_timing_enable": (i32, [vp, ctypes.c_int]),
+            "ssd_timing_reset": (i32, [vp]),
+            "ssd_timing_read": (i32, [vp, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != SSD_OK:
+        raise SSDError(status, lib().ssd_last_error().decode())
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def make_desc(mesh, case, N):
+    """Fill an ssd_mesh_desc from a mesh dict and a case dict.  Returns the
+    descriptor and the numpy arrays it points into (keep them alive)."""
+    keep = dict(
+        xy=np.ascontiguousarray(mesh["xy"], dtype=np.float64),
+        geom=np.ascontiguousarray(mesh["geom"], dtype=np.int32),
+        zone=np.ascontiguousarray(mesh["zone"], dtype=np.int32),
+        nbr=np.ascontiguousarray(mesh["nbr"], dtype=np.int32),
+        nf=np.ascontiguousarray(mesh["nbr_face"], dtype=np.int32),
+        kind=np.ascontiguousarray(mesh["face_kind"], dtype=np.int32))
+    d = MeshDesc()
+    d.N = int(N)
+    d.n_elem = int(keep["zone"].shape[0])
+    d.elem_xy = _ptr(keep["xy"], ctypes.c_double)
+    d.elem_geom = _ptr(keep["geom"], ctypes.c_int32)
+    d.elem_zone = _ptr(keep["zone"], ctypes.c_int32)
+    d.nbr_elem = _ptr(keep["nbr"], ctypes.c_int32)
+    d.nbr_face = _ptr(keep["nf"], ctypes.c_int32)
+    d.face_kind = _ptr(keep["kind"], ctypes.c_int32)
+    c = mesh.get("center", (0.0, 0.0))
+    d.rot_center[0], d.rot_center[1] = float(c[0]), float(c[1])
+    d.iface_radius = float(mesh.get("radius", 0.0))
+    d.omega = float(case["omega"])
+    d.theta0 = float(case.get("theta0", 0.0))
+    d.gamma = float(case["gamma"])
+    d.gas_R = float(case["gas_R"])
+    d.mu = float(case["mu"])
+    d.prandtl = float(case["prandtl"])
+    d.T_wall = float(case["T_wall"])
+    for i, v in enumerate(case["farfield"]):
+        d.farfield[i] = float(v)
+    return d, keep
+
+
+def _stream_ptr(stream, device):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(int(s.cuda_stream))
+
+
+class Mesh:
+    """One SSD mesh on one GPU (a handle of the C library)."""
+
+    def __init__(self, mesh, case, N, device=0):
+        d, keep = make_desc(mesh, case, N)
+        h = ctypes.c_void_p()
+        _check(lib().ssd_create_mesh(ctypes.byref(d), int(device), ctypes.byref(h)))
+        del keep
+        self._h = h
+        self.device = int(device)
+        self.info = self.query()
+
+    def query(self):
+        inf = Info()
+        _check(lib().ssd_query(self._h, ctypes.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in Info._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ssd_destroy_mesh(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _tensor(self, t, n, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise TypeError(f"{name} must be a CUDA tensor")
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"{name} must be contiguous float32 with {n} elements")
+        if t.device.index != self.device:
+            raise ValueError(f"{name} lives on device {t.device.index}, mesh on {self.device}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def set_rotation(self, theta, omega):
+        _check(lib().ssd_set_rotation(self._h, float(theta), float(omega)))
+
+    def mortar_rebuild(self, stream=None):
+        _check(lib().ssd_mortar_rebuild(self._h, _stream_ptr(stream, self.device)))
+
+    def residual(self, q, r, stream=None):
+        n = self.info["state_len"]
+        _check(lib().ssd_residual(self._h, self._tensor(q, n, "q"), self._tensor(r, n, "r"),
+                                  _stream_ptr(stream, self.device)))
+
+    def rk_step(self, q, work, t, dt, stream=None):
+        n = self.info["state_len"]
+        _check(lib().ssd_rk_step(self._h, self._tensor(q, n, "q"),
+                                 self._tensor(work, self.info["work_len"], "work"),
+                                 float(t), float(dt), 0, _stream_ptr(stream, self.device)))
+
+    def check(self, stream=None):
+        _check(lib().ssd_check(self._h, _stream_ptr(stream, self.device)))
+
+    def timing_enable(self, on=True):
+        _check(lib().ssd_timing_enable(self._h, int(bool(on))))
+
+    def timing_reset(self):
+        _check(lib().ssd_timing_reset(self._h))
+
+    def timing_read(self, kernel):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(lib().ssd_timing_read(self._h, KERNELS[kernel], ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

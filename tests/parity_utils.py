@@ -1,0 +1,66 @@
+"""Helpers shared by the GPU parity tests: run the HIP path through the C
+ABI binding and the FP64 oracle on the same inputs, and the error norms.
+
+Tolerances (FP32 state and fluxes, FP64 metrics and mortar projections):
+  residual  per variable, ||R_gpu - R_oracle||_2 / ||S||_2 <= 1e-5, where S
+            is the oracle's flux-derivative scale sum_k |D_ik||F~_k| / |J|
+            (the residual is a small difference of O(|S|) terms, so FP32
+            rounding is bounded relative to S, not to R);
+  state     per variable, ||Q_gpu - Q_oracle||_2 / ||Q_oracle||_2 <= 1e-5,
+            with both momentum components measured against the norm of
+            the momentum vector.
+"""
+import numpy as np
+
+TOL = 1e-5
+
+
+def residual_error(R_gpu, R_ora, scale):
+    R_gpu = np.asarray(R_gpu, dtype=np.float64)
+    out = []
+    for v in range(4):
+        out.append(np.linalg.norm(R_gpu[v] - R_ora[v]) / np.linalg.norm(scale[v]))
+    return np.array(out)
+
+
+def state_error(Q_gpu, Q_ora):
+    Q_gpu = np.asarray(Q_gpu, dtype=np.float64)
+    mom = np.sqrt(np.linalg.norm(Q_ora[1]) ** 2 + np.linalg.norm(Q_ora[2]) ** 2)
+    den = [np.linalg.norm(Q_ora[0]), mom, mom, np.linalg.norm(Q_ora[3])]
+    return np.array([np.linalg.norm(Q_gpu[v] - Q_ora[v]) / den[v] for v in range(4)])
+
+
+def to_gpu(Q, device=0):
+    import torch
+    return torch.tensor(np.ascontiguousarray(Q, dtype=np.float32).ravel(), device=f"cuda:{device}")
+
+
+def from_gpu(t, N, E):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64).reshape(4, N, N, E)
+
+
+def gpu_residual(gm, Q, theta, omega):
+    import torch
+    N, E = gm.info["N"], gm.info["n_elem"]
+    q = to_gpu(Q, gm.device)
+    r = torch.empty_like(q)
+    gm.set_rotation(theta, omega)
+    gm.mortar_rebuild()
+    gm.residual(q, r)
+    return from_gpu(r, N, E)
+
+
+def gpu_run(gm, Q, t0, dt, nsteps, check=True):
+    import torch
+    N, E = gm.info["N"], gm.info["n_elem"]
+    q = to_gpu(Q, gm.device)
+    work = torch.empty(gm.info["work_len"], dtype=torch.float32, device=q.device)
+    t = t0
+    for _ in range(nsteps):
+        gm.rk_step(q, work, t, dt)
+        t += dt
+    if check:
+        gm.check()
+    return from_gpu(q, N, E)

@@ -1,0 +1,58 @@
+"""The C-ABI library loads and exports every entry point of include/ssd.h;
+argument checks that return before any device work behave as documented.
+No GPU is needed."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1503_02198_amd import ssd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ssd.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(ssd_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(ssd.LIB_PATH):
+        pytest.fail("libssd.so is not built (python -m paper_1503_02198_amd.build)")
+    return ssd.lib()
+
+
+def test_exports_match_header(L):
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(ssd.EXPORTS) == names
+
+
+def test_struct_layout_matches_header():
+    # ssd_mesh_desc: 2 ints, 6 pointers, 14 doubles (incl. arrays) on LP64
+    assert ctypes.sizeof(ssd.MeshDesc) == 8 + 6 * 8 + 14 * 8
+    assert ctypes.sizeof(ssd.Info) == 6 * 4 + 2 * 8
+
+
+def test_argument_errors_without_device(L):
+    h = ctypes.c_void_p()
+    assert L.ssd_create_mesh(None, 0, ctypes.byref(h)) == -1
+    assert b"null" in L.ssd_last_error()
+    d = ssd.MeshDesc()
+    d.N = 7
+    d.n_elem = 4
+    assert L.ssd_create_mesh(ctypes.byref(d), 0, ctypes.byref(h)) == -1
+    assert b"N must be" in L.ssd_last_error()
+    d.N = 3
+    d.n_elem = 0
+    assert L.ssd_create_mesh(ctypes.byref(d), 0, ctypes.byref(h)) == -1
+    assert L.ssd_query(None, None) == -1
+    assert L.ssd_set_rotation(None, 0.0, 0.0) == -1
+    assert L.ssd_residual(None, None, None, None) == -1
+    assert L.ssd_rk_step(None, None, None, 0.0, 1.0, 0, None) == -1
+    assert L.ssd_destroy_mesh(None) == 0

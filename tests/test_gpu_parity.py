@@ -1,0 +1,184 @@
+"""HIP path vs the FP64 oracle on identical seeded inputs (through the C ABI).
+
+Every case prints its name before touching the GPU so a failure names it.
+"""
+import numpy as np
+import pytest
+
+from oracle.exact import vortex_state
+from oracle.ssd import SSD
+from tests.parity_utils import TOL, gpu_residual, gpu_run, residual_error, state_error
+from workloads import cases as C
+from workloads import meshes as M
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _mesh(mesh, case, N):
+    from paper_1503_02198_amd import Mesh
+    return Mesh(mesh, case, N, device=0)
+
+
+def _vortex(N=3, f=1, omega=0.5, theta0=0.0):
+    case = C.vortex_case(omega=omega, theta0=theta0)
+    mesh = M.vortex_mesh(f)
+    ora = SSD(mesh, case, N)
+    x, y = ora.sp_coords(theta0)
+    return mesh, case, ora, vortex_state(x, y, 0.0, case)
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.05, 0.1963495408, -0.4, 2.0])
+def test_residual_vortex(torch_cuda, theta):
+    print(f"case: vortex residual N=3 theta={theta}", flush=True)
+    mesh, case, ora, Q = _vortex()
+    gm = _mesh(mesh, case, 3)
+    Rg = gpu_residual(gm, Q, theta, case["omega"])
+    Ro, diag = ora.residual(Q, theta, case["omega"], diag=True)
+    err = residual_error(Rg, Ro, diag["flux_scale"])
+    print("residual error", err)
+    assert np.all(err <= TOL), err
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
+@pytest.mark.parametrize("curved", [False, True])
+def test_residual_box_all_orders(torch_cuda, N, curved):
+    print(f"case: box residual N={N} curved={curved}", flush=True)
+    case = C.vortex_case()
+    mesh = M.box_mesh(7, 5, L=(3.0, 2.0), distort=0.15, curved=0.06 if curved else 0.0, zone=1)
+    ora = SSD(mesh, case, N)
+    x, y = ora.sp_coords(0.0)
+    case["vortex"]["period"] = 100.0
+    case["vortex"]["center"] = (1.5, 1.0)
+    Q = vortex_state(x, y, 0.0, case)
+    gm = _mesh(mesh, case, N)
+    Rg = gpu_residual(gm, Q, 0.3, 0.8)
+    Ro, diag = ora.residual(Q, 0.3, 0.8, diag=True)
+    err = residual_error(Rg, Ro, diag["flux_scale"])
+    print("residual error", err)
+    assert np.all(err <= TOL), err
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_residual_relabelled_sliding_mesh(torch_cuda, N):
+    """Random corner relabelling flips face parameters on the interface."""
+    print(f"case: relabelled vortex residual N={N}", flush=True)
+    case = C.vortex_case(omega=0.5)
+    mesh = M.relabel(M.vortex_mesh(1), np.random.default_rng(11).integers(0, 4, 384))
+    ora = SSD(mesh, case, N)
+    x, y = ora.sp_coords(0.0)
+    Q = vortex_state(x, y, 0.0, case)
+    gm = _mesh(mesh, case, N)
+    for th in (0.0, 0.137):
+        Rg = gpu_residual(gm, Q, th, 0.5)
+        Ro, diag = ora.residual(Q, th, 0.5, diag=True)
+        err = residual_error(Rg, Ro, diag["flux_scale"])
+        print("theta", th, "residual error", err)
+        assert np.all(err <= TOL), err
+
+
+def test_rk3_vortex_100_steps(torch_cuda):
+    """The vortex workload: 384 cells, N=3, SSP-RK3, dt = 1e-3, 100 steps."""
+    print("case: vortex SSP-RK3 100 steps", flush=True)
+    mesh, case, ora, Q = _vortex()
+    gm = _mesh(mesh, case, 3)
+    Qg = gpu_run(gm, Q, 0.0, 1e-3, 100)
+    Qo = ora.run(Q, 0.0, 1e-3, 100)
+    err = state_error(Qg, Qo)
+    pert = np.linalg.norm(Qg - Qo) / np.linalg.norm(Qo - Q)
+    print("state error", err, "relative to the change", pert)
+    assert np.all(err <= TOL), err
+
+
+def test_rk3_vortex_offset_wraps(torch_cuda):
+    """Start just below a face-width offset so the mortars wrap mid-run."""
+    print("case: vortex SSP-RK3 wrap", flush=True)
+    mesh, case, ora, Q = _vortex(theta0=2 * np.pi / 32 - 0.02)
+    gm = _mesh(mesh, case, 3)
+    Qg = gpu_run(gm, Q, 0.0, 2e-3, 30)
+    Qo = ora.run(Q, 0.0, 2e-3, 30)
+    err = state_error(Qg, Qo)
+    print("state error", err)
+    assert np.all(err <= TOL), err
+
+
+def test_deterministic_and_restartable(torch_cuda):
+    import torch
+    print("case: determinism / restart", flush=True)
+    mesh, case, ora, Q = _vortex()
+    gm = _mesh(mesh, case, 3)
+    a = gpu_run(gm, Q, 0.0, 1e-3, 20)
+    b = gpu_run(gm, Q, 0.0, 1e-3, 20)
+    assert np.array_equal(a, b)
+    half = gpu_run(gm, Q, 0.0, 1e-3, 10)
+    c = gpu_run(gm, half, 10e-3, 1e-3, 10)
+    # the restart passes through FP32 host copies exactly
+    assert np.array_equal(a, c)
+
+
+def test_error_paths(torch_cuda):
+    import torch
+    from paper_1503_02198_amd.ssd import SSDError
+    print("case: error paths", flush=True)
+    mesh, case, ora, Q = _vortex()
+    gm = _mesh(mesh, case, 3)
+    n = gm.info["state_len"]
+    q = torch.zeros(n, device="cuda:0")
+    r = torch.zeros(n, device="cuda:0")
+    gm.set_rotation(0.1, 0.5)
+    with pytest.raises(SSDError) as ei:
+        gm.residual(q, r)
+    assert ei.value.status == -3
+    with pytest.raises(SSDError) as ei:
+        gm.rk_step(q, torch.zeros(gm.info["work_len"], device="cuda:0"), 0.0, -1.0)
+    assert ei.value.status == -1
+    # a negative density is reported by ssd_check
+    Qb = Q.copy()
+    Qb[0, 1, 1, 7] = -1.0
+    from tests.parity_utils import to_gpu
+    qb = to_gpu(Qb)
+    work = torch.zeros(gm.info["work_len"], device="cuda:0")
+    gm.rk_step(qb, work, 0.0, 1e-3)
+    with pytest.raises(SSDError) as ei:
+        gm.check()
+    assert ei.value.status == -6
+    gm.check()     # flag cleared
+
+
+def test_mesh_validation(torch_cuda):
+    from paper_1503_02198_amd import Mesh
+    from paper_1503_02198_amd.ssd import SSDError
+    print("case: mesh validation", flush=True)
+    case = C.vortex_case()
+    mesh = M.vortex_mesh(1)
+    bad = dict(mesh)
+    bad["nbr"] = mesh["nbr"].copy()
+    e = int(np.nonzero(mesh["face_kind"][:, 0] == 0)[0][0])
+    bad["nbr"][e, 0] = (bad["nbr"][e, 0] + 5) % 384
+    with pytest.raises(SSDError) as ei:
+        Mesh(bad, case, 3)
+    assert ei.value.status == -2
+    bad = dict(mesh)
+    bad["xy"] = mesh["xy"].copy()
+    bad["xy"][10] = bad["xy"][10][::-1]         # clockwise cell: |J| < 0
+    with pytest.raises(SSDError) as ei:
+        Mesh(bad, case, 3)
+    assert ei.value.status == -2
+    bad = dict(mesh)
+    kind = mesh["face_kind"].copy()
+    sl = np.argwhere(kind == M.FACE_SLIDING)
+    kind[sl[0][0], sl[0][1]] = M.FACE_WALL_SLIP    # one side loses a face
+    bad["face_kind"] = kind
+    with pytest.raises(SSDError) as ei:
+        Mesh(bad, case, 3)
+    assert ei.value.status == -2
+    with pytest.raises(SSDError) as ei:
+        Mesh(mesh, case, 7)
+    assert ei.value.status == -1
