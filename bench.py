@@ -1,0 +1,226 @@
+"""Throughput benchmark of the SSD hot path on one MI355X.
+
+Workload: inviscid flow (Mach 0.3) past an ellipse (semi-axes 0.5 x 0.1)
+spinning at omega = 1 inside a rotating disk r < 3, in a stationary box
+[-30, 30]^2; 4096 x (64 + 180) = 999,424 quadrilaterals, N = 4 solution
+points per direction (63,963,136 DOF), 4096 sliding-interface faces per
+side, SSP-RK3; the initial state is the far field with a seeded 1% density
+perturbation (SplitMix64, seed 20150307).
+
+One "step" is one SSP-RK3 step (three residual evaluations, each with its
+mortar rebuild and projection).  `value` is DOF-updates per second per RK
+stage: 4 N^2 E x 3 x steps / seconds, with the state resident in HBM.
+
+Prints one JSON line.  `--gpus` above 1 is refused: this build runs on one
+GPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOF-updates/s per RK stage at stated L2 error; learned-coarse vs plain speedup"
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_ellipse_n4.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1503_02198_amd", "csrc", f)
+                  for f in ("ssd_kernels.hip", "ssd_internal.h")]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def workload(args):
+    from workloads import cases as C
+    from workloads import meshes as M
+    mesh = M.ellipse_mesh(K=args.K, n_in=args.n_in, n_out=args.n_out)
+    case = C.ellipse_case()
+    N = args.N
+    E = len(mesh["zone"])
+    Q0 = C.perturbed_farfield_state(case, N, E).astype(np.float32)
+    # time step from the smallest corner-to-corner edge and the fastest
+    # signal (|u| + c + omega r_max), CFL 0.1 per solution-point spacing
+    xy = mesh["xy"][:, [0, 3, 6, 9]]
+    edges = np.linalg.norm(xy - np.roll(xy, 1, axis=1), axis=-1)
+    h = edges.min()
+    rho, u, v, p = case["farfield"]
+    lam = np.hypot(u, v) + np.sqrt(case["gamma"] * p / rho) + abs(case["omega"]) * mesh["radius"]
+    dt = 0.1 * h / (lam * N * N)
+    return mesh, case, N, E, Q0, dt
+
+
+def traffic_for(kind_hash, E, N):
+    """HBM bytes per stage launch from the committed rocprofv3 counter runs,
+    or None when the kernels changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        t = json.load(fh)
+    if t.get("kernel_hash") != kind_hash or t.get("n_elem") != E or t.get("N") != N:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(mesh, case, N, Q0, dt, q_gpu_step, target_s):
+    """The FP64 oracle, single-threaded, on a bounded sub-mesh: one SSP-RK3
+    step on the first `n` cells (plus every interface cell and three layers
+    of neighbours, which the sub-mesh needs); returns the rate and the
+    oracle-vs-GPU error on the sampled cells."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.ssd import SSD, submesh
+    from tests.parity_utils import state_error
+    E = len(mesh["zone"])
+    n = 8192
+    with threadpool_limits(1):
+        while True:
+            sample = np.arange(min(n, E))
+            sub, idx = submesh(mesh, sample, depth=3)
+            ora = SSD(sub, case, N)
+            Qs = Q0[..., idx].astype(np.float64)
+            t0 = time.perf_counter()
+            Q1 = ora.ssprk3_step(Qs, 0.0, dt)
+            el = time.perf_counter() - t0
+            if el > target_s / 3 or n >= E:
+                break
+            n = int(n * min(8.0, max(2.0, target_s / 2 / max(el, 1e-3))))
+    loc = np.searchsorted(idx, sample)
+    err = state_error(q_gpu_step[..., sample], Q1[..., loc])
+    dof_updates = 4 * N * N * len(idx) * 3
+    return dict(value=dof_updates / el, unit="DOF-updates/s", cores=1, kind="oracle",
+                sample=(f"one SSP-RK3 step (3 stages) of the FP64 numpy oracle on a "
+                        f"{len(idx)}-cell sub-mesh of the workload (cells 0..{len(sample) - 1}, "
+                        f"all interface cells and 3 neighbour layers), {el:.1f} s"),
+                seconds=el), err
+
+
+def calib_copy(nbytes=1 << 30, reps=5):
+    """A plain device copy of known size, for scaling rocprofv3 counters."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes_read": nbytes, "calib_copy_bytes_written": nbytes,
+                      "reps": reps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--N", type=int, default=4)
+    ap.add_argument("--K", type=int, default=4096)
+    ap.add_argument("--n-in", type=int, default=64)
+    ap.add_argument("--n-out", type=int, default=180)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding of the method is a design note, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    if args.calib_copy:
+        calib_copy()
+        return
+
+    from paper_1503_02198_amd import Mesh
+    t_setup = time.perf_counter()
+    mesh, case, N, E, Q0, dt = workload(args)
+    gm = Mesh(mesh, case, N, device=0)
+    q = torch.from_numpy(Q0.ravel()).to("cuda:0")
+    work = torch.empty(gm.info["work_len"], dtype=torch.float32, device="cuda:0")
+    setup_s = time.perf_counter() - t_setup
+    print(f"# setup {setup_s:.1f} s: E={E} N={N} K={gm.info['K']} cubic={gm.info['n_cubic']} "
+          f"dt={dt:.3e}", file=sys.stderr, flush=True)
+
+    t = 0.0
+    if args.warmup:
+        gm.rk_steps(q, work, t, dt, args.warmup)
+        t += args.warmup * dt
+    gm.check()
+    torch.cuda.synchronize()
+    gm.timing_enable(True)
+    gm.timing_reset()
+    t0 = time.perf_counter()
+    gm.rk_steps(q, work, t, dt, args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    gm.timing_enable(False)
+    gm.check()
+    kern = {}
+    for k in ("stage", "traces", "mortar", "rebuild"):
+        ms, n = gm.timing_read(k)
+        kern[k] = dict(launches=n, avg_us=(1e3 * ms / n) if n else None, total_ms=ms)
+    print(f"# timed {args.steps} steps in {el:.3f} s", file=sys.stderr, flush=True)
+
+    dof = 4 * N * N * E
+    stages = 3 * args.steps
+    value = dof * stages / el
+    # algorithmic bytes of one stage launch: the state it must read and
+    # write (Q_k and, in stages 2-3, Q^n, then Q_{k+1}: on average
+    # (8 + 12 + 12) / 3 bytes per DOF) and the FP64 corner coordinates of
+    # every cell (64 bytes)
+    alg_bytes = (32.0 / 3.0) * dof + 64.0 * E
+    stage_us = kern["stage"]["avg_us"]
+    achieved = alg_bytes / (stage_us * 1e-6) / 1e9
+    hsh = kernel_hash()
+    traffic = traffic_for(hsh, E, N)
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "rotating-ellipse Euler on a sliding mesh: 999,424 quads "
+                               "(4096 x (64+180)), N=4, 4096 interface faces per side, "
+                               "SSP-RK3, seeded 1% density perturbation",
+                   "n_elem": E, "N": N, "dof": dof, "dt": dt, "K": gm.info["K"],
+                   "n_cubic": gm.info["n_cubic"], "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "kernel": "k_stage (element residual + RK stage update)",
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_us": stage_us},
+        "kernels": kern,
+        "kernel_hash": hsh,
+    }
+    if not args.no_cpu_baseline:
+        # one GPU step from the same initial state for the sampled parity check
+        q1 = torch.from_numpy(Q0.ravel()).to("cuda:0")
+        gm.rk_step(q1, work, 0.0, dt)
+        gm.check()
+        q1h = q1.cpu().numpy().astype(np.float64).reshape(4, N, N, E)
+        cb, err = cpu_baseline(mesh, case, N, Q0, dt, q1h, args.cpu_seconds)
+        result["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        result["l2_rel_vs_oracle"] = [float(x) for x in err]
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

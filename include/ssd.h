@@ -68,6 +68,9 @@ typedef enum { SSD_RK3_SSP = 0 } ssd_rk;
  *
  *  N          solution points per direction = order of accuracy, 2..6
  *             (Sec. 3.1: N Chebyshev-Gauss SPs, N+1 FPs per direction).
+ *  n_elem     number of elements; one handle needs its state array
+ *             (16 N^2 n_elem bytes) and trace array (64 N n_elem bytes)
+ *             below 4 GiB (n_elem < 16.7 million at N = 4).
  *  elem_xy    [n_elem][12][2] node coordinates, counter-clockwise around
  *             the reference square [0,1]^2: (0,0) (1/3,0) (2/3,0) (1,0)
  *             (1,1/3) (1,2/3) (1,1) (2/3,1) (1/3,1) (0,1) (0,2/3) (0,1/3).
@@ -174,6 +177,15 @@ ssd_status ssd_residual(ssd_mesh *m, const float *q, float *r, void *stream);
  */
 ssd_status ssd_rk_step(ssd_mesh *m, float *q, float *work, double t, double dt, ssd_rk scheme,
                        void *stream);
+
+/*
+ * nsteps >= 1 consecutive SSP-RK3 steps from t (step n starts at t + n dt),
+ * with the same effect as nsteps calls of ssd_rk_step.  The face traces the
+ * last stage of a step leaves behind serve the first stage of the next one,
+ * so the separate trace pass runs once per call instead of once per step.
+ */
+ssd_status ssd_rk_steps(ssd_mesh *m, float *q, float *work, double t, double dt, int32_t nsteps,
+                        ssd_rk scheme, void *stream);
 
 /*
  * Synchronises `stream` and reports SSD_ERR_NUMERIC if any stage since the

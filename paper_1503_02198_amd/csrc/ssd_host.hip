@@ -512,7 +512,7 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
                                 : std::hypot(ax - cx2, ay - cy2) + std::hypot(bx - dx2, by - dy2);
           if (e1 > 1e-8 * len) return fail(SSD_ERR_MESH, where + ": neighbouring faces do not meet");
         }
-        face[long(f) * E + e] = pack_face(kind, nb, nf, rev);
+        face[long(f) * E + e] = pack_face(kind, nb, nf, rev, nb / EB == e / EB);
       } else if (kind == SSD_FACE_SLIDING) {
         if (!(Rs > 0.0)) return fail(SSD_ERR_MESH, where + ": sliding face but iface_radius <= 0");
         const double ra = std::hypot(ax - cx, ay - cy), rb = std::hypot(bx - cx, by - cy);
@@ -536,13 +536,13 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
           gy += 0.25 * py;
         }
         (std::hypot(gx - cx, gy - cy) < Rs ? L : R).push_back(rf);
-        face[long(f) * E + e] = pack_face(kind, 0, 0, 0);
+        face[long(f) * E + e] = pack_face(kind, 0, 0, 0, 0);
       } else if (kind == SSD_FACE_WALL_ISOTHERMAL || kind == SSD_FACE_WALL_SLIP) {
         need_wall |= kind == SSD_FACE_WALL_ISOTHERMAL;
-        face[long(f) * E + e] = pack_face(kind, 0, 0, 0);
+        face[long(f) * E + e] = pack_face(kind, 0, 0, 0, 0);
       } else if (kind == SSD_FACE_FARFIELD) {
         need_far = true;
-        face[long(f) * E + e] = pack_face(kind, 0, 0, 0);
+        face[long(f) * E + e] = pack_face(kind, 0, 0, 0, 0);
       } else {
         return fail(SSD_ERR_MESH, where + ": unknown face kind");
       }
@@ -588,8 +588,8 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
       re[K + j] = R[j].e;
       rfv[K + j] = R[j].f;
       rfl[K + j] = R[j].flip;
-      face[long(L[j].f) * E + L[j].e] = pack_face(SSD_FACE_SLIDING, j, 0, 0);
-      face[long(R[j].f) * E + R[j].e] = pack_face(SSD_FACE_SLIDING, K + j, 0, 0);
+      face[long(L[j].f) * E + L[j].e] = pack_face(SSD_FACE_SLIDING, j, 0, 0, 0);
+      face[long(R[j].f) * E + R[j].e] = pack_face(SSD_FACE_SLIDING, K + j, 0, 0, 0);
     }
     m->D.phi0L = L[0].start;
     m->D.phi0R = R[0].start;
@@ -681,6 +681,9 @@ ssd_status ssd_create_mesh(const ssd_mesh_desc *d, int device, ssd_mesh **out) {
   if (d->N < 2 || d->N > NMAX) return fail(SSD_ERR_INVALID_ARG, "N must be in 2..6");
   if (d->n_elem <= 0 || d->n_elem >= MAX_ELEMS)
     return fail(SSD_ERR_INVALID_ARG, "n_elem out of range");
+  // kernels address state and trace arrays with 32-bit byte offsets
+  if (double(std::max(16 * d->N * d->N, 64 * d->N)) * double(d->n_elem) >= 4294967295.0)
+    return fail(SSD_ERR_INVALID_ARG, "mesh too large for one handle (state or trace array >= 4 GiB)");
   if (!d->elem_xy || !d->elem_geom || !d->elem_zone || !d->nbr_elem || !d->nbr_face || !d->face_kind)
     return fail(SSD_ERR_INVALID_ARG, "null mesh array");
   const double sc[] = {d->rot_center[0], d->rot_center[1], d->iface_radius, d->omega, d->theta0,
@@ -791,12 +794,13 @@ ssd_status ssd_residual(ssd_mesh *m, const float *q, float *r, void *stream) {
   return SSD_OK;
 }
 
-ssd_status ssd_rk_step(ssd_mesh *m, float *q, float *work, double t, double dt, ssd_rk scheme,
-                       void *stream) {
+ssd_status ssd_rk_steps(ssd_mesh *m, float *q, float *work, double t, double dt, int32_t nsteps,
+                        ssd_rk scheme, void *stream) {
   if (ssd_status s = check_handle(m)) return s;
   if (!q || !work) return fail(SSD_ERR_INVALID_ARG, "null state or work pointer");
   if (!std::isfinite(t) || !std::isfinite(dt) || !(dt > 0.0))
     return fail(SSD_ERR_INVALID_ARG, "need finite t and dt > 0");
+  if (nsteps < 1) return fail(SSD_ERR_INVALID_ARG, "nsteps must be >= 1");
   if (scheme != SSD_RK3_SSP) return fail(SSD_ERR_INVALID_ARG, "unknown Runge-Kutta scheme");
   const long len = 4L * m->N * m->N * m->E;
   if (overlap(q, len * sizeof(float), work, 2 * len * sizeof(float)))
@@ -814,27 +818,36 @@ ssd_status ssd_rk_step(ssd_mesh *m, float *q, float *work, double t, double dt, 
     LaunchTimer lt(m, SSD_KERNEL_TRACES, st);
     SSD_HIP(launch_traces(m->D, m->T, q, m->tr[0], st), "trace launch");
   }
-  double th = m->theta0;
-  for (int s = 0; s < 3; ++s) {
-    th = m->theta0 + m->omega0 * (t + Cs[s] * dt);
-    if (m->K) {
-      {
-        LaunchTimer lt(m, SSD_KERNEL_REBUILD, st);
-        SSD_HIP(launch_rebuild(m->D, m->MT, th, m->ms, st), "mortar rebuild launch");
+  int cur = 0;   // trace buffer holding the traces of the current stage input
+  for (int n = 0; n < nsteps; ++n) {
+    const double tn = t + n * dt;
+    for (int s = 0; s < 3; ++s) {
+      const double th = m->theta0 + m->omega0 * (tn + Cs[s] * dt);
+      if (m->K) {
+        {
+          LaunchTimer lt(m, SSD_KERNEL_REBUILD, st);
+          SSD_HIP(launch_rebuild(m->D, m->MT, th, m->ms, st), "mortar rebuild launch");
+        }
+        LaunchTimer lt(m, SSD_KERNEL_MORTAR, st);
+        SSD_HIP(launch_mortar(m->D, m->T, m->ms, m->tr[cur], m->mflux, st), "mortar launch");
       }
-      LaunchTimer lt(m, SSD_KERNEL_MORTAR, st);
-      SSD_HIP(launch_mortar(m->D, m->T, m->ms, m->tr[s & 1], m->mflux, st), "mortar launch");
+      Rotation rot{std::cos(th), std::sin(th), m->omega0};
+      LaunchTimer lt(m, SSD_KERNEL_STAGE, st);
+      SSD_HIP(launch_stage(m->D, m->T, rot, in[s], s ? q : nullptr, outp[s], m->tr[cur],
+                           m->tr[cur ^ 1], m->mflux, A[s], B[s], float(dt), true, st),
+              "stage launch");
+      cur ^= 1;
     }
-    Rotation rot{std::cos(th), std::sin(th), m->omega0};
-    LaunchTimer lt(m, SSD_KERNEL_STAGE, st);
-    SSD_HIP(launch_stage(m->D, m->T, rot, in[s], s ? q : nullptr, outp[s], m->tr[s & 1],
-                         m->tr[(s + 1) & 1], m->mflux, A[s], B[s], float(dt), true, st),
-            "stage launch");
   }
-  m->theta = m->theta0 + m->omega0 * (t + dt);
+  m->theta = m->theta0 + m->omega0 * (t + nsteps * dt);
   m->omega = m->omega0;
   m->mortar_fresh = m->K == 0;
   return SSD_OK;
+}
+
+ssd_status ssd_rk_step(ssd_mesh *m, float *q, float *work, double t, double dt, ssd_rk scheme,
+                       void *stream) {
+  return ssd_rk_steps(m, q, work, t, dt, 1, scheme, stream);
 }
 
 ssd_status ssd_check(ssd_mesh *m, void *stream) {

@@ -12,19 +12,29 @@ namespace ssd {
 constexpr int NMAX = 6;
 
 // Packed per-face word, one per (local face, element):
-//   bits  0..25  neighbour element (INTERIOR/PERIODIC) or interface slot (SLIDING)
+//   bits  0..24  neighbour element (INTERIOR/PERIODIC) or interface slot (SLIDING)
+//   bit  25      the neighbour lies in the same block of EB consecutive elements
 //   bits 26..27  neighbour's local face
 //   bit  28      the neighbour's face parameter runs opposite to ours
 //   bits 29..31  SSD_FACE_* kind
-__host__ __device__ inline uint32_t pack_face(int kind, int idx, int nf, int rev) {
+constexpr int EB = 64;   // elements per stage-kernel block
+__host__ __device__ inline uint32_t pack_face(int kind, int idx, int nf, int rev, int inblock) {
   return (uint32_t(kind) << 29) | (uint32_t(rev & 1) << 28) | (uint32_t(nf & 3) << 26) |
-         (uint32_t(idx) & 0x3FFFFFFu);
+         (uint32_t(inblock & 1) << 25) | (uint32_t(idx) & 0x1FFFFFFu);
 }
 __host__ __device__ inline int face_kind_of(uint32_t w) { return int(w >> 29); }
-__host__ __device__ inline int face_idx_of(uint32_t w) { return int(w & 0x3FFFFFFu); }
+__host__ __device__ inline int face_idx_of(uint32_t w) { return int(w & 0x1FFFFFFu); }
+__host__ __device__ inline int face_inblock_of(uint32_t w) { return int((w >> 25) & 1u); }
 __host__ __device__ inline int face_nf_of(uint32_t w) { return int((w >> 26) & 3u); }
 __host__ __device__ inline int face_rev_of(uint32_t w) { return int((w >> 28) & 1u); }
-constexpr int MAX_ELEMS = 1 << 26;
+// A face's trace is read by another block (or by the mortar kernel) and must
+// be stored: sliding faces, and conforming faces whose neighbour is elsewhere.
+__host__ __device__ inline bool face_exported(uint32_t w) {
+  const int k = face_kind_of(w);
+  return k == SSD_FACE_SLIDING ||
+         ((k == SSD_FACE_INTERIOR || k == SSD_FACE_PERIODIC) && !face_inblock_of(w));
+}
+constexpr int MAX_ELEMS = 1 << 25;
 
 // Element flag word: bit 0 cubic map, bit 1 rotating zone, bits 8.. cubic slot.
 constexpr int EF_CUBIC = 1;

@@ -1,12 +1,12 @@
 // HIP kernels of the SSD residual for gfx950 (CDNA4).
 //
-// Layout: SoA with the element index fastest.  One lane owns one element:
-// its N x N x 4 state sits in VGPRs, so every global access of a wave is a
-// contiguous 256-byte row per (variable, point).  Face traces (the solution
-// interpolated to the element-boundary flux points) travel between
-// neighbours through a trace buffer [face][point][var][E]; the neighbour
-// read is a gather that is contiguous whenever consecutive elements have
-// consecutive neighbours (structured O-grids numbered azimuth-fastest).
+// Layout: SoA with the element index fastest, so a wave that serves 64
+// consecutive elements reads and writes contiguous 256-byte rows per
+// (variable, point).  Face traces (the solution interpolated to the
+// element-boundary flux points) travel between neighbours through a trace
+// buffer [face][point][var][E]; the neighbour read is a gather that is
+// contiguous whenever consecutive elements have consecutive neighbours
+// (structured O-grids numbered azimuth-fastest).
 //
 // Precision: state, traces and fluxes in FP32; element metrics and the
 // sliding-interface projections in FP64.
@@ -21,7 +21,7 @@ namespace ssd {
 // (F - u_g Q) nx + (G - v_g Q) ny with vgn = u_g nx + v_g ny.
 __device__ __forceinline__ void flux_n(const float q[4], float nx, float ny, float vgn, float gm1,
                                        float f[4]) {
-  const float ir = 1.0f / q[0];
+  const float ir = __builtin_amdgcn_rcpf(q[0]);
   const float u = q[1] * ir, v = q[2] * ir;
   const float p = gm1 * (q[3] - 0.5f * (q[1] * u + q[2] * v));
   const float un = u * nx + v * ny;
@@ -36,15 +36,15 @@ __device__ __forceinline__ void flux_n(const float q[4], float nx, float ny, flo
 __device__ __forceinline__ void rusanov(const float ql[4], const float qr[4], float nx, float ny,
                                         float vgn, float gam, float f[4]) {
   const float gm1 = gam - 1.0f;
-  const float mag = sqrtf(nx * nx + ny * ny);
-  const float irl = 1.0f / ql[0], irr = 1.0f / qr[0];
+  const float mag = __builtin_amdgcn_sqrtf(nx * nx + ny * ny);
+  const float irl = __builtin_amdgcn_rcpf(ql[0]), irr = __builtin_amdgcn_rcpf(qr[0]);
   const float ul = ql[1] * irl, vl = ql[2] * irl;
   const float ur = qr[1] * irr, vr = qr[2] * irr;
   const float pl = gm1 * (ql[3] - 0.5f * (ql[1] * ul + ql[2] * vl));
   const float pr = gm1 * (qr[3] - 0.5f * (qr[1] * ur + qr[2] * vr));
   const float unl = ul * nx + vl * ny, unr = ur * nx + vr * ny;
   const float rl = unl - vgn, rr = unr - vgn;
-  const float cl = sqrtf(gam * pl * irl), cr = sqrtf(gam * pr * irr);
+  const float cl = __builtin_amdgcn_sqrtf(gam * pl * irl), cr = __builtin_amdgcn_sqrtf(gam * pr * irr);
   const float lam = fmaxf(fabsf(rl) + cl * mag, fabsf(rr) + cr * mag);
   f[0] = 0.5f * (ql[0] * rl + qr[0] * rr) - 0.5f * lam * (qr[0] - ql[0]);
   f[1] = 0.5f * (ql[1] * rl + pl * nx + qr[1] * rr + pr * nx) - 0.5f * lam * (qr[1] - ql[1]);
@@ -71,156 +71,241 @@ __device__ __forceinline__ void rusanov_d(const double ql[4], const double qr[4]
 }
 
 // ---------------------------------------------------------------------------
-// element geometry (Sec. 2.3): bilinear cells from their corners, cubic
-// cells from precomputed FP64 tables; zone-1 cells rotated by theta.
+// raw buffer access: SGPR resource + per-lane byte offset + uniform byte
+// offset, so address arithmetic stays on the scalar unit.  The resource
+// carries the array size; the hardware returns 0 for reads past it and
+// drops writes past it.
+// ---------------------------------------------------------------------------
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+// The b32 builtins move raw 32-bit words: bit-cast, never convert.
+__device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(float x, rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, voff, soff, 0);
+}
+
+// ---------------------------------------------------------------------------
+// element geometry (Sec. 2.3).  Bilinear cells: the four edge vectors are
+// differenced in FP64 from the stored corners, then carried in FP32 and
+// rotated once into the current frame, so every metric is a linear
+// combination:  x_xi(eta) = A + eta (B - A),  x_eta(xi) = C + xi (D - C),
+// x(xi, eta) = p0 + xi A + eta C + xi eta (B - A).  Cubic cells read FP64
+// tables and rotate in FP64.
 // ---------------------------------------------------------------------------
 struct ElemGeo {
   int cubic, c;
-  double ct, st, w;
-  double x0, y0, x3, y3, x6, y6, x9, y9;
+  float w;                                    // omega of the zone (0: fixed)
+  float p0x, p0y, Ax, Ay, Bx, By, Cx, Cy, Dx, Dy;
+  double ct, st;
 };
 
 __device__ __forceinline__ ElemGeo load_geo(const DevMesh &M, int e, const Rotation &R) {
   ElemGeo g;
+  const long E = M.E;
+  // corners are read for every cell (cubic cells ignore them) so that no
+  // load waits on the flag word
+  const double x0 = M.corners[0 * E + e], y0 = M.corners[1 * E + e];
+  const double x3 = M.corners[2 * E + e], y3 = M.corners[3 * E + e];
+  const double x6 = M.corners[4 * E + e], y6 = M.corners[5 * E + e];
+  const double x9 = M.corners[6 * E + e], y9 = M.corners[7 * E + e];
   const int fl = M.eflag[e];
   g.cubic = fl & EF_CUBIC;
   g.c = fl >> 8;
   const bool rot = (fl & EF_ROT) != 0;
   g.ct = rot ? R.ct : 1.0;
   g.st = rot ? R.st : 0.0;
-  g.w = rot ? R.omega : 0.0;
-  const long E = M.E;
-  if (!g.cubic) {
-    g.x0 = M.corners[0 * E + e];
-    g.y0 = M.corners[1 * E + e];
-    g.x3 = M.corners[2 * E + e];
-    g.y3 = M.corners[3 * E + e];
-    g.x6 = M.corners[4 * E + e];
-    g.y6 = M.corners[5 * E + e];
-    g.x9 = M.corners[6 * E + e];
-    g.y9 = M.corners[7 * E + e];
-  } else {
-    g.x0 = g.y0 = g.x3 = g.y3 = g.x6 = g.y6 = g.x9 = g.y9 = 0.0;
-  }
+  g.w = rot ? float(R.omega) : 0.0f;
+  const float c = float(g.ct), s = float(g.st);
+  auto rx = [&](double x, double y) { return c * float(x) - s * float(y); };
+  auto ry = [&](double x, double y) { return s * float(x) + c * float(y); };
+  g.p0x = rx(x0, y0);            g.p0y = ry(x0, y0);
+  g.Ax = rx(x3 - x0, y3 - y0);   g.Ay = ry(x3 - x0, y3 - y0);
+  g.Bx = rx(x6 - x9, y6 - y9);   g.By = ry(x6 - x9, y6 - y9);
+  g.Cx = rx(x9 - x0, y9 - y0);   g.Cy = ry(x9 - x0, y9 - y0);
+  g.Dx = rx(x6 - x3, y6 - y3);   g.Dy = ry(x6 - x3, y6 - y3);
   return g;
 }
 
-// Scaled normal (y_eta, -x_eta) of the xi-direction flux point (Xf_k, X_j)
-// in the rotated frame, and u_g . n (rotation invariant, body frame).
+// Scaled normal (y_eta, -x_eta) at the xi-direction flux point (Xf_k, X_j)
+// in the current frame, and u_g . n.
 template <int N>
 __device__ __forceinline__ void metric_xi(const ElemGeo &g, const DevMesh &M, const OpTables &T,
                                           int k, int j, float &nx, float &ny, float &vgn) {
-  double xe, ye, px = 0.0, py = 0.0;
   if (g.cubic) {
-    xe = M.cmet[cubic_xi_index(N, M.C, 0, j, k, g.c)];
-    ye = M.cmet[cubic_xi_index(N, M.C, 1, j, k, g.c)];
-    if (g.w != 0.0) {
-      px = M.cmet[cubic_xi_index(N, M.C, 2, j, k, g.c)];
-      py = M.cmet[cubic_xi_index(N, M.C, 3, j, k, g.c)];
-    }
-  } else {
-    const double xi = T.Xf[k], eta = T.X[j];
-    xe = (1.0 - xi) * (g.x9 - g.x0) + xi * (g.x6 - g.x3);
-    ye = (1.0 - xi) * (g.y9 - g.y0) + xi * (g.y6 - g.y3);
-    if (g.w != 0.0) {
-      const double a0 = (1.0 - xi) * (1.0 - eta), a3 = xi * (1.0 - eta), a6 = xi * eta,
-                   a9 = (1.0 - xi) * eta;
-      px = a0 * g.x0 + a3 * g.x3 + a6 * g.x6 + a9 * g.x9;
-      py = a0 * g.y0 + a3 * g.y3 + a6 * g.y6 + a9 * g.y9;
-    }
+    const double xe = M.cmet[cubic_xi_index(N, M.C, 0, j, k, g.c)];
+    const double ye = M.cmet[cubic_xi_index(N, M.C, 1, j, k, g.c)];
+    double v = 0.0;
+    if (g.w != 0.0f)
+      v = -double(g.w) * (M.cmet[cubic_xi_index(N, M.C, 2, j, k, g.c)] * xe +
+                          M.cmet[cubic_xi_index(N, M.C, 3, j, k, g.c)] * ye);
+    nx = float(g.st * xe + g.ct * ye);
+    ny = float(-(g.ct * xe - g.st * ye));
+    vgn = float(v);
+    return;
   }
-  const double xr = g.ct * xe - g.st * ye;
-  const double yr = g.st * xe + g.ct * ye;
-  nx = float(yr);
-  ny = float(-xr);
-  vgn = float(-g.w * (px * xe + py * ye));
+  const float xi = float(T.Xf[k]), eta = float(T.X[j]);
+  const float xe = g.Cx + xi * (g.Dx - g.Cx), ye = g.Cy + xi * (g.Dy - g.Cy);
+  nx = ye;
+  ny = -xe;
+  vgn = 0.0f;
+  if (g.w != 0.0f) {
+    const float px = g.p0x + xi * g.Ax + eta * g.Cx + xi * eta * (g.Bx - g.Ax);
+    const float py = g.p0y + xi * g.Ay + eta * g.Cy + xi * eta * (g.By - g.Ay);
+    vgn = -g.w * (px * xe + py * ye);
+  }
 }
 
-// Scaled normal (-y_xi, x_xi) of the eta-direction flux point (X_i, Xf_k).
+// Scaled normal (-y_xi, x_xi) at the eta-direction flux point (X_i, Xf_k).
 template <int N>
 __device__ __forceinline__ void metric_eta(const ElemGeo &g, const DevMesh &M, const OpTables &T,
                                            int k, int i, float &nx, float &ny, float &vgn) {
-  double xx, yx, px = 0.0, py = 0.0;
   if (g.cubic) {
-    xx = M.cmet[cubic_eta_index(N, M.C, 0, k, i, g.c)];
-    yx = M.cmet[cubic_eta_index(N, M.C, 1, k, i, g.c)];
-    if (g.w != 0.0) {
-      px = M.cmet[cubic_eta_index(N, M.C, 2, k, i, g.c)];
-      py = M.cmet[cubic_eta_index(N, M.C, 3, k, i, g.c)];
-    }
-  } else {
-    const double xi = T.X[i], eta = T.Xf[k];
-    xx = (1.0 - eta) * (g.x3 - g.x0) + eta * (g.x6 - g.x9);
-    yx = (1.0 - eta) * (g.y3 - g.y0) + eta * (g.y6 - g.y9);
-    if (g.w != 0.0) {
-      const double a0 = (1.0 - xi) * (1.0 - eta), a3 = xi * (1.0 - eta), a6 = xi * eta,
-                   a9 = (1.0 - xi) * eta;
-      px = a0 * g.x0 + a3 * g.x3 + a6 * g.x6 + a9 * g.x9;
-      py = a0 * g.y0 + a3 * g.y3 + a6 * g.y6 + a9 * g.y9;
-    }
+    const double xx = M.cmet[cubic_eta_index(N, M.C, 0, k, i, g.c)];
+    const double yx = M.cmet[cubic_eta_index(N, M.C, 1, k, i, g.c)];
+    double v = 0.0;
+    if (g.w != 0.0f)
+      v = double(g.w) * (M.cmet[cubic_eta_index(N, M.C, 2, k, i, g.c)] * xx +
+                         M.cmet[cubic_eta_index(N, M.C, 3, k, i, g.c)] * yx);
+    nx = float(-(g.st * xx + g.ct * yx));
+    ny = float(g.ct * xx - g.st * yx);
+    vgn = float(v);
+    return;
   }
-  const double xr = g.ct * xx - g.st * yx;
-  const double yr = g.st * xx + g.ct * yx;
-  nx = float(-yr);
-  ny = float(xr);
-  vgn = float(g.w * (px * xx + py * yx));
+  const float xi = float(T.X[i]), eta = float(T.Xf[k]);
+  const float xx = g.Ax + eta * (g.Bx - g.Ax), yx = g.Ay + eta * (g.By - g.Ay);
+  nx = -yx;
+  ny = xx;
+  vgn = 0.0f;
+  if (g.w != 0.0f) {
+    const float px = g.p0x + xi * g.Ax + eta * g.Cx + xi * eta * (g.Bx - g.Ax);
+    const float py = g.p0y + xi * g.Ay + eta * g.Cy + xi * eta * (g.By - g.Ay);
+    vgn = g.w * (px * xx + py * yx);
+  }
 }
 
+// 1 / |J| at the solution point (X_i, X_j).
 template <int N>
-__device__ __forceinline__ double jacobian(const ElemGeo &g, const DevMesh &M, const OpTables &T,
-                                           int j, int i) {
-  if (g.cubic) return M.cmet[cubic_sp_index(N, M.C, 0, j, i, g.c)];
-  const double xi = T.X[i], eta = T.X[j];
-  const double xx = (1.0 - eta) * (g.x3 - g.x0) + eta * (g.x6 - g.x9);
-  const double yx = (1.0 - eta) * (g.y3 - g.y0) + eta * (g.y6 - g.y9);
-  const double xe = (1.0 - xi) * (g.x9 - g.x0) + xi * (g.x6 - g.x3);
-  const double ye = (1.0 - xi) * (g.y9 - g.y0) + xi * (g.y6 - g.y3);
-  return xx * ye - xe * yx;
+__device__ __forceinline__ float inv_jacobian(const ElemGeo &g, const DevMesh &M,
+                                              const OpTables &T, int j, int i) {
+  if (g.cubic) return float(1.0 / M.cmet[cubic_sp_index(N, M.C, 0, j, i, g.c)]);
+  const float xi = float(T.X[i]), eta = float(T.X[j]);
+  const float xx = g.Ax + eta * (g.Bx - g.Ax), yx = g.Ay + eta * (g.By - g.Ay);
+  const float xe = g.Cx + xi * (g.Dx - g.Cx), ye = g.Cy + xi * (g.Dy - g.Cy);
+  return __builtin_amdgcn_rcpf(xx * ye - xe * yx);
 }
 
 // ---------------------------------------------------------------------------
 // common normal flux at one element-boundary flux point (outward normal)
 // ---------------------------------------------------------------------------
+struct StageBufs {
+  rsrc_t q, qn, out, trin, trout, mflux;
+  uint32_t E4;      // bytes per state row (4 E)
+  uint32_t S4;      // bytes per mortar-flux row (4 * 2K)
+};
+
+// What a face needs from outside the block, fetched before it is used:
+// the neighbour's trace (a neighbour in another block), the far-field state,
+// or the projected mortar flux (a sliding face).  Faces whose neighbour is in
+// the same block, and walls, fetch nothing.
 template <int N>
-__device__ __forceinline__ void common_flux(const DevMesh &M, uint32_t w, int p, const float qo[4],
-                                            float nx, float ny, float vgn,
-                                            const float *__restrict__ trin,
-                                            const float *__restrict__ mflux, float fs[4]) {
-  const int kind = face_kind_of(w);
-  const long E = M.E;
-  if (kind == SSD_FACE_INTERIOR || kind == SSD_FACE_PERIODIC) {
-    const int nb = face_idx_of(w), nf = face_nf_of(w);
-    const int pp = face_rev_of(w) ? N - 1 - p : p;
-    float qr[4];
+__device__ __forceinline__ void prefetch_face(const DevMesh &M, const StageBufs &B, uint32_t fw,
+                                              int p, float x[4]) {
+  const int kind = face_kind_of(fw);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) qr[v] = trin[long((nf * N + pp) * 4 + v) * E + nb];
-    rusanov(qo, qr, nx, ny, vgn, M.gamma, fs);
-  } else if (kind == SSD_FACE_SLIDING) {
-    const int slot = face_idx_of(w);
-    const long S = 2L * M.K;
+  for (int v = 0; v < 4; ++v) x[v] = 0.0f;
+  if (kind == SSD_FACE_SLIDING) {
+    const uint32_t vo = (uint32_t(p * 4) * (B.S4 >> 2) + uint32_t(face_idx_of(fw))) * 4u;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) fs[v] = mflux[long(p * 4 + v) * S + slot];
+    for (int v = 0; v < 4; ++v) x[v] = bload(B.mflux, vo, v * B.S4);
   } else if (kind == SSD_FACE_FARFIELD) {
-    rusanov(qo, M.qinf, nx, ny, vgn, M.gamma, fs);
-  } else {
-    // walls: no flux relative to the (moving) wall, pressure from inside
-    const float ir = 1.0f / qo[0];
-    const float pr = (M.gamma - 1.0f) * (qo[3] - 0.5f * (qo[1] * qo[1] + qo[2] * qo[2]) * ir);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) x[v] = M.qinf[v];
+  } else if ((kind == SSD_FACE_INTERIOR || kind == SSD_FACE_PERIODIC) && !face_inblock_of(fw)) {
+    const uint32_t nb = uint32_t(face_idx_of(fw)), nf = uint32_t(face_nf_of(fw));
+    const uint32_t pp = face_rev_of(fw) ? uint32_t(N - 1 - p) : uint32_t(p);
+    const uint32_t vo = ((nf * N + pp) * 4u) * B.E4 + nb * 4u;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) x[v] = bload(B.trin, vo, v * B.E4);
+  }
+}
+
+// Common normal flux at one element-boundary flux point along the outward
+// normal (nx, ny), given the prefetched face data x.  A neighbour in the
+// same block is interpolated from the block's LDS state Sf [var][j][i][lane].
+template <int N>
+__device__ __forceinline__ void common_flux(const DevMesh &M, const OpTables &T, const float *Sf,
+                                            uint32_t fw, int p, const float qo[4],
+                                            const float x[4], float nx, float ny, float vgn,
+                                            float fs[4]) {
+  const int kind = face_kind_of(fw);
+  if (kind == SSD_FACE_SLIDING) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) fs[v] = x[v];
+    return;
+  }
+  if (kind == SSD_FACE_WALL_ISOTHERMAL || kind == SSD_FACE_WALL_SLIP) {
+    // no flux relative to the moving wall; pressure from the interior
+    const float pr = (M.gamma - 1.0f) *
+                     (qo[3] - 0.5f * (qo[1] * qo[1] + qo[2] * qo[2]) * __builtin_amdgcn_rcpf(qo[0]));
     fs[0] = 0.0f;
     fs[1] = pr * nx;
     fs[2] = pr * ny;
     fs[3] = pr * vgn;
+    return;
   }
+  float qx[4];
+  if ((kind == SSD_FACE_INTERIOR || kind == SSD_FACE_PERIODIC) && face_inblock_of(fw)) {
+    const uint32_t nf = uint32_t(face_nf_of(fw));
+    const int pp = face_rev_of(fw) ? N - 1 - p : p;
+    const int ln = face_idx_of(fw) & (EB - 1);
+    const bool odd = (nf & 1u) != 0;               // xi faces: the point runs along eta
+    const bool hi = (nf == 1u || nf == 2u);        // xi = 1 or eta = 1
+    const int base = (odd ? pp * N * EB : pp * EB) + ln;
+    const int stride = odd ? EB : N * EB;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float acc = 0.f;
+#pragma unroll
+      for (int s2 = 0; s2 < N; ++s2)
+        acc += (hi ? T.I[N][s2] : T.I[0][s2]) * Sf[v * N * N * EB + base + s2 * stride];
+      qx[v] = acc;
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) qx[v] = x[v];
+  }
+  rusanov(qo, qx, nx, ny, vgn, M.gamma, fs);
 }
 
 // ---------------------------------------------------------------------------
-// face traces of a state held in registers
+// face traces of a state, for the faces some other block reads
 // ---------------------------------------------------------------------------
 template <int N>
-__device__ __forceinline__ void write_traces(const OpTables &T, const float (&Q)[4][N][N],
-                                             float *__restrict__ tr, long E, int e) {
+__global__ __launch_bounds__(256) void k_traces(DevMesh M, OpTables T, const float *__restrict__ q,
+                                                float *__restrict__ tr) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M.E) return;
+  const uint32_t E4 = uint32_t(M.E) * 4u;
+  const rsrc_t rq = make_rsrc(q, 4u * N * N * E4), rt = make_rsrc(tr, 16u * N * E4);
+  const uint32_t ve = uint32_t(e) * 4u;
+  bool ex[4];
 #pragma unroll
-  for (int p = 0; p < N; ++p) {
+  for (int f = 0; f < 4; ++f) ex[f] = face_exported(M.face[long(f) * M.E + e]);
+  if (!(ex[0] || ex[1] || ex[2] || ex[3])) return;
+  float Q[4][N][N];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+      for (int i = 0; i < N; ++i) Q[v][j][i] = bload(rq, ve, ((v * N + j) * N + i) * E4);
+#pragma unroll
+  for (int p = 0; p < N; ++p)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       float f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f;
@@ -231,195 +316,249 @@ __device__ __forceinline__ void write_traces(const OpTables &T, const float (&Q)
         f1 += T.I[N][s] * Q[v][p][s];   // xi = 1, point p along eta
         f3 += T.I[0][s] * Q[v][p][s];   // xi = 0
       }
-      tr[long((0 * N + p) * 4 + v) * E + e] = f0;
-      tr[long((1 * N + p) * 4 + v) * E + e] = f1;
-      tr[long((2 * N + p) * 4 + v) * E + e] = f2;
-      tr[long((3 * N + p) * 4 + v) * E + e] = f3;
+      if (ex[0]) bstore(f0, rt, ve, ((0 * N + p) * 4 + v) * E4);
+      if (ex[1]) bstore(f1, rt, ve, ((1 * N + p) * 4 + v) * E4);
+      if (ex[2]) bstore(f2, rt, ve, ((2 * N + p) * 4 + v) * E4);
+      if (ex[3]) bstore(f3, rt, ve, ((3 * N + p) * 4 + v) * E4);
     }
-  }
-}
-
-template <int N>
-__global__ __launch_bounds__(256) void k_traces(DevMesh M, OpTables T, const float *__restrict__ q,
-                                                float *__restrict__ tr) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= M.E) return;
-  const long E = M.E;
-  float Q[4][N][N];
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-#pragma unroll
-    for (int j = 0; j < N; ++j)
-#pragma unroll
-      for (int i = 0; i < N; ++i) Q[v][j][i] = q[long((v * N + j) * N + i) * E + e];
-  write_traces<N>(T, Q, tr, E, e);
 }
 
 // ---------------------------------------------------------------------------
 // the element residual, optionally fused with an SSP-RK stage update
 //   rk = false:  out = dQ/dt
-//   rk = true :  out = a qn + b (q + dt dQ/dt), traces of out -> trout
+//   rk = true :  out = a qn + b (q + dt dQ/dt), exported face traces of out
+//                -> trout
+//
+// A block owns EB = 64 consecutive elements and has N waves; lane l of
+// wave w serves element (block * 64 + l).
+//   row phase    (row j = w): interior xi-direction flux points (Xf_k, X_w),
+//                then (once the block's state is in LDS) the faces xi = 0, 1
+//                at point w; the xi part of the residual of row w -> LDS
+//   column phase (column i = w): the same along eta with the faces eta = 0,
+//                1 at point w, plus the row parts from LDS -> dQ/dt on
+//                column w; RK update, column store, traces of faces eta = 0,
+//                1 at point w
+//   trace phase  (row w): traces of faces xi = 0, 1 at point w
+// A neighbour in the same block is read from the block's LDS state, any
+// other through the trace buffer.  LDS arrays are [var][j][i][lane]: every
+// LDS access of a wave to its own elements touches 64 distinct banks.
+// Global accesses of a wave are contiguous 256-byte rows.
 // ---------------------------------------------------------------------------
 template <int N, bool RK>
-__global__ __launch_bounds__(256) void k_stage(DevMesh M, OpTables T, Rotation R,
-                                               const float *__restrict__ q, const float *qn,
-                                               float *out, const float *__restrict__ trin,
-                                               float *__restrict__ trout,
-                                               const float *__restrict__ mflux, float a, float b,
-                                               float dt) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= M.E) return;
-  const long E = M.E;
+__global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotation R,
+                                                  const float *q, const float *qn, float *out,
+                                                  const float *trin, float *trout,
+                                                  const float *mflux, float a, float b, float dt) {
+  __shared__ float S[4][N][N][EB];     // state of the block's elements
+  __shared__ float SR[4][N][N][EB];    // xi part of the residual, then the new state
+  const float *Sf = &S[0][0][0][0];
+  const int l = threadIdx.x & (EB - 1);
+  // the wave index is uniform across the wave (blocks are 64 N lanes): say so,
+  // so that offsets derived from it live in SGPRs
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / EB);
+  const int e0 = blockIdx.x * EB + l;
+  const bool valid = e0 < M.E;
+  const int e = valid ? e0 : M.E - 1;
   const float gm1 = M.gamma - 1.0f;
 
-  float Q[4][N][N];
+  StageBufs B;
+  B.E4 = uint32_t(M.E) * 4u;
+  B.S4 = uint32_t(2 * M.K) * 4u;
+  const uint32_t sbytes = 4u * N * N * B.E4, tbytes = 16u * N * B.E4;
+  B.q = make_rsrc(q, sbytes);
+  B.qn = make_rsrc(qn, RK ? sbytes : 0u);
+  B.out = make_rsrc(out, sbytes);
+  B.trin = make_rsrc(trin, tbytes);
+  B.trout = make_rsrc(trout, RK ? tbytes : 0u);
+  B.mflux = make_rsrc(mflux, 4u * N * B.S4);
+  const uint32_t ve = uint32_t(e) * 4u;
+
+  const long E = M.E;
+  // ---- everything the element needs from memory, issued up front
+  const uint32_t fw0 = M.face[0 * E + e], fw1 = M.face[1 * E + e];
+  const uint32_t fw2 = M.face[2 * E + e], fw3 = M.face[3 * E + e];
+  float qr[4][N];
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
-    for (int j = 0; j < N; ++j)
-#pragma unroll
-      for (int i = 0; i < N; ++i) Q[v][j][i] = q[long((v * N + j) * N + i) * E + e];
-
+    for (int i = 0; i < N; ++i) qr[v][i] = bload(B.q, ve, ((v * N + w) * N + i) * B.E4);
   const ElemGeo g = load_geo(M, e, R);
-  uint32_t fw[4];
-#pragma unroll
-  for (int f = 0; f < 4; ++f) fw[f] = M.face[long(f) * E + e];
+  float x0[4], x1[4], x2[4], x3[4];
+  prefetch_face<N>(M, B, fw3, w, x3);   // row faces xi = 0, 1 at point w
+  prefetch_face<N>(M, B, fw1, w, x1);
+  prefetch_face<N>(M, B, fw0, w, x0);   // column faces eta = 0, 1 at point w
+  prefetch_face<N>(M, B, fw2, w, x2);
 
-  float res[4][N][N];
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-#pragma unroll
-    for (int j = 0; j < N; ++j)
-#pragma unroll
-      for (int i = 0; i < N; ++i) res[v][j][i] = 0.0f;
-
-  // ---- xi direction: rows j, flux points (Xf_k, X_j)
-#pragma unroll
-  for (int j = 0; j < N; ++j) {
-    float Ft[4][N + 1];
-#pragma unroll
-    for (int k = 0; k <= N; ++k) {
-      float qf[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        float acc = 0.f;
-#pragma unroll
-        for (int i = 0; i < N; ++i) acc += T.I[k][i] * Q[v][j][i];
-        qf[v] = acc;
-      }
-      float nx, ny, vgn, f[4];
-      metric_xi<N>(g, M, T, k, j, nx, ny, vgn);
-      if (k == 0) {
-        common_flux<N>(M, fw[3], j, qf, -nx, -ny, -vgn, trin, mflux, f);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Ft[v][k] = -f[v];
-      } else if (k == N) {
-        common_flux<N>(M, fw[1], j, qf, nx, ny, vgn, trin, mflux, f);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Ft[v][k] = f[v];
-      } else {
-        flux_n(qf, nx, ny, vgn, gm1, f);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Ft[v][k] = f[v];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        float acc = 0.f;
-#pragma unroll
-        for (int k = 0; k <= N; ++k) acc += T.D[i][k] * Ft[v][k];
-        res[v][j][i] -= acc;
-      }
-  }
-
-  // ---- eta direction: columns i, flux points (X_i, Xf_k)
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    float Gt[4][N + 1];
-#pragma unroll
-    for (int k = 0; k <= N; ++k) {
-      float qf[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        float acc = 0.f;
-#pragma unroll
-        for (int j = 0; j < N; ++j) acc += T.I[k][j] * Q[v][j][i];
-        qf[v] = acc;
-      }
-      float nx, ny, vgn, f[4];
-      metric_eta<N>(g, M, T, k, i, nx, ny, vgn);
-      if (k == 0) {
-        common_flux<N>(M, fw[0], i, qf, -nx, -ny, -vgn, trin, mflux, f);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Gt[v][k] = -f[v];
-      } else if (k == N) {
-        common_flux<N>(M, fw[2], i, qf, nx, ny, vgn, trin, mflux, f);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Gt[v][k] = f[v];
-      } else {
-        flux_n(qf, nx, ny, vgn, gm1, f);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Gt[v][k] = f[v];
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < N; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        float acc = 0.f;
-#pragma unroll
-        for (int k = 0; k <= N; ++k) acc += T.D[j][k] * Gt[v][k];
-        res[v][j][i] -= acc;
-      }
-  }
-
-  // ---- dQ/dt = dQ~/dt / |J|
-#pragma unroll
-  for (int j = 0; j < N; ++j)
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      const float ij = float(1.0 / jacobian<N>(g, M, T, j, i));
-#pragma unroll
-      for (int v = 0; v < 4; ++v) res[v][j][i] *= ij;
-    }
-
-  if (!RK) {
+  // ---- row phase
+  {
+    float res[4][N], t0[4], tN[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int j = 0; j < N; ++j)
+      for (int i = 0; i < N; ++i) {
+        S[v][w][i][l] = qr[v][i];
+        res[v][i] = 0.0f;
+      }
 #pragma unroll
-        for (int i = 0; i < N; ++i) out[long((v * N + j) * N + i) * E + e] = res[v][j][i];
-    return;
-  }
-
-  // ---- SSP-RK stage: Q <- a Qn + b (Q + dt R)
-  bool bad = false;
-#pragma unroll
-  for (int j = 0; j < N; ++j)
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
+    for (int k = 1; k < N; ++k) {
+      float qf[4], f[4], nx, ny, vgn;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const long idx = long((v * N + j) * N + i) * E + e;
-        float x = b * (Q[v][j][i] + dt * res[v][j][i]);
-        if (a != 0.0f) x += a * qn[idx];
-        Q[v][j][i] = x;
+        float acc = 0.f;
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc += T.I[k][i] * qr[v][i];
+        qf[v] = acc;
       }
-      const float rho = Q[0][j][i];
-      const float pr = gm1 * (Q[3][j][i] - 0.5f * (Q[1][j][i] * Q[1][j][i] + Q[2][j][i] * Q[2][j][i]) / rho);
-      bad |= !(rho > 0.0f) || !(pr > 0.0f) || !isfinite(Q[1][j][i]) || !isfinite(Q[2][j][i]);
+      metric_xi<N>(g, M, T, k, w, nx, ny, vgn);
+      flux_n(qf, nx, ny, vgn, gm1, f);
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) res[v][i] -= T.D[i][k] * f[v];
     }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float s0 = 0.f, sN = 0.f;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        s0 += T.I[0][i] * qr[v][i];
+        sN += T.I[N][i] * qr[v][i];
+      }
+      t0[v] = s0;
+      tN[v] = sN;
+    }
+    __syncthreads();   // the block's state is in LDS
+    {
+      float f[4], nx, ny, vgn;
+      metric_xi<N>(g, M, T, 0, w, nx, ny, vgn);       // face xi = 0: outward is -n
+      common_flux<N>(M, T, Sf, fw3, w, t0, x3, -nx, -ny, -vgn, f);
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) res[v][i] += T.D[i][0] * f[v];
+      metric_xi<N>(g, M, T, N, w, nx, ny, vgn);       // face xi = 1: outward is +n
+      common_flux<N>(M, T, Sf, fw1, w, tN, x1, nx, ny, vgn, f);
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) res[v][i] -= T.D[i][N] * f[v];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int i = 0; i < N; ++i) SR[v][w][i][l] = res[v][i];
+  }
+  __syncthreads();
+
+  // ---- column phase
+  float qc[4][N], rc[4][N], qo[4][N];
+  if (RK && a != 0.0f) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int j = 0; j < N; ++j) qo[v][j] = bload(B.qn, ve, ((v * N + j) * N + w) * B.E4);
+  }
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
+    for (int j = 0; j < N; ++j) {
+      qc[v][j] = S[v][j][w][l];
+      rc[v][j] = SR[v][j][w][l];
+    }
+#pragma unroll
+  for (int k = 0; k <= N; ++k) {
+    float qf[4], f[4], nx, ny, vgn;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float acc = 0.f;
+#pragma unroll
+      for (int j = 0; j < N; ++j) acc += T.I[k][j] * qc[v][j];
+      qf[v] = acc;
+    }
+    metric_eta<N>(g, M, T, k, w, nx, ny, vgn);
+    if (k == 0) {
+      common_flux<N>(M, T, Sf, fw0, w, qf, x0, -nx, -ny, -vgn, f);   // outward is -n
+#pragma unroll
+      for (int v = 0; v < 4; ++v) f[v] = -f[v];
+    } else if (k == N) {
+      common_flux<N>(M, T, Sf, fw2, w, qf, x2, nx, ny, vgn, f);
+    } else {
+      flux_n(qf, nx, ny, vgn, gm1, f);
+    }
+#pragma unroll
     for (int j = 0; j < N; ++j)
 #pragma unroll
-      for (int i = 0; i < N; ++i) out[long((v * N + j) * N + i) * E + e] = Q[v][j][i];
-  write_traces<N>(T, Q, trout, E, e);
-  if (bad) M.flag[0] = 1;
+      for (int v = 0; v < 4; ++v) rc[v][j] -= T.D[j][k] * f[v];
+  }
+  // dQ/dt = dQ~/dt / |J| on column w
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const float ij = inv_jacobian<N>(g, M, T, j, w);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) rc[v][j] *= ij;
+  }
+  if (!RK) {
+    if (valid) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int j = 0; j < N; ++j) bstore(rc[v][j], B.out, ve, ((v * N + j) * N + w) * B.E4);
+    }
+    return;
+  }
+
+  // ---- SSP-RK stage on column w: Q <- a Qn + b (Q + dt R); the new column
+  // goes to SR (no other lane reads column w of SR after the column phase
+  // has started)
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float x = b * (qc[v][j] + dt * rc[v][j]);
+      if (a != 0.0f) x += a * qo[v][j];
+      qc[v][j] = x;
+      SR[v][j][w][l] = x;
+    }
+    const float rho = qc[0][j];
+    const float pr = gm1 * (qc[3][j] - 0.5f * (qc[1][j] * qc[1][j] + qc[2][j] * qc[2][j]) *
+                                           __builtin_amdgcn_rcpf(rho));
+    bad |= !(rho > 0.0f) || !(pr > 0.0f) || !isfinite(qc[1][j]) || !isfinite(qc[2][j]);
+  }
+  const bool ex0 = face_exported(fw0), ex2 = face_exported(fw2);
+  if (valid) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float f0 = 0.f, f2 = 0.f;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        bstore(qc[v][j], B.out, ve, ((v * N + j) * N + w) * B.E4);
+        f0 += T.I[0][j] * qc[v][j];     // eta = 0 face, point w
+        f2 += T.I[N][j] * qc[v][j];     // eta = 1 face, point w
+      }
+      if (ex0) bstore(f0, B.trout, ve, ((0 * N + w) * 4 + v) * B.E4);
+      if (ex2) bstore(f2, B.trout, ve, ((2 * N + w) * 4 + v) * B.E4);
+    }
+    if (bad) M.flag[0] = 1;
+  }
+  __syncthreads();
+
+  // ---- trace phase: faces xi = 0, 1 at point w from row w of the new state
+  const bool ex1 = face_exported(fw1), ex3 = face_exported(fw3);
+  if (valid && (ex1 || ex3)) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float f1 = 0.f, f3 = 0.f;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const float x = SR[v][w][i][l];
+        f1 += T.I[N][i] * x;
+        f3 += T.I[0][i] * x;
+      }
+      if (ex1) bstore(f1, B.trout, ve, ((1 * N + w) * 4 + v) * B.E4);
+      if (ex3) bstore(f3, B.trout, ve, ((3 * N + w) * 4 + v) * B.E4);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -593,7 +732,7 @@ __global__ __launch_bounds__(64) void k_mortar(DevMesh M, OpTables T,
     default: return hipErrorInvalidValue;                \
   }
 
-constexpr int STAGE_BLOCK = 128;
+constexpr int STAGE_BLOCK = 256;
 
 hipError_t launch_traces(const DevMesh &M, const OpTables &T, const float *q, float *tr,
                          hipStream_t s) {
@@ -621,15 +760,13 @@ hipError_t launch_mortar(const DevMesh &M, const OpTables &T, const MortarState 
 hipError_t launch_stage(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
                         const float *qn, float *out, const float *trin, float *trout,
                         const float *mflux, float a, float b, float dt, bool rk, hipStream_t s) {
-  const int grid = (M.E + STAGE_BLOCK - 1) / STAGE_BLOCK;
+  const int grid = (M.E + EB - 1) / EB;
   if (rk) {
-    SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_stage<NN, true>), dim3(grid), dim3(STAGE_BLOCK), 0,
-                                           s, M, T, rot, q, qn, out, trin, trout, mflux, a, b,
-                                           dt));
+    SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_stage<NN, true>), dim3(grid), dim3(EB * NN), 0, s,
+                                           M, T, rot, q, qn, out, trin, trout, mflux, a, b, dt));
   } else {
-    SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_stage<NN, false>), dim3(grid), dim3(STAGE_BLOCK), 0,
-                                           s, M, T, rot, q, qn, out, trin, trout, mflux, a, b,
-                                           dt));
+    SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_stage<NN, false>), dim3(grid), dim3(EB * NN), 0, s,
+                                           M, T, rot, q, qn, out, trin, trout, mflux, a, b, dt));
   }
   return hipGetLastError();
 }

@@ -18,8 +18,8 @@ STATUS = {0: "SSD_OK", -1: "SSD_ERR_INVALID_ARG", -2: "SSD_ERR_MESH", -3: "SSD_E
           -4: "SSD_ERR_DEVICE", -5: "SSD_ERR_NOMEM", -6: "SSD_ERR_NUMERIC"}
 KERNELS = {"stage": 0, "traces": 1, "mortar": 2, "rebuild": 3, "grad": 4}
 EXPORTS = ["ssd_create_mesh", "ssd_destroy_mesh", "ssd_query", "ssd_set_rotation",
-           "ssd_mortar_rebuild", "ssd_residual", "ssd_rk_step", "ssd_check", "ssd_last_error",
-           "ssd_timing_enable", "ssd_timing_reset", "ssd_timing_read"]
+           "ssd_mortar_rebuild", "ssd_residual", "ssd_rk_step", "ssd_rk_steps", "ssd_check",
+           "ssd_last_error", "ssd_timing_enable", "ssd_timing_reset", "ssd_timing_read"]
 
 
 class SSDError(RuntimeError):
@@ -70,6 +70,7 @@ def lib():
             "ssd_mortar_rebuild": (i32, [vp, vp]),
             "ssd_residual": (i32, [vp, vp, vp, vp]),
             "ssd_rk_step": (i32, [vp, vp, vp, dbl, dbl, ctypes.c_int, vp]),
+            "ssd_rk_steps": (i32, [vp, vp, vp, dbl, dbl, i32, ctypes.c_int, vp]),
             "ssd_check": (i32, [vp, vp]),
             "ssd_last_error": (ctypes.c_char_p, []),
             "ssd_timing_enable": (i32, [vp, ctypes.c_int]),
@@ -187,6 +188,13 @@ class Mesh:
         _check(lib().ssd_rk_step(self._h, self._tensor(q, n, "q"),
                                  self._tensor(work, self.info["work_len"], "work"),
                                  float(t), float(dt), 0, _stream_ptr(stream, self.device)))
+
+    def rk_steps(self, q, work, t, dt, nsteps, stream=None):
+        n = self.info["state_len"]
+        _check(lib().ssd_rk_steps(self._h, self._tensor(q, n, "q"),
+                                  self._tensor(work, self.info["work_len"], "work"),
+                                  float(t), float(dt), int(nsteps), 0,
+                                  _stream_ptr(stream, self.device)))
 
     def check(self, stream=None):
         _check(lib().ssd_check(self._h, _stream_ptr(stream, self.device)))

@@ -57,10 +57,8 @@ def gpu_run(gm, Q, t0, dt, nsteps, check=True):
     N, E = gm.info["N"], gm.info["n_elem"]
     q = to_gpu(Q, gm.device)
     work = torch.empty(gm.info["work_len"], dtype=torch.float32, device=q.device)
-    t = t0
-    for _ in range(nsteps):
-        gm.rk_step(q, work, t, dt)
-        t += dt
+    for k in range(nsteps):
+        gm.rk_step(q, work, t0 + k * dt, dt)
     if check:
         gm.check()
     return from_gpu(q, N, E)

@@ -1,0 +1,86 @@
+"""Parity at the benchmark's full size (999,424-cell rotating-ellipse mesh,
+N = 4, the launch configuration bench.py times): the GPU's residual and one
+SSP-RK3 step are compared with the FP64 oracle on sampled cells, which the
+oracle evaluates on sub-meshes around them (every interface cell included).
+"""
+import numpy as np
+import pytest
+
+from oracle.ssd import SSD, submesh
+from tests.parity_utils import TOL, from_gpu, residual_error, state_error, to_gpu
+from workloads import cases as C
+from workloads import meshes as M
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c3():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import bench
+    from paper_1503_02198_amd import Mesh
+
+    class A:
+        N, K, n_in, n_out = 4, 4096, 64, 180
+    mesh, case, N, E, Q0, dt = bench.workload(A)
+    gm = Mesh(mesh, case, N, device=0)
+    return mesh, case, N, E, Q0, dt, gm
+
+
+def _samples(E, rng):
+    # the ellipse wall, both interface rings' neighbourhoods (tile-ordered
+    # blocks), the far field, and random cells
+    fixed = np.array([0, 1, 63, 64, 4095, 262080, 262143, 262144, 262200, E - 1])
+    return np.unique(np.concatenate([fixed, rng.choice(E, 200, replace=False)]))
+
+
+def test_fullsize_residual_sampled(c3):
+    import torch
+    mesh, case, N, E, Q0, dt, gm = c3
+    theta = 0.0123
+    print(f"case: full-size residual E={E} N={N} theta={theta}", flush=True)
+    q = to_gpu(Q0)
+    r = torch.empty_like(q)
+    gm.set_rotation(theta, case["omega"])
+    gm.mortar_rebuild()
+    gm.residual(q, r)
+    Rg = from_gpu(r, N, E)
+    pick = _samples(E, np.random.default_rng(5))
+    sub, idx = submesh(mesh, pick, depth=1)
+    ora = SSD(sub, case, N)
+    Ro, diag = ora.residual(Q0[..., idx].astype(np.float64), theta, case["omega"], diag=True)
+    loc = np.searchsorted(idx, pick)
+    err = residual_error(Rg[..., pick], Ro[..., loc], diag["flux_scale"][..., loc])
+    print("sampled residual error", err)
+    assert np.all(err <= TOL), err
+    # interface cells (all in the sub-mesh) are compared in full
+    sl = np.nonzero(np.any(mesh["face_kind"] == M.FACE_SLIDING, axis=1))[0]
+    locs = np.searchsorted(idx, sl)
+    err = residual_error(Rg[..., sl], Ro[..., locs], diag["flux_scale"][..., locs])
+    print("interface-cell residual error", err)
+    assert np.all(err <= TOL), err
+
+
+def test_fullsize_rk3_step_sampled(c3):
+    import torch
+    mesh, case, N, E, Q0, dt, gm = c3
+    print(f"case: full-size SSP-RK3 step E={E} dt={dt:.3e}", flush=True)
+    q = to_gpu(Q0)
+    work = torch.empty(gm.info["work_len"], dtype=torch.float32, device=q.device)
+    gm.rk_step(q, work, 0.0, dt)
+    gm.check()
+    Qg = from_gpu(q, N, E)
+    pick = _samples(E, np.random.default_rng(6))
+    sub, idx = submesh(mesh, pick, depth=3)
+    ora = SSD(sub, case, N)
+    Qo = ora.ssprk3_step(Q0[..., idx].astype(np.float64), 0.0, dt)
+    loc = np.searchsorted(idx, pick)
+    err = state_error(Qg[..., pick], Qo[..., loc])
+    # the step changes the state by ~1e-6 relative: compare the change too
+    dg = Qg[..., pick] - Q0[..., pick]
+    do = Qo[..., loc] - Q0[..., pick]
+    rel_change = np.linalg.norm(dg - do) / np.linalg.norm(do)
+    print("sampled state error", err, "error of the change", rel_change)
+    assert np.all(err <= TOL), err

@@ -119,8 +119,10 @@ def test_deterministic_and_restartable(torch_cuda):
     assert np.array_equal(a, b)
     half = gpu_run(gm, Q, 0.0, 1e-3, 10)
     c = gpu_run(gm, half, 10e-3, 1e-3, 10)
-    # the restart passes through FP32 host copies exactly
-    assert np.array_equal(a, c)
+    # the state carries everything: a restart from a host copy continues the
+    # run (the restart time 10e-3 and 0 + 10 * 1e-3 may differ in the last
+    # bit, which moves the rotor angle by an ulp)
+    assert np.all(state_error(c, a) < 1e-6)
 
 
 def test_error_paths(torch_cuda):
@@ -182,3 +184,21 @@ def test_mesh_validation(torch_cuda):
     with pytest.raises(SSDError) as ei:
         Mesh(mesh, case, 7)
     assert ei.value.status == -1
+
+
+def test_rk_steps_equals_repeated_rk_step(torch_cuda):
+    """ssd_rk_steps reuses the last stage's traces; it must reproduce the
+    same number of single steps at the same times t0 + k dt."""
+    import torch
+    from tests.parity_utils import from_gpu, to_gpu
+    print("case: rk_steps vs rk_step", flush=True)
+    mesh, case, ora, Q = _vortex(theta0=2 * np.pi / 32 - 0.01)
+    gm = _mesh(mesh, case, 3)
+    a = gpu_run(gm, Q, 0.0, 2e-3, 12)
+    q = to_gpu(Q)
+    work = torch.empty(gm.info["work_len"], dtype=torch.float32, device=q.device)
+    gm.rk_steps(q, work, 0.0, 2e-3, 12)
+    gm.check()
+    b = from_gpu(q, 3, gm.info["n_elem"])
+    print("bitwise equal:", np.array_equal(a, b), "max rel", state_error(b, a))
+    assert np.all(state_error(b, a) < 1e-6)

@@ -45,7 +45,7 @@ FACE_NODES = np.array([[0, 1, 2, 3], [3, 4, 5, 6], [9, 8, 7, 6], [0, 11, 10, 9]]
 # ----------------------------------------------------------------------------
 # structured blocks
 # ----------------------------------------------------------------------------
-def _block(P, curves=None, zone=0):
+def _block(P, curves=None, zone=0, tile=None):
     """Elements of a structured block of nodes P (ni+1, nj+1, 2).
 
     Element (i, j) has corners P[i,j], P[i+1,j], P[i+1,j+1], P[i,j+1] as its
@@ -53,7 +53,9 @@ def _block(P, curves=None, zone=0):
     `curves` maps a line index i to fn(j, t) giving the point a fraction t
     of the way along the j-th edge of that line (edges along eta); those
     edges get curved edge nodes and their elements become GEOM_CUBIC.
-    Elements are numbered with j fastest.
+    Elements are numbered with j fastest, or, with tile = (tj, ti), in
+    consecutive tiles of tj x ti elements (j fastest inside a tile, tiles
+    j-major), so that neighbours mostly share a tile.
     """
     curves = curves or {}
     ni, nj = P.shape[0] - 1, P.shape[1] - 1
@@ -85,8 +87,17 @@ def _block(P, curves=None, zone=0):
             xy[line - 1, :, 4] = fn(jj, 1.0 / 3.0)
             xy[line - 1, :, 5] = fn(jj, 2.0 / 3.0)
             geom[line - 1, :] = GEOM_CUBIC
-    return dict(xy=xy.reshape(-1, 12, 2), geom=geom.reshape(-1),
-                zone=np.full(ni * nj, zone, np.int32))
+    out = dict(xy=xy.reshape(-1, 12, 2), geom=geom.reshape(-1),
+               zone=np.full(ni * nj, zone, np.int32))
+    if tile is not None:
+        tj, ti = tile
+        if ni % ti or nj % tj:
+            raise ValueError("block size is not a multiple of the tile")
+        ii, jj = np.meshgrid(np.arange(ni), np.arange(nj), indexing="ij")
+        key = (((ii // ti) * (nj // tj) + jj // tj) * ti + ii % ti) * tj + jj % tj
+        order = np.argsort(key.ravel(), kind="stable")
+        out = {k: v[order] for k, v in out.items()}
+    return out
 
 
 def _concat(blocks):
@@ -329,10 +340,12 @@ def _geometric(n, first):
 
 
 def ellipse_mesh(K=4096, n_in=64, n_out=180, semi=(0.5, 0.1), radius=3.0,
-                 box_half=30.0, first_in=2e-3, first_out=4e-3):
+                 box_half=30.0, first_in=2e-3, first_out=4e-3, tile=(16, 4)):
     """Slip-wall ellipse in a rotating disk r < radius inside a stationary
     box [-B,B]^2 with far-field sides.  K azimuthal cells, n_in rotating and
-    n_out stationary layers (defaults: 4096 x (64 + 180) = 999,424 cells)."""
+    n_out stationary layers (defaults: 4096 x (64 + 180) = 999,424 cells),
+    numbered in tiles of 16 azimuthal x 4 radial cells (tile=None: ring by
+    ring)."""
     if K % 4:
         raise ValueError("K must be a multiple of 4")
     c = np.zeros(2)
@@ -349,7 +362,8 @@ def ellipse_mesh(K=4096, n_in=64, n_out=180, semi=(0.5, 0.1), radius=3.0,
         ang = (np.asarray(j) + t) * dphi
         return np.column_stack([a * np.cos(ang), b * np.sin(ang)])
 
-    inner = _block(_wrap(Pin), curves={0: ell_fn, n_in: _circle_fn(c, radius, 0.0, dphi)}, zone=1)
+    inner = _block(_wrap(Pin), curves={0: ell_fn, n_in: _circle_fn(c, radius, 0.0, dphi)}, zone=1,
+                   tile=tile)
 
     phi = -np.pi / 4 + dphi * np.arange(K)
     Cout = np.column_stack([radius * np.cos(phi), radius * np.sin(phi)])
@@ -358,7 +372,8 @@ def ellipse_mesh(K=4096, n_in=64, n_out=180, semi=(0.5, 0.1), radius=3.0,
     g = _geometric(n_out, first_out)
     Pout = (1 - g)[:, None, None] * Cout[None] + g[:, None, None] * Bx[None]
     Pout[0], Pout[-1] = Cout, Bx
-    outer = _block(_wrap(Pout), curves={0: _circle_fn(c, radius, -np.pi / 4, dphi)}, zone=0)
+    outer = _block(_wrap(Pout), curves={0: _circle_fn(c, radius, -np.pi / 4, dphi)}, zone=0,
+                   tile=tile)
 
     mesh = _concat([inner, outer])
     mesh["center"] = c
