@@ -105,6 +105,43 @@ def cpu_baseline(mesh, case, N, Q0, dt, q_gpu_step, target_s):
                 seconds=el), err
 
 
+def _counter_means(csv_path, counter):
+    """Mean value of one counter per kernel name in a rocprofv3 counter CSV."""
+    import csv
+    acc = {}
+    with open(csv_path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] != counter:
+                continue
+            k = r["Kernel_Name"]
+            acc.setdefault(k, []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def ingest_counters(fetch_csv, write_csv, calib_fetch_csv, calib_write_csv, E, N):
+    """Write the stage kernel's measured HBM bytes per launch from rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch), each scaled by what the
+    same counter reads for a plain 1 GiB device copy."""
+    def pick(d, key):
+        vals = [v for k, v in d.items() if key in k]
+        if not vals:
+            raise SystemExit(f"no {key} dispatches in the counter file")
+        return max(vals)
+    copy = float(1 << 30)
+    f_scale = copy / (pick(_counter_means(calib_fetch_csv, "FETCH_SIZE"), "copyBuffer") * 1024)
+    w_scale = copy / (pick(_counter_means(calib_write_csv, "WRITE_SIZE"), "copyBuffer") * 1024)
+    fetch = pick(_counter_means(fetch_csv, "FETCH_SIZE"), "k_stage<") * 1024 * f_scale
+    write = pick(_counter_means(write_csv, "WRITE_SIZE"), "k_stage<") * 1024 * w_scale
+    rec = {"kernel": "k_stage", "kernel_hash": kernel_hash(), "n_elem": E, "N": N,
+           "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+           "bytes_per_launch": fetch + write, "fetch_scale": f_scale, "write_scale": w_scale,
+           "note": "mean over the stage launches of a short run (stages 1-3 averaged)"}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
 def calib_copy(nbytes=1 << 30, reps=5):
     """A plain device copy of known size, for scaling rocprofv3 counters."""
     import torch
@@ -129,7 +166,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true")
+    ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV",
+                                                          "CALIB_FETCH_CSV", "CALIB_WRITE_CSV"))
     args = ap.parse_args()
+    if args.ingest_counters:
+        E = args.K * (args.n_in + args.n_out)
+        ingest_counters(*args.ingest_counters, E=E, N=args.N)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding of the method is a design note, not part of this build.", file=sys.stderr)

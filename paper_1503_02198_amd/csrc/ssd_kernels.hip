@@ -3,10 +3,10 @@
 // Layout: SoA with the element index fastest, so a wave that serves 64
 // consecutive elements reads and writes contiguous 256-byte rows per
 // (variable, point).  Face traces (the solution interpolated to the
-// element-boundary flux points) travel between neighbours through a trace
-// buffer [face][point][var][E]; the neighbour read is a gather that is
-// contiguous whenever consecutive elements have consecutive neighbours
-// (structured O-grids numbered azimuth-fastest).
+// element-boundary flux points) travel between blocks through a trace buffer
+// laid out [face][element][point][var]: one lane moves the 4 variables of a
+// point as one 16-byte access, and the N waves of a block together touch
+// whole 16 N-byte face records.
 //
 // Precision: state, traces and fluxes in FP32; element metrics and the
 // sliding-interface projections in FP64.
@@ -81,7 +81,21 @@ typedef __amdgpu_buffer_rsrc_t rsrc_t;
 __device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
 }
-// The b32 builtins move raw 32-bit words: bit-cast, never convert.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+struct f4 {
+  float x[4];
+};
+
+// The buffer builtins move raw 32-bit words: bit-cast, never convert.
+__device__ __forceinline__ f4 bload4(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore4(const float x[4], rsrc_t r, uint32_t voff, uint32_t soff) {
+  f4 t;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) t.x[v] = x[v];
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, t), r, voff, soff, 0);
+}
 __device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
@@ -219,18 +233,18 @@ __device__ __forceinline__ void prefetch_face(const DevMesh &M, const StageBufs 
 #pragma unroll
   for (int v = 0; v < 4; ++v) x[v] = 0.0f;
   if (kind == SSD_FACE_SLIDING) {
-    const uint32_t vo = (uint32_t(p * 4) * (B.S4 >> 2) + uint32_t(face_idx_of(fw))) * 4u;
+    const f4 t = bload4(B.mflux, (uint32_t(face_idx_of(fw)) * N + uint32_t(p)) * 16u, 0u);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) x[v] = bload(B.mflux, vo, v * B.S4);
+    for (int v = 0; v < 4; ++v) x[v] = t.x[v];
   } else if (kind == SSD_FACE_FARFIELD) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) x[v] = M.qinf[v];
   } else if ((kind == SSD_FACE_INTERIOR || kind == SSD_FACE_PERIODIC) && !face_inblock_of(fw)) {
     const uint32_t nb = uint32_t(face_idx_of(fw)), nf = uint32_t(face_nf_of(fw));
     const uint32_t pp = face_rev_of(fw) ? uint32_t(N - 1 - p) : uint32_t(p);
-    const uint32_t vo = ((nf * N + pp) * 4u) * B.E4 + nb * 4u;
+    const f4 t = bload4(B.trin, ((nf * (B.E4 >> 2) + nb) * N + pp) * 16u, 0u);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) x[v] = bload(B.trin, vo, v * B.E4);
+    for (int v = 0; v < 4; ++v) x[v] = t.x[v];
   }
 }
 
@@ -305,22 +319,25 @@ __global__ __launch_bounds__(256) void k_traces(DevMesh M, OpTables T, const flo
 #pragma unroll
       for (int i = 0; i < N; ++i) Q[v][j][i] = bload(rq, ve, ((v * N + j) * N + i) * E4);
 #pragma unroll
-  for (int p = 0; p < N; ++p)
+  for (int p = 0; p < N; ++p) {
+    float f0[4], f1[4], f2[4], f3[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      float f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f;
+      f0[v] = f1[v] = f2[v] = f3[v] = 0.f;
 #pragma unroll
       for (int s = 0; s < N; ++s) {
-        f0 += T.I[0][s] * Q[v][s][p];   // eta = 0, point p along xi
-        f2 += T.I[N][s] * Q[v][s][p];   // eta = 1
-        f1 += T.I[N][s] * Q[v][p][s];   // xi = 1, point p along eta
-        f3 += T.I[0][s] * Q[v][p][s];   // xi = 0
+        f0[v] += T.I[0][s] * Q[v][s][p];   // eta = 0, point p along xi
+        f2[v] += T.I[N][s] * Q[v][s][p];   // eta = 1
+        f1[v] += T.I[N][s] * Q[v][p][s];   // xi = 1, point p along eta
+        f3[v] += T.I[0][s] * Q[v][p][s];   // xi = 0
       }
-      if (ex[0]) bstore(f0, rt, ve, ((0 * N + p) * 4 + v) * E4);
-      if (ex[1]) bstore(f1, rt, ve, ((1 * N + p) * 4 + v) * E4);
-      if (ex[2]) bstore(f2, rt, ve, ((2 * N + p) * 4 + v) * E4);
-      if (ex[3]) bstore(f3, rt, ve, ((3 * N + p) * 4 + v) * E4);
     }
+    const uint32_t vo = (uint32_t(e) * N + p) * 16u, fs = uint32_t(M.E) * N * 16u;
+    if (ex[0]) bstore4(f0, rt, vo, 0 * fs);
+    if (ex[1]) bstore4(f1, rt, vo, 1 * fs);
+    if (ex[2]) bstore4(f2, rt, vo, 2 * fs);
+    if (ex[3]) bstore4(f3, rt, vo, 3 * fs);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -526,19 +543,21 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
     bad |= !(rho > 0.0f) || !(pr > 0.0f) || !isfinite(qc[1][j]) || !isfinite(qc[2][j]);
   }
   const bool ex0 = face_exported(fw0), ex2 = face_exported(fw2);
+  const uint32_t tvo = (uint32_t(e) * N + uint32_t(w)) * 16u, tfs = uint32_t(M.E) * N * 16u;
   if (valid) {
+    float f0[4], f2[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      float f0 = 0.f, f2 = 0.f;
+      f0[v] = f2[v] = 0.f;
 #pragma unroll
       for (int j = 0; j < N; ++j) {
         bstore(qc[v][j], B.out, ve, ((v * N + j) * N + w) * B.E4);
-        f0 += T.I[0][j] * qc[v][j];     // eta = 0 face, point w
-        f2 += T.I[N][j] * qc[v][j];     // eta = 1 face, point w
+        f0[v] += T.I[0][j] * qc[v][j];     // eta = 0 face, point w
+        f2[v] += T.I[N][j] * qc[v][j];     // eta = 1 face, point w
       }
-      if (ex0) bstore(f0, B.trout, ve, ((0 * N + w) * 4 + v) * B.E4);
-      if (ex2) bstore(f2, B.trout, ve, ((2 * N + w) * 4 + v) * B.E4);
     }
+    if (ex0) bstore4(f0, B.trout, tvo, 0 * tfs);
+    if (ex2) bstore4(f2, B.trout, tvo, 2 * tfs);
     if (bad) M.flag[0] = 1;
   }
   __syncthreads();
@@ -546,18 +565,19 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
   // ---- trace phase: faces xi = 0, 1 at point w from row w of the new state
   const bool ex1 = face_exported(fw1), ex3 = face_exported(fw3);
   if (valid && (ex1 || ex3)) {
+    float f1[4], f3[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      float f1 = 0.f, f3 = 0.f;
+      f1[v] = f3[v] = 0.f;
 #pragma unroll
       for (int i = 0; i < N; ++i) {
         const float x = SR[v][w][i][l];
-        f1 += T.I[N][i] * x;
-        f3 += T.I[0][i] * x;
+        f1[v] += T.I[N][i] * x;
+        f3[v] += T.I[0][i] * x;
       }
-      if (ex1) bstore(f1, B.trout, ve, ((1 * N + w) * 4 + v) * B.E4);
-      if (ex3) bstore(f3, B.trout, ve, ((3 * N + w) * 4 + v) * B.E4);
     }
+    if (ex1) bstore4(f1, B.trout, tvo, 1 * tfs);
+    if (ex3) bstore4(f3, B.trout, tvo, 3 * tfs);
   }
 }
 
@@ -636,7 +656,7 @@ __device__ __forceinline__ void load_canon(const DevMesh &M, const float *__rest
   for (int a = 0; a < N; ++a) {
     const int pa = flip ? N - 1 - a : a;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) q[v][a] = double(tr[long((f * N + pa) * 4 + v) * E + e]);
+    for (int v = 0; v < 4; ++v) q[v][a] = double(tr[((long(f) * E + e) * N + pa) * 4 + v]);
   }
 }
 
@@ -645,7 +665,7 @@ __device__ __forceinline__ void load_canon(const DevMesh &M, const float *__rest
 // (eq. prjQ2), takes the Rusanov flux with the exact radial normal, scales
 // it to flux per unit face parameter (R_s Delta), and projects back to its
 // own face (eq. prjF2).  Output: outward common flux in the element's face
-// parameter order, mflux[point][var][slot].
+// parameter order, mflux[slot][point][var].
 template <int N>
 __global__ __launch_bounds__(64) void k_mortar(DevMesh M, OpTables T,
                                                const MortarState *__restrict__ ms,
@@ -710,12 +730,11 @@ __global__ __launch_bounds__(64) void k_mortar(DevMesh M, OpTables T,
   }
   const int flip = M.ring_flip[t];
   const double sign = right ? -1.0 : 1.0;
-  const long S = 2L * K;
 #pragma unroll
   for (int a = 0; a < N; ++a) {
     const int pa = flip ? N - 1 - a : a;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) mflux[long(pa * 4 + v) * S + t] = float(sign * acc[v][a]);
+    for (int v = 0; v < 4; ++v) mflux[(long(t) * N + pa) * 4 + v] = float(sign * acc[v][a]);
   }
 }
 
