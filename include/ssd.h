@@ -70,7 +70,8 @@ typedef enum { SSD_RK3_SSP = 0 } ssd_rk;
  *             (Sec. 3.1: N Chebyshev-Gauss SPs, N+1 FPs per direction).
  *  n_elem     number of elements; one handle needs its state array
  *             (16 N^2 n_elem bytes) and trace array (64 N n_elem bytes)
- *             below 4 GiB (n_elem < 16.7 million at N = 4).
+ *             below 4 GiB (n_elem < 16.7 million at N = 4); with mu > 0
+ *             the gradient arrays, twice those sizes, as well.
  *  elem_xy    [n_elem][12][2] node coordinates, counter-clockwise around
  *             the reference square [0,1]^2: (0,0) (1/3,0) (2/3,0) (1,0)
  *             (1,1/3) (1,2/3) (1,1) (2/3,1) (1/3,1) (0,1) (0,2/3) (0,1/3).
@@ -199,7 +200,10 @@ const char *ssd_last_error(void);
 
 /*
  * Kernel timing.  While enabled, every kernel launch of the handle is
- * bracketed by HIP events on its stream.  ssd_timing_read synchronises and
+ * bracketed by HIP events on its stream.  Classes: the stage kernel
+ * (residual or fused RK stage), the face-trace kernel, the mortar kernels
+ * (inviscid and, with mu > 0, viscous), the mortar rebuild, and the
+ * gradient pass of viscous meshes.  ssd_timing_read synchronises and
  * returns the summed milliseconds and the launch count of one kernel class
  * (SSD_KERNEL_*) since the last reset; ssd_timing_reset clears them.
  */

@@ -1,0 +1,434 @@
+// Device-side building blocks of the SSD kernels (gfx950): buffer access,
+// fluxes, element geometry and the common values at element faces.
+#pragma once
+
+#include "ssd_internal.h"
+
+namespace ssd {
+
+// ---------------------------------------------------------------------------
+// raw buffer access: SGPR resource + per-lane byte offset + uniform byte
+// offset, so address arithmetic stays on the scalar unit.  The resource
+// carries the array size; the hardware returns 0 for reads past it and
+// drops writes past it.
+// ---------------------------------------------------------------------------
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+struct f4 {
+  float x[4];
+};
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+// The buffer builtins move raw 32-bit words: bit-cast, never convert.
+__device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(float x, rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, voff, soff, 0);
+}
+__device__ __forceinline__ f4 bload4(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore4(const float x[4], rsrc_t r, uint32_t voff, uint32_t soff) {
+  f4 t;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) t.x[v] = x[v];
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, t), r, voff, soff, 0);
+}
+
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// ---------------------------------------------------------------------------
+// fluxes (Sec. 2.1, 2.2, 3.1)
+// ---------------------------------------------------------------------------
+// Normal inviscid ALE flux along the scaled normal (nx, ny):
+// (F - u_g Q) nx + (G - v_g Q) ny with vgn = u_g nx + v_g ny.
+__device__ __forceinline__ void flux_n(const float q[4], float nx, float ny, float vgn, float gm1,
+                                       float f[4]) {
+  const float ir = rcp(q[0]);
+  const float u = q[1] * ir, v = q[2] * ir;
+  const float p = gm1 * (q[3] - 0.5f * (q[1] * u + q[2] * v));
+  const float un = u * nx + v * ny;
+  const float rel = un - vgn;
+  f[0] = q[0] * rel;
+  f[1] = q[1] * rel + p * nx;
+  f[2] = q[2] * rel + p * ny;
+  f[3] = q[3] * rel + p * un;
+}
+
+// Rusanov common flux from the owner (l) towards the neighbour (r).
+__device__ __forceinline__ void rusanov(const float ql[4], const float qr[4], float nx, float ny,
+                                        float vgn, float gam, float f[4]) {
+  const float gm1 = gam - 1.0f;
+  const float mag = __builtin_amdgcn_sqrtf(nx * nx + ny * ny);
+  const float irl = rcp(ql[0]), irr = rcp(qr[0]);
+  const float ul = ql[1] * irl, vl = ql[2] * irl;
+  const float ur = qr[1] * irr, vr = qr[2] * irr;
+  const float pl = gm1 * (ql[3] - 0.5f * (ql[1] * ul + ql[2] * vl));
+  const float pr = gm1 * (qr[3] - 0.5f * (qr[1] * ur + qr[2] * vr));
+  const float unl = ul * nx + vl * ny, unr = ur * nx + vr * ny;
+  const float rl = unl - vgn, rr = unr - vgn;
+  const float cl = __builtin_amdgcn_sqrtf(gam * pl * irl), cr = __builtin_amdgcn_sqrtf(gam * pr * irr);
+  const float lam = fmaxf(fabsf(rl) + cl * mag, fabsf(rr) + cr * mag);
+  f[0] = 0.5f * (ql[0] * rl + qr[0] * rr) - 0.5f * lam * (qr[0] - ql[0]);
+  f[1] = 0.5f * (ql[1] * rl + pl * nx + qr[1] * rr + pr * nx) - 0.5f * lam * (qr[1] - ql[1]);
+  f[2] = 0.5f * (ql[2] * rl + pl * ny + qr[2] * rr + pr * ny) - 0.5f * lam * (qr[2] - ql[2]);
+  f[3] = 0.5f * (ql[3] * rl + pl * unl + qr[3] * rr + pr * unr) - 0.5f * lam * (qr[3] - ql[3]);
+}
+
+// FP64 Rusanov flux for the mortars (no grid velocity: u_g . n = 0 on the circle).
+__device__ __forceinline__ void rusanov_d(const double ql[4], const double qr[4], double nx,
+                                          double ny, double gam, double f[4]) {
+  const double gm1 = gam - 1.0;
+  const double mag = sqrt(nx * nx + ny * ny);
+  const double ul = ql[1] / ql[0], vl = ql[2] / ql[0];
+  const double ur = qr[1] / qr[0], vr = qr[2] / qr[0];
+  const double pl = gm1 * (ql[3] - 0.5 * (ql[1] * ul + ql[2] * vl));
+  const double pr = gm1 * (qr[3] - 0.5 * (qr[1] * ur + qr[2] * vr));
+  const double unl = ul * nx + vl * ny, unr = ur * nx + vr * ny;
+  const double cl = sqrt(gam * pl / ql[0]), cr = sqrt(gam * pr / qr[0]);
+  const double lam = fmax(fabs(unl) + cl * mag, fabs(unr) + cr * mag);
+  f[0] = 0.5 * (ql[0] * unl + qr[0] * unr) - 0.5 * lam * (qr[0] - ql[0]);
+  f[1] = 0.5 * (ql[1] * unl + pl * nx + qr[1] * unr + pr * nx) - 0.5 * lam * (qr[1] - ql[1]);
+  f[2] = 0.5 * (ql[2] * unl + pl * ny + qr[2] * unr + pr * ny) - 0.5 * lam * (qr[2] - ql[2]);
+  f[3] = 0.5 * (ql[3] * unl + pl * unl + qr[3] * unr + pr * unr) - 0.5 * lam * (qr[3] - ql[3]);
+}
+
+// Gas constants of the viscous terms.
+struct ViscParams {
+  float gamma, R, mu, kcond;   // kcond = mu gamma R / ((gamma - 1) Pr)
+};
+
+__device__ __forceinline__ ViscParams visc_params(const DevMesh &M) {
+  ViscParams P;
+  P.gamma = M.gamma;
+  P.R = M.gas_R;
+  P.mu = M.mu;
+  P.kcond = M.mu * M.gamma * M.gas_R / ((M.gamma - 1.0f) * M.prandtl);
+  return P;
+}
+
+// Normal viscous flux F_vis nx + G_vis ny (Sec. 2.1) from the conservative
+// state and its x, y gradients: tau_ij = mu (u_i,j + u_j,i) - 2/3 mu
+// delta_ij div u, heat flux k grad T with T = p / (rho R).
+template <typename R>
+__device__ __forceinline__ void visc_flux_n(const R q[4], const R gx[4], const R gy[4], R nx, R ny,
+                                            R gamma, R Rg, R mu, R kc, R f[4]) {
+  const R ir = R(1) / q[0];
+  const R u = q[1] * ir, v = q[2] * ir;
+  const R p = (gamma - R(1)) * (q[3] - R(0.5) * (q[1] * u + q[2] * v));
+  const R ux = (gx[1] - u * gx[0]) * ir, vx = (gx[2] - v * gx[0]) * ir;
+  const R uy = (gy[1] - u * gy[0]) * ir, vy = (gy[2] - v * gy[0]) * ir;
+  const R k2 = R(0.5) * (u * u + v * v);
+  const R px = (gamma - R(1)) * (gx[3] - u * gx[1] - v * gx[2] + k2 * gx[0]);
+  const R py = (gamma - R(1)) * (gy[3] - u * gy[1] - v * gy[2] + k2 * gy[0]);
+  const R Tx = (px - p * ir * gx[0]) * ir / Rg;
+  const R Ty = (py - p * ir * gy[0]) * ir / Rg;
+  const R div = ux + vy;
+  const R txx = R(2) * mu * ux - R(2.0 / 3.0) * mu * div;
+  const R tyy = R(2) * mu * vy - R(2.0 / 3.0) * mu * div;
+  const R txy = mu * (uy + vx);
+  f[0] = R(0);
+  f[1] = -(txx * nx + txy * ny);
+  f[2] = -(txy * nx + tyy * ny);
+  f[3] = -((u * txx + v * txy + kc * Tx) * nx + (u * txy + v * tyy + kc * Ty) * ny);
+}
+
+// ---------------------------------------------------------------------------
+// element geometry (Sec. 2.3).  Bilinear cells: the four edge vectors are
+// differenced in FP64 from the stored corners, then carried in FP32 and
+// rotated once into the current frame, so every metric is a linear
+// combination:  x_xi(eta) = A + eta (B - A),  x_eta(xi) = C + xi (D - C),
+// x(xi, eta) = p0 + xi A + eta C + xi eta (B - A).  Cubic cells read FP64
+// tables and rotate in FP64.
+// ---------------------------------------------------------------------------
+struct ElemGeo {
+  int cubic, c;
+  float w;                                    // omega of the zone (0: fixed)
+  float p0x, p0y, Ax, Ay, Bx, By, Cx, Cy, Dx, Dy;
+  double ct, st;
+};
+
+__device__ __forceinline__ ElemGeo load_geo(const DevMesh &M, int e, const Rotation &R) {
+  ElemGeo g;
+  const long E = M.E;
+  // corners are read for every cell (cubic cells ignore them) so that no
+  // load waits on the flag word
+  const double x0 = M.corners[0 * E + e], y0 = M.corners[1 * E + e];
+  const double x3 = M.corners[2 * E + e], y3 = M.corners[3 * E + e];
+  const double x6 = M.corners[4 * E + e], y6 = M.corners[5 * E + e];
+  const double x9 = M.corners[6 * E + e], y9 = M.corners[7 * E + e];
+  const int fl = M.eflag[e];
+  g.cubic = fl & EF_CUBIC;
+  g.c = fl >> 8;
+  const bool rot = (fl & EF_ROT) != 0;
+  g.ct = rot ? R.ct : 1.0;
+  g.st = rot ? R.st : 0.0;
+  g.w = rot ? float(R.omega) : 0.0f;
+  const float c = float(g.ct), s = float(g.st);
+  auto rx = [&](double x, double y) { return c * float(x) - s * float(y); };
+  auto ry = [&](double x, double y) { return s * float(x) + c * float(y); };
+  g.p0x = rx(x0, y0);            g.p0y = ry(x0, y0);
+  g.Ax = rx(x3 - x0, y3 - y0);   g.Ay = ry(x3 - x0, y3 - y0);
+  g.Bx = rx(x6 - x9, y6 - y9);   g.By = ry(x6 - x9, y6 - y9);
+  g.Cx = rx(x9 - x0, y9 - y0);   g.Cy = ry(x9 - x0, y9 - y0);
+  g.Dx = rx(x6 - x3, y6 - y3);   g.Dy = ry(x6 - x3, y6 - y3);
+  return g;
+}
+
+// Metric data of one flux point: scaled normal (nx, ny) of the flux-point
+// line, u_g . n, and the grid velocity (ug, vg) there (zero on fixed cells).
+struct FPGeo {
+  float nx, ny, vgn, ug, vg;
+};
+
+// xi-direction flux point (Xf_k, X_j): n = (y_eta, -x_eta) in the current frame.
+template <int N>
+__device__ __forceinline__ FPGeo metric_xi(const ElemGeo &g, const DevMesh &M, const OpTables &T,
+                                           int k, int j) {
+  FPGeo r;
+  r.ug = r.vg = r.vgn = 0.0f;
+  if (g.cubic) {
+    const double xe = M.cmet[cubic_xi_index(N, M.C, 0, j, k, g.c)];
+    const double ye = M.cmet[cubic_xi_index(N, M.C, 1, j, k, g.c)];
+    r.nx = float(g.st * xe + g.ct * ye);
+    r.ny = float(-(g.ct * xe - g.st * ye));
+    if (g.w != 0.0f) {
+      const double px = M.cmet[cubic_xi_index(N, M.C, 2, j, k, g.c)];
+      const double py = M.cmet[cubic_xi_index(N, M.C, 3, j, k, g.c)];
+      r.vgn = float(-double(g.w) * (px * xe + py * ye));
+      r.ug = float(-double(g.w) * (g.st * px + g.ct * py));
+      r.vg = float(double(g.w) * (g.ct * px - g.st * py));
+    }
+    return r;
+  }
+  const float xi = float(T.Xf[k]), eta = float(T.X[j]);
+  const float xe = g.Cx + xi * (g.Dx - g.Cx), ye = g.Cy + xi * (g.Dy - g.Cy);
+  r.nx = ye;
+  r.ny = -xe;
+  if (g.w != 0.0f) {
+    const float px = g.p0x + xi * g.Ax + eta * g.Cx + xi * eta * (g.Bx - g.Ax);
+    const float py = g.p0y + xi * g.Ay + eta * g.Cy + xi * eta * (g.By - g.Ay);
+    r.vgn = -g.w * (px * xe + py * ye);
+    r.ug = -g.w * py;
+    r.vg = g.w * px;
+  }
+  return r;
+}
+
+// eta-direction flux point (X_i, Xf_k): n = (-y_xi, x_xi) in the current frame.
+template <int N>
+__device__ __forceinline__ FPGeo metric_eta(const ElemGeo &g, const DevMesh &M, const OpTables &T,
+                                            int k, int i) {
+  FPGeo r;
+  r.ug = r.vg = r.vgn = 0.0f;
+  if (g.cubic) {
+    const double xx = M.cmet[cubic_eta_index(N, M.C, 0, k, i, g.c)];
+    const double yx = M.cmet[cubic_eta_index(N, M.C, 1, k, i, g.c)];
+    r.nx = float(-(g.st * xx + g.ct * yx));
+    r.ny = float(g.ct * xx - g.st * yx);
+    if (g.w != 0.0f) {
+      const double px = M.cmet[cubic_eta_index(N, M.C, 2, k, i, g.c)];
+      const double py = M.cmet[cubic_eta_index(N, M.C, 3, k, i, g.c)];
+      r.vgn = float(double(g.w) * (px * xx + py * yx));
+      r.ug = float(-double(g.w) * (g.st * px + g.ct * py));
+      r.vg = float(double(g.w) * (g.ct * px - g.st * py));
+    }
+    return r;
+  }
+  const float xi = float(T.X[i]), eta = float(T.Xf[k]);
+  const float xx = g.Ax + eta * (g.Bx - g.Ax), yx = g.Ay + eta * (g.By - g.Ay);
+  r.nx = -yx;
+  r.ny = xx;
+  if (g.w != 0.0f) {
+    const float px = g.p0x + xi * g.Ax + eta * g.Cx + xi * eta * (g.Bx - g.Ax);
+    const float py = g.p0y + xi * g.Ay + eta * g.Cy + xi * eta * (g.By - g.Ay);
+    r.vgn = g.w * (px * xx + py * yx);
+    r.ug = -g.w * py;
+    r.vg = g.w * px;
+  }
+  return r;
+}
+
+// Metric derivatives x_xi, y_xi, x_eta, y_eta at the solution point
+// (X_i, X_j) in the current frame, and 1 / |J|.
+struct SPGeo {
+  float xx, yx, xe, ye, ij;
+};
+
+template <int N>
+__device__ __forceinline__ SPGeo metric_sp(const ElemGeo &g, const DevMesh &M, const OpTables &T,
+                                           int j, int i) {
+  SPGeo r;
+  if (g.cubic) {
+    const double J = M.cmet[cubic_sp_index(N, M.C, 0, j, i, g.c)];
+    const double xx = M.cmet[cubic_sp_index(N, M.C, 1, j, i, g.c)];
+    const double xe = M.cmet[cubic_sp_index(N, M.C, 2, j, i, g.c)];
+    const double yx = M.cmet[cubic_sp_index(N, M.C, 3, j, i, g.c)];
+    const double ye = M.cmet[cubic_sp_index(N, M.C, 4, j, i, g.c)];
+    r.xx = float(g.ct * xx - g.st * yx);
+    r.yx = float(g.st * xx + g.ct * yx);
+    r.xe = float(g.ct * xe - g.st * ye);
+    r.ye = float(g.st * xe + g.ct * ye);
+    r.ij = float(1.0 / J);
+    return r;
+  }
+  const float xi = float(T.X[i]), eta = float(T.X[j]);
+  r.xx = g.Ax + eta * (g.Bx - g.Ax);
+  r.yx = g.Ay + eta * (g.By - g.Ay);
+  r.xe = g.Cx + xi * (g.Dx - g.Cx);
+  r.ye = g.Cy + xi * (g.Dy - g.Cy);
+  r.ij = rcp(r.xx * r.ye - r.xe * r.yx);
+  return r;
+}
+
+// 1 / |J| at the solution point (X_i, X_j).
+template <int N>
+__device__ __forceinline__ float inv_jacobian(const ElemGeo &g, const DevMesh &M,
+                                              const OpTables &T, int j, int i) {
+  if (g.cubic) return float(1.0 / M.cmet[cubic_sp_index(N, M.C, 0, j, i, g.c)]);
+  const float xi = float(T.X[i]), eta = float(T.X[j]);
+  const float xx = g.Ax + eta * (g.Bx - g.Ax), yx = g.Ay + eta * (g.By - g.Ay);
+  const float xe = g.Cx + xi * (g.Dx - g.Cx), ye = g.Cy + xi * (g.Dy - g.Cy);
+  return rcp(xx * ye - xe * yx);
+}
+
+// ---------------------------------------------------------------------------
+// face data
+// ---------------------------------------------------------------------------
+// What a face needs from outside the block, fetched before it is used: the
+// neighbour's trace (a neighbour in another block), the far-field state, or
+// a per-interface-face record `side` (the projected mortar flux, or the
+// projected common solution) of a sliding face.  Faces whose neighbour is
+// in the same block, and walls, fetch nothing.
+template <int N>
+__device__ __forceinline__ void prefetch_face(const DevMesh &M, rsrc_t trin, rsrc_t side,
+                                              uint32_t E, uint32_t fw, int p, float x[4]) {
+  const int kind = face_kind_of(fw);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) x[v] = 0.0f;
+  if (kind == SSD_FACE_SLIDING) {
+    const f4 t = bload4(side, (uint32_t(face_idx_of(fw)) * N + uint32_t(p)) * 16u, 0u);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) x[v] = t.x[v];
+  } else if (kind == SSD_FACE_FARFIELD) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) x[v] = M.qinf[v];
+  } else if ((kind == SSD_FACE_INTERIOR || kind == SSD_FACE_PERIODIC) && !face_inblock_of(fw)) {
+    const uint32_t nb = uint32_t(face_idx_of(fw)), nf = uint32_t(face_nf_of(fw));
+    const uint32_t pp = face_rev_of(fw) ? uint32_t(N - 1 - p) : uint32_t(p);
+    const f4 t = bload4(trin, ((nf * E + nb) * N + pp) * 16u, 0u);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) x[v] = t.x[v];
+  }
+}
+
+__device__ __forceinline__ bool conforming(int kind) {
+  return kind == SSD_FACE_INTERIOR || kind == SSD_FACE_PERIODIC;
+}
+
+// The neighbour's solution at the face point matching point p of face word
+// fw: interpolated from the block's LDS state Sf [var][j][i][lane] when the
+// neighbour is in the same block, else the prefetched value.
+template <int N>
+__device__ __forceinline__ void neighbor_state(const OpTables &T, const float *Sf, uint32_t fw,
+                                               int p, const float x[4], float qx[4]) {
+  if (face_inblock_of(fw)) {
+    const uint32_t nf = uint32_t(face_nf_of(fw));
+    const int pp = face_rev_of(fw) ? N - 1 - p : p;
+    const int ln = face_idx_of(fw) & (EB - 1);
+    const bool odd = (nf & 1u) != 0;               // xi faces: the point runs along eta
+    const bool hi = (nf == 1u || nf == 2u);        // xi = 1 or eta = 1
+    const int base = (odd ? pp * N * EB : pp * EB) + ln;
+    const int stride = odd ? EB : N * EB;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float acc = 0.f;
+#pragma unroll
+      for (int s2 = 0; s2 < N; ++s2)
+        acc += (hi ? T.I[N][s2] : T.I[0][s2]) * Sf[v * N * N * EB + base + s2 * stride];
+      qx[v] = acc;
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) qx[v] = x[v];
+  }
+}
+
+// Common inviscid normal flux at one element-boundary flux point along the
+// outward normal of `G`, given the face data x (see prefetch_face).  For a
+// conforming face the neighbour's state is returned in qx.
+template <int N>
+__device__ __forceinline__ void common_flux(const DevMesh &M, const OpTables &T, const float *Sf,
+                                            uint32_t fw, int p, const float qo[4],
+                                            const float x[4], const FPGeo &G, float fs[4],
+                                            float qx[4]) {
+  const int kind = face_kind_of(fw);
+  if (kind == SSD_FACE_SLIDING) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) fs[v] = x[v];
+    return;
+  }
+  if (kind == SSD_FACE_WALL_ISOTHERMAL || kind == SSD_FACE_WALL_SLIP) {
+    // no flux relative to the moving wall; pressure from the interior
+    const float pr = (M.gamma - 1.0f) * (qo[3] - 0.5f * (qo[1] * qo[1] + qo[2] * qo[2]) * rcp(qo[0]));
+    fs[0] = 0.0f;
+    fs[1] = pr * G.nx;
+    fs[2] = pr * G.ny;
+    fs[3] = pr * G.vgn;
+    return;
+  }
+  if (conforming(kind)) {
+    neighbor_state<N>(T, Sf, fw, p, x, qx);
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) qx[v] = x[v];
+  }
+  rusanov(qo, qx, G.nx, G.ny, G.vgn, M.gamma, fs);
+}
+
+// Common solution at a face point for the gradient (BR1 reading): the mean
+// of both sides on conforming faces; the wall state on isothermal walls
+// (interior pressure, wall temperature, wall velocity = grid velocity);
+// the interior state without its normal velocity relative to the wall on
+// slip walls; the far-field state; the projected mortar value on sliding
+// faces (x).  qx is the neighbour's state on conforming faces.
+__device__ __forceinline__ void common_solution(const DevMesh &M, int kind, const float qo[4],
+                                                const float qx[4], const float x[4],
+                                                const FPGeo &G, float qc[4]) {
+  if (kind == SSD_FACE_INTERIOR || kind == SSD_FACE_PERIODIC) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) qc[v] = 0.5f * (qo[v] + qx[v]);
+    return;
+  }
+  if (kind == SSD_FACE_SLIDING || kind == SSD_FACE_FARFIELD) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) qc[v] = x[v];
+    return;
+  }
+  const float gm1 = M.gamma - 1.0f;
+  const float ir = rcp(qo[0]);
+  const float u = qo[1] * ir, v = qo[2] * ir;
+  const float p = gm1 * (qo[3] - 0.5f * (qo[1] * u + qo[2] * v));
+  if (kind == SSD_FACE_WALL_ISOTHERMAL) {
+    const float rb = p / (M.gas_R * M.T_wall);
+    qc[0] = rb;
+    qc[1] = rb * G.ug;
+    qc[2] = rb * G.vg;
+    qc[3] = p / gm1 + 0.5f * rb * (G.ug * G.ug + G.vg * G.vg);
+    return;
+  }
+  // slip wall
+  const float im = rcp(__builtin_amdgcn_sqrtf(G.nx * G.nx + G.ny * G.ny));
+  const float hx = G.nx * im, hy = G.ny * im;
+  const float un = (u - G.ug) * hx + (v - G.vg) * hy;
+  const float ub = u - un * hx, vb = v - un * hy;
+  qc[0] = qo[0];
+  qc[1] = qo[0] * ub;
+  qc[2] = qo[0] * vb;
+  qc[3] = p / gm1 + 0.5f * qo[0] * (ub * ub + vb * vb);
+}
+
+}  // namespace ssd

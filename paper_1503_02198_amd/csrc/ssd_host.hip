@@ -294,6 +294,7 @@ struct ssd_mesh {
   std::vector<void *> allocs;
   float *tr[2] = {nullptr, nullptr};
   float *mflux = nullptr;
+  ViscIO V{};                          // viscous work buffers (mu > 0)
   MortarState *ms = nullptr;
   int *flag = nullptr;
   bool timing = false;
@@ -608,6 +609,10 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
     m->D.ring_f = drf;
     m->D.ring_flip = drl;
     SSD_HIP(dev_alloc(m, &m->mflux, 2L * K * 4 * N), "alloc mortar flux");
+    if (m->viscous) {
+      SSD_HIP(dev_alloc(m, &m->V.mqc, 2L * K * 4 * N), "alloc mortar common solution");
+      SSD_HIP(dev_alloc(m, &m->V.mvflux, 2L * K * 4 * N), "alloc viscous mortar flux");
+    }
     SSD_HIP(dev_alloc(m, &m->ms, 1), "alloc mortar state");
     SSD_HIP(hipMemset(m->ms, 0, sizeof(MortarState)), "clear mortar state");
   }
@@ -629,6 +634,10 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
     SSD_HIP(hipMemcpy(dcmet, cmet.data(), cmet.size() * sizeof(double), hipMemcpyHostToDevice),
             "upload cubic metrics");
   for (int b = 0; b < 2; ++b) SSD_HIP(dev_alloc(m, &m->tr[b], 16L * N * E), "alloc traces");
+  if (m->viscous) {
+    SSD_HIP(dev_alloc(m, &m->V.G, 8L * N * N * E), "alloc gradients");
+    SSD_HIP(dev_alloc(m, &m->V.gtr, 32L * N * E), "alloc gradient traces");
+  }
   SSD_HIP(dev_alloc(m, &m->flag, 1), "alloc flag");
   SSD_HIP(hipMemset(m->flag, 0, sizeof(int)), "clear flag");
 
@@ -666,6 +675,38 @@ ssd_status check_handle(const ssd_mesh *m) {
   return SSD_OK;
 }
 
+// One evaluation of the residual of `in` (face traces in trin) at rotor
+// angle th with the mortar state already rebuilt for th: the inviscid
+// mortar; on viscous meshes the gradient pass and the viscous mortar; then
+// the stage kernel (rk: the fused SSP-RK stage writing out and trout).
+ssd_status residual_pass(ssd_mesh *m, double th, double omega, const float *in, const float *qn,
+                         float *out, const float *trin, float *trout, float a, float b, float dt,
+                         bool rk, hipStream_t st) {
+  ViscIO *V = m->viscous ? &m->V : nullptr;
+  if (m->K) {
+    LaunchTimer lt(m, SSD_KERNEL_MORTAR, st);
+    SSD_HIP(launch_mortar(m->D, m->T, m->ms, trin, m->mflux, V ? V->mqc : nullptr, st),
+            "mortar launch");
+  }
+  const Rotation rot{std::cos(th), std::sin(th), omega};
+  if (V) {
+    {
+      LaunchTimer lt(m, SSD_KERNEL_GRAD, st);
+      SSD_HIP(launch_grad(m->D, m->T, rot, in, trin, V->mqc, V->G, V->gtr, st),
+              "gradient launch");
+    }
+    if (m->K) {
+      LaunchTimer lt(m, SSD_KERNEL_MORTAR, st);
+      SSD_HIP(launch_mortar_visc(m->D, m->T, m->ms, V->mqc, V->gtr, V->mvflux, st),
+              "viscous mortar launch");
+    }
+  }
+  LaunchTimer lt(m, SSD_KERNEL_STAGE, st);
+  SSD_HIP(launch_stage(m->D, m->T, rot, in, qn, out, trin, trout, m->mflux, V, a, b, dt, rk, st),
+          rk ? "stage launch" : "residual launch");
+  return SSD_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -681,9 +722,11 @@ ssd_status ssd_create_mesh(const ssd_mesh_desc *d, int device, ssd_mesh **out) {
   if (d->N < 2 || d->N > NMAX) return fail(SSD_ERR_INVALID_ARG, "N must be in 2..6");
   if (d->n_elem <= 0 || d->n_elem >= MAX_ELEMS)
     return fail(SSD_ERR_INVALID_ARG, "n_elem out of range");
-  // kernels address state and trace arrays with 32-bit byte offsets
-  if (double(std::max(16 * d->N * d->N, 64 * d->N)) * double(d->n_elem) >= 4294967295.0)
-    return fail(SSD_ERR_INVALID_ARG, "mesh too large for one handle (state or trace array >= 4 GiB)");
+  // kernels address state, trace and gradient arrays with 32-bit byte offsets
+  if (double(std::max(16 * d->N * d->N, 64 * d->N)) * double(d->n_elem) * (d->mu > 0.0 ? 2.0 : 1.0) >=
+      4294967295.0)
+    return fail(SSD_ERR_INVALID_ARG,
+                "mesh too large for one handle (state, trace or gradient array >= 4 GiB)");
   if (!d->elem_xy || !d->elem_geom || !d->elem_zone || !d->nbr_elem || !d->nbr_face || !d->face_kind)
     return fail(SSD_ERR_INVALID_ARG, "null mesh array");
   const double sc[] = {d->rot_center[0], d->rot_center[1], d->iface_radius, d->omega, d->theta0,
@@ -693,7 +736,6 @@ ssd_status ssd_create_mesh(const ssd_mesh_desc *d, int device, ssd_mesh **out) {
   if (!(d->gamma > 1.0) || !(d->gas_R > 0.0) || d->mu < 0.0)
     return fail(SSD_ERR_INVALID_ARG, "need gamma > 1, gas_R > 0, mu >= 0");
   if (d->mu > 0.0 && !(d->prandtl > 0.0)) return fail(SSD_ERR_INVALID_ARG, "need prandtl > 0");
-  if (d->mu > 0.0) return fail(SSD_ERR_INVALID_ARG, "viscous meshes are not supported yet");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
     return fail(SSD_ERR_DEVICE, "no HIP device");
@@ -780,18 +822,8 @@ ssd_status ssd_residual(ssd_mesh *m, const float *q, float *r, void *stream) {
     LaunchTimer lt(m, SSD_KERNEL_TRACES, st);
     SSD_HIP(launch_traces(m->D, m->T, q, m->tr[0], st), "trace launch");
   }
-  if (m->K) {
-    LaunchTimer lt(m, SSD_KERNEL_MORTAR, st);
-    SSD_HIP(launch_mortar(m->D, m->T, m->ms, m->tr[0], m->mflux, st), "mortar launch");
-  }
-  Rotation rot{std::cos(m->theta), std::sin(m->theta), m->omega};
-  {
-    LaunchTimer lt(m, SSD_KERNEL_STAGE, st);
-    SSD_HIP(launch_stage(m->D, m->T, rot, q, nullptr, r, m->tr[0], nullptr, m->mflux, 0.f, 1.f,
-                         0.f, false, st),
-            "residual launch");
-  }
-  return SSD_OK;
+  return residual_pass(m, m->theta, m->omega, q, nullptr, r, m->tr[0], nullptr, 0.f, 1.f, 0.f,
+                       false, st);
 }
 
 ssd_status ssd_rk_steps(ssd_mesh *m, float *q, float *work, double t, double dt, int32_t nsteps,
@@ -824,18 +856,13 @@ ssd_status ssd_rk_steps(ssd_mesh *m, float *q, float *work, double t, double dt,
     for (int s = 0; s < 3; ++s) {
       const double th = m->theta0 + m->omega0 * (tn + Cs[s] * dt);
       if (m->K) {
-        {
-          LaunchTimer lt(m, SSD_KERNEL_REBUILD, st);
-          SSD_HIP(launch_rebuild(m->D, m->MT, th, m->ms, st), "mortar rebuild launch");
-        }
-        LaunchTimer lt(m, SSD_KERNEL_MORTAR, st);
-        SSD_HIP(launch_mortar(m->D, m->T, m->ms, m->tr[cur], m->mflux, st), "mortar launch");
+        LaunchTimer lt(m, SSD_KERNEL_REBUILD, st);
+        SSD_HIP(launch_rebuild(m->D, m->MT, th, m->ms, st), "mortar rebuild launch");
       }
-      Rotation rot{std::cos(th), std::sin(th), m->omega0};
-      LaunchTimer lt(m, SSD_KERNEL_STAGE, st);
-      SSD_HIP(launch_stage(m->D, m->T, rot, in[s], s ? q : nullptr, outp[s], m->tr[cur],
-                           m->tr[cur ^ 1], m->mflux, A[s], B[s], float(dt), true, st),
-              "stage launch");
+      if (ssd_status e = residual_pass(m, th, m->omega0, in[s], s ? q : nullptr, outp[s],
+                                       m->tr[cur], m->tr[cur ^ 1], A[s], B[s], float(dt), true,
+                                       st))
+        return e;
       cur ^= 1;
     }
   }

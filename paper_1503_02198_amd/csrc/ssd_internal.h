@@ -115,15 +115,30 @@ struct Rotation {
   double ct, st, omega;
 };
 
+// Viscous work buffers (device, owned by the mesh handle).
+struct ViscIO {
+  float *G;        // grad Q at the SPs [(c*4+v)][j][i][E], c = 0 x, 1 y
+  float *gtr;      // gradient traces [face][E][point][8]
+  float *mqc;      // common solution of the interface faces [slot][point][4]
+  float *mvflux;   // viscous mortar flux [slot][point][4]
+};
+
 // Kernel launchers (defined in ssd_kernels.hip).
 hipError_t launch_traces(const DevMesh &M, const OpTables &T, const float *q, float *tr,
                          hipStream_t s);
 hipError_t launch_rebuild(const DevMesh &M, const MortarTables &MT, double theta, MortarState *ms,
                           hipStream_t s);
+// mqc may be null (inviscid): then only the inviscid mortar flux is formed.
 hipError_t launch_mortar(const DevMesh &M, const OpTables &T, const MortarState *ms,
-                         const float *tr, float *mflux, hipStream_t s);
+                         const float *tr, float *mflux, float *mqc, hipStream_t s);
+hipError_t launch_grad(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
+                       const float *trin, const float *mqc, float *G, float *gtr, hipStream_t s);
+hipError_t launch_mortar_visc(const DevMesh &M, const OpTables &T, const MortarState *ms,
+                              const float *mqc, const float *gtr, float *mvflux, hipStream_t s);
+// visc null: inviscid residual.
 hipError_t launch_stage(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
                         const float *qn, float *out, const float *trin, float *trout,
-                        const float *mflux, float a, float b, float dt, bool rk, hipStream_t s);
+                        const float *mflux, const ViscIO *visc, float a, float b, float dt,
+                        bool rk, hipStream_t s);
 
 }  // namespace ssd

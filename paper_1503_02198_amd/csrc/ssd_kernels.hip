@@ -6,295 +6,14 @@
 // element-boundary flux points) travel between blocks through a trace buffer
 // laid out [face][element][point][var]: one lane moves the 4 variables of a
 // point as one 16-byte access, and the N waves of a block together touch
-// whole 16 N-byte face records.
+// whole 16 N-byte face records.  Viscous gradient traces use the same layout
+// with 8 values per point (x derivatives of the 4 variables, then y).
 //
 // Precision: state, traces and fluxes in FP32; element metrics and the
 // sliding-interface projections in FP64.
-#include "ssd_internal.h"
+#include "ssd_device.h"
 
 namespace ssd {
-
-// ---------------------------------------------------------------------------
-// fluxes (Sec. 2.1, 2.2, 3.1)
-// ---------------------------------------------------------------------------
-// Normal inviscid ALE flux along the scaled normal (nx, ny):
-// (F - u_g Q) nx + (G - v_g Q) ny with vgn = u_g nx + v_g ny.
-__device__ __forceinline__ void flux_n(const float q[4], float nx, float ny, float vgn, float gm1,
-                                       float f[4]) {
-  const float ir = __builtin_amdgcn_rcpf(q[0]);
-  const float u = q[1] * ir, v = q[2] * ir;
-  const float p = gm1 * (q[3] - 0.5f * (q[1] * u + q[2] * v));
-  const float un = u * nx + v * ny;
-  const float rel = un - vgn;
-  f[0] = q[0] * rel;
-  f[1] = q[1] * rel + p * nx;
-  f[2] = q[2] * rel + p * ny;
-  f[3] = q[3] * rel + p * un;
-}
-
-// Rusanov common flux from the owner (l) towards the neighbour (r).
-__device__ __forceinline__ void rusanov(const float ql[4], const float qr[4], float nx, float ny,
-                                        float vgn, float gam, float f[4]) {
-  const float gm1 = gam - 1.0f;
-  const float mag = __builtin_amdgcn_sqrtf(nx * nx + ny * ny);
-  const float irl = __builtin_amdgcn_rcpf(ql[0]), irr = __builtin_amdgcn_rcpf(qr[0]);
-  const float ul = ql[1] * irl, vl = ql[2] * irl;
-  const float ur = qr[1] * irr, vr = qr[2] * irr;
-  const float pl = gm1 * (ql[3] - 0.5f * (ql[1] * ul + ql[2] * vl));
-  const float pr = gm1 * (qr[3] - 0.5f * (qr[1] * ur + qr[2] * vr));
-  const float unl = ul * nx + vl * ny, unr = ur * nx + vr * ny;
-  const float rl = unl - vgn, rr = unr - vgn;
-  const float cl = __builtin_amdgcn_sqrtf(gam * pl * irl), cr = __builtin_amdgcn_sqrtf(gam * pr * irr);
-  const float lam = fmaxf(fabsf(rl) + cl * mag, fabsf(rr) + cr * mag);
-  f[0] = 0.5f * (ql[0] * rl + qr[0] * rr) - 0.5f * lam * (qr[0] - ql[0]);
-  f[1] = 0.5f * (ql[1] * rl + pl * nx + qr[1] * rr + pr * nx) - 0.5f * lam * (qr[1] - ql[1]);
-  f[2] = 0.5f * (ql[2] * rl + pl * ny + qr[2] * rr + pr * ny) - 0.5f * lam * (qr[2] - ql[2]);
-  f[3] = 0.5f * (ql[3] * rl + pl * unl + qr[3] * rr + pr * unr) - 0.5f * lam * (qr[3] - ql[3]);
-}
-
-// FP64 Rusanov flux for the mortars (no grid velocity: u_g . n = 0 on the circle).
-__device__ __forceinline__ void rusanov_d(const double ql[4], const double qr[4], double nx,
-                                          double ny, double gam, double f[4]) {
-  const double gm1 = gam - 1.0;
-  const double mag = sqrt(nx * nx + ny * ny);
-  const double ul = ql[1] / ql[0], vl = ql[2] / ql[0];
-  const double ur = qr[1] / qr[0], vr = qr[2] / qr[0];
-  const double pl = gm1 * (ql[3] - 0.5 * (ql[1] * ul + ql[2] * vl));
-  const double pr = gm1 * (qr[3] - 0.5 * (qr[1] * ur + qr[2] * vr));
-  const double unl = ul * nx + vl * ny, unr = ur * nx + vr * ny;
-  const double cl = sqrt(gam * pl / ql[0]), cr = sqrt(gam * pr / qr[0]);
-  const double lam = fmax(fabs(unl) + cl * mag, fabs(unr) + cr * mag);
-  f[0] = 0.5 * (ql[0] * unl + qr[0] * unr) - 0.5 * lam * (qr[0] - ql[0]);
-  f[1] = 0.5 * (ql[1] * unl + pl * nx + qr[1] * unr + pr * nx) - 0.5 * lam * (qr[1] - ql[1]);
-  f[2] = 0.5 * (ql[2] * unl + pl * ny + qr[2] * unr + pr * ny) - 0.5 * lam * (qr[2] - ql[2]);
-  f[3] = 0.5 * (ql[3] * unl + pl * unl + qr[3] * unr + pr * unr) - 0.5 * lam * (qr[3] - ql[3]);
-}
-
-// ---------------------------------------------------------------------------
-// raw buffer access: SGPR resource + per-lane byte offset + uniform byte
-// offset, so address arithmetic stays on the scalar unit.  The resource
-// carries the array size; the hardware returns 0 for reads past it and
-// drops writes past it.
-// ---------------------------------------------------------------------------
-typedef __amdgpu_buffer_rsrc_t rsrc_t;
-
-__device__ __forceinline__ rsrc_t make_rsrc(const void *p, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
-}
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-struct f4 {
-  float x[4];
-};
-
-// The buffer builtins move raw 32-bit words: bit-cast, never convert.
-__device__ __forceinline__ f4 bload4(rsrc_t r, uint32_t voff, uint32_t soff) {
-  return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
-}
-__device__ __forceinline__ void bstore4(const float x[4], rsrc_t r, uint32_t voff, uint32_t soff) {
-  f4 t;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) t.x[v] = x[v];
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, t), r, voff, soff, 0);
-}
-__device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-}
-__device__ __forceinline__ void bstore(float x, rsrc_t r, uint32_t voff, uint32_t soff) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, voff, soff, 0);
-}
-
-// ---------------------------------------------------------------------------
-// element geometry (Sec. 2.3).  Bilinear cells: the four edge vectors are
-// differenced in FP64 from the stored corners, then carried in FP32 and
-// rotated once into the current frame, so every metric is a linear
-// combination:  x_xi(eta) = A + eta (B - A),  x_eta(xi) = C + xi (D - C),
-// x(xi, eta) = p0 + xi A + eta C + xi eta (B - A).  Cubic cells read FP64
-// tables and rotate in FP64.
-// ---------------------------------------------------------------------------
-struct ElemGeo {
-  int cubic, c;
-  float w;                                    // omega of the zone (0: fixed)
-  float p0x, p0y, Ax, Ay, Bx, By, Cx, Cy, Dx, Dy;
-  double ct, st;
-};
-
-__device__ __forceinline__ ElemGeo load_geo(const DevMesh &M, int e, const Rotation &R) {
-  ElemGeo g;
-  const long E = M.E;
-  // corners are read for every cell (cubic cells ignore them) so that no
-  // load waits on the flag word
-  const double x0 = M.corners[0 * E + e], y0 = M.corners[1 * E + e];
-  const double x3 = M.corners[2 * E + e], y3 = M.corners[3 * E + e];
-  const double x6 = M.corners[4 * E + e], y6 = M.corners[5 * E + e];
-  const double x9 = M.corners[6 * E + e], y9 = M.corners[7 * E + e];
-  const int fl = M.eflag[e];
-  g.cubic = fl & EF_CUBIC;
-  g.c = fl >> 8;
-  const bool rot = (fl & EF_ROT) != 0;
-  g.ct = rot ? R.ct : 1.0;
-  g.st = rot ? R.st : 0.0;
-  g.w = rot ? float(R.omega) : 0.0f;
-  const float c = float(g.ct), s = float(g.st);
-  auto rx = [&](double x, double y) { return c * float(x) - s * float(y); };
-  auto ry = [&](double x, double y) { return s * float(x) + c * float(y); };
-  g.p0x = rx(x0, y0);            g.p0y = ry(x0, y0);
-  g.Ax = rx(x3 - x0, y3 - y0);   g.Ay = ry(x3 - x0, y3 - y0);
-  g.Bx = rx(x6 - x9, y6 - y9);   g.By = ry(x6 - x9, y6 - y9);
-  g.Cx = rx(x9 - x0, y9 - y0);   g.Cy = ry(x9 - x0, y9 - y0);
-  g.Dx = rx(x6 - x3, y6 - y3);   g.Dy = ry(x6 - x3, y6 - y3);
-  return g;
-}
-
-// Scaled normal (y_eta, -x_eta) at the xi-direction flux point (Xf_k, X_j)
-// in the current frame, and u_g . n.
-template <int N>
-__device__ __forceinline__ void metric_xi(const ElemGeo &g, const DevMesh &M, const OpTables &T,
-                                          int k, int j, float &nx, float &ny, float &vgn) {
-  if (g.cubic) {
-    const double xe = M.cmet[cubic_xi_index(N, M.C, 0, j, k, g.c)];
-    const double ye = M.cmet[cubic_xi_index(N, M.C, 1, j, k, g.c)];
-    double v = 0.0;
-    if (g.w != 0.0f)
-      v = -double(g.w) * (M.cmet[cubic_xi_index(N, M.C, 2, j, k, g.c)] * xe +
-                          M.cmet[cubic_xi_index(N, M.C, 3, j, k, g.c)] * ye);
-    nx = float(g.st * xe + g.ct * ye);
-    ny = float(-(g.ct * xe - g.st * ye));
-    vgn = float(v);
-    return;
-  }
-  const float xi = float(T.Xf[k]), eta = float(T.X[j]);
-  const float xe = g.Cx + xi * (g.Dx - g.Cx), ye = g.Cy + xi * (g.Dy - g.Cy);
-  nx = ye;
-  ny = -xe;
-  vgn = 0.0f;
-  if (g.w != 0.0f) {
-    const float px = g.p0x + xi * g.Ax + eta * g.Cx + xi * eta * (g.Bx - g.Ax);
-    const float py = g.p0y + xi * g.Ay + eta * g.Cy + xi * eta * (g.By - g.Ay);
-    vgn = -g.w * (px * xe + py * ye);
-  }
-}
-
-// Scaled normal (-y_xi, x_xi) at the eta-direction flux point (X_i, Xf_k).
-template <int N>
-__device__ __forceinline__ void metric_eta(const ElemGeo &g, const DevMesh &M, const OpTables &T,
-                                           int k, int i, float &nx, float &ny, float &vgn) {
-  if (g.cubic) {
-    const double xx = M.cmet[cubic_eta_index(N, M.C, 0, k, i, g.c)];
-    const double yx = M.cmet[cubic_eta_index(N, M.C, 1, k, i, g.c)];
-    double v = 0.0;
-    if (g.w != 0.0f)
-      v = double(g.w) * (M.cmet[cubic_eta_index(N, M.C, 2, k, i, g.c)] * xx +
-                         M.cmet[cubic_eta_index(N, M.C, 3, k, i, g.c)] * yx);
-    nx = float(-(g.st * xx + g.ct * yx));
-    ny = float(g.ct * xx - g.st * yx);
-    vgn = float(v);
-    return;
-  }
-  const float xi = float(T.X[i]), eta = float(T.Xf[k]);
-  const float xx = g.Ax + eta * (g.Bx - g.Ax), yx = g.Ay + eta * (g.By - g.Ay);
-  nx = -yx;
-  ny = xx;
-  vgn = 0.0f;
-  if (g.w != 0.0f) {
-    const float px = g.p0x + xi * g.Ax + eta * g.Cx + xi * eta * (g.Bx - g.Ax);
-    const float py = g.p0y + xi * g.Ay + eta * g.Cy + xi * eta * (g.By - g.Ay);
-    vgn = g.w * (px * xx + py * yx);
-  }
-}
-
-// 1 / |J| at the solution point (X_i, X_j).
-template <int N>
-__device__ __forceinline__ float inv_jacobian(const ElemGeo &g, const DevMesh &M,
-                                              const OpTables &T, int j, int i) {
-  if (g.cubic) return float(1.0 / M.cmet[cubic_sp_index(N, M.C, 0, j, i, g.c)]);
-  const float xi = float(T.X[i]), eta = float(T.X[j]);
-  const float xx = g.Ax + eta * (g.Bx - g.Ax), yx = g.Ay + eta * (g.By - g.Ay);
-  const float xe = g.Cx + xi * (g.Dx - g.Cx), ye = g.Cy + xi * (g.Dy - g.Cy);
-  return __builtin_amdgcn_rcpf(xx * ye - xe * yx);
-}
-
-// ---------------------------------------------------------------------------
-// common normal flux at one element-boundary flux point (outward normal)
-// ---------------------------------------------------------------------------
-struct StageBufs {
-  rsrc_t q, qn, out, trin, trout, mflux;
-  uint32_t E4;      // bytes per state row (4 E)
-  uint32_t S4;      // bytes per mortar-flux row (4 * 2K)
-};
-
-// What a face needs from outside the block, fetched before it is used:
-// the neighbour's trace (a neighbour in another block), the far-field state,
-// or the projected mortar flux (a sliding face).  Faces whose neighbour is in
-// the same block, and walls, fetch nothing.
-template <int N>
-__device__ __forceinline__ void prefetch_face(const DevMesh &M, const StageBufs &B, uint32_t fw,
-                                              int p, float x[4]) {
-  const int kind = face_kind_of(fw);
-#pragma unroll
-  for (int v = 0; v < 4; ++v) x[v] = 0.0f;
-  if (kind == SSD_FACE_SLIDING) {
-    const f4 t = bload4(B.mflux, (uint32_t(face_idx_of(fw)) * N + uint32_t(p)) * 16u, 0u);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) x[v] = t.x[v];
-  } else if (kind == SSD_FACE_FARFIELD) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) x[v] = M.qinf[v];
-  } else if ((kind == SSD_FACE_INTERIOR || kind == SSD_FACE_PERIODIC) && !face_inblock_of(fw)) {
-    const uint32_t nb = uint32_t(face_idx_of(fw)), nf = uint32_t(face_nf_of(fw));
-    const uint32_t pp = face_rev_of(fw) ? uint32_t(N - 1 - p) : uint32_t(p);
-    const f4 t = bload4(B.trin, ((nf * (B.E4 >> 2) + nb) * N + pp) * 16u, 0u);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) x[v] = t.x[v];
-  }
-}
-
-// Common normal flux at one element-boundary flux point along the outward
-// normal (nx, ny), given the prefetched face data x.  A neighbour in the
-// same block is interpolated from the block's LDS state Sf [var][j][i][lane].
-template <int N>
-__device__ __forceinline__ void common_flux(const DevMesh &M, const OpTables &T, const float *Sf,
-                                            uint32_t fw, int p, const float qo[4],
-                                            const float x[4], float nx, float ny, float vgn,
-                                            float fs[4]) {
-  const int kind = face_kind_of(fw);
-  if (kind == SSD_FACE_SLIDING) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) fs[v] = x[v];
-    return;
-  }
-  if (kind == SSD_FACE_WALL_ISOTHERMAL || kind == SSD_FACE_WALL_SLIP) {
-    // no flux relative to the moving wall; pressure from the interior
-    const float pr = (M.gamma - 1.0f) *
-                     (qo[3] - 0.5f * (qo[1] * qo[1] + qo[2] * qo[2]) * __builtin_amdgcn_rcpf(qo[0]));
-    fs[0] = 0.0f;
-    fs[1] = pr * nx;
-    fs[2] = pr * ny;
-    fs[3] = pr * vgn;
-    return;
-  }
-  float qx[4];
-  if ((kind == SSD_FACE_INTERIOR || kind == SSD_FACE_PERIODIC) && face_inblock_of(fw)) {
-    const uint32_t nf = uint32_t(face_nf_of(fw));
-    const int pp = face_rev_of(fw) ? N - 1 - p : p;
-    const int ln = face_idx_of(fw) & (EB - 1);
-    const bool odd = (nf & 1u) != 0;               // xi faces: the point runs along eta
-    const bool hi = (nf == 1u || nf == 2u);        // xi = 1 or eta = 1
-    const int base = (odd ? pp * N * EB : pp * EB) + ln;
-    const int stride = odd ? EB : N * EB;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      float acc = 0.f;
-#pragma unroll
-      for (int s2 = 0; s2 < N; ++s2)
-        acc += (hi ? T.I[N][s2] : T.I[0][s2]) * Sf[v * N * N * EB + base + s2 * stride];
-      qx[v] = acc;
-    }
-  } else {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) qx[v] = x[v];
-  }
-  rusanov(qo, qx, nx, ny, vgn, M.gamma, fs);
-}
 
 // ---------------------------------------------------------------------------
 // face traces of a state, for the faces some other block reads
@@ -340,11 +59,69 @@ __global__ __launch_bounds__(256) void k_traces(DevMesh M, OpTables T, const flo
   }
 }
 
+// Viscous inputs of the stage kernel (null on inviscid meshes).
+struct ViscBufs {
+  const float *G;       // grad Q at the SPs [(c*4+v)][j][i][E], c = 0 x, 1 y
+  const float *gtr;     // gradient traces [face][E][point][8]
+  const float *mvflux;  // viscous mortar flux [slot][point][4]
+};
+
+// Conforming faces export their gradient traces (both sides average the
+// two), sliding faces for the viscous mortar.
+__device__ __forceinline__ bool grad_exported(uint32_t fw) {
+  const int k = face_kind_of(fw);
+  return k == SSD_FACE_INTERIOR || k == SSD_FACE_PERIODIC || k == SSD_FACE_SLIDING;
+}
+
+// Common viscous normal flux at one element-boundary flux point (BR1
+// reading): F_vis(Q_c, mean of both gradients) . n on conforming faces,
+// F_vis(Q_b, interior gradient) . n on isothermal walls and the far field,
+// zero on slip walls, the mortar value on sliding faces.  qx: neighbour's
+// state from common_flux; g: own gradient at the point [x0..x3, y0..y3].
+template <int N>
+__device__ __forceinline__ void common_visc(const DevMesh &M, const ViscParams &P, rsrc_t rgtr,
+                                            rsrc_t rmv, uint32_t fw, int p, const float qo[4],
+                                            const float qx[4], const float x[4],
+                                            const float g[8], const FPGeo &G, float fv[4]) {
+  const int kind = face_kind_of(fw);
+  if (kind == SSD_FACE_WALL_SLIP) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) fv[v] = 0.0f;
+    return;
+  }
+  if (kind == SSD_FACE_SLIDING) {
+    const f4 t = bload4(rmv, (uint32_t(face_idx_of(fw)) * N + uint32_t(p)) * 16u, 0u);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) fv[v] = t.x[v];
+    return;
+  }
+  float qc[4], gx[4], gy[4];
+  common_solution(M, kind, qo, qx, x, G, qc);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    gx[v] = g[v];
+    gy[v] = g[4 + v];
+  }
+  if (conforming(kind)) {
+    const uint32_t nb = uint32_t(face_idx_of(fw)), nf = uint32_t(face_nf_of(fw));
+    const uint32_t pp = face_rev_of(fw) ? uint32_t(N - 1 - p) : uint32_t(p);
+    const uint32_t vo = ((nf * uint32_t(M.E) + nb) * N + pp) * 32u;
+    const f4 a = bload4(rgtr, vo, 0u), b = bload4(rgtr, vo + 16u, 0u);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      gx[v] = 0.5f * (gx[v] + a.x[v]);
+      gy[v] = 0.5f * (gy[v] + b.x[v]);
+    }
+  }
+  visc_flux_n<float>(qc, gx, gy, G.nx, G.ny, P.gamma, P.R, P.mu, P.kcond, fv);
+}
+
 // ---------------------------------------------------------------------------
 // the element residual, optionally fused with an SSP-RK stage update
 //   rk = false:  out = dQ/dt
 //   rk = true :  out = a qn + b (q + dt dQ/dt), exported face traces of out
 //                -> trout
+//   visc:        adds the viscous fluxes, from the gradients of k_grad
 //
 // A block owns EB = 64 consecutive elements and has N waves; lane l of
 // wave w serves element (block * 64 + l).
@@ -361,11 +138,12 @@ __global__ __launch_bounds__(256) void k_traces(DevMesh M, OpTables T, const flo
 // LDS access of a wave to its own elements touches 64 distinct banks.
 // Global accesses of a wave are contiguous 256-byte rows.
 // ---------------------------------------------------------------------------
-template <int N, bool RK>
+template <int N, bool RK, bool VISC>
 __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotation R,
                                                   const float *q, const float *qn, float *out,
                                                   const float *trin, float *trout,
-                                                  const float *mflux, float a, float b, float dt) {
+                                                  const float *mflux, ViscBufs V, float a, float b,
+                                                  float dt) {
   __shared__ float S[4][N][N][EB];     // state of the block's elements
   __shared__ float SR[4][N][N][EB];    // xi part of the residual, then the new state
   const float *Sf = &S[0][0][0][0];
@@ -377,20 +155,22 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
   const bool valid = e0 < M.E;
   const int e = valid ? e0 : M.E - 1;
   const float gm1 = M.gamma - 1.0f;
-
-  StageBufs B;
-  B.E4 = uint32_t(M.E) * 4u;
-  B.S4 = uint32_t(2 * M.K) * 4u;
-  const uint32_t sbytes = 4u * N * N * B.E4, tbytes = 16u * N * B.E4;
-  B.q = make_rsrc(q, sbytes);
-  B.qn = make_rsrc(qn, RK ? sbytes : 0u);
-  B.out = make_rsrc(out, sbytes);
-  B.trin = make_rsrc(trin, tbytes);
-  B.trout = make_rsrc(trout, RK ? tbytes : 0u);
-  B.mflux = make_rsrc(mflux, 4u * N * B.S4);
+  const uint32_t E4 = uint32_t(M.E) * 4u;
+  const uint32_t sbytes = 4u * N * N * E4, tbytes = 16u * N * E4;
+  const uint32_t mbytes = uint32_t(2 * M.K) * N * 16u;
+  const rsrc_t rq = make_rsrc(q, sbytes);
+  const rsrc_t rqn = make_rsrc(qn, RK ? sbytes : 0u);
+  const rsrc_t rout = make_rsrc(out, sbytes);
+  const rsrc_t rtin = make_rsrc(trin, tbytes);
+  const rsrc_t rtout = make_rsrc(trout, RK ? tbytes : 0u);
+  const rsrc_t rmf = make_rsrc(mflux, mbytes);
+  const rsrc_t rG = make_rsrc(V.G, VISC ? 2u * sbytes : 0u);
+  const rsrc_t rgtr = make_rsrc(V.gtr, VISC ? 2u * tbytes : 0u);
+  const rsrc_t rmv = make_rsrc(V.mvflux, VISC ? mbytes : 0u);
+  const ViscParams P = visc_params(M);
   const uint32_t ve = uint32_t(e) * 4u;
-
   const long E = M.E;
+
   // ---- everything the element needs from memory, issued up front
   const uint32_t fw0 = M.face[0 * E + e], fw1 = M.face[1 * E + e];
   const uint32_t fw2 = M.face[2 * E + e], fw3 = M.face[3 * E + e];
@@ -398,17 +178,24 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
-    for (int i = 0; i < N; ++i) qr[v][i] = bload(B.q, ve, ((v * N + w) * N + i) * B.E4);
+    for (int i = 0; i < N; ++i) qr[v][i] = bload(rq, ve, ((v * N + w) * N + i) * E4);
   const ElemGeo g = load_geo(M, e, R);
   float x0[4], x1[4], x2[4], x3[4];
-  prefetch_face<N>(M, B, fw3, w, x3);   // row faces xi = 0, 1 at point w
-  prefetch_face<N>(M, B, fw1, w, x1);
-  prefetch_face<N>(M, B, fw0, w, x0);   // column faces eta = 0, 1 at point w
-  prefetch_face<N>(M, B, fw2, w, x2);
+  prefetch_face<N>(M, rtin, rmf, uint32_t(M.E), fw3, w, x3);   // row faces xi = 0, 1 at point w
+  prefetch_face<N>(M, rtin, rmf, uint32_t(M.E), fw1, w, x1);
+  prefetch_face<N>(M, rtin, rmf, uint32_t(M.E), fw0, w, x0);   // column faces eta = 0, 1
+  prefetch_face<N>(M, rtin, rmf, uint32_t(M.E), fw2, w, x2);
 
   // ---- row phase
   {
     float res[4][N], t0[4], tN[4];
+    float gr[8][N];   // gradient on row w
+    if (VISC) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int i = 0; i < N; ++i) gr[c][i] = bload(rG, ve, ((c * N + w) * N + i) * E4);
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -418,7 +205,7 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
       }
 #pragma unroll
     for (int k = 1; k < N; ++k) {
-      float qf[4], f[4], nx, ny, vgn;
+      float qf[4], f[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         float acc = 0.f;
@@ -426,8 +213,21 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
         for (int i = 0; i < N; ++i) acc += T.I[k][i] * qr[v][i];
         qf[v] = acc;
       }
-      metric_xi<N>(g, M, T, k, w, nx, ny, vgn);
-      flux_n(qf, nx, ny, vgn, gm1, f);
+      const FPGeo G = metric_xi<N>(g, M, T, k, w);
+      flux_n(qf, G.nx, G.ny, G.vgn, gm1, f);
+      if (VISC) {
+        float gf[8], fv[4];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          float acc = 0.f;
+#pragma unroll
+          for (int i = 0; i < N; ++i) acc += T.I[k][i] * gr[c][i];
+          gf[c] = acc;
+        }
+        visc_flux_n<float>(qf, gf, gf + 4, G.nx, G.ny, P.gamma, P.R, P.mu, P.kcond, fv);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) f[v] += fv[v];
+      }
 #pragma unroll
       for (int i = 0; i < N; ++i)
 #pragma unroll
@@ -445,20 +245,34 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
       tN[v] = sN;
     }
     __syncthreads();   // the block's state is in LDS
-    {
-      float f[4], nx, ny, vgn;
-      metric_xi<N>(g, M, T, 0, w, nx, ny, vgn);       // face xi = 0: outward is -n
-      common_flux<N>(M, T, Sf, fw3, w, t0, x3, -nx, -ny, -vgn, f);
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int k = side ? N : 0;
+      const float sg = side ? 1.0f : -1.0f;   // outward normal of face xi = 1 / xi = 0
+      const uint32_t fw = side ? fw1 : fw3;
+      FPGeo G = metric_xi<N>(g, M, T, k, w);
+      G.nx *= sg;
+      G.ny *= sg;
+      G.vgn *= sg;
+      float f[4], qx[4];
+      common_flux<N>(M, T, Sf, fw, w, side ? tN : t0, side ? x1 : x3, G, f, qx);
+      if (VISC) {
+        float gf[8], fv[4];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          float acc = 0.f;
+#pragma unroll
+          for (int i = 0; i < N; ++i) acc += T.I[k][i] * gr[c][i];
+          gf[c] = acc;
+        }
+        common_visc<N>(M, P, rgtr, rmv, fw, w, side ? tN : t0, qx, side ? x1 : x3, gf, G, fv);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) f[v] += fv[v];
+      }
 #pragma unroll
       for (int i = 0; i < N; ++i)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) res[v][i] += T.D[i][0] * f[v];
-      metric_xi<N>(g, M, T, N, w, nx, ny, vgn);       // face xi = 1: outward is +n
-      common_flux<N>(M, T, Sf, fw1, w, tN, x1, nx, ny, vgn, f);
-#pragma unroll
-      for (int i = 0; i < N; ++i)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) res[v][i] -= T.D[i][N] * f[v];
+        for (int v = 0; v < 4; ++v) res[v][i] -= T.D[i][k] * (sg * f[v]);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v)
@@ -473,39 +287,74 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int j = 0; j < N; ++j) qo[v][j] = bload(B.qn, ve, ((v * N + j) * N + w) * B.E4);
+      for (int j = 0; j < N; ++j) qo[v][j] = bload(rqn, ve, ((v * N + j) * N + w) * E4);
   }
+  {
+    float gc[8][N];   // gradient on column w
+    if (VISC) {
 #pragma unroll
-  for (int v = 0; v < 4; ++v)
+      for (int c = 0; c < 8; ++c)
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-      qc[v][j] = S[v][j][w][l];
-      rc[v][j] = SR[v][j][w][l];
+        for (int j = 0; j < N; ++j) gc[c][j] = bload(rG, ve, ((c * N + j) * N + w) * E4);
     }
 #pragma unroll
-  for (int k = 0; k <= N; ++k) {
-    float qf[4], f[4], nx, ny, vgn;
+    for (int v = 0; v < 4; ++v)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      float acc = 0.f;
+      for (int j = 0; j < N; ++j) {
+        qc[v][j] = S[v][j][w][l];
+        rc[v][j] = SR[v][j][w][l];
+      }
 #pragma unroll
-      for (int j = 0; j < N; ++j) acc += T.I[k][j] * qc[v][j];
-      qf[v] = acc;
+    for (int k = 0; k <= N; ++k) {
+      float qf[4], f[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < N; ++j) acc += T.I[k][j] * qc[v][j];
+        qf[v] = acc;
+      }
+      FPGeo G = metric_eta<N>(g, M, T, k, w);
+      float gf[8];
+      if (VISC) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          float acc = 0.f;
+#pragma unroll
+          for (int j = 0; j < N; ++j) acc += T.I[k][j] * gc[c][j];
+          gf[c] = acc;
+        }
+      }
+      if (k == 0 || k == N) {
+        const float sg = k == 0 ? -1.0f : 1.0f;   // outward normal of face eta = 0 / eta = 1
+        const uint32_t fw = k == 0 ? fw0 : fw2;
+        G.nx *= sg;
+        G.ny *= sg;
+        G.vgn *= sg;
+        float qx[4];
+        common_flux<N>(M, T, Sf, fw, w, qf, k == 0 ? x0 : x2, G, f, qx);
+        if (VISC) {
+          float fv[4];
+          common_visc<N>(M, P, rgtr, rmv, fw, w, qf, qx, k == 0 ? x0 : x2, gf, G, fv);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) f[v] += fv[v];
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) f[v] *= sg;
+      } else {
+        flux_n(qf, G.nx, G.ny, G.vgn, gm1, f);
+        if (VISC) {
+          float fv[4];
+          visc_flux_n<float>(qf, gf, gf + 4, G.nx, G.ny, P.gamma, P.R, P.mu, P.kcond, fv);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) f[v] += fv[v];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < N; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) rc[v][j] -= T.D[j][k] * f[v];
     }
-    metric_eta<N>(g, M, T, k, w, nx, ny, vgn);
-    if (k == 0) {
-      common_flux<N>(M, T, Sf, fw0, w, qf, x0, -nx, -ny, -vgn, f);   // outward is -n
-#pragma unroll
-      for (int v = 0; v < 4; ++v) f[v] = -f[v];
-    } else if (k == N) {
-      common_flux<N>(M, T, Sf, fw2, w, qf, x2, nx, ny, vgn, f);
-    } else {
-      flux_n(qf, nx, ny, vgn, gm1, f);
-    }
-#pragma unroll
-    for (int j = 0; j < N; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) rc[v][j] -= T.D[j][k] * f[v];
   }
   // dQ/dt = dQ~/dt / |J| on column w
 #pragma unroll
@@ -519,7 +368,7 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int j = 0; j < N; ++j) bstore(rc[v][j], B.out, ve, ((v * N + j) * N + w) * B.E4);
+        for (int j = 0; j < N; ++j) bstore(rc[v][j], rout, ve, ((v * N + j) * N + w) * E4);
     }
     return;
   }
@@ -538,8 +387,7 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
       SR[v][j][w][l] = x;
     }
     const float rho = qc[0][j];
-    const float pr = gm1 * (qc[3][j] - 0.5f * (qc[1][j] * qc[1][j] + qc[2][j] * qc[2][j]) *
-                                           __builtin_amdgcn_rcpf(rho));
+    const float pr = gm1 * (qc[3][j] - 0.5f * (qc[1][j] * qc[1][j] + qc[2][j] * qc[2][j]) * rcp(rho));
     bad |= !(rho > 0.0f) || !(pr > 0.0f) || !isfinite(qc[1][j]) || !isfinite(qc[2][j]);
   }
   const bool ex0 = face_exported(fw0), ex2 = face_exported(fw2);
@@ -551,13 +399,13 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
       f0[v] = f2[v] = 0.f;
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        bstore(qc[v][j], B.out, ve, ((v * N + j) * N + w) * B.E4);
+        bstore(qc[v][j], rout, ve, ((v * N + j) * N + w) * E4);
         f0[v] += T.I[0][j] * qc[v][j];     // eta = 0 face, point w
         f2[v] += T.I[N][j] * qc[v][j];     // eta = 1 face, point w
       }
     }
-    if (ex0) bstore4(f0, B.trout, tvo, 0 * tfs);
-    if (ex2) bstore4(f2, B.trout, tvo, 2 * tfs);
+    if (ex0) bstore4(f0, rtout, tvo, 0 * tfs);
+    if (ex2) bstore4(f2, rtout, tvo, 2 * tfs);
     if (bad) M.flag[0] = 1;
   }
   __syncthreads();
@@ -576,8 +424,220 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
         f3[v] += T.I[0][i] * x;
       }
     }
-    if (ex1) bstore4(f1, B.trout, tvo, 1 * tfs);
-    if (ex3) bstore4(f3, B.trout, tvo, 3 * tfs);
+    if (ex1) bstore4(f1, rtout, tvo, 1 * tfs);
+    if (ex3) bstore4(f3, rtout, tvo, 3 * tfs);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// viscous gradient pass (Sec. 3.1, BR1 reading)
+//   Q_xi and Q_eta at the SPs are the derivatives of the degree-N
+//   polynomials through the solution interpolated to the interior flux
+//   points and the common solution at the element's faces (eqs. Ft, Gt
+//   applied to Q); grad Q follows by the chain rule with the SP metrics.
+// Outputs: grad Q at the SPs, G [(c*4+v)][j][i][E]; gradient traces of
+// conforming and sliding faces, gtr [face][E][point][8].
+// Same block and wave organisation as k_stage.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(64 * N) void k_grad(DevMesh M, OpTables T, Rotation R,
+                                                 const float *q, const float *trin,
+                                                 const float *mqc, float *Gout, float *gtr) {
+  // LDS: the state and Q_xi while the derivatives are formed, then the
+  // gradient of the whole block
+  __shared__ float L[8][N][N][EB];
+  float(*S)[N][N][EB] = L;        // [var][j][i][lane]
+  float(*QX)[N][N][EB] = L + 4;   // Q_xi
+  const float *Sf = &L[0][0][0][0];
+  const int l = threadIdx.x & (EB - 1);
+  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / EB);
+  const int e0 = blockIdx.x * EB + l;
+  const bool valid = e0 < M.E;
+  const int e = valid ? e0 : M.E - 1;
+  const uint32_t E4 = uint32_t(M.E) * 4u;
+  const uint32_t sbytes = 4u * N * N * E4, tbytes = 16u * N * E4;
+  const rsrc_t rq = make_rsrc(q, sbytes);
+  const rsrc_t rtin = make_rsrc(trin, tbytes);
+  const rsrc_t rqc = make_rsrc(mqc, uint32_t(2 * M.K) * N * 16u);
+  const rsrc_t rG = make_rsrc(Gout, 2u * sbytes);
+  const rsrc_t rgtr = make_rsrc(gtr, 2u * tbytes);
+  const uint32_t ve = uint32_t(e) * 4u;
+  const long E = M.E;
+
+  const uint32_t fw0 = M.face[0 * E + e], fw1 = M.face[1 * E + e];
+  const uint32_t fw2 = M.face[2 * E + e], fw3 = M.face[3 * E + e];
+  float qr[4][N];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int i = 0; i < N; ++i) qr[v][i] = bload(rq, ve, ((v * N + w) * N + i) * E4);
+  const ElemGeo g = load_geo(M, e, R);
+  float x0[4], x1[4], x2[4], x3[4];
+  prefetch_face<N>(M, rtin, rqc, uint32_t(M.E), fw3, w, x3);
+  prefetch_face<N>(M, rtin, rqc, uint32_t(M.E), fw1, w, x1);
+  prefetch_face<N>(M, rtin, rqc, uint32_t(M.E), fw0, w, x0);
+  prefetch_face<N>(M, rtin, rqc, uint32_t(M.E), fw2, w, x2);
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int i = 0; i < N; ++i) S[v][w][i][l] = qr[v][i];
+  __syncthreads();   // the block's state is in LDS
+
+  // common solution at point p of a face with outward normal sign sg
+  auto face_common = [&](uint32_t fw, bool xi_face, int k, float sg, const float qo[4],
+                         const float x[4], float qcm[4]) {
+    FPGeo G = xi_face ? metric_xi<N>(g, M, T, k, w) : metric_eta<N>(g, M, T, k, w);
+    G.nx *= sg;
+    G.ny *= sg;
+    G.vgn *= sg;
+    float qx[4];
+    const int kind = face_kind_of(fw);
+    neighbor_state<N>(T, Sf, fw, w, x, qx);
+    common_solution(M, kind, qo, qx, x, G, qcm);
+  };
+
+  // ---- row w: Q_xi
+  {
+    float qs[4][N + 1];
+#pragma unroll
+    for (int k = 0; k <= N; ++k)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float acc = 0.f;
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc += T.I[k][i] * qr[v][i];
+        qs[v][k] = acc;
+      }
+    float c0[4], cN[4], o0[4], oN[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      o0[v] = qs[v][0];
+      oN[v] = qs[v][N];
+    }
+    face_common(fw3, true, 0, -1.0f, o0, x3, c0);
+    face_common(fw1, true, N, 1.0f, oN, x1, cN);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      qs[v][0] = c0[v];
+      qs[v][N] = cN[v];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k <= N; ++k) acc += T.D[i][k] * qs[v][k];
+        QX[v][w][i][l] = acc;
+      }
+  }
+
+  // ---- column w: Q_eta
+  float qe[4][N];
+  {
+    float qcol[4][N], qs[4][N + 1];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int j = 0; j < N; ++j) qcol[v][j] = S[v][j][w][l];
+#pragma unroll
+    for (int k = 0; k <= N; ++k)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < N; ++j) acc += T.I[k][j] * qcol[v][j];
+        qs[v][k] = acc;
+      }
+    float c0[4], cN[4], o0[4], oN[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      o0[v] = qs[v][0];
+      oN[v] = qs[v][N];
+    }
+    face_common(fw0, false, 0, -1.0f, o0, x0, c0);
+    face_common(fw2, false, N, 1.0f, oN, x2, cN);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      qs[v][0] = c0[v];
+      qs[v][N] = cN[v];
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k <= N; ++k) acc += T.D[j][k] * qs[v][k];
+        qe[v][j] = acc;
+      }
+  }
+  __syncthreads();   // Q_xi of every row is in LDS
+
+  // ---- grad Q on column w:  Q_x = (y_eta Q_xi - y_xi Q_eta) / |J|,
+  //                           Q_y = (x_xi Q_eta - x_eta Q_xi) / |J|
+  float gcol[8][N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const SPGeo sp = metric_sp<N>(g, M, T, j, w);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float qxi = QX[v][j][w][l];
+      gcol[v][j] = (sp.ye * qxi - sp.yx * qe[v][j]) * sp.ij;
+      gcol[4 + v][j] = (sp.xx * qe[v][j] - sp.xe * qxi) * sp.ij;
+    }
+  }
+  const uint32_t gvo = (uint32_t(e) * N + uint32_t(w)) * 32u, gfs = uint32_t(M.E) * N * 32u;
+  if (valid) {
+    float f0[8], f2[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      f0[c] = f2[c] = 0.f;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        bstore(gcol[c][j], rG, ve, ((c * N + j) * N + w) * E4);
+        f0[c] += T.I[0][j] * gcol[c][j];
+        f2[c] += T.I[N][j] * gcol[c][j];
+      }
+    }
+    if (grad_exported(fw0)) {
+      bstore4(f0, rgtr, gvo, 0 * gfs);
+      bstore4(f0 + 4, rgtr, gvo + 16u, 0 * gfs);
+    }
+    if (grad_exported(fw2)) {
+      bstore4(f2, rgtr, gvo, 2 * gfs);
+      bstore4(f2 + 4, rgtr, gvo + 16u, 2 * gfs);
+    }
+  }
+  __syncthreads();   // every wave has read its column of Q_xi: L is free
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int j = 0; j < N; ++j) L[c][j][w][l] = gcol[c][j];
+  __syncthreads();
+
+  // ---- gradient traces of faces xi = 0, 1 at point w from row w
+  const bool gx1 = grad_exported(fw1), gx3 = grad_exported(fw3);
+  if (valid && (gx1 || gx3)) {
+    float f1[8], f3[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      f1[c] = f3[c] = 0.f;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const float x = L[c][w][i][l];
+        f1[c] += T.I[N][i] * x;
+        f3[c] += T.I[0][i] * x;
+      }
+    }
+    if (gx1) {
+      bstore4(f1, rgtr, gvo, 1 * gfs);
+      bstore4(f1 + 4, rgtr, gvo + 16u, 1 * gfs);
+    }
+    if (gx3) {
+      bstore4(f3, rgtr, gvo, 3 * gfs);
+      bstore4(f3 + 4, rgtr, gvo + 16u, 3 * gfs);
+    }
   }
 }
 
@@ -647,17 +707,60 @@ __global__ __launch_bounds__(64) void k_rebuild(DevMesh M, MortarTables MT, doub
   if (threadIdx.x == 0) ms->valid = 1;
 }
 
-template <int N>
+// C values per point of ring slot `slot` in the face's canonical
+// (counter-clockwise) point order, from a [face][E][point][C] trace array.
+template <int N, int C>
 __device__ __forceinline__ void load_canon(const DevMesh &M, const float *__restrict__ tr, int slot,
-                                           double q[4][N]) {
+                                           double q[C][N]) {
   const long E = M.E;
   const int e = M.ring_e[slot], f = M.ring_f[slot], flip = M.ring_flip[slot];
 #pragma unroll
   for (int a = 0; a < N; ++a) {
     const int pa = flip ? N - 1 - a : a;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) q[v][a] = double(tr[((long(f) * E + e) * N + pa) * 4 + v]);
+    for (int v = 0; v < C; ++v) q[v][a] = double(tr[((long(f) * E + e) * N + pa) * C + v]);
   }
+}
+
+// The same from a per-slot record array [slot][point][4].
+template <int N>
+__device__ __forceinline__ void load_slot(const DevMesh &M, const float *__restrict__ rec, int slot,
+                                          double q[4][N]) {
+  const int flip = M.ring_flip[slot];
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    const int pa = flip ? N - 1 - a : a;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) q[v][a] = double(rec[(long(slot) * N + pa) * 4 + v]);
+  }
+}
+
+// Canonical-order face data -> record of `slot` in the element's order.
+template <int N>
+__device__ __forceinline__ void store_slot(const DevMesh &M, float *__restrict__ rec, int slot,
+                                           const double q[4][N], double sign) {
+  const int flip = M.ring_flip[slot];
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    const int pa = flip ? N - 1 - a : a;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) rec[(long(slot) * N + pa) * 4 + v] = float(sign * q[v][a]);
+  }
+}
+
+// y = P x for each variable (P one of the mortar projections).
+template <int N>
+__device__ __forceinline__ void project(const double (*P)[NMAX], const double x[4][N],
+                                        double y[4][N]) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      double s = 0.0;
+#pragma unroll
+      for (int b = 0; b < N; ++b) s += P[a][b] * x[v][b];
+      y[v][a] = s;
+    }
 }
 
 // One lane per interface face (L faces 0..K-1, R faces K..2K-1).  Each lane
@@ -665,12 +768,14 @@ __device__ __forceinline__ void load_canon(const DevMesh &M, const float *__rest
 // (eq. prjQ2), takes the Rusanov flux with the exact radial normal, scales
 // it to flux per unit face parameter (R_s Delta), and projects back to its
 // own face (eq. prjF2).  Output: outward common flux in the element's face
-// parameter order, mflux[slot][point][var].
-template <int N>
+// parameter order, mflux[slot][point][var].  With VISC also the common
+// solution of its face for the gradient pass: the mean of the two sides'
+// projections on each mortar, projected back (Sec. 3.2), mqc[slot][point][var].
+template <int N, bool VISC>
 __global__ __launch_bounds__(64) void k_mortar(DevMesh M, OpTables T,
                                                const MortarState *__restrict__ ms,
                                                const float *__restrict__ tr,
-                                               float *__restrict__ mflux) {
+                                               float *__restrict__ mflux, float *__restrict__ mqc) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int K = M.K;
   if (t >= 2 * K) return;
@@ -678,32 +783,21 @@ __global__ __launch_bounds__(64) void k_mortar(DevMesh M, OpTables T,
   const int j = right ? t - K : t;
   const int m = ms->m;
   const double sc = M.Rs * M.dphi;
-  double acc[4][N];
+  double acc[4][N], accq[4][N];
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
-    for (int a = 0; a < N; ++a) acc[v][a] = 0.0;
+    for (int a = 0; a < N; ++a) acc[v][a] = accq[v][a] = 0.0;
 
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     const int jl = right ? ((j - m - k) % K + K) % K : j;
     const int jr = right ? j : (j + m + k) % K;
     double tl[4][N], trr[4][N], ql[4][N], qr[4][N];
-    load_canon<N>(M, tr, jl, tl);
-    load_canon<N>(M, tr, K + jr, trr);
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-      for (int a = 0; a < N; ++a) {
-        double sl = 0.0, sr = 0.0;
-#pragma unroll
-        for (int b = 0; b < N; ++b) {
-          sl += ms->Pf[k][a][b] * tl[v][b];
-          sr += ms->Pf[2 + k][a][b] * trr[v][b];
-        }
-        ql[v][a] = sl;
-        qr[v][a] = sr;
-      }
+    load_canon<N, 4>(M, tr, jl, tl);
+    load_canon<N, 4>(M, tr, K + jr, trr);
+    project<N>(ms->Pf[k], tl, ql);
+    project<N>(ms->Pf[2 + k], trr, qr);
     double fm[4][N];
 #pragma unroll
     for (int a = 0; a < N; ++a) {
@@ -712,30 +806,104 @@ __global__ __launch_bounds__(64) void k_mortar(DevMesh M, OpTables T,
       sincos(phi, &sn, &cs);
       double l4[4] = {ql[0][a], ql[1][a], ql[2][a], ql[3][a]};
       double r4[4] = {qr[0][a], qr[1][a], qr[2][a], qr[3][a]};
-      double f4[4];
-      rusanov_d(l4, r4, cs * sc, sn * sc, double(M.gamma), f4);
+      double f4v[4];
+      rusanov_d(l4, r4, cs * sc, sn * sc, double(M.gamma), f4v);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) fm[v][a] = f4[v];
+      for (int v = 0; v < 4; ++v) fm[v][a] = f4v[v];
     }
     const int pb = (right ? 2 : 0) + k;
+    double y[4][N];
+    project<N>(ms->Pb[pb], fm, y);
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int a = 0; a < N; ++a) {
-        double s = 0.0;
+      for (int a = 0; a < N; ++a) acc[v][a] += y[v][a];
+    if (VISC) {
 #pragma unroll
-        for (int b = 0; b < N; ++b) s += ms->Pb[pb][a][b] * fm[v][b];
-        acc[v][a] += s;
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int a = 0; a < N; ++a) ql[v][a] = 0.5 * (ql[v][a] + qr[v][a]);
+      project<N>(ms->Pb[pb], ql, y);
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int a = 0; a < N; ++a) accq[v][a] += y[v][a];
+    }
+  }
+  store_slot<N>(M, mflux, t, acc, right ? -1.0 : 1.0);
+  if (VISC) store_slot<N>(M, mqc, t, accq, 1.0);
+}
+
+// Viscous mortar (Sec. 3.2): each side's face viscous flux along the radial
+// (L -> R) normal per unit face parameter, from the face's common solution
+// (mqc) and its own gradient trace, is projected onto the mortars; the two
+// sides are averaged and the mean is projected back to the lane's face.
+// Output: outward viscous flux, mvflux[slot][point][var].
+template <int N>
+__global__ __launch_bounds__(64) void k_mortar_visc(DevMesh M, OpTables T,
+                                                    const MortarState *__restrict__ ms,
+                                                    const float *__restrict__ mqc,
+                                                    const float *__restrict__ gtr,
+                                                    float *__restrict__ mvflux) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int K = M.K;
+  if (t >= 2 * K) return;
+  const bool right = t >= K;
+  const int j = right ? t - K : t;
+  const int m = ms->m;
+  const double sc = M.Rs * M.dphi;
+  const double gam = M.gamma, Rg = M.gas_R, mu = M.mu;
+  const double kc = mu * gam * Rg / ((gam - 1.0) * double(M.prandtl));
+  double acc[4][N];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int a = 0; a < N; ++a) acc[v][a] = 0.0;
+
+  // viscous flux of ring slot s (face jj of its side), canonical order
+  auto face_flux = [&](int s, double phi0, double th, int jj, double fv[4][N]) {
+    double qc[4][N], gg[8][N];
+    load_slot<N>(M, mqc, s, qc);
+    load_canon<N, 8>(M, gtr, s, gg);
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      const double phi = phi0 + th + M.dphi * (jj + T.X[a]);
+      double sn, cs;
+      sincos(phi, &sn, &cs);
+      double q4[4], gx[4], gy[4], f[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        q4[v] = qc[v][a];
+        gx[v] = gg[v][a];
+        gy[v] = gg[4 + v][a];
       }
-  }
-  const int flip = M.ring_flip[t];
-  const double sign = right ? -1.0 : 1.0;
+      visc_flux_n<double>(q4, gx, gy, cs * sc, sn * sc, gam, Rg, mu, kc, f);
 #pragma unroll
-  for (int a = 0; a < N; ++a) {
-    const int pa = flip ? N - 1 - a : a;
+      for (int v = 0; v < 4; ++v) fv[v][a] = f[v];
+    }
+  };
+
 #pragma unroll
-    for (int v = 0; v < 4; ++v) mflux[(long(t) * N + pa) * 4 + v] = float(sign * acc[v][a]);
+  for (int k = 0; k < 2; ++k) {
+    const int jl = right ? ((j - m - k) % K + K) % K : j;
+    const int jr = right ? j : (j + m + k) % K;
+    double fl[4][N], fr[4][N], pl[4][N], pr[4][N];
+    face_flux(jl, M.phi0L, ms->thL, jl, fl);
+    face_flux(K + jr, M.phi0R, ms->thR, jr, fr);
+    project<N>(ms->Pf[k], fl, pl);
+    project<N>(ms->Pf[2 + k], fr, pr);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int a = 0; a < N; ++a) pl[v][a] = 0.5 * (pl[v][a] + pr[v][a]);
+    double y[4][N];
+    project<N>(ms->Pb[(right ? 2 : 0) + k], pl, y);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int a = 0; a < N; ++a) acc[v][a] += y[v][a];
   }
+  store_slot<N>(M, mvflux, t, acc, right ? -1.0 : 1.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -751,12 +919,12 @@ __global__ __launch_bounds__(64) void k_mortar(DevMesh M, OpTables T,
     default: return hipErrorInvalidValue;                \
   }
 
-constexpr int STAGE_BLOCK = 256;
+constexpr int TRACE_BLOCK = 256;
 
 hipError_t launch_traces(const DevMesh &M, const OpTables &T, const float *q, float *tr,
                          hipStream_t s) {
-  const int grid = (M.E + STAGE_BLOCK - 1) / STAGE_BLOCK;
-  SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_traces<NN>, dim3(grid), dim3(STAGE_BLOCK), 0, s, M, T,
+  const int grid = (M.E + TRACE_BLOCK - 1) / TRACE_BLOCK;
+  SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_traces<NN>, dim3(grid), dim3(TRACE_BLOCK), 0, s, M, T,
                                          q, tr));
   return hipGetLastError();
 }
@@ -769,24 +937,54 @@ hipError_t launch_rebuild(const DevMesh &M, const MortarTables &MT, double theta
 }
 
 hipError_t launch_mortar(const DevMesh &M, const OpTables &T, const MortarState *ms,
-                         const float *tr, float *mflux, hipStream_t s) {
+                         const float *tr, float *mflux, float *mqc, hipStream_t s) {
   const int grid = (2 * M.K + 63) / 64;
-  SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_mortar<NN>, dim3(grid), dim3(64), 0, s, M, T, ms, tr,
-                                         mflux));
+  if (mqc) {
+    SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_mortar<NN, true>), dim3(grid), dim3(64), 0, s, M, T,
+                                           ms, tr, mflux, mqc));
+  } else {
+    SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_mortar<NN, false>), dim3(grid), dim3(64), 0, s, M,
+                                           T, ms, tr, mflux, mqc));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_mortar_visc(const DevMesh &M, const OpTables &T, const MortarState *ms,
+                              const float *mqc, const float *gtr, float *mvflux, hipStream_t s) {
+  const int grid = (2 * M.K + 63) / 64;
+  SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_mortar_visc<NN>, dim3(grid), dim3(64), 0, s, M, T, ms,
+                                         mqc, gtr, mvflux));
+  return hipGetLastError();
+}
+
+hipError_t launch_grad(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
+                       const float *trin, const float *mqc, float *G, float *gtr, hipStream_t s) {
+  const int grid = (M.E + EB - 1) / EB;
+  SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_grad<NN>, dim3(grid), dim3(EB * NN), 0, s, M, T, rot, q,
+                                         trin, mqc, G, gtr));
   return hipGetLastError();
 }
 
 hipError_t launch_stage(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
                         const float *qn, float *out, const float *trin, float *trout,
-                        const float *mflux, float a, float b, float dt, bool rk, hipStream_t s) {
+                        const float *mflux, const ViscIO *visc, float a, float b, float dt,
+                        bool rk, hipStream_t s) {
   const int grid = (M.E + EB - 1) / EB;
-  if (rk) {
-    SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_stage<NN, true>), dim3(grid), dim3(EB * NN), 0, s,
-                                           M, T, rot, q, qn, out, trin, trout, mflux, a, b, dt));
+  const ViscBufs V{visc ? visc->G : nullptr, visc ? visc->gtr : nullptr,
+                   visc ? visc->mvflux : nullptr};
+#define SSD_STAGE(RKV, VV)                                                                        \
+  SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_stage<NN, RKV, VV>), dim3(grid), dim3(EB * NN), 0, s, \
+                                         M, T, rot, q, qn, out, trin, trout, mflux, V, a, b, dt))
+  if (rk && visc) {
+    SSD_STAGE(true, true);
+  } else if (rk) {
+    SSD_STAGE(true, false);
+  } else if (visc) {
+    SSD_STAGE(false, true);
   } else {
-    SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_stage<NN, false>), dim3(grid), dim3(EB * NN), 0, s,
-                                           M, T, rot, q, qn, out, trin, trout, mflux, a, b, dt));
+    SSD_STAGE(false, false);
   }
+#undef SSD_STAGE
   return hipGetLastError();
 }
 
