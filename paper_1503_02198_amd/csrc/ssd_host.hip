@@ -680,7 +680,7 @@ ssd_status check_handle(const ssd_mesh *m) {
 // mortar; on viscous meshes the gradient pass and the viscous mortar; then
 // the stage kernel (rk: the fused SSP-RK stage writing out and trout).
 ssd_status residual_pass(ssd_mesh *m, double th, double omega, const float *in, const float *qn,
-                         float *out, const float *trin, float *trout, float a, float b, float dt,
+                         float *out, const float *trin, float *trout, float b, float dt,
                          bool rk, hipStream_t st) {
   ViscIO *V = m->viscous ? &m->V : nullptr;
   if (m->K) {
@@ -702,7 +702,7 @@ ssd_status residual_pass(ssd_mesh *m, double th, double omega, const float *in, 
     }
   }
   LaunchTimer lt(m, SSD_KERNEL_STAGE, st);
-  SSD_HIP(launch_stage(m->D, m->T, rot, in, qn, out, trin, trout, m->mflux, V, a, b, dt, rk, st),
+  SSD_HIP(launch_stage(m->D, m->T, rot, in, qn, out, trin, trout, m->mflux, V, b, dt, rk, st),
           rk ? "stage launch" : "residual launch");
   return SSD_OK;
 }
@@ -822,7 +822,7 @@ ssd_status ssd_residual(ssd_mesh *m, const float *q, float *r, void *stream) {
     LaunchTimer lt(m, SSD_KERNEL_TRACES, st);
     SSD_HIP(launch_traces(m->D, m->T, q, m->tr[0], st), "trace launch");
   }
-  return residual_pass(m, m->theta, m->omega, q, nullptr, r, m->tr[0], nullptr, 0.f, 1.f, 0.f,
+  return residual_pass(m, m->theta, m->omega, q, nullptr, r, m->tr[0], nullptr, 1.f, 0.f,
                        false, st);
 }
 
@@ -839,8 +839,7 @@ ssd_status ssd_rk_steps(ssd_mesh *m, float *q, float *work, double t, double dt,
     return fail(SSD_ERR_INVALID_ARG, "q and work overlap");
   DeviceGuard guard(m->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  // Shu-Osher SSP-RK3: stage s gives a_s Q^n + b_s (Q_s + dt R(Q_s, t + c_s dt))
-  const float A[3] = {0.0f, 0.75f, 1.0f / 3.0f};
+  // Shu-Osher SSP-RK3: stage s gives (1 - b_s) Q^n + b_s (Q_s + dt R(Q_s, t + c_s dt))
   const float B[3] = {1.0f, 0.25f, 2.0f / 3.0f};
   const double Cs[3] = {0.0, 1.0, 0.5};
   float *w1 = work, *w2 = work + len;
@@ -860,7 +859,7 @@ ssd_status ssd_rk_steps(ssd_mesh *m, float *q, float *work, double t, double dt,
         SSD_HIP(launch_rebuild(m->D, m->MT, th, m->ms, st), "mortar rebuild launch");
       }
       if (ssd_status e = residual_pass(m, th, m->omega0, in[s], s ? q : nullptr, outp[s],
-                                       m->tr[cur], m->tr[cur ^ 1], A[s], B[s], float(dt), true,
+                                       m->tr[cur], m->tr[cur ^ 1], B[s], float(dt), true,
                                        st))
         return e;
       cur ^= 1;

@@ -135,10 +135,11 @@ hipError_t launch_grad(const DevMesh &M, const OpTables &T, Rotation rot, const 
                        const float *trin, const float *mqc, float *G, float *gtr, hipStream_t s);
 hipError_t launch_mortar_visc(const DevMesh &M, const OpTables &T, const MortarState *ms,
                               const float *mqc, const float *gtr, float *mvflux, hipStream_t s);
-// visc null: inviscid residual.
+// visc null: inviscid residual.  rk: out = (1 - b) qn + b (q + dt dQ/dt)
+// with qn null standing for q.
 hipError_t launch_stage(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
                         const float *qn, float *out, const float *trin, float *trout,
-                        const float *mflux, const ViscIO *visc, float a, float b, float dt,
-                        bool rk, hipStream_t s);
+                        const float *mflux, const ViscIO *visc, float b, float dt, bool rk,
+                        hipStream_t s);
 
 }  // namespace ssd

@@ -119,8 +119,11 @@ __device__ __forceinline__ void common_visc(const DevMesh &M, const ViscParams &
 // ---------------------------------------------------------------------------
 // the element residual, optionally fused with an SSP-RK stage update
 //   rk = false:  out = dQ/dt
-//   rk = true :  out = a qn + b (q + dt dQ/dt), exported face traces of out
-//                -> trout
+//   rk = true :  out = (1 - b) qn + b (q + dt dQ/dt), exported face traces of
+//                out -> trout; qn = null stands for qn = q (first stage).
+//                Evaluated as qn + b ((q - qn) + dt dQ/dt): the rounding then
+//                scales with the stage increment, not with Q, and a steady
+//                state stays fixed instead of drifting by an ulp per stage
 //   visc:        adds the viscous fluxes, from the gradients of k_grad
 //
 // A block owns EB = 64 consecutive elements and has N waves; lane l of
@@ -142,7 +145,7 @@ template <int N, bool RK, bool VISC>
 __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotation R,
                                                   const float *q, const float *qn, float *out,
                                                   const float *trin, float *trout,
-                                                  const float *mflux, ViscBufs V, float a, float b,
+                                                  const float *mflux, ViscBufs V, float b,
                                                   float dt) {
   __shared__ float S[4][N][N][EB];     // state of the block's elements
   __shared__ float SR[4][N][N][EB];    // xi part of the residual, then the new state
@@ -283,7 +286,8 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
 
   // ---- column phase
   float qc[4][N], rc[4][N], qo[4][N];
-  if (RK && a != 0.0f) {
+  const bool with_qn = RK && qn != nullptr;
+  if (with_qn) {
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -373,16 +377,16 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
     return;
   }
 
-  // ---- SSP-RK stage on column w: Q <- a Qn + b (Q + dt R); the new column
-  // goes to SR (no other lane reads column w of SR after the column phase
-  // has started)
+  // ---- SSP-RK stage on column w: Q <- Qn + b ((Q - Qn) + dt R); the new
+  // column goes to SR (no other lane reads column w of SR after the column
+  // phase has started)
   bool bad = false;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      float x = b * (qc[v][j] + dt * rc[v][j]);
-      if (a != 0.0f) x += a * qo[v][j];
+      const float x = with_qn ? qo[v][j] + b * ((qc[v][j] - qo[v][j]) + dt * rc[v][j])
+                              : qc[v][j] + b * (dt * rc[v][j]);
       qc[v][j] = x;
       SR[v][j][w][l] = x;
     }
@@ -967,14 +971,14 @@ hipError_t launch_grad(const DevMesh &M, const OpTables &T, Rotation rot, const 
 
 hipError_t launch_stage(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
                         const float *qn, float *out, const float *trin, float *trout,
-                        const float *mflux, const ViscIO *visc, float a, float b, float dt,
+                        const float *mflux, const ViscIO *visc, float b, float dt,
                         bool rk, hipStream_t s) {
   const int grid = (M.E + EB - 1) / EB;
   const ViscBufs V{visc ? visc->G : nullptr, visc ? visc->gtr : nullptr,
                    visc ? visc->mvflux : nullptr};
 #define SSD_STAGE(RKV, VV)                                                                        \
   SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_stage<NN, RKV, VV>), dim3(grid), dim3(EB * NN), 0, s, \
-                                         M, T, rot, q, qn, out, trin, trout, mflux, V, a, b, dt))
+                                         M, T, rot, q, qn, out, trin, trout, mflux, V, b, dt))
   if (rk && visc) {
     SSD_STAGE(true, true);
   } else if (rk) {
