@@ -40,6 +40,16 @@ __device__ __forceinline__ void bstore4(const float x[4], rsrc_t r, uint32_t vof
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// A wave-uniform float as an opaque register value.
+__device__ __forceinline__ float uniform(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+
+// Number of set bits of the wave mask m below the calling lane.
+__device__ __forceinline__ int lane_rank(uint64_t m) {
+  return int(__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
+}
+
 // ---------------------------------------------------------------------------
 // fluxes (Sec. 2.1, 2.2, 3.1)
 // ---------------------------------------------------------------------------
@@ -300,29 +310,28 @@ __device__ __forceinline__ float inv_jacobian(const ElemGeo &g, const DevMesh &M
 // ---------------------------------------------------------------------------
 // What a face needs from outside the block, fetched before it is used: the
 // neighbour's trace (a neighbour in another block), the far-field state, or
-// a per-interface-face record `side` (the projected mortar flux, or the
-// projected common solution) of a sliding face.  Faces whose neighbour is
-// in the same block, and walls, fetch nothing.
+// the interface record (projected mortar flux, or projected common
+// solution) of a sliding face.  Traces and interface records share one face
+// data buffer (rface, `bytes` long), the records from byte `side_base`.
+// Faces whose neighbour is in the same block, and walls, need nothing: their
+// lanes point the load past the end of the buffer, where a buffer load
+// returns zero without a memory access.  One load per lane, no branch.
 template <int N>
-__device__ __forceinline__ void prefetch_face(const DevMesh &M, rsrc_t trin, rsrc_t side,
-                                              uint32_t E, uint32_t fw, int p, float x[4]) {
+__device__ __forceinline__ void prefetch_face(const DevMesh &M, rsrc_t rface, uint32_t bytes,
+                                              uint32_t side_base, uint32_t E, uint32_t fw, int p,
+                                              float x[4]) {
   const int kind = face_kind_of(fw);
+  const uint32_t idx = uint32_t(face_idx_of(fw)), nf = uint32_t(face_nf_of(fw));
+  const uint32_t pp = face_rev_of(fw) ? uint32_t(N - 1 - p) : uint32_t(p);
+  const bool from_trace =
+      (kind == SSD_FACE_INTERIOR || kind == SSD_FACE_PERIODIC) && !face_inblock_of(fw);
+  const uint32_t off = from_trace ? ((nf * E + idx) * N + pp) * 16u
+                       : kind == SSD_FACE_SLIDING ? side_base + (idx * N + uint32_t(p)) * 16u
+                                                  : bytes;
+  const f4 a = bload4(rface, off, 0u);
+  const bool far = kind == SSD_FACE_FARFIELD;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) x[v] = 0.0f;
-  if (kind == SSD_FACE_SLIDING) {
-    const f4 t = bload4(side, (uint32_t(face_idx_of(fw)) * N + uint32_t(p)) * 16u, 0u);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) x[v] = t.x[v];
-  } else if (kind == SSD_FACE_FARFIELD) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) x[v] = M.qinf[v];
-  } else if ((kind == SSD_FACE_INTERIOR || kind == SSD_FACE_PERIODIC) && !face_inblock_of(fw)) {
-    const uint32_t nb = uint32_t(face_idx_of(fw)), nf = uint32_t(face_nf_of(fw));
-    const uint32_t pp = face_rev_of(fw) ? uint32_t(N - 1 - p) : uint32_t(p);
-    const f4 t = bload4(trin, ((nf * E + nb) * N + pp) * 16u, 0u);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) x[v] = t.x[v];
-  }
+  for (int v = 0; v < 4; ++v) x[v] = far ? M.qinf[v] : a.x[v];
 }
 
 __device__ __forceinline__ bool conforming(int kind) {
@@ -343,12 +352,20 @@ __device__ __forceinline__ void neighbor_state(const OpTables &T, const float *S
     const bool hi = (nf == 1u || nf == 2u);        // xi = 1 or eta = 1
     const int base = (odd ? pp * N * EB : pp * EB) + ln;
     const int stride = odd ? EB : N * EB;
+    // the weights are uniform values selected per lane; taken through
+    // readfirstlane so that the selection stays a register select instead
+    // of becoming a per-lane load from the kernel argument segment
+    float wgt[N];
+#pragma unroll
+    for (int s2 = 0; s2 < N; ++s2) {
+      const float a0 = uniform(T.I[0][s2]), aN = uniform(T.I[N][s2]);
+      wgt[s2] = hi ? aN : a0;
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       float acc = 0.f;
 #pragma unroll
-      for (int s2 = 0; s2 < N; ++s2)
-        acc += (hi ? T.I[N][s2] : T.I[0][s2]) * Sf[v * N * N * EB + base + s2 * stride];
+      for (int s2 = 0; s2 < N; ++s2) acc += wgt[s2] * Sf[v * N * N * EB + base + s2 * stride];
       qx[v] = acc;
     }
   } else {
@@ -359,34 +376,26 @@ __device__ __forceinline__ void neighbor_state(const OpTables &T, const float *S
 
 // Common inviscid normal flux at one element-boundary flux point along the
 // outward normal of `G`, given the face data x (see prefetch_face).  For a
-// conforming face the neighbour's state is returned in qx.
+// conforming face the neighbour's state is returned in qx.  The Rusanov flux
+// and the wall flux are formed for every lane and the face kind selects
+// between them (values of the unselected forms are discarded), so a wave
+// with mixed face kinds runs one path.
 template <int N>
 __device__ __forceinline__ void common_flux(const DevMesh &M, const OpTables &T, const float *Sf,
                                             uint32_t fw, int p, const float qo[4],
                                             const float x[4], const FPGeo &G, float fs[4],
                                             float qx[4]) {
   const int kind = face_kind_of(fw);
-  if (kind == SSD_FACE_SLIDING) {
+  neighbor_state<N>(T, Sf, fw, p, x, qx);
+  float fr[4];
+  rusanov(qo, qx, G.nx, G.ny, G.vgn, M.gamma, fr);
+  // walls: no flux relative to the moving wall; pressure from the interior
+  const float pr = (M.gamma - 1.0f) * (qo[3] - 0.5f * (qo[1] * qo[1] + qo[2] * qo[2]) * rcp(qo[0]));
+  const bool wall = kind == SSD_FACE_WALL_ISOTHERMAL || kind == SSD_FACE_WALL_SLIP;
+  const bool sliding = kind == SSD_FACE_SLIDING;
+  const float fw4[4] = {0.0f, pr * G.nx, pr * G.ny, pr * G.vgn};
 #pragma unroll
-    for (int v = 0; v < 4; ++v) fs[v] = x[v];
-    return;
-  }
-  if (kind == SSD_FACE_WALL_ISOTHERMAL || kind == SSD_FACE_WALL_SLIP) {
-    // no flux relative to the moving wall; pressure from the interior
-    const float pr = (M.gamma - 1.0f) * (qo[3] - 0.5f * (qo[1] * qo[1] + qo[2] * qo[2]) * rcp(qo[0]));
-    fs[0] = 0.0f;
-    fs[1] = pr * G.nx;
-    fs[2] = pr * G.ny;
-    fs[3] = pr * G.vgn;
-    return;
-  }
-  if (conforming(kind)) {
-    neighbor_state<N>(T, Sf, fw, p, x, qx);
-  } else {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) qx[v] = x[v];
-  }
-  rusanov(qo, qx, G.nx, G.ny, G.vgn, M.gamma, fs);
+  for (int v = 0; v < 4; ++v) fs[v] = sliding ? x[v] : (wall ? fw4[v] : fr[v]);
 }
 
 // Common solution at a face point for the gradient (BR1 reading): the mean

@@ -293,7 +293,6 @@ struct ssd_mesh {
   bool mortar_fresh = false;
   std::vector<void *> allocs;
   float *tr[2] = {nullptr, nullptr};
-  float *mflux = nullptr;
   ViscIO V{};                          // viscous work buffers (mu > 0)
   MortarState *ms = nullptr;
   int *flag = nullptr;
@@ -581,6 +580,8 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
     if (d->elem_zone[L[0].e] == d->elem_zone[R[0].e])
       return fail(SSD_ERR_MESH, "both sides of the sliding interface are in the same zone");
     m->K = K;
+    if (4.0 * double(face_buffer_floats(N, E, K)) >= 4294967295.0)
+      return fail(SSD_ERR_INVALID_ARG, "mesh too large for one handle (face data buffer >= 4 GiB)");
     std::vector<int> re(2 * K), rfv(2 * K), rfl(2 * K);
     for (int j = 0; j < K; ++j) {
       re[j] = L[j].e;
@@ -608,11 +609,8 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
     m->D.ring_e = dre;
     m->D.ring_f = drf;
     m->D.ring_flip = drl;
-    SSD_HIP(dev_alloc(m, &m->mflux, 2L * K * 4 * N), "alloc mortar flux");
-    if (m->viscous) {
-      SSD_HIP(dev_alloc(m, &m->V.mqc, 2L * K * 4 * N), "alloc mortar common solution");
+    if (m->viscous)
       SSD_HIP(dev_alloc(m, &m->V.mvflux, 2L * K * 4 * N), "alloc viscous mortar flux");
-    }
     SSD_HIP(dev_alloc(m, &m->ms, 1), "alloc mortar state");
     SSD_HIP(hipMemset(m->ms, 0, sizeof(MortarState)), "clear mortar state");
   }
@@ -633,7 +631,8 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
   if (!cmet.empty())
     SSD_HIP(hipMemcpy(dcmet, cmet.data(), cmet.size() * sizeof(double), hipMemcpyHostToDevice),
             "upload cubic metrics");
-  for (int b = 0; b < 2; ++b) SSD_HIP(dev_alloc(m, &m->tr[b], 16L * N * E), "alloc traces");
+  for (int b = 0; b < 2; ++b)
+    SSD_HIP(dev_alloc(m, &m->tr[b], face_buffer_floats(N, E, m->K)), "alloc face data");
   if (m->viscous) {
     SSD_HIP(dev_alloc(m, &m->V.G, 8L * N * N * E), "alloc gradients");
     SSD_HIP(dev_alloc(m, &m->V.gtr, 32L * N * E), "alloc gradient traces");
@@ -680,29 +679,31 @@ ssd_status check_handle(const ssd_mesh *m) {
 // mortar; on viscous meshes the gradient pass and the viscous mortar; then
 // the stage kernel (rk: the fused SSP-RK stage writing out and trout).
 ssd_status residual_pass(ssd_mesh *m, double th, double omega, const float *in, const float *qn,
-                         float *out, const float *trin, float *trout, float b, float dt,
-                         bool rk, hipStream_t st) {
+                         float *out, float *facein, float *trout, float b, float dt, bool rk,
+                         hipStream_t st) {
   ViscIO *V = m->viscous ? &m->V : nullptr;
+  // interface records of `in` live behind its traces in the same face buffer
+  float *mflux = facein + face_trace_floats(m->N, m->E);
+  float *mqc = mflux + face_record_floats(m->N, m->K);
   if (m->K) {
     LaunchTimer lt(m, SSD_KERNEL_MORTAR, st);
-    SSD_HIP(launch_mortar(m->D, m->T, m->ms, trin, m->mflux, V ? V->mqc : nullptr, st),
+    SSD_HIP(launch_mortar(m->D, m->T, m->ms, facein, mflux, V ? mqc : nullptr, st),
             "mortar launch");
   }
   const Rotation rot{std::cos(th), std::sin(th), omega};
   if (V) {
     {
       LaunchTimer lt(m, SSD_KERNEL_GRAD, st);
-      SSD_HIP(launch_grad(m->D, m->T, rot, in, trin, V->mqc, V->G, V->gtr, st),
-              "gradient launch");
+      SSD_HIP(launch_grad(m->D, m->T, rot, in, facein, V->G, V->gtr, st), "gradient launch");
     }
     if (m->K) {
       LaunchTimer lt(m, SSD_KERNEL_MORTAR, st);
-      SSD_HIP(launch_mortar_visc(m->D, m->T, m->ms, V->mqc, V->gtr, V->mvflux, st),
+      SSD_HIP(launch_mortar_visc(m->D, m->T, m->ms, mqc, V->gtr, V->mvflux, st),
               "viscous mortar launch");
     }
   }
   LaunchTimer lt(m, SSD_KERNEL_STAGE, st);
-  SSD_HIP(launch_stage(m->D, m->T, rot, in, qn, out, trin, trout, m->mflux, V, b, dt, rk, st),
+  SSD_HIP(launch_stage(m->D, m->T, rot, in, qn, out, facein, trout, V, b, dt, rk, st),
           rk ? "stage launch" : "residual launch");
   return SSD_OK;
 }
@@ -722,7 +723,8 @@ ssd_status ssd_create_mesh(const ssd_mesh_desc *d, int device, ssd_mesh **out) {
   if (d->N < 2 || d->N > NMAX) return fail(SSD_ERR_INVALID_ARG, "N must be in 2..6");
   if (d->n_elem <= 0 || d->n_elem >= MAX_ELEMS)
     return fail(SSD_ERR_INVALID_ARG, "n_elem out of range");
-  // kernels address state, trace and gradient arrays with 32-bit byte offsets
+  // kernels address state, face data and gradient arrays with 32-bit byte
+  // offsets (the face data buffer adds 64 N bytes per interface face)
   if (double(std::max(16 * d->N * d->N, 64 * d->N)) * double(d->n_elem) * (d->mu > 0.0 ? 2.0 : 1.0) >=
       4294967295.0)
     return fail(SSD_ERR_INVALID_ARG,

@@ -115,11 +115,20 @@ struct Rotation {
   double ct, st, omega;
 };
 
+// Face data buffer of a state (two per handle, one per RK stage parity), in
+// floats: the exported face traces [face][E][point][4] (16 N E), the mortar
+// flux of the interface faces [slot][point][4] (8 K N), and on viscous
+// meshes the mortar common solution [slot][point][4] (8 K N).
+inline long face_trace_floats(int N, int E) { return 16L * N * E; }
+inline long face_record_floats(int N, int K) { return 8L * K * N; }
+inline long face_buffer_floats(int N, int E, int K) {
+  return face_trace_floats(N, E) + 2 * face_record_floats(N, K);
+}
+
 // Viscous work buffers (device, owned by the mesh handle).
 struct ViscIO {
   float *G;        // grad Q at the SPs [(c*4+v)][j][i][E], c = 0 x, 1 y
   float *gtr;      // gradient traces [face][E][point][8]
-  float *mqc;      // common solution of the interface faces [slot][point][4]
   float *mvflux;   // viscous mortar flux [slot][point][4]
 };
 
@@ -131,15 +140,17 @@ hipError_t launch_rebuild(const DevMesh &M, const MortarTables &MT, double theta
 // mqc may be null (inviscid): then only the inviscid mortar flux is formed.
 hipError_t launch_mortar(const DevMesh &M, const OpTables &T, const MortarState *ms,
                          const float *tr, float *mflux, float *mqc, hipStream_t s);
+// facein: face data buffer of q with its traces and mortar common solution.
 hipError_t launch_grad(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
-                       const float *trin, const float *mqc, float *G, float *gtr, hipStream_t s);
+                       const float *facein, float *G, float *gtr, hipStream_t s);
 hipError_t launch_mortar_visc(const DevMesh &M, const OpTables &T, const MortarState *ms,
                               const float *mqc, const float *gtr, float *mvflux, hipStream_t s);
-// visc null: inviscid residual.  rk: out = (1 - b) qn + b (q + dt dQ/dt)
-// with qn null standing for q.
+// facein: face data buffer of q with its traces and mortar flux; trout:
+// the face data buffer the new state's traces go to (rk).  visc null:
+// inviscid residual.  rk: out = (1 - b) qn + b (q + dt dQ/dt) with qn null
+// standing for q.
 hipError_t launch_stage(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
-                        const float *qn, float *out, const float *trin, float *trout,
-                        const float *mflux, const ViscIO *visc, float b, float dt, bool rk,
-                        hipStream_t s);
+                        const float *qn, float *out, const float *facein, float *trout,
+                        const ViscIO *visc, float b, float dt, bool rk, hipStream_t s);
 
 }  // namespace ssd

@@ -133,9 +133,10 @@ __device__ __forceinline__ void common_visc(const DevMesh &M, const ViscParams &
 //                at point w; the xi part of the residual of row w -> LDS
 //   column phase (column i = w): the same along eta with the faces eta = 0,
 //                1 at point w, plus the row parts from LDS -> dQ/dt on
-//                column w; RK update, column store, traces of faces eta = 0,
-//                1 at point w
-//   trace phase  (row w): traces of faces xi = 0, 1 at point w
+//                column w; RK update into LDS, column store
+//   pack phase   the face records some other block reads, computed from the
+//                new state in LDS, one face per wave, whole records per
+//                element
 // A neighbour in the same block is read from the block's LDS state, any
 // other through the trace buffer.  LDS arrays are [var][j][i][lane]: every
 // LDS access of a wave to its own elements touches 64 distinct banks.
@@ -144,11 +145,11 @@ __device__ __forceinline__ void common_visc(const DevMesh &M, const ViscParams &
 template <int N, bool RK, bool VISC>
 __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotation R,
                                                   const float *q, const float *qn, float *out,
-                                                  const float *trin, float *trout,
-                                                  const float *mflux, ViscBufs V, float b,
-                                                  float dt) {
+                                                  const float *facein, float *trout, ViscBufs V,
+                                                  float b, float dt) {
   __shared__ float S[4][N][N][EB];     // state of the block's elements
   __shared__ float SR[4][N][N][EB];    // xi part of the residual, then the new state
+  __shared__ uint8_t XL[4][EB];        // exporting lanes per face
   const float *Sf = &S[0][0][0][0];
   const int l = threadIdx.x & (EB - 1);
   // the wave index is uniform across the wave (blocks are 64 N lanes): say so,
@@ -164,9 +165,10 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
   const rsrc_t rq = make_rsrc(q, sbytes);
   const rsrc_t rqn = make_rsrc(qn, RK ? sbytes : 0u);
   const rsrc_t rout = make_rsrc(out, sbytes);
-  const rsrc_t rtin = make_rsrc(trin, tbytes);
+  // face data of q: traces, then the mortar flux records
+  const uint32_t fbytes = tbytes + mbytes;
+  const rsrc_t rtin = make_rsrc(facein, fbytes);
   const rsrc_t rtout = make_rsrc(trout, RK ? tbytes : 0u);
-  const rsrc_t rmf = make_rsrc(mflux, mbytes);
   const rsrc_t rG = make_rsrc(V.G, VISC ? 2u * sbytes : 0u);
   const rsrc_t rgtr = make_rsrc(V.gtr, VISC ? 2u * tbytes : 0u);
   const rsrc_t rmv = make_rsrc(V.mvflux, VISC ? mbytes : 0u);
@@ -184,10 +186,18 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
     for (int i = 0; i < N; ++i) qr[v][i] = bload(rq, ve, ((v * N + w) * N + i) * E4);
   const ElemGeo g = load_geo(M, e, R);
   float x0[4], x1[4], x2[4], x3[4];
-  prefetch_face<N>(M, rtin, rmf, uint32_t(M.E), fw3, w, x3);   // row faces xi = 0, 1 at point w
-  prefetch_face<N>(M, rtin, rmf, uint32_t(M.E), fw1, w, x1);
-  prefetch_face<N>(M, rtin, rmf, uint32_t(M.E), fw0, w, x0);   // column faces eta = 0, 1
-  prefetch_face<N>(M, rtin, rmf, uint32_t(M.E), fw2, w, x2);
+  prefetch_face<N>(M, rtin, fbytes, tbytes, uint32_t(M.E), fw3, w, x3);   // row faces xi = 0, 1 at point w
+  prefetch_face<N>(M, rtin, fbytes, tbytes, uint32_t(M.E), fw1, w, x1);
+  prefetch_face<N>(M, rtin, fbytes, tbytes, uint32_t(M.E), fw0, w, x0);   // column faces eta = 0, 1
+  prefetch_face<N>(M, rtin, fbytes, tbytes, uint32_t(M.E), fw2, w, x2);
+  float qo[4][N];   // column w of Qn (RK stages after the first)
+  const bool with_qn = RK && qn != nullptr;
+  if (with_qn) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int j = 0; j < N; ++j) qo[v][j] = bload(rqn, ve, ((v * N + j) * N + w) * E4);
+  }
 
   // ---- row phase
   {
@@ -285,14 +295,7 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
   __syncthreads();
 
   // ---- column phase
-  float qc[4][N], rc[4][N], qo[4][N];
-  const bool with_qn = RK && qn != nullptr;
-  if (with_qn) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-      for (int j = 0; j < N; ++j) qo[v][j] = bload(rqn, ve, ((v * N + j) * N + w) * E4);
-  }
+  float qc[4][N], rc[4][N];
   {
     float gc[8][N];   // gradient on column w
     if (VISC) {
@@ -394,42 +397,55 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
     const float pr = gm1 * (qc[3][j] - 0.5f * (qc[1][j] * qc[1][j] + qc[2][j] * qc[2][j]) * rcp(rho));
     bad |= !(rho > 0.0f) || !(pr > 0.0f) || !isfinite(qc[1][j]) || !isfinite(qc[2][j]);
   }
-  const bool ex0 = face_exported(fw0), ex2 = face_exported(fw2);
-  const uint32_t tvo = (uint32_t(e) * N + uint32_t(w)) * 16u, tfs = uint32_t(M.E) * N * 16u;
   if (valid) {
-    float f0[4], f2[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      f0[v] = f2[v] = 0.f;
+    for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        bstore(qc[v][j], rout, ve, ((v * N + j) * N + w) * E4);
-        f0[v] += T.I[0][j] * qc[v][j];     // eta = 0 face, point w
-        f2[v] += T.I[N][j] * qc[v][j];     // eta = 1 face, point w
-      }
-    }
-    if (ex0) bstore4(f0, rtout, tvo, 0 * tfs);
-    if (ex2) bstore4(f2, rtout, tvo, 2 * tfs);
+      for (int j = 0; j < N; ++j) bstore(qc[v][j], rout, ve, ((v * N + j) * N + w) * E4);
     if (bad) M.flag[0] = 1;
   }
+  // lanes whose face f is read by another block, in lane order (wave w lists
+  // the faces it packs below)
+  const uint64_t xm[4] = {__builtin_amdgcn_ballot_w64(valid && face_exported(fw0)),
+                          __builtin_amdgcn_ballot_w64(valid && face_exported(fw1)),
+                          __builtin_amdgcn_ballot_w64(valid && face_exported(fw2)),
+                          __builtin_amdgcn_ballot_w64(valid && face_exported(fw3))};
+  for (int f = w; f < 4; f += N)
+    if ((xm[f] >> l) & 1u) XL[f][lane_rank(xm[f])] = uint8_t(l);
   __syncthreads();
 
-  // ---- trace phase: faces xi = 0, 1 at point w from row w of the new state
-  const bool ex1 = face_exported(fw1), ex3 = face_exported(fw3);
-  if (valid && (ex1 || ex3)) {
-    float f1[4], f3[4];
+  // ---- pack phase: wave w writes the face records of faces f = w, w + N,
+  // ...  Lane k of a chunk takes point k % N of the (k / N)-th listed
+  // element, so the N lanes of an element write its whole 16 N-byte record
+  // and one store instruction covers the records of 64 / N elements:
+  // consecutive exporting elements give one contiguous span.
+  constexpr int EPC = EB / N;   // elements per chunk
+  const uint32_t tile0 = uint32_t(blockIdx.x) * EB;
+  for (int f = w; f < 4; f += N) {
+    const int cnt = __builtin_popcountll(xm[f]);
+    for (int c0 = 0; c0 < cnt; c0 += EPC) {
+      const int j = c0 + l / N, p = l % N;
+      if (l < EPC * N && j < cnt) {
+        const int src = XL[f][j];
+        float tv[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      f1[v] = f3[v] = 0.f;
+        for (int v = 0; v < 4; ++v) {
+          float acc = 0.f;
+          if (f == 0 || f == 2) {   // eta = 0 / eta = 1 at point p along xi
+            const float *I = T.I[f == 0 ? 0 : N];
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        const float x = SR[v][w][i][l];
-        f1[v] += T.I[N][i] * x;
-        f3[v] += T.I[0][i] * x;
+            for (int jj = 0; jj < N; ++jj) acc += I[jj] * SR[v][jj][p][src];
+          } else {                  // xi = 1 / xi = 0 at point p along eta
+            const float *I = T.I[f == 3 ? 0 : N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) acc += I[i] * SR[v][p][i][src];
+          }
+          tv[v] = acc;
+        }
+        bstore4(tv, rtout, ((uint32_t(f) * uint32_t(M.E) + tile0 + uint32_t(src)) * N + p) * 16u,
+                0u);
       }
     }
-    if (ex1) bstore4(f1, rtout, tvo, 1 * tfs);
-    if (ex3) bstore4(f3, rtout, tvo, 3 * tfs);
   }
 }
 
@@ -445,8 +461,8 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
 // ---------------------------------------------------------------------------
 template <int N>
 __global__ __launch_bounds__(64 * N) void k_grad(DevMesh M, OpTables T, Rotation R,
-                                                 const float *q, const float *trin,
-                                                 const float *mqc, float *Gout, float *gtr) {
+                                                 const float *q, const float *facein, float *Gout,
+                                                 float *gtr) {
   // LDS: the state and Q_xi while the derivatives are formed, then the
   // gradient of the whole block
   __shared__ float L[8][N][N][EB];
@@ -461,8 +477,11 @@ __global__ __launch_bounds__(64 * N) void k_grad(DevMesh M, OpTables T, Rotation
   const uint32_t E4 = uint32_t(M.E) * 4u;
   const uint32_t sbytes = 4u * N * N * E4, tbytes = 16u * N * E4;
   const rsrc_t rq = make_rsrc(q, sbytes);
-  const rsrc_t rtin = make_rsrc(trin, tbytes);
-  const rsrc_t rqc = make_rsrc(mqc, uint32_t(2 * M.K) * N * 16u);
+  // face data of q: traces, mortar flux records, then the mortar common
+  // solution records read here
+  const uint32_t mbytes = uint32_t(2 * M.K) * N * 16u;
+  const uint32_t fbytes = tbytes + 2u * mbytes;
+  const rsrc_t rtin = make_rsrc(facein, fbytes);
   const rsrc_t rG = make_rsrc(Gout, 2u * sbytes);
   const rsrc_t rgtr = make_rsrc(gtr, 2u * tbytes);
   const uint32_t ve = uint32_t(e) * 4u;
@@ -477,10 +496,10 @@ __global__ __launch_bounds__(64 * N) void k_grad(DevMesh M, OpTables T, Rotation
     for (int i = 0; i < N; ++i) qr[v][i] = bload(rq, ve, ((v * N + w) * N + i) * E4);
   const ElemGeo g = load_geo(M, e, R);
   float x0[4], x1[4], x2[4], x3[4];
-  prefetch_face<N>(M, rtin, rqc, uint32_t(M.E), fw3, w, x3);
-  prefetch_face<N>(M, rtin, rqc, uint32_t(M.E), fw1, w, x1);
-  prefetch_face<N>(M, rtin, rqc, uint32_t(M.E), fw0, w, x0);
-  prefetch_face<N>(M, rtin, rqc, uint32_t(M.E), fw2, w, x2);
+  prefetch_face<N>(M, rtin, fbytes, tbytes + mbytes, uint32_t(M.E), fw3, w, x3);
+  prefetch_face<N>(M, rtin, fbytes, tbytes + mbytes, uint32_t(M.E), fw1, w, x1);
+  prefetch_face<N>(M, rtin, fbytes, tbytes + mbytes, uint32_t(M.E), fw0, w, x0);
+  prefetch_face<N>(M, rtin, fbytes, tbytes + mbytes, uint32_t(M.E), fw2, w, x2);
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -962,23 +981,22 @@ hipError_t launch_mortar_visc(const DevMesh &M, const OpTables &T, const MortarS
 }
 
 hipError_t launch_grad(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
-                       const float *trin, const float *mqc, float *G, float *gtr, hipStream_t s) {
+                       const float *facein, float *G, float *gtr, hipStream_t s) {
   const int grid = (M.E + EB - 1) / EB;
   SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_grad<NN>, dim3(grid), dim3(EB * NN), 0, s, M, T, rot, q,
-                                         trin, mqc, G, gtr));
+                                         facein, G, gtr));
   return hipGetLastError();
 }
 
 hipError_t launch_stage(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
-                        const float *qn, float *out, const float *trin, float *trout,
-                        const float *mflux, const ViscIO *visc, float b, float dt,
-                        bool rk, hipStream_t s) {
+                        const float *qn, float *out, const float *facein, float *trout,
+                        const ViscIO *visc, float b, float dt, bool rk, hipStream_t s) {
   const int grid = (M.E + EB - 1) / EB;
   const ViscBufs V{visc ? visc->G : nullptr, visc ? visc->gtr : nullptr,
                    visc ? visc->mvflux : nullptr};
 #define SSD_STAGE(RKV, VV)                                                                        \
   SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_stage<NN, RKV, VV>), dim3(grid), dim3(EB * NN), 0, s, \
-                                         M, T, rot, q, qn, out, trin, trout, mflux, V, b, dt))
+                                         M, T, rot, q, qn, out, facein, trout, V, b, dt))
   if (rk && visc) {
     SSD_STAGE(true, true);
   } else if (rk) {
