@@ -201,18 +201,26 @@ def main():
         t += args.warmup * dt
     gm.check()
     torch.cuda.synchronize()
-    gm.timing_enable(True)
+    # timed region: only the stage kernel is bracketed by events (each
+    # bracket adds two event records to the stream)
+    gm.timing_enable(kernels=["stage"])
     gm.timing_reset()
     t0 = time.perf_counter()
     gm.rk_steps(q, work, t, dt, args.steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    gm.timing_enable(False)
-    gm.check()
-    kern = {}
-    for k in ("stage", "traces", "mortar", "rebuild"):
+    t += args.steps * dt
+    ms, n = gm.timing_read("stage")
+    kern = {"stage": dict(launches=n, avg_us=1e3 * ms / n, total_ms=ms)}
+    # the other kernels, from a short run after the timed region
+    gm.timing_enable(kernels=["traces", "mortar"])
+    gm.timing_reset()
+    gm.rk_steps(q, work, t, dt, 20)
+    for k in ("traces", "mortar"):
         ms, n = gm.timing_read(k)
         kern[k] = dict(launches=n, avg_us=(1e3 * ms / n) if n else None, total_ms=ms)
+    gm.timing_enable(False)
+    gm.check()
     print(f"# timed {args.steps} steps in {el:.3f} s", file=sys.stderr, flush=True)
 
     dof = 4 * N * N * E

@@ -199,17 +199,22 @@ ssd_status ssd_check(ssd_mesh *m, void *stream);
 const char *ssd_last_error(void);
 
 /*
- * Kernel timing.  While enabled, every kernel launch of the handle is
- * bracketed by HIP events on its stream.  Classes: the stage kernel
+ * Kernel timing.  ssd_timing_enable selects the kernel classes whose
+ * launches are bracketed by HIP events on their stream: `classes` is a bit
+ * mask, bit SSD_KERNEL_x for class x (SSD_TIMING_ALL: every class, 0: off).
+ * Each bracket costs two event records in the stream, so time only the
+ * classes of interest in a throughput run.  Classes: the stage kernel
  * (residual or fused RK stage), the face-trace kernel, the mortar kernels
- * (inviscid and, with mu > 0, viscous), the mortar rebuild, and the
+ * (the rebuild fused with the inviscid mortar, and with mu > 0 the viscous
+ * mortar), the stand-alone mortar rebuild (ssd_mortar_rebuild), and the
  * gradient pass of viscous meshes.  ssd_timing_read synchronises and
  * returns the summed milliseconds and the launch count of one kernel class
  * (SSD_KERNEL_*) since the last reset; ssd_timing_reset clears them.
  */
 enum { SSD_KERNEL_STAGE = 0, SSD_KERNEL_TRACES = 1, SSD_KERNEL_MORTAR = 2, SSD_KERNEL_REBUILD = 3,
        SSD_KERNEL_GRAD = 4, SSD_KERNEL_COUNT = 5 };
-ssd_status ssd_timing_enable(ssd_mesh *m, int enable);
+enum { SSD_TIMING_ALL = (1 << SSD_KERNEL_COUNT) - 1 };
+ssd_status ssd_timing_enable(ssd_mesh *m, int classes);
 ssd_status ssd_timing_reset(ssd_mesh *m);
 ssd_status ssd_timing_read(ssd_mesh *m, int kernel, double *total_ms, int64_t *launches);
 

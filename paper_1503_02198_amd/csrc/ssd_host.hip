@@ -296,7 +296,7 @@ struct ssd_mesh {
   ViscIO V{};                          // viscous work buffers (mu > 0)
   MortarState *ms = nullptr;
   int *flag = nullptr;
-  bool timing = false;
+  int timing = 0;                      // bit mask of timed kernel classes
   struct Timer {
     std::vector<hipEvent_t> ev;   // start/stop pairs
     size_t used = 0;
@@ -333,7 +333,7 @@ struct LaunchTimer {
   hipStream_t s;
   hipEvent_t stop = nullptr;
   LaunchTimer(ssd_mesh *m_, int k, hipStream_t s_) : m(m_), kind(k), s(s_) {
-    if (!m->timing) return;
+    if (!((m->timing >> kind) & 1)) return;
     auto &t = m->timers[kind];
     if (t.used + 2 > t.ev.size()) {
       for (int i = 0; i < 2; ++i) {
@@ -674,10 +674,10 @@ ssd_status check_handle(const ssd_mesh *m) {
   return SSD_OK;
 }
 
-// One evaluation of the residual of `in` (face traces in trin) at rotor
-// angle th with the mortar state already rebuilt for th: the inviscid
-// mortar; on viscous meshes the gradient pass and the viscous mortar; then
-// the stage kernel (rk: the fused SSP-RK stage writing out and trout).
+// One evaluation of the residual of `in` (face data in facein) at rotor
+// angle th: the mortar rebuild for th fused with the inviscid mortar; on
+// viscous meshes the gradient pass and the viscous mortar; then the stage
+// kernel (rk: the fused SSP-RK stage writing out and the traces trout).
 ssd_status residual_pass(ssd_mesh *m, double th, double omega, const float *in, const float *qn,
                          float *out, float *facein, float *trout, float b, float dt, bool rk,
                          hipStream_t st) {
@@ -687,7 +687,7 @@ ssd_status residual_pass(ssd_mesh *m, double th, double omega, const float *in, 
   float *mqc = mflux + face_record_floats(m->N, m->K);
   if (m->K) {
     LaunchTimer lt(m, SSD_KERNEL_MORTAR, st);
-    SSD_HIP(launch_mortar(m->D, m->T, m->ms, facein, mflux, V ? mqc : nullptr, st),
+    SSD_HIP(launch_mortar(m->D, m->T, m->MT, th, m->ms, facein, mflux, V ? mqc : nullptr, st),
             "mortar launch");
   }
   const Rotation rot{std::cos(th), std::sin(th), omega};
@@ -856,10 +856,7 @@ ssd_status ssd_rk_steps(ssd_mesh *m, float *q, float *work, double t, double dt,
     const double tn = t + n * dt;
     for (int s = 0; s < 3; ++s) {
       const double th = m->theta0 + m->omega0 * (tn + Cs[s] * dt);
-      if (m->K) {
-        LaunchTimer lt(m, SSD_KERNEL_REBUILD, st);
-        SSD_HIP(launch_rebuild(m->D, m->MT, th, m->ms, st), "mortar rebuild launch");
-      }
+      // the mortar kernel rebuilds the projections for th itself
       if (ssd_status e = residual_pass(m, th, m->omega0, in[s], s ? q : nullptr, outp[s],
                                        m->tr[cur], m->tr[cur ^ 1], B[s], float(dt), true,
                                        st))
@@ -892,9 +889,10 @@ ssd_status ssd_check(ssd_mesh *m, void *stream) {
   return SSD_OK;
 }
 
-ssd_status ssd_timing_enable(ssd_mesh *m, int enable) {
+ssd_status ssd_timing_enable(ssd_mesh *m, int classes) {
   if (ssd_status s = check_handle(m)) return s;
-  m->timing = enable != 0;
+  if (classes & ~int(SSD_TIMING_ALL)) return fail(SSD_ERR_INVALID_ARG, "unknown kernel class bit");
+  m->timing = classes;
   return SSD_OK;
 }
 

@@ -137,9 +137,12 @@ hipError_t launch_traces(const DevMesh &M, const OpTables &T, const float *q, fl
                          hipStream_t s);
 hipError_t launch_rebuild(const DevMesh &M, const MortarTables &MT, double theta, MortarState *ms,
                           hipStream_t s);
-// mqc may be null (inviscid): then only the inviscid mortar flux is formed.
-hipError_t launch_mortar(const DevMesh &M, const OpTables &T, const MortarState *ms,
-                         const float *tr, float *mflux, float *mqc, hipStream_t s);
+// Rebuilds the mortars for theta (stored to ms) and forms the inviscid
+// mortar flux; mqc may be null (inviscid), else it also receives the
+// mortar common solution.
+hipError_t launch_mortar(const DevMesh &M, const OpTables &T, const MortarTables &MT,
+                         double theta, MortarState *ms, const float *tr, float *mflux, float *mqc,
+                         hipStream_t s);
 // facein: face data buffer of q with its traces and mortar common solution.
 hipError_t launch_grad(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
                        const float *facein, float *G, float *gtr, hipStream_t s);

@@ -674,14 +674,14 @@ __device__ __forceinline__ double lagrange_d(const MortarTables &MT, int N, int 
   return r;
 }
 
-// One workgroup: placement (m, delta) of the faces for the rotor angle and
-// the 8 projection matrices.  A_k(i,j) = int_0^1 h_i(z) h_j(o_k + s_k z) dz
-// by N-point Gauss-Legendre quadrature (exact: degree 2N-2).
+// Placement (m, delta) of the interface faces for the rotor angle and the 8
+// projection matrices, computed by the calling workgroup into `ms` (LDS).
+// A_k(i,j) = int_0^1 h_i(z) h_j(o_k + s_k z) dz by N-point Gauss-Legendre
+// quadrature (exact: degree 2N-2); P_fwd = M^-1 A (eq. prjQ2), P_back =
+// s M^-1 A^T (eq. prjF2).
 template <int N>
-__global__ __launch_bounds__(64) void k_rebuild(DevMesh M, MortarTables MT, double theta,
-                                                MortarState *__restrict__ ms) {
-  __shared__ double A[4][N][N];
-  __shared__ double so[4], ss[4];
+__device__ void build_mortar(const DevMesh &M, const MortarTables &MT, double theta,
+                             MortarState &ms, double (&A)[4][N][N]) {
   if (threadIdx.x == 0) {
     const double thL = M.rotL ? theta : 0.0;
     const double thR = M.rotR ? theta : 0.0;
@@ -695,25 +695,22 @@ __global__ __launch_bounds__(64) void k_rebuild(DevMesh M, MortarTables MT, doub
       d = 0.0;
       mm = (mm + 1) % M.K;
     }
-    so[0] = 0.0;     ss[0] = 1.0 - d;   // L face, first mortar
-    so[1] = 1.0 - d; ss[1] = d;         // L face, second mortar
-    so[2] = d;       ss[2] = 1.0 - d;   // R face, first mortar
-    so[3] = 0.0;     ss[3] = d;         // R face, second mortar
-    ms->m = int(mm);
-    ms->delta = d;
-    ms->thL = thL;
-    ms->thR = thR;
-    for (int k = 0; k < 4; ++k) {
-      ms->o[k] = so[k];
-      ms->s[k] = ss[k];
-    }
+    ms.o[0] = 0.0;     ms.s[0] = 1.0 - d;   // L face, first mortar
+    ms.o[1] = 1.0 - d; ms.s[1] = d;         // L face, second mortar
+    ms.o[2] = d;       ms.s[2] = 1.0 - d;   // R face, first mortar
+    ms.o[3] = 0.0;     ms.s[3] = d;         // R face, second mortar
+    ms.m = int(mm);
+    ms.delta = d;
+    ms.thL = thL;
+    ms.thR = thR;
+    ms.valid = 1;
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < 4 * N * N; idx += blockDim.x) {
     const int k = idx / (N * N), i = (idx / N) % N, j = idx % N;
     double acc = 0.0;
     for (int q = 0; q < N; ++q)
-      acc += MT.wq[q] * MT.hq[q][i] * lagrange_d(MT, N, j, so[k] + ss[k] * MT.zq[q]);
+      acc += MT.wq[q] * MT.hq[q][i] * lagrange_d(MT, N, j, ms.o[k] + ms.s[k] * MT.zq[q]);
     A[k][i][j] = acc;
   }
   __syncthreads();
@@ -724,10 +721,28 @@ __global__ __launch_bounds__(64) void k_rebuild(DevMesh M, MortarTables MT, doub
       f += MT.Minv[i][l] * A[k][l][j];
       bk += MT.Minv[i][l] * A[k][j][l];
     }
-    ms->Pf[k][i][j] = f;
-    ms->Pb[k][i][j] = ss[k] * bk;
+    ms.Pf[k][i][j] = f;
+    ms.Pb[k][i][j] = ms.s[k] * bk;
   }
-  if (threadIdx.x == 0) ms->valid = 1;
+  __syncthreads();
+}
+
+// Copy of a mortar state from LDS to device memory by the workgroup.
+__device__ __forceinline__ void store_mortar(const MortarState &src, MortarState *dst) {
+  static_assert(sizeof(MortarState) % 8 == 0, "mortar state is copied as 8-byte words");
+  const uint64_t *a = reinterpret_cast<const uint64_t *>(&src);
+  uint64_t *b = reinterpret_cast<uint64_t *>(dst);
+  for (int i = threadIdx.x; i < int(sizeof(MortarState) / 8); i += blockDim.x) b[i] = a[i];
+}
+
+// Mortar rebuild on its own (one workgroup), for the residual entry point.
+template <int N>
+__global__ __launch_bounds__(64) void k_rebuild(DevMesh M, MortarTables MT, double theta,
+                                                MortarState *__restrict__ ms) {
+  __shared__ MortarState S;
+  __shared__ double A[4][N][N];
+  build_mortar<N>(M, MT, theta, S, A);
+  store_mortar(S, ms);
 }
 
 // C values per point of ring slot `slot` in the face's canonical
@@ -745,188 +760,198 @@ __device__ __forceinline__ void load_canon(const DevMesh &M, const float *__rest
   }
 }
 
-// The same from a per-slot record array [slot][point][4].
-template <int N>
-__device__ __forceinline__ void load_slot(const DevMesh &M, const float *__restrict__ rec, int slot,
-                                          double q[4][N]) {
-  const int flip = M.ring_flip[slot];
-#pragma unroll
-  for (int a = 0; a < N; ++a) {
-    const int pa = flip ? N - 1 - a : a;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) q[v][a] = double(rec[(long(slot) * N + pa) * 4 + v]);
-  }
-}
+// Sliding interface, inviscid: N lanes per interface face (L faces 0..K-1,
+// R faces K..2K-1), lane a for point a.  Each workgroup first rebuilds the
+// placement and projections for the rotor angle (block 0 also stores them
+// for the viscous mortar).  For each of its face's two mortars a lane
+// projects both sides' traces to mortar point a (eq. prjQ2), takes the
+// Rusanov flux with the exact radial normal there, scaled to flux per unit
+// face parameter (R_s Delta), and shares it through LDS; then it projects
+// the mortar fluxes back to its own face point (eq. prjF2).  Output: outward
+// common flux in the element's face parameter order, mflux[slot][point][var].
+// With VISC also the common solution on the face for the gradient pass: the
+// mean of the two sides' projections on each mortar, projected back
+// (Sec. 3.2), mqc[slot][point][var].
+constexpr int MORTAR_BLOCK = 256;
 
-// Canonical-order face data -> record of `slot` in the element's order.
-template <int N>
-__device__ __forceinline__ void store_slot(const DevMesh &M, float *__restrict__ rec, int slot,
-                                           const double q[4][N], double sign) {
-  const int flip = M.ring_flip[slot];
-#pragma unroll
-  for (int a = 0; a < N; ++a) {
-    const int pa = flip ? N - 1 - a : a;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) rec[(long(slot) * N + pa) * 4 + v] = float(sign * q[v][a]);
-  }
-}
-
-// y = P x for each variable (P one of the mortar projections).
-template <int N>
-__device__ __forceinline__ void project(const double (*P)[NMAX], const double x[4][N],
-                                        double y[4][N]) {
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-#pragma unroll
-    for (int a = 0; a < N; ++a) {
-      double s = 0.0;
-#pragma unroll
-      for (int b = 0; b < N; ++b) s += P[a][b] * x[v][b];
-      y[v][a] = s;
-    }
-}
-
-// One lane per interface face (L faces 0..K-1, R faces K..2K-1).  Each lane
-// forms its face's two mortars: projects both sides' traces onto the mortar
-// (eq. prjQ2), takes the Rusanov flux with the exact radial normal, scales
-// it to flux per unit face parameter (R_s Delta), and projects back to its
-// own face (eq. prjF2).  Output: outward common flux in the element's face
-// parameter order, mflux[slot][point][var].  With VISC also the common
-// solution of its face for the gradient pass: the mean of the two sides'
-// projections on each mortar, projected back (Sec. 3.2), mqc[slot][point][var].
 template <int N, bool VISC>
-__global__ __launch_bounds__(64) void k_mortar(DevMesh M, OpTables T,
-                                               const MortarState *__restrict__ ms,
-                                               const float *__restrict__ tr,
-                                               float *__restrict__ mflux, float *__restrict__ mqc) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(MORTAR_BLOCK) void k_mortar(DevMesh M, OpTables T, MortarTables MT,
+                                                         double theta, MortarState *ms_out,
+                                                         const float *__restrict__ tr,
+                                                         float *__restrict__ mflux,
+                                                         float *__restrict__ mqc) {
+  constexpr int FPB = MORTAR_BLOCK / N;   // faces per workgroup
+  __shared__ MortarState S;
+  __shared__ double A[4][N][N];
+  __shared__ double FM[FPB][2][N][4];     // mortar fluxes at the mortar points
+  __shared__ double QM[VISC ? FPB : 1][2][N][4];
+  build_mortar<N>(M, MT, theta, S, A);
+  if (blockIdx.x == 0) store_mortar(S, ms_out);
   const int K = M.K;
-  if (t >= 2 * K) return;
+  const int fl = threadIdx.x / N, a = threadIdx.x % N;
+  const int t = blockIdx.x * FPB + fl;
+  const bool act = fl < FPB && t < 2 * K;
   const bool right = t >= K;
   const int j = right ? t - K : t;
-  const int m = ms->m;
-  const double sc = M.Rs * M.dphi;
-  double acc[4][N], accq[4][N];
+  const int m = S.m;
+  if (act) {
+    const double sc = M.Rs * M.dphi;
 #pragma unroll
-  for (int v = 0; v < 4; ++v)
+    for (int k = 0; k < 2; ++k) {
+      const int jl = right ? ((j - m - k) % K + K) % K : j;
+      const int jr = right ? j : (j + m + k) % K;
+      double tl[4][N], trr[4][N];
+      load_canon<N, 4>(M, tr, jl, tl);
+      load_canon<N, 4>(M, tr, K + jr, trr);
+      double l4[4], r4[4], f4v[4];
 #pragma unroll
-    for (int a = 0; a < N; ++a) acc[v][a] = accq[v][a] = 0.0;
-
+      for (int v = 0; v < 4; ++v) {
+        double sl = 0.0, sr = 0.0;
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const int jl = right ? ((j - m - k) % K + K) % K : j;
-    const int jr = right ? j : (j + m + k) % K;
-    double tl[4][N], trr[4][N], ql[4][N], qr[4][N];
-    load_canon<N, 4>(M, tr, jl, tl);
-    load_canon<N, 4>(M, tr, K + jr, trr);
-    project<N>(ms->Pf[k], tl, ql);
-    project<N>(ms->Pf[2 + k], trr, qr);
-    double fm[4][N];
-#pragma unroll
-    for (int a = 0; a < N; ++a) {
-      const double phi = M.phi0L + ms->thL + M.dphi * (jl + ms->o[k] + ms->s[k] * T.X[a]);
+        for (int bb = 0; bb < N; ++bb) {
+          sl += S.Pf[k][a][bb] * tl[v][bb];
+          sr += S.Pf[2 + k][a][bb] * trr[v][bb];
+        }
+        l4[v] = sl;
+        r4[v] = sr;
+      }
+      const double phi = M.phi0L + S.thL + M.dphi * (jl + S.o[k] + S.s[k] * T.X[a]);
       double sn, cs;
       sincos(phi, &sn, &cs);
-      double l4[4] = {ql[0][a], ql[1][a], ql[2][a], ql[3][a]};
-      double r4[4] = {qr[0][a], qr[1][a], qr[2][a], qr[3][a]};
-      double f4v[4];
       rusanov_d(l4, r4, cs * sc, sn * sc, double(M.gamma), f4v);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) fm[v][a] = f4v[v];
-    }
-    const int pb = (right ? 2 : 0) + k;
-    double y[4][N];
-    project<N>(ms->Pb[pb], fm, y);
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-      for (int a = 0; a < N; ++a) acc[v][a] += y[v][a];
-    if (VISC) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int a = 0; a < N; ++a) ql[v][a] = 0.5 * (ql[v][a] + qr[v][a]);
-      project<N>(ms->Pb[pb], ql, y);
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int a = 0; a < N; ++a) accq[v][a] += y[v][a];
+      for (int v = 0; v < 4; ++v) {
+        FM[fl][k][a][v] = f4v[v];
+        if (VISC) QM[fl][k][a][v] = 0.5 * (l4[v] + r4[v]);
+      }
     }
   }
-  store_slot<N>(M, mflux, t, acc, right ? -1.0 : 1.0);
-  if (VISC) store_slot<N>(M, mqc, t, accq, 1.0);
+  __syncthreads();
+  if (!act) return;
+  double acc[4], accq[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) acc[v] = accq[v] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int pb = (right ? 2 : 0) + k;
+#pragma unroll
+    for (int bb = 0; bb < N; ++bb) {
+      const double w = S.Pb[pb][a][bb];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        acc[v] += w * FM[fl][k][bb][v];
+        if (VISC) accq[v] += w * QM[fl][k][bb][v];
+      }
+    }
+  }
+  const int pa = M.ring_flip[t] ? N - 1 - a : a;
+  const double sign = right ? -1.0 : 1.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    mflux[(long(t) * N + pa) * 4 + v] = float(sign * acc[v]);
+    if (VISC) mqc[(long(t) * N + pa) * 4 + v] = float(accq[v]);
+  }
 }
 
-// Viscous mortar (Sec. 3.2): each side's face viscous flux along the radial
-// (L -> R) normal per unit face parameter, from the face's common solution
-// (mqc) and its own gradient trace, is projected onto the mortars; the two
-// sides are averaged and the mean is projected back to the lane's face.
-// Output: outward viscous flux, mvflux[slot][point][var].
+// Canonical point a of ring slot `slot`: C values from a [face][E][point][C]
+// trace array, or 4 values from a per-slot record array [slot][point][4].
+template <int N, int C>
+__device__ __forceinline__ void load_canon_point(const DevMesh &M, const float *__restrict__ tr,
+                                                 int slot, int a, double q[C]) {
+  const long E = M.E;
+  const int e = M.ring_e[slot], f = M.ring_f[slot];
+  const int pa = M.ring_flip[slot] ? N - 1 - a : a;
+#pragma unroll
+  for (int v = 0; v < C; ++v) q[v] = double(tr[((long(f) * E + e) * N + pa) * C + v]);
+}
+
 template <int N>
-__global__ __launch_bounds__(64) void k_mortar_visc(DevMesh M, OpTables T,
-                                                    const MortarState *__restrict__ ms,
-                                                    const float *__restrict__ mqc,
-                                                    const float *__restrict__ gtr,
-                                                    float *__restrict__ mvflux) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void load_slot_point(const DevMesh &M, const float *__restrict__ rec,
+                                                int slot, int a, double q[4]) {
+  const int pa = M.ring_flip[slot] ? N - 1 - a : a;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) q[v] = double(rec[(long(slot) * N + pa) * 4 + v]);
+}
+
+// Viscous mortar (Sec. 3.2), N lanes per interface face as in k_mortar: each
+// side's face viscous flux along the radial (L -> R) normal per unit face
+// parameter, from the face's common solution (mqc) and its own gradient
+// trace, is projected onto the mortars; the two sides are averaged and the
+// mean is projected back to the lane's face point.  Output: outward viscous
+// flux, mvflux[slot][point][var].
+template <int N>
+__global__ __launch_bounds__(MORTAR_BLOCK) void k_mortar_visc(DevMesh M, OpTables T,
+                                                              const MortarState *__restrict__ ms,
+                                                              const float *__restrict__ mqc,
+                                                              const float *__restrict__ gtr,
+                                                              float *__restrict__ mvflux) {
+  constexpr int FPB = MORTAR_BLOCK / N;
+  __shared__ double VF[FPB][2][2][N][4];   // [mortar][side][face point][var]
+  __shared__ double VM[FPB][2][N][4];      // averaged flux at the mortar points
   const int K = M.K;
-  if (t >= 2 * K) return;
+  const int fl = threadIdx.x / N, a = threadIdx.x % N;
+  const int t = blockIdx.x * FPB + fl;
+  const bool act = fl < FPB && t < 2 * K;
   const bool right = t >= K;
   const int j = right ? t - K : t;
   const int m = ms->m;
   const double sc = M.Rs * M.dphi;
   const double gam = M.gamma, Rg = M.gas_R, mu = M.mu;
   const double kc = mu * gam * Rg / ((gam - 1.0) * double(M.prandtl));
-  double acc[4][N];
+  if (act) {
 #pragma unroll
-  for (int v = 0; v < 4; ++v)
+    for (int k = 0; k < 2; ++k) {
+      const int jl = right ? ((j - m - k) % K + K) % K : j;
+      const int jr = right ? j : (j + m + k) % K;
 #pragma unroll
-    for (int a = 0; a < N; ++a) acc[v][a] = 0.0;
-
-  // viscous flux of ring slot s (face jj of its side), canonical order
-  auto face_flux = [&](int s, double phi0, double th, int jj, double fv[4][N]) {
-    double qc[4][N], gg[8][N];
-    load_slot<N>(M, mqc, s, qc);
-    load_canon<N, 8>(M, gtr, s, gg);
+      for (int side = 0; side < 2; ++side) {
+        const int slot = side ? K + jr : jl;
+        const int jj = side ? jr : jl;
+        const double phi = (side ? M.phi0R + ms->thR : M.phi0L + ms->thL) + M.dphi * (jj + T.X[a]);
+        double sn, cs;
+        sincos(phi, &sn, &cs);
+        double q4[4], g8[8], f[4];
+        load_slot_point<N>(M, mqc, slot, a, q4);
+        load_canon_point<N, 8>(M, gtr, slot, a, g8);
+        visc_flux_n<double>(q4, g8, g8 + 4, cs * sc, sn * sc, gam, Rg, mu, kc, f);
 #pragma unroll
-    for (int a = 0; a < N; ++a) {
-      const double phi = phi0 + th + M.dphi * (jj + T.X[a]);
-      double sn, cs;
-      sincos(phi, &sn, &cs);
-      double q4[4], gx[4], gy[4], f[4];
+        for (int v = 0; v < 4; ++v) VF[fl][k][side][a][v] = f[v];
+      }
+    }
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        q4[v] = qc[v][a];
-        gx[v] = gg[v][a];
-        gy[v] = gg[4 + v][a];
-      }
-      visc_flux_n<double>(q4, gx, gy, cs * sc, sn * sc, gam, Rg, mu, kc, f);
+        double sl = 0.0, sr = 0.0;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) fv[v][a] = f[v];
+        for (int bb = 0; bb < N; ++bb) {
+          sl += ms->Pf[k][a][bb] * VF[fl][k][0][bb][v];
+          sr += ms->Pf[2 + k][a][bb] * VF[fl][k][1][bb][v];
+        }
+        VM[fl][k][a][v] = 0.5 * (sl + sr);
+      }
     }
-  };
-
+  }
+  __syncthreads();
+  if (!act) return;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
-    const int jl = right ? ((j - m - k) % K + K) % K : j;
-    const int jr = right ? j : (j + m + k) % K;
-    double fl[4][N], fr[4][N], pl[4][N], pr[4][N];
-    face_flux(jl, M.phi0L, ms->thL, jl, fl);
-    face_flux(K + jr, M.phi0R, ms->thR, jr, fr);
-    project<N>(ms->Pf[k], fl, pl);
-    project<N>(ms->Pf[2 + k], fr, pr);
+    const int pb = (right ? 2 : 0) + k;
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
+    for (int bb = 0; bb < N; ++bb) {
+      const double w = ms->Pb[pb][a][bb];
 #pragma unroll
-      for (int a = 0; a < N; ++a) pl[v][a] = 0.5 * (pl[v][a] + pr[v][a]);
-    double y[4][N];
-    project<N>(ms->Pb[(right ? 2 : 0) + k], pl, y);
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-      for (int a = 0; a < N; ++a) acc[v][a] += y[v][a];
+      for (int v = 0; v < 4; ++v) acc[v] += w * VM[fl][k][bb][v];
+    }
   }
-  store_slot<N>(M, mvflux, t, acc, right ? -1.0 : 1.0);
+  const int pa = M.ring_flip[t] ? N - 1 - a : a;
+  const double sign = right ? -1.0 : 1.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) mvflux[(long(t) * N + pa) * 4 + v] = float(sign * acc[v]);
 }
 
 // ---------------------------------------------------------------------------
@@ -959,24 +984,28 @@ hipError_t launch_rebuild(const DevMesh &M, const MortarTables &MT, double theta
   return hipGetLastError();
 }
 
-hipError_t launch_mortar(const DevMesh &M, const OpTables &T, const MortarState *ms,
-                         const float *tr, float *mflux, float *mqc, hipStream_t s) {
-  const int grid = (2 * M.K + 63) / 64;
-  if (mqc) {
-    SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_mortar<NN, true>), dim3(grid), dim3(64), 0, s, M, T,
-                                           ms, tr, mflux, mqc));
-  } else {
-    SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_mortar<NN, false>), dim3(grid), dim3(64), 0, s, M,
-                                           T, ms, tr, mflux, mqc));
-  }
+hipError_t launch_mortar(const DevMesh &M, const OpTables &T, const MortarTables &MT,
+                         double theta, MortarState *ms, const float *tr, float *mflux, float *mqc,
+                         hipStream_t s) {
+  SSD_DISPATCH_N(M.N, {
+    const int grid = (2 * M.K + MORTAR_BLOCK / NN - 1) / (MORTAR_BLOCK / NN);
+    if (mqc)
+      hipLaunchKernelGGL((k_mortar<NN, true>), dim3(grid), dim3(MORTAR_BLOCK), 0, s, M, T, MT,
+                         theta, ms, tr, mflux, mqc);
+    else
+      hipLaunchKernelGGL((k_mortar<NN, false>), dim3(grid), dim3(MORTAR_BLOCK), 0, s, M, T, MT,
+                         theta, ms, tr, mflux, mqc);
+  });
   return hipGetLastError();
 }
 
 hipError_t launch_mortar_visc(const DevMesh &M, const OpTables &T, const MortarState *ms,
                               const float *mqc, const float *gtr, float *mvflux, hipStream_t s) {
-  const int grid = (2 * M.K + 63) / 64;
-  SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_mortar_visc<NN>, dim3(grid), dim3(64), 0, s, M, T, ms,
-                                         mqc, gtr, mvflux));
+  SSD_DISPATCH_N(M.N, {
+    const int grid = (2 * M.K + MORTAR_BLOCK / NN - 1) / (MORTAR_BLOCK / NN);
+    hipLaunchKernelGGL(k_mortar_visc<NN>, dim3(grid), dim3(MORTAR_BLOCK), 0, s, M, T, ms, mqc,
+                       gtr, mvflux);
+  });
   return hipGetLastError();
 }
 

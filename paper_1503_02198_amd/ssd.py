@@ -199,8 +199,18 @@ class Mesh:
     def check(self, stream=None):
         _check(lib().ssd_check(self._h, _stream_ptr(stream, self.device)))
 
-    def timing_enable(self, on=True):
-        _check(lib().ssd_timing_enable(self._h, int(bool(on))))
+    def timing_enable(self, on=True, kernels=None):
+        """Bracket launches with HIP events: every kernel class, or only
+        `kernels` (names from KERNELS), or none (on=False)."""
+        if not on:
+            mask = 0
+        elif kernels is None:
+            mask = (1 << len(KERNELS)) - 1
+        else:
+            mask = 0
+            for k in kernels:
+                mask |= 1 << KERNELS[k]
+        _check(lib().ssd_timing_enable(self._h, mask))
 
     def timing_reset(self):
         _check(lib().ssd_timing_reset(self._h))
