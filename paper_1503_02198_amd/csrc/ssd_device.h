@@ -194,13 +194,75 @@ struct FPGeo {
   float nx, ny, vgn, ug, vg;
 };
 
-// xi-direction flux point (Xf_k, X_j): n = (y_eta, -x_eta) in the current frame.
-template <int N>
-__device__ __forceinline__ FPGeo metric_xi(const ElemGeo &g, const DevMesh &M, const OpTables &T,
-                                           int k, int j) {
+// Metric data of a bilinear cell along one line of flux points, as
+// polynomials in the line parameter t: the scaled normal is linear in t, the
+// position (for the grid velocity) linear, and u_g . n quadratic.  Built
+// once per line, then two fused multiply-adds per quantity and point.
+struct LineGeo {
+  float n0x, n1x, n0y, n1y;   // n(t) = n0 + t n1
+  float p0x, p1x, p0y, p1y;   // position x(t) = p0 + t p1 (current frame)
+  float v0, v1, v2;           // u_g . n = v0 + t (v1 + t v2)
+  float w;                    // omega of the zone (0: fixed)
+};
+
+// xi-direction line at eta: n = (y_eta, -x_eta), x_eta(xi) = C + xi (D - C),
+// u_g . n = -w (x . x_eta + y . y_eta).
+__device__ __forceinline__ LineGeo line_xi(const ElemGeo &g, float eta) {
+  LineGeo L;
+  const float ex0 = g.Cx, ex1 = g.Dx - g.Cx, ey0 = g.Cy, ey1 = g.Dy - g.Cy;
+  L.n0x = ey0;
+  L.n1x = ey1;
+  L.n0y = -ex0;
+  L.n1y = -ex1;
+  L.p0x = g.p0x + eta * g.Cx;
+  L.p1x = g.Ax + eta * (g.Bx - g.Ax);
+  L.p0y = g.p0y + eta * g.Cy;
+  L.p1y = g.Ay + eta * (g.By - g.Ay);
+  L.w = g.w;
+  L.v0 = -g.w * (L.p0x * ex0 + L.p0y * ey0);
+  L.v1 = -g.w * (L.p0x * ex1 + L.p1x * ex0 + L.p0y * ey1 + L.p1y * ey0);
+  L.v2 = -g.w * (L.p1x * ex1 + L.p1y * ey1);
+  return L;
+}
+
+// eta-direction line at xi: n = (-y_xi, x_xi), x_xi(eta) = A + eta (B - A),
+// u_g . n = w (x . x_xi + y . y_xi).
+__device__ __forceinline__ LineGeo line_eta(const ElemGeo &g, float xi) {
+  LineGeo L;
+  const float ex0 = g.Ax, ex1 = g.Bx - g.Ax, ey0 = g.Ay, ey1 = g.By - g.Ay;
+  L.n0x = -ey0;
+  L.n1x = -ey1;
+  L.n0y = ex0;
+  L.n1y = ex1;
+  L.p0x = g.p0x + xi * g.Ax;
+  L.p1x = g.Cx + xi * (g.Bx - g.Ax);
+  L.p0y = g.p0y + xi * g.Ay;
+  L.p1y = g.Cy + xi * (g.By - g.Ay);
+  L.w = g.w;
+  L.v0 = g.w * (L.p0x * ex0 + L.p0y * ey0);
+  L.v1 = g.w * (L.p0x * ex1 + L.p1x * ex0 + L.p0y * ey1 + L.p1y * ey0);
+  L.v2 = g.w * (L.p1x * ex1 + L.p1y * ey1);
+  return L;
+}
+
+__device__ __forceinline__ FPGeo line_at(const LineGeo &L, float t) {
   FPGeo r;
-  r.ug = r.vg = r.vgn = 0.0f;
+  r.nx = L.n0x + t * L.n1x;
+  r.ny = L.n0y + t * L.n1y;
+  r.vgn = L.v0 + t * (L.v1 + t * L.v2);
+  r.ug = -L.w * (L.p0y + t * L.p1y);
+  r.vg = L.w * (L.p0x + t * L.p1x);
+  return r;
+}
+
+// xi-direction flux point (Xf_k, X_j): n = (y_eta, -x_eta) in the current
+// frame; L = line_xi(g, X_j) for bilinear cells.
+template <int N>
+__device__ __forceinline__ FPGeo metric_xi(const ElemGeo &g, const LineGeo &L, const DevMesh &M,
+                                           const OpTables &T, int k, int j) {
   if (g.cubic) {
+    FPGeo r;
+    r.ug = r.vg = r.vgn = 0.0f;
     const double xe = M.cmet[cubic_xi_index(N, M.C, 0, j, k, g.c)];
     const double ye = M.cmet[cubic_xi_index(N, M.C, 1, j, k, g.c)];
     r.nx = float(g.st * xe + g.ct * ye);
@@ -214,27 +276,17 @@ __device__ __forceinline__ FPGeo metric_xi(const ElemGeo &g, const DevMesh &M, c
     }
     return r;
   }
-  const float xi = float(T.Xf[k]), eta = float(T.X[j]);
-  const float xe = g.Cx + xi * (g.Dx - g.Cx), ye = g.Cy + xi * (g.Dy - g.Cy);
-  r.nx = ye;
-  r.ny = -xe;
-  if (g.w != 0.0f) {
-    const float px = g.p0x + xi * g.Ax + eta * g.Cx + xi * eta * (g.Bx - g.Ax);
-    const float py = g.p0y + xi * g.Ay + eta * g.Cy + xi * eta * (g.By - g.Ay);
-    r.vgn = -g.w * (px * xe + py * ye);
-    r.ug = -g.w * py;
-    r.vg = g.w * px;
-  }
-  return r;
+  return line_at(L, float(T.Xf[k]));
 }
 
-// eta-direction flux point (X_i, Xf_k): n = (-y_xi, x_xi) in the current frame.
+// eta-direction flux point (X_i, Xf_k): n = (-y_xi, x_xi) in the current
+// frame; L = line_eta(g, X_i) for bilinear cells.
 template <int N>
-__device__ __forceinline__ FPGeo metric_eta(const ElemGeo &g, const DevMesh &M, const OpTables &T,
-                                            int k, int i) {
-  FPGeo r;
-  r.ug = r.vg = r.vgn = 0.0f;
+__device__ __forceinline__ FPGeo metric_eta(const ElemGeo &g, const LineGeo &L, const DevMesh &M,
+                                            const OpTables &T, int k, int i) {
   if (g.cubic) {
+    FPGeo r;
+    r.ug = r.vg = r.vgn = 0.0f;
     const double xx = M.cmet[cubic_eta_index(N, M.C, 0, k, i, g.c)];
     const double yx = M.cmet[cubic_eta_index(N, M.C, 1, k, i, g.c)];
     r.nx = float(-(g.st * xx + g.ct * yx));
@@ -248,18 +300,7 @@ __device__ __forceinline__ FPGeo metric_eta(const ElemGeo &g, const DevMesh &M, 
     }
     return r;
   }
-  const float xi = float(T.X[i]), eta = float(T.Xf[k]);
-  const float xx = g.Ax + eta * (g.Bx - g.Ax), yx = g.Ay + eta * (g.By - g.Ay);
-  r.nx = -yx;
-  r.ny = xx;
-  if (g.w != 0.0f) {
-    const float px = g.p0x + xi * g.Ax + eta * g.Cx + xi * eta * (g.Bx - g.Ax);
-    const float py = g.p0y + xi * g.Ay + eta * g.Cy + xi * eta * (g.By - g.Ay);
-    r.vgn = g.w * (px * xx + py * yx);
-    r.ug = -g.w * py;
-    r.vg = g.w * px;
-  }
-  return r;
+  return line_at(L, float(T.Xf[k]));
 }
 
 // Metric derivatives x_xi, y_xi, x_eta, y_eta at the solution point
@@ -375,18 +416,16 @@ __device__ __forceinline__ void neighbor_state(const OpTables &T, const float *S
 }
 
 // Common inviscid normal flux at one element-boundary flux point along the
-// outward normal of `G`, given the face data x (see prefetch_face).  For a
-// conforming face the neighbour's state is returned in qx.  The Rusanov flux
-// and the wall flux are formed for every lane and the face kind selects
-// between them (values of the unselected forms are discarded), so a wave
-// with mixed face kinds runs one path.
-template <int N>
-__device__ __forceinline__ void common_flux(const DevMesh &M, const OpTables &T, const float *Sf,
-                                            uint32_t fw, int p, const float qo[4],
-                                            const float x[4], const FPGeo &G, float fs[4],
-                                            float qx[4]) {
+// outward normal of `G`, given the state across the face qx (the
+// neighbour's on conforming faces, the far-field state on far-field faces)
+// and the face data x (see prefetch_face).  The Rusanov flux and the wall
+// flux are formed for every lane and the face kind selects between them
+// (values of the unselected forms are discarded), so a wave with mixed face
+// kinds runs one path.
+__device__ __forceinline__ void common_flux(const DevMesh &M, uint32_t fw, const float qo[4],
+                                            const float qx[4], const float x[4], const FPGeo &G,
+                                            float fs[4]) {
   const int kind = face_kind_of(fw);
-  neighbor_state<N>(T, Sf, fw, p, x, qx);
   float fr[4];
   rusanov(qo, qx, G.nx, G.ny, G.vgn, M.gamma, fr);
   // walls: no flux relative to the moving wall; pressure from the interior

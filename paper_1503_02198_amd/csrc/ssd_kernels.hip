@@ -201,6 +201,7 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
 
   // ---- row phase
   {
+    const LineGeo Lr = line_xi(g, float(T.X[w]));   // bilinear-cell metrics along row w
     float res[4][N], t0[4], tN[4];
     float gr[8][N];   // gradient on row w
     if (VISC) {
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
         for (int i = 0; i < N; ++i) acc += T.I[k][i] * qr[v][i];
         qf[v] = acc;
       }
-      const FPGeo G = metric_xi<N>(g, M, T, k, w);
+      const FPGeo G = metric_xi<N>(g, Lr, M, T, k, w);
       flux_n(qf, G.nx, G.ny, G.vgn, gm1, f);
       if (VISC) {
         float gf[8], fv[4];
@@ -263,12 +264,13 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
       const int k = side ? N : 0;
       const float sg = side ? 1.0f : -1.0f;   // outward normal of face xi = 1 / xi = 0
       const uint32_t fw = side ? fw1 : fw3;
-      FPGeo G = metric_xi<N>(g, M, T, k, w);
+      FPGeo G = metric_xi<N>(g, Lr, M, T, k, w);
       G.nx *= sg;
       G.ny *= sg;
       G.vgn *= sg;
       float f[4], qx[4];
-      common_flux<N>(M, T, Sf, fw, w, side ? tN : t0, side ? x1 : x3, G, f, qx);
+      neighbor_state<N>(T, Sf, fw, w, side ? x1 : x3, qx);
+      common_flux(M, fw, side ? tN : t0, qx, side ? x1 : x3, G, f);
       if (VISC) {
         float gf[8], fv[4];
 #pragma unroll
@@ -297,6 +299,7 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
   // ---- column phase
   float qc[4][N], rc[4][N];
   {
+    const LineGeo Lc = line_eta(g, float(T.X[w]));  // bilinear-cell metrics along column w
     float gc[8][N];   // gradient on column w
     if (VISC) {
 #pragma unroll
@@ -321,7 +324,7 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
         for (int j = 0; j < N; ++j) acc += T.I[k][j] * qc[v][j];
         qf[v] = acc;
       }
-      FPGeo G = metric_eta<N>(g, M, T, k, w);
+      FPGeo G = metric_eta<N>(g, Lc, M, T, k, w);
       float gf[8];
       if (VISC) {
 #pragma unroll
@@ -339,7 +342,8 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
         G.ny *= sg;
         G.vgn *= sg;
         float qx[4];
-        common_flux<N>(M, T, Sf, fw, w, qf, k == 0 ? x0 : x2, G, f, qx);
+        neighbor_state<N>(T, Sf, fw, w, k == 0 ? x0 : x2, qx);
+        common_flux(M, fw, qf, qx, k == 0 ? x0 : x2, G, f);
         if (VISC) {
           float fv[4];
           common_visc<N>(M, P, rgtr, rmv, fw, w, qf, qx, k == 0 ? x0 : x2, gf, G, fv);
@@ -364,18 +368,15 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
     }
   }
   // dQ/dt = dQ~/dt / |J| on column w
+  float ij[N];
 #pragma unroll
-  for (int j = 0; j < N; ++j) {
-    const float ij = inv_jacobian<N>(g, M, T, j, w);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) rc[v][j] *= ij;
-  }
+  for (int j = 0; j < N; ++j) ij[j] = inv_jacobian<N>(g, M, T, j, w);
   if (!RK) {
     if (valid) {
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int j = 0; j < N; ++j) bstore(rc[v][j], rout, ve, ((v * N + j) * N + w) * E4);
+        for (int j = 0; j < N; ++j) bstore(rc[v][j] * ij[j], rout, ve, ((v * N + j) * N + w) * E4);
     }
     return;
   }
@@ -386,10 +387,11 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
   bool bad = false;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
+    const float dtj = dt * ij[j];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const float x = with_qn ? qo[v][j] + b * ((qc[v][j] - qo[v][j]) + dt * rc[v][j])
-                              : qc[v][j] + b * (dt * rc[v][j]);
+      const float x = with_qn ? qo[v][j] + b * ((qc[v][j] - qo[v][j]) + dtj * rc[v][j])
+                              : qc[v][j] + b * (dtj * rc[v][j]);
       qc[v][j] = x;
       SR[v][j][w][l] = x;
     }
@@ -509,7 +511,8 @@ __global__ __launch_bounds__(64 * N) void k_grad(DevMesh M, OpTables T, Rotation
   // common solution at point p of a face with outward normal sign sg
   auto face_common = [&](uint32_t fw, bool xi_face, int k, float sg, const float qo[4],
                          const float x[4], float qcm[4]) {
-    FPGeo G = xi_face ? metric_xi<N>(g, M, T, k, w) : metric_eta<N>(g, M, T, k, w);
+    FPGeo G = xi_face ? metric_xi<N>(g, line_xi(g, float(T.X[w])), M, T, k, w)
+                      : metric_eta<N>(g, line_eta(g, float(T.X[w])), M, T, k, w);
     G.nx *= sg;
     G.ny *= sg;
     G.vgn *= sg;
