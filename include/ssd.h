@@ -59,8 +59,14 @@ enum {
  * 12-node cubic cells along curved boundaries). */
 enum { SSD_GEOM_LINEAR = 0, SSD_GEOM_CUBIC = 1 };
 
-/* Time integrators. SSP-RK3 in Shu-Osher form, stage times t, t+dt, t+dt/2. */
-typedef enum { SSD_RK3_SSP = 0 } ssd_rk;
+/* Explicit SSP Runge-Kutta time integrators (Sec. 3: an explicit SSP
+ * scheme; Sec. 4: the five-stage fourth-order one for every test case).
+ *  SSD_RK3_SSP    three-stage third order, Shu-Osher form, stage times
+ *                 t, t + dt, t + dt/2; work: 2 state_len floats.
+ *  SSD_RK54_SSP   five-stage fourth order (SSPRK(5,4), the published
+ *                 coefficients of Spiteri and Ruuth), each stage at the
+ *                 time of its stage value; work: 3 state_len floats. */
+typedef enum { SSD_RK3_SSP = 0, SSD_RK54_SSP = 1 } ssd_rk;
 
 /*
  * Mesh and case description.  All arrays are host memory, read during
@@ -121,7 +127,7 @@ typedef struct {
   int32_t viscous;    /* 1 when mu > 0                                  */
   int32_t device;     /* HIP device the handle lives on                 */
   int64_t state_len;  /* floats in one state array: 4 N^2 n_elem        */
-  int64_t work_len;   /* floats ssd_rk_step needs in `work`: 2 state_len */
+  int64_t work_len;   /* floats ssd_rk_step needs in `work` for any scheme: 3 state_len */
 } ssd_info;
 
 /*
@@ -169,18 +175,19 @@ ssd_status ssd_mortar_rebuild(ssd_mesh *m, void *stream);
 ssd_status ssd_residual(ssd_mesh *m, const float *q, float *r, void *stream);
 
 /*
- * One SSP-RK3 step from t to t + dt in place on q (device, state_len
- * floats), using `work` (device, work_len floats) as scratch.  Before each
- * stage it sets the angle theta0 + omega t_stage and rebuilds the mortars
- * (Sec. 3.2: the connectivity is updated at every Runge-Kutta stage).
- * SSD_ERR_INVALID_ARG for dt <= 0 or a non-finite t; work must not
- * overlap q.
+ * One step of `scheme` (ssd_rk) from t to t + dt in place on q (device,
+ * state_len floats), using `work` (device, at least the floats the scheme
+ * needs, work_len covers all) as scratch.  Before each stage it sets the
+ * angle theta0 + omega t_stage and rebuilds the mortars (Sec. 3.2: the
+ * connectivity is updated at every Runge-Kutta stage).
+ * SSD_ERR_INVALID_ARG for dt <= 0, a non-finite t or an unknown scheme;
+ * work must not overlap q.
  */
 ssd_status ssd_rk_step(ssd_mesh *m, float *q, float *work, double t, double dt, ssd_rk scheme,
                        void *stream);
 
 /*
- * nsteps >= 1 consecutive SSP-RK3 steps from t (step n starts at t + n dt),
+ * nsteps >= 1 consecutive steps of `scheme` from t (step n starts at t + n dt),
  * with the same effect as nsteps calls of ssd_rk_step.  The face traces the
  * last stage of a step leaves behind serve the first stage of the next one,
  * so the separate trace pass runs once per call instead of once per step.

@@ -29,6 +29,32 @@ from . import physics as ph
 FACE_EXTERNAL = 100   # face of a sub-mesh whose neighbour lies outside it
 
 
+# SSPRK54 (five stages, fourth order, strong-stability preserving), Shu-Osher
+# form: U1 = U + a[0][2] dt L(U); U_k = a[k-1][0] U + a[k-1][1] U_{k-1} +
+# a[k-1][2] dt L(U_{k-1}) for k = 2, 3, 4; U^{n+1} = c[0] U2 + c[1] U3 +
+# c[2] dt L(U3) + c[3] U4 + c[4] dt L(U4).  The published SSPRK(5,4)
+# coefficients of Spiteri and Ruuth; tests check fourth order on a
+# nonlinear, time-dependent ODE.
+SSPRK54 = {
+    "a": [[0.0, 1.0, 0.391752226571890],
+          [0.444370493651235, 0.555629506348765, 0.368410593050371],
+          [0.620101851488403, 0.379898148511597, 0.251891774271694],
+          [0.178079954393132, 0.821920045606868, 0.544974750228521]],
+    "c": [0.517231671970585, 0.096059710526147, 0.063692468666290,
+          0.386708617503269, 0.226007483236906],
+}
+
+
+def ssprk54_stage_times():
+    """Times (in units of dt after t) at which SSPRK54 evaluates L: the
+    time of each stage value, following the same combinations as U."""
+    a = SSPRK54["a"]
+    tau = [0.0, a[0][2]]
+    for k in (1, 2, 3):
+        tau.append(a[k][1] * tau[-1] + a[k][2])
+    return tau
+
+
 def _wrap_pi(a):
     return (a + np.pi) % (2 * np.pi) - np.pi
 
@@ -386,11 +412,30 @@ class SSD:
         Q2 = 0.75 * Q + 0.25 * (Q1 + dt * self.residual(Q1, self.theta(t + dt), w))
         return Q / 3.0 + 2.0 / 3.0 * (Q2 + dt * self.residual(Q2, self.theta(t + 0.5 * dt), w))
 
-    def run(self, Q, t0, dt, nsteps):
+    def ssprk54_step(self, Q, t, dt):
+        """Five-stage fourth-order SSP Runge-Kutta step (the explicit SSP
+        scheme the paper uses for all its tests, Sec. 4), in Shu-Osher form
+        with the coefficients of SSPRK54; every stage evaluates the
+        residual (and rebuilds the mortars) at its own stage time."""
+        a, c = SSPRK54["a"], SSPRK54["c"]
+        w = self.case["omega"]
+
+        def L(U, tau):
+            return dt * self.residual(U, self.theta(t + tau * dt), w)
+        tau = ssprk54_stage_times()
+        U1 = Q + a[0][2] * L(Q, 0.0)
+        U2 = a[1][0] * Q + a[1][1] * U1 + a[1][2] * L(U1, tau[1])
+        U3 = a[2][0] * Q + a[2][1] * U2 + a[2][2] * L(U2, tau[2])
+        L3 = L(U3, tau[3])
+        U4 = a[3][0] * Q + a[3][1] * U3 + a[3][2] * L3
+        return c[0] * U2 + c[1] * U3 + c[2] * L3 + c[3] * U4 + c[4] * L(U4, tau[4])
+
+    def run(self, Q, t0, dt, nsteps, scheme="rk3"):
+        step = {"rk3": self.ssprk3_step, "rk54": self.ssprk54_step}[scheme]
         Q = np.array(Q, dtype=float)
         t = t0
         for _ in range(nsteps):
-            Q = self.ssprk3_step(Q, t, dt)
+            Q = step(Q, t, dt)
             t += dt
         return Q
 

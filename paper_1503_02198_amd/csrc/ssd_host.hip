@@ -679,7 +679,7 @@ ssd_status check_handle(const ssd_mesh *m) {
 // viscous meshes the gradient pass and the viscous mortar; then the stage
 // kernel (rk: the fused SSP-RK stage writing out and the traces trout).
 ssd_status residual_pass(ssd_mesh *m, double th, double omega, const float *in, const float *qn,
-                         float *out, float *facein, float *trout, float b, float dt, bool rk,
+                         float *out, float *facein, float *trout, const RKCoef &C, bool rk,
                          hipStream_t st) {
   ViscIO *V = m->viscous ? &m->V : nullptr;
   // interface records of `in` live behind its traces in the same face buffer
@@ -703,7 +703,7 @@ ssd_status residual_pass(ssd_mesh *m, double th, double omega, const float *in, 
     }
   }
   LaunchTimer lt(m, SSD_KERNEL_STAGE, st);
-  SSD_HIP(launch_stage(m->D, m->T, rot, in, qn, out, facein, trout, V, b, dt, rk, st),
+  SSD_HIP(launch_stage(m->D, m->T, rot, in, qn, out, facein, trout, V, C, rk, st),
           rk ? "stage launch" : "residual launch");
   return SSD_OK;
 }
@@ -781,7 +781,7 @@ ssd_status ssd_query(const ssd_mesh *m, ssd_info *info) {
   info->viscous = m->viscous;
   info->device = m->device;
   info->state_len = 4L * m->N * m->N * m->E;
-  info->work_len = 2 * info->state_len;
+  info->work_len = 3 * info->state_len;   // enough for every ssd_rk scheme
   return SSD_OK;
 }
 
@@ -824,9 +824,20 @@ ssd_status ssd_residual(ssd_mesh *m, const float *q, float *r, void *stream) {
     LaunchTimer lt(m, SSD_KERNEL_TRACES, st);
     SSD_HIP(launch_traces(m->D, m->T, q, m->tr[0], st), "trace launch");
   }
-  return residual_pass(m, m->theta, m->omega, q, nullptr, r, m->tr[0], nullptr, 1.f, 0.f,
-                       false, st);
+  return residual_pass(m, m->theta, m->omega, q, nullptr, r, m->tr[0], nullptr,
+                       RKCoef{1.f, 1.f, 0.f, nullptr}, false, st);
 }
+
+// SSPRK54 (five stages, fourth order) in Shu-Osher form, the published
+// coefficients of Spiteri and Ruuth: stage 1 U1 = U + A[0][2] dt L(U);
+// stage k = 2..4 Uk = A[k-1][0] U + A[k-1][1] U(k-1) + A[k-1][2] dt L(U(k-1));
+// U^{n+1} = C5[0] U2 + C5[1] U3 + C5[2] dt L(U3) + C5[3] U4 + C5[4] dt L(U4).
+constexpr double RK54_A[4][3] = {{0.0, 1.0, 0.391752226571890},
+                                 {0.444370493651235, 0.555629506348765, 0.368410593050371},
+                                 {0.620101851488403, 0.379898148511597, 0.251891774271694},
+                                 {0.178079954393132, 0.821920045606868, 0.544974750228521}};
+constexpr double RK54_C[5] = {0.517231671970585, 0.096059710526147, 0.063692468666290,
+                              0.386708617503269, 0.226007483236906};
 
 ssd_status ssd_rk_steps(ssd_mesh *m, float *q, float *work, double t, double dt, int32_t nsteps,
                         ssd_rk scheme, void *stream) {
@@ -835,33 +846,63 @@ ssd_status ssd_rk_steps(ssd_mesh *m, float *q, float *work, double t, double dt,
   if (!std::isfinite(t) || !std::isfinite(dt) || !(dt > 0.0))
     return fail(SSD_ERR_INVALID_ARG, "need finite t and dt > 0");
   if (nsteps < 1) return fail(SSD_ERR_INVALID_ARG, "nsteps must be >= 1");
-  if (scheme != SSD_RK3_SSP) return fail(SSD_ERR_INVALID_ARG, "unknown Runge-Kutta scheme");
+  if (scheme != SSD_RK3_SSP && scheme != SSD_RK54_SSP)
+    return fail(SSD_ERR_INVALID_ARG, "unknown Runge-Kutta scheme");
   const long len = 4L * m->N * m->N * m->E;
-  if (overlap(q, len * sizeof(float), work, 2 * len * sizeof(float)))
+  const int nwork = scheme == SSD_RK3_SSP ? 2 : 3;
+  if (overlap(q, len * sizeof(float), work, nwork * len * sizeof(float)))
     return fail(SSD_ERR_INVALID_ARG, "q and work overlap");
   DeviceGuard guard(m->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  // Shu-Osher SSP-RK3: stage s gives (1 - b_s) Q^n + b_s (Q_s + dt R(Q_s, t + c_s dt))
-  const float B[3] = {1.0f, 0.25f, 2.0f / 3.0f};
-  const double Cs[3] = {0.0, 1.0, 0.5};
-  float *w1 = work, *w2 = work + len;
-  const float *in[3] = {q, w1, w2};
-  float *outp[3] = {w1, w2, q};
+  float *w1 = work, *w2 = work + len, *w3 = work + 2 * len;
   {
     LaunchTimer lt(m, SSD_KERNEL_TRACES, st);
     SSD_HIP(launch_traces(m->D, m->T, q, m->tr[0], st), "trace launch");
   }
-  int cur = 0;   // trace buffer holding the traces of the current stage input
+  int cur = 0;   // face data buffer holding the traces of the current stage input
+  // one stage: the residual of `in` at t + c dt, fused with the update
+  auto stage = [&](double tn, double c, const float *in, const float *qn, float *out, float beta,
+                   float gamma, const float *add) -> ssd_status {
+    const double th = m->theta0 + m->omega0 * (tn + c * dt);
+    // the mortar kernel rebuilds the projections for th itself
+    ssd_status e = residual_pass(m, th, m->omega0, in, qn, out, m->tr[cur], m->tr[cur ^ 1],
+                                 RKCoef{beta, gamma, float(dt), add}, true, st);
+    cur ^= 1;
+    return e;
+  };
   for (int n = 0; n < nsteps; ++n) {
     const double tn = t + n * dt;
-    for (int s = 0; s < 3; ++s) {
-      const double th = m->theta0 + m->omega0 * (tn + Cs[s] * dt);
-      // the mortar kernel rebuilds the projections for th itself
-      if (ssd_status e = residual_pass(m, th, m->omega0, in[s], s ? q : nullptr, outp[s],
-                                       m->tr[cur], m->tr[cur ^ 1], B[s], float(dt), true,
-                                       st))
+    if (scheme == SSD_RK3_SSP) {
+      // Shu-Osher SSP-RK3: stage k gives (1 - b_k) Q^n + b_k (Q_k + dt R(Q_k, t + c_k dt))
+      const float B[3] = {1.0f, 0.25f, 2.0f / 3.0f};
+      const double Cs[3] = {0.0, 1.0, 0.5};
+      const float *in[3] = {q, w1, w2};
+      float *outp[3] = {w1, w2, q};
+      for (int k = 0; k < 3; ++k)
+        if (ssd_status e = stage(tn, Cs[k], in[k], k ? q : nullptr, outp[k], B[k], B[k], nullptr))
+          return e;
+    } else {
+      // SSPRK54 with U1, U3 in w1, U2 then the last stage's increment in w2,
+      // U4 in w3; stage times follow the stage values
+      double tau[5] = {0.0, RK54_A[0][2], 0.0, 0.0, 0.0};
+      for (int k = 1; k < 4; ++k) tau[k + 1] = RK54_A[k][1] * tau[k] + RK54_A[k][2];
+      const float *in[4] = {q, w1, w2, w1};
+      float *outp[4] = {w1, w2, w1, w3};
+      for (int k = 0; k < 4; ++k)
+        if (ssd_status e = stage(tn, tau[k], in[k], k ? q : nullptr, outp[k], float(RK54_A[k][1]),
+                                 float(RK54_A[k][2]), nullptr))
+          return e;
+      // U^{n+1} = U + W + C5[3] (U4 - U) + C5[4] dt L(U4), where
+      // W = C5[0] (U2 - U) + C5[1] (U3 - U) + C5[2] dt L(U3) and dt L(U3) is
+      // recovered from stage 4: (U4 - U - A[3][1] (U3 - U)) / A[3][2]
+      const double g4 = RK54_A[3][2];
+      const double w2c = RK54_C[0];
+      const double w3c = RK54_C[1] - RK54_C[2] * RK54_A[3][1] / g4;
+      const double w4c = RK54_C[2] / g4;
+      SSD_HIP(launch_rk_combine(len, q, w2, w1, w3, float(w2c), float(w3c), float(w4c), w2, st),
+              "stage combination launch");
+      if (ssd_status e = stage(tn, tau[4], w3, q, q, float(RK54_C[3]), float(RK54_C[4]), w2))
         return e;
-      cur ^= 1;
     }
   }
   m->theta = m->theta0 + m->omega0 * (t + nsteps * dt);

@@ -148,12 +148,22 @@ hipError_t launch_grad(const DevMesh &M, const OpTables &T, Rotation rot, const 
                        const float *facein, float *G, float *gtr, hipStream_t s);
 hipError_t launch_mortar_visc(const DevMesh &M, const OpTables &T, const MortarState *ms,
                               const float *mqc, const float *gtr, float *mvflux, hipStream_t s);
+// Coefficients of one Runge-Kutta stage: out = qn + beta (q - qn) +
+// gamma dt dQ/dt [+ add] (qn null: qn = q).
+struct RKCoef {
+  float beta, gamma, dt;
+  const float *add;   // null: nothing added
+};
+
 // facein: face data buffer of q with its traces and mortar flux; trout:
 // the face data buffer the new state's traces go to (rk).  visc null:
-// inviscid residual.  rk: out = (1 - b) qn + b (q + dt dQ/dt) with qn null
-// standing for q.
+// inviscid residual.
 hipError_t launch_stage(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
                         const float *qn, float *out, const float *facein, float *trout,
-                        const ViscIO *visc, float b, float dt, bool rk, hipStream_t s);
+                        const ViscIO *visc, const RKCoef &C, bool rk, hipStream_t s);
+// W = w2 (u2 - un) + w3 (u3 - un) + w4 (u4 - un) over n floats.
+hipError_t launch_rk_combine(long n, const float *un, const float *u2, const float *u3,
+                             const float *u4, float w2, float w3, float w4, float *W,
+                             hipStream_t s);
 
 }  // namespace ssd

@@ -117,13 +117,16 @@ __device__ __forceinline__ void common_visc(const DevMesh &M, const ViscParams &
 }
 
 // ---------------------------------------------------------------------------
-// the element residual, optionally fused with an SSP-RK stage update
+// the element residual, optionally fused with an SSP Runge-Kutta stage
 //   rk = false:  out = dQ/dt
-//   rk = true :  out = (1 - b) qn + b (q + dt dQ/dt), exported face traces of
-//                out -> trout; qn = null stands for qn = q (first stage).
-//                Evaluated as qn + b ((q - qn) + dt dQ/dt): the rounding then
-//                scales with the stage increment, not with Q, and a steady
-//                state stays fixed instead of drifting by an ulp per stage
+//   rk = true :  out = qn + beta (q - qn) + gamma dt dQ/dt [+ add], the
+//                Shu-Osher stage (1 - beta) qn + beta q + gamma dt dQ/dt
+//                written around qn: the rounding then scales with the stage
+//                increment, not with Q, and a steady state stays fixed
+//                instead of drifting by an ulp per stage.  qn = null stands
+//                for qn = q (first stage).  ADD: plus a precomputed increment
+//                (the last SSPRK54 stage).  Exported face traces of out ->
+//                trout.
 //   visc:        adds the viscous fluxes, from the gradients of k_grad
 //
 // A block owns EB = 64 consecutive elements and has N waves; lane l of
@@ -142,11 +145,11 @@ __device__ __forceinline__ void common_visc(const DevMesh &M, const ViscParams &
 // LDS access of a wave to its own elements touches 64 distinct banks.
 // Global accesses of a wave are contiguous 256-byte rows.
 // ---------------------------------------------------------------------------
-template <int N, bool RK, bool VISC>
+template <int N, bool RK, bool VISC, bool ADD>
 __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotation R,
                                                   const float *q, const float *qn, float *out,
                                                   const float *facein, float *trout, ViscBufs V,
-                                                  float b, float dt) {
+                                                  RKCoef C) {
   __shared__ float S[4][N][N][EB];     // state of the block's elements
   __shared__ float SR[4][N][N][EB];    // xi part of the residual, then the new state
   __shared__ uint8_t XL[4][EB];        // exporting lanes per face
@@ -197,6 +200,14 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
     for (int v = 0; v < 4; ++v)
 #pragma unroll
       for (int j = 0; j < N; ++j) qo[v][j] = bload(rqn, ve, ((v * N + j) * N + w) * E4);
+  }
+  float qa[4][N];   // column w of the added increment (ADD)
+  if (RK && ADD) {
+    const rsrc_t radd = make_rsrc(C.add, sbytes);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int j = 0; j < N; ++j) qa[v][j] = bload(radd, ve, ((v * N + j) * N + w) * E4);
   }
 
   // ---- row phase
@@ -381,17 +392,18 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
     return;
   }
 
-  // ---- SSP-RK stage on column w: Q <- Qn + b ((Q - Qn) + dt R); the new
-  // column goes to SR (no other lane reads column w of SR after the column
-  // phase has started)
+  // ---- SSP-RK stage on column w: Q <- Qn + beta (Q - Qn) + gamma dt R
+  // [+ add]; the new column goes to SR (no other lane reads column w of SR
+  // after the column phase has started)
   bool bad = false;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
-    const float dtj = dt * ij[j];
+    const float gdt = C.gamma * C.dt * ij[j];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const float x = with_qn ? qo[v][j] + b * ((qc[v][j] - qo[v][j]) + dtj * rc[v][j])
-                              : qc[v][j] + b * (dtj * rc[v][j]);
+      float x = with_qn ? qo[v][j] + (C.beta * (qc[v][j] - qo[v][j]) + gdt * rc[v][j])
+                        : qc[v][j] + gdt * rc[v][j];
+      if (ADD) x += qa[v][j];
       qc[v][j] = x;
       SR[v][j][w][l] = x;
     }
@@ -1022,23 +1034,55 @@ hipError_t launch_grad(const DevMesh &M, const OpTables &T, Rotation rot, const 
 
 hipError_t launch_stage(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
                         const float *qn, float *out, const float *facein, float *trout,
-                        const ViscIO *visc, float b, float dt, bool rk, hipStream_t s) {
+                        const ViscIO *visc, const RKCoef &C, bool rk, hipStream_t s) {
   const int grid = (M.E + EB - 1) / EB;
   const ViscBufs V{visc ? visc->G : nullptr, visc ? visc->gtr : nullptr,
                    visc ? visc->mvflux : nullptr};
-#define SSD_STAGE(RKV, VV)                                                                        \
-  SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_stage<NN, RKV, VV>), dim3(grid), dim3(EB * NN), 0, s, \
-                                         M, T, rot, q, qn, out, facein, trout, V, b, dt))
+#define SSD_STAGE(RKV, VV, AV)                                                               \
+  SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_stage<NN, RKV, VV, AV>), dim3(grid), dim3(EB * NN), \
+                                         0, s, M, T, rot, q, qn, out, facein, trout, V, C))
+  const bool add = rk && C.add != nullptr;
   if (rk && visc) {
-    SSD_STAGE(true, true);
+    if (add) {
+      SSD_STAGE(true, true, true);
+    } else {
+      SSD_STAGE(true, true, false);
+    }
   } else if (rk) {
-    SSD_STAGE(true, false);
+    if (add) {
+      SSD_STAGE(true, false, true);
+    } else {
+      SSD_STAGE(true, false, false);
+    }
   } else if (visc) {
-    SSD_STAGE(false, true);
+    SSD_STAGE(false, true, false);
   } else {
-    SSD_STAGE(false, false);
+    SSD_STAGE(false, false, false);
   }
 #undef SSD_STAGE
+  return hipGetLastError();
+}
+
+// SSPRK54 increment of the last stage (see the host stage loop):
+// W = w2 (u2 - un) + w3 (u3 - un) + w4 (u4 - un), elementwise.
+__global__ __launch_bounds__(256) void k_rk_combine(long n, const float *__restrict__ un,
+                                                    const float *__restrict__ u2,
+                                                    const float *__restrict__ u3,
+                                                    const float *__restrict__ u4, float w2,
+                                                    float w3, float w4, float *__restrict__ W) {
+  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float b = un[i];
+  W[i] = w2 * (u2[i] - b) + w3 * (u3[i] - b) + w4 * (u4[i] - b);
+}
+
+hipError_t launch_rk_combine(long n, const float *un, const float *u2, const float *u3,
+                             const float *u4, float w2, float w3, float w4, float *W,
+                             hipStream_t s) {
+  const long grid = (n + 255) / 256;
+  if (grid > 0x7fffffffL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_rk_combine, dim3(unsigned(grid)), dim3(256), 0, s, n, un, u2, u3, u4, w2,
+                     w3, w4, W);
   return hipGetLastError();
 }
 

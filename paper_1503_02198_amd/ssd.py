@@ -17,6 +17,7 @@ SSD_OK = 0
 STATUS = {0: "SSD_OK", -1: "SSD_ERR_INVALID_ARG", -2: "SSD_ERR_MESH", -3: "SSD_ERR_STATE",
           -4: "SSD_ERR_DEVICE", -5: "SSD_ERR_NOMEM", -6: "SSD_ERR_NUMERIC"}
 KERNELS = {"stage": 0, "traces": 1, "mortar": 2, "rebuild": 3, "grad": 4}
+SCHEMES = {"rk3": 0, "rk54": 1}   # ssd_rk
 EXPORTS = ["ssd_create_mesh", "ssd_destroy_mesh", "ssd_query", "ssd_set_rotation",
            "ssd_mortar_rebuild", "ssd_residual", "ssd_rk_step", "ssd_rk_steps", "ssd_check",
            "ssd_last_error", "ssd_timing_enable", "ssd_timing_reset", "ssd_timing_read"]
@@ -183,17 +184,18 @@ class Mesh:
         _check(lib().ssd_residual(self._h, self._tensor(q, n, "q"), self._tensor(r, n, "r"),
                                   _stream_ptr(stream, self.device)))
 
-    def rk_step(self, q, work, t, dt, stream=None):
+    def rk_step(self, q, work, t, dt, stream=None, scheme="rk3"):
         n = self.info["state_len"]
         _check(lib().ssd_rk_step(self._h, self._tensor(q, n, "q"),
                                  self._tensor(work, self.info["work_len"], "work"),
-                                 float(t), float(dt), 0, _stream_ptr(stream, self.device)))
+                                 float(t), float(dt), SCHEMES[scheme],
+                                 _stream_ptr(stream, self.device)))
 
-    def rk_steps(self, q, work, t, dt, nsteps, stream=None):
+    def rk_steps(self, q, work, t, dt, nsteps, stream=None, scheme="rk3"):
         n = self.info["state_len"]
         _check(lib().ssd_rk_steps(self._h, self._tensor(q, n, "q"),
                                   self._tensor(work, self.info["work_len"], "work"),
-                                  float(t), float(dt), int(nsteps), 0,
+                                  float(t), float(dt), int(nsteps), SCHEMES[scheme],
                                   _stream_ptr(stream, self.device)))
 
     def check(self, stream=None):

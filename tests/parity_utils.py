@@ -52,13 +52,13 @@ def gpu_residual(gm, Q, theta, omega):
     return from_gpu(r, N, E)
 
 
-def gpu_run(gm, Q, t0, dt, nsteps, check=True):
+def gpu_run(gm, Q, t0, dt, nsteps, check=True, scheme="rk3"):
     import torch
     N, E = gm.info["N"], gm.info["n_elem"]
     q = to_gpu(Q, gm.device)
     work = torch.empty(gm.info["work_len"], dtype=torch.float32, device=q.device)
     for k in range(nsteps):
-        gm.rk_step(q, work, t0 + k * dt, dt)
+        gm.rk_step(q, work, t0 + k * dt, dt, scheme=scheme)
     if check:
         gm.check()
     return from_gpu(q, N, E)

@@ -202,3 +202,32 @@ def test_rk_steps_equals_repeated_rk_step(torch_cuda):
     b = from_gpu(q, 3, gm.info["n_elem"])
     print("bitwise equal:", np.array_equal(a, b), "max rel", state_error(b, a))
     assert np.all(state_error(b, a) < 1e-6)
+
+
+def test_ssprk54_vortex_steps(torch_cuda):
+    """SSPRK54 (the paper's integrator) on the vortex workload, through a
+    mortar wrap, against the oracle's SSPRK54."""
+    print("case: vortex SSPRK54 40 steps", flush=True)
+    mesh, case, ora, Q = _vortex(theta0=2 * np.pi / 32 - 0.02)
+    gm = _mesh(mesh, case, 3)
+    Qg = gpu_run(gm, Q, 0.0, 2e-3, 40, scheme="rk54")
+    Qo = ora.run(Q, 0.0, 2e-3, 40, scheme="rk54")
+    err = state_error(Qg, Qo)
+    print("state error", err, "relative to the change",
+          np.linalg.norm(Qg - Qo) / np.linalg.norm(Qo - Q), flush=True)
+    assert np.all(err <= TOL), err
+
+
+def test_ssprk54_rk_steps_equals_repeated(torch_cuda):
+    import torch
+    from tests.parity_utils import from_gpu, to_gpu
+    print("case: SSPRK54 rk_steps vs rk_step", flush=True)
+    mesh, case, ora, Q = _vortex()
+    gm = _mesh(mesh, case, 3)
+    a = gpu_run(gm, Q, 0.0, 2e-3, 8, scheme="rk54")
+    q = to_gpu(Q)
+    work = torch.empty(gm.info["work_len"], dtype=torch.float32, device=q.device)
+    gm.rk_steps(q, work, 0.0, 2e-3, 8, scheme="rk54")
+    gm.check()
+    b = from_gpu(q, 3, gm.info["n_elem"])
+    assert np.all(state_error(b, a) < 1e-6)

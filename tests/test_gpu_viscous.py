@@ -144,3 +144,18 @@ def test_rk_steps_viscous_equals_repeated(torch_cuda):
     gm.check()
     b = from_gpu(q, 3, gm.info["n_elem"])
     assert np.all(state_error(b, a) < 1e-6)
+
+
+def test_ssprk54_couette_steps(torch_cuda):
+    """SSPRK54 on the viscous Couette mesh."""
+    print("case: couette SSPRK54 15 steps", flush=True)
+    case = C.couette_case()
+    mesh = M.couette_mesh(4, 16, phi_offset=0.11)
+    ora = SSD(mesh, case, 3)
+    Q = _couette_state(ora, case, 0.0)
+    gm = _mesh(mesh, case, 3)
+    Qg = gpu_run(gm, Q, 0.0, 3e-3, 15, scheme="rk54")
+    Qo = ora.run(Q, 0.0, 3e-3, 15, scheme="rk54")
+    err = state_error(Qg, Qo)
+    print("state error", err, flush=True)
+    assert np.all(err <= TOL), err

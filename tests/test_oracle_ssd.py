@@ -264,6 +264,54 @@ def test_ssprk3_third_order():
     assert np.all(np.abs(orders - 3.0) < 0.15), orders
 
 
+class _Riccati(SSD):
+    """y' = -2 t y^2, y(0) = 1: y = 1 / (1 + t^2).  Nonlinear and explicitly
+    time dependent (through the rotor angle theta = t), so it checks the
+    nonlinear order conditions and the stage times of a scheme."""
+
+    def __init__(self):
+        self.case = dict(theta0=0.0, omega=1.0)
+
+    def residual(self, Q, theta, omega, diag=False):
+        return -2.0 * theta * Q * Q
+
+
+@pytest.mark.parametrize("scheme,order", [("rk3", 3.0), ("rk54", 4.0)])
+def test_ssprk_order_nonlinear_time_dependent(scheme, order):
+    s = _Riccati()
+    errs = []
+    for n in (8, 16, 32, 64):
+        Q = s.run(np.array([1.0]), 0.0, 2.0 / n, n, scheme=scheme)
+        errs.append(abs(Q[0] - 1.0 / 5.0))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(orders[1:] - order) < 0.25), orders
+
+
+def test_ssprk54_coefficients():
+    """Consistency of the Shu-Osher form: each stage is a convex combination
+    plus a time step, the final combination sums to one, and the stage
+    times lie in [0, 1]."""
+    from oracle.ssd import SSPRK54, ssprk54_stage_times
+    a, c = SSPRK54["a"], SSPRK54["c"]
+    for k in (1, 2, 3):
+        assert abs(a[k][0] + a[k][1] - 1.0) < 1e-14
+    assert abs(c[0] + c[1] + c[3] - 1.0) < 1e-14
+    assert all(x >= 0.0 for row in a for x in row) and all(x >= 0.0 for x in c)
+    tau = ssprk54_stage_times()
+    assert all(0.0 <= x <= 1.0 for x in tau)
+    # the update is exact for L = 1 (dU/dt = 1): U^{n+1} = U + dt
+    U = 0.0
+    L = lambda V: 1.0
+    U1 = U + a[0][2] * L(U)
+    U2 = a[1][0] * U + a[1][1] * U1 + a[1][2] * L(U1)
+    U3 = a[2][0] * U + a[2][1] * U2 + a[2][2] * L(U2)
+    U4 = a[3][0] * U + a[3][1] * U3 + a[3][2] * L(U3)
+    U5 = c[0] * U2 + c[1] * U3 + c[2] * L(U3) + c[3] * U4 + c[4] * L(U4)
+    assert abs(U5 - 1.0) < 1e-14
+    # the stage values are the stage times for dU/dt = 1
+    assert np.allclose([U1, U2, U3, U4], tau[1:], atol=1e-14)
+
+
 # ---------------------------------------------------------------- convergence
 def _vortex_errors(N, fs, T, dt0):
     case = C.vortex_case(omega=1.0)
