@@ -228,9 +228,9 @@ def main():
     value = dof * stages / el
     # algorithmic bytes of one stage launch: the state it must read and
     # write (Q_k and, in stages 2-3, Q^n, then Q_{k+1}: on average
-    # (8 + 12 + 12) / 3 bytes per DOF) and the FP64 corner coordinates of
-    # every cell (64 bytes)
-    alg_bytes = (32.0 / 3.0) * dof + 64.0 * E
+    # (8 + 12 + 12) / 3 bytes per DOF) and the cell geometry (the bilinear
+    # map, 8 floats = 32 bytes per cell)
+    alg_bytes = (32.0 / 3.0) * dof + 32.0 * E
     stage_us = kern["stage"]["avg_us"]
     achieved = alg_bytes / (stage_us * 1e-6) / 1e9
     hsh = kernel_hash()

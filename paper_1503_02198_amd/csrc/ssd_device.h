@@ -147,29 +147,29 @@ __device__ __forceinline__ void visc_flux_n(const R q[4], const R gx[4], const R
 }
 
 // ---------------------------------------------------------------------------
-// element geometry (Sec. 2.3).  Bilinear cells: the four edge vectors are
-// differenced in FP64 from the stored corners, then carried in FP32 and
-// rotated once into the current frame, so every metric is a linear
-// combination:  x_xi(eta) = A + eta (B - A),  x_eta(xi) = C + xi (D - C),
-// x(xi, eta) = p0 + xi A + eta C + xi eta (B - A).  Cubic cells read FP64
-// tables and rotate in FP64.
+// element geometry (Sec. 2.3).  A bilinear cell is x(xi, eta) = p0 + xi A +
+// eta C + xi eta T with corner 0 at p0, edges A = x3 - x0, C = x9 - x0 and
+// twist T = x6 - x3 - x9 + x0; the host differences them in FP64 and stores
+// them in FP32 (8 floats per cell, all cells).  They are rotated once into
+// the current frame, so every metric is a linear combination:
+//   x_xi(eta) = A + eta T,  x_eta(xi) = C + xi T.
+// Cubic cells read FP64 tables and rotate in FP64.
 // ---------------------------------------------------------------------------
 struct ElemGeo {
   int cubic, c;
   float w;                                    // omega of the zone (0: fixed)
-  float p0x, p0y, Ax, Ay, Bx, By, Cx, Cy, Dx, Dy;
+  float p0x, p0y, Ax, Ay, Cx, Cy, Tx, Ty;
   double ct, st;
 };
 
 __device__ __forceinline__ ElemGeo load_geo(const DevMesh &M, int e, const Rotation &R) {
   ElemGeo g;
   const long E = M.E;
-  // corners are read for every cell (cubic cells ignore them) so that no
-  // load waits on the flag word
-  const double x0 = M.corners[0 * E + e], y0 = M.corners[1 * E + e];
-  const double x3 = M.corners[2 * E + e], y3 = M.corners[3 * E + e];
-  const double x6 = M.corners[4 * E + e], y6 = M.corners[5 * E + e];
-  const double x9 = M.corners[6 * E + e], y9 = M.corners[7 * E + e];
+  // the edge vectors are read for every cell (cubic cells ignore them) so
+  // that no load waits on the flag word
+  float v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = M.geo[k * E + e];
   const int fl = M.eflag[e];
   g.cubic = fl & EF_CUBIC;
   g.c = fl >> 8;
@@ -178,13 +178,10 @@ __device__ __forceinline__ ElemGeo load_geo(const DevMesh &M, int e, const Rotat
   g.st = rot ? R.st : 0.0;
   g.w = rot ? float(R.omega) : 0.0f;
   const float c = float(g.ct), s = float(g.st);
-  auto rx = [&](double x, double y) { return c * float(x) - s * float(y); };
-  auto ry = [&](double x, double y) { return s * float(x) + c * float(y); };
-  g.p0x = rx(x0, y0);            g.p0y = ry(x0, y0);
-  g.Ax = rx(x3 - x0, y3 - y0);   g.Ay = ry(x3 - x0, y3 - y0);
-  g.Bx = rx(x6 - x9, y6 - y9);   g.By = ry(x6 - x9, y6 - y9);
-  g.Cx = rx(x9 - x0, y9 - y0);   g.Cy = ry(x9 - x0, y9 - y0);
-  g.Dx = rx(x6 - x3, y6 - y3);   g.Dy = ry(x6 - x3, y6 - y3);
+  g.p0x = c * v[0] - s * v[1];   g.p0y = s * v[0] + c * v[1];
+  g.Ax = c * v[2] - s * v[3];    g.Ay = s * v[2] + c * v[3];
+  g.Cx = c * v[4] - s * v[5];    g.Cy = s * v[4] + c * v[5];
+  g.Tx = c * v[6] - s * v[7];    g.Ty = s * v[6] + c * v[7];
   return g;
 }
 
@@ -209,15 +206,15 @@ struct LineGeo {
 // u_g . n = -w (x . x_eta + y . y_eta).
 __device__ __forceinline__ LineGeo line_xi(const ElemGeo &g, float eta) {
   LineGeo L;
-  const float ex0 = g.Cx, ex1 = g.Dx - g.Cx, ey0 = g.Cy, ey1 = g.Dy - g.Cy;
+  const float ex0 = g.Cx, ex1 = g.Tx, ey0 = g.Cy, ey1 = g.Ty;
   L.n0x = ey0;
   L.n1x = ey1;
   L.n0y = -ex0;
   L.n1y = -ex1;
   L.p0x = g.p0x + eta * g.Cx;
-  L.p1x = g.Ax + eta * (g.Bx - g.Ax);
+  L.p1x = g.Ax + eta * g.Tx;
   L.p0y = g.p0y + eta * g.Cy;
-  L.p1y = g.Ay + eta * (g.By - g.Ay);
+  L.p1y = g.Ay + eta * g.Ty;
   L.w = g.w;
   L.v0 = -g.w * (L.p0x * ex0 + L.p0y * ey0);
   L.v1 = -g.w * (L.p0x * ex1 + L.p1x * ex0 + L.p0y * ey1 + L.p1y * ey0);
@@ -229,15 +226,15 @@ __device__ __forceinline__ LineGeo line_xi(const ElemGeo &g, float eta) {
 // u_g . n = w (x . x_xi + y . y_xi).
 __device__ __forceinline__ LineGeo line_eta(const ElemGeo &g, float xi) {
   LineGeo L;
-  const float ex0 = g.Ax, ex1 = g.Bx - g.Ax, ey0 = g.Ay, ey1 = g.By - g.Ay;
+  const float ex0 = g.Ax, ex1 = g.Tx, ey0 = g.Ay, ey1 = g.Ty;
   L.n0x = -ey0;
   L.n1x = -ey1;
   L.n0y = ex0;
   L.n1y = ex1;
   L.p0x = g.p0x + xi * g.Ax;
-  L.p1x = g.Cx + xi * (g.Bx - g.Ax);
+  L.p1x = g.Cx + xi * g.Tx;
   L.p0y = g.p0y + xi * g.Ay;
-  L.p1y = g.Cy + xi * (g.By - g.Ay);
+  L.p1y = g.Cy + xi * g.Ty;
   L.w = g.w;
   L.v0 = g.w * (L.p0x * ex0 + L.p0y * ey0);
   L.v1 = g.w * (L.p0x * ex1 + L.p1x * ex0 + L.p0y * ey1 + L.p1y * ey0);
@@ -327,10 +324,10 @@ __device__ __forceinline__ SPGeo metric_sp(const ElemGeo &g, const DevMesh &M, c
     return r;
   }
   const float xi = float(T.X[i]), eta = float(T.X[j]);
-  r.xx = g.Ax + eta * (g.Bx - g.Ax);
-  r.yx = g.Ay + eta * (g.By - g.Ay);
-  r.xe = g.Cx + xi * (g.Dx - g.Cx);
-  r.ye = g.Cy + xi * (g.Dy - g.Cy);
+  r.xx = g.Ax + eta * g.Tx;
+  r.yx = g.Ay + eta * g.Ty;
+  r.xe = g.Cx + xi * g.Tx;
+  r.ye = g.Cy + xi * g.Ty;
   r.ij = rcp(r.xx * r.ye - r.xe * r.yx);
   return r;
 }
@@ -341,8 +338,8 @@ __device__ __forceinline__ float inv_jacobian(const ElemGeo &g, const DevMesh &M
                                               const OpTables &T, int j, int i) {
   if (g.cubic) return float(1.0 / M.cmet[cubic_sp_index(N, M.C, 0, j, i, g.c)]);
   const float xi = float(T.X[i]), eta = float(T.X[j]);
-  const float xx = g.Ax + eta * (g.Bx - g.Ax), yx = g.Ay + eta * (g.By - g.Ay);
-  const float xe = g.Cx + xi * (g.Dx - g.Cx), ye = g.Cy + xi * (g.Dy - g.Cy);
+  const float xx = g.Ax + eta * g.Tx, yx = g.Ay + eta * g.Ty;
+  const float xe = g.Cx + xi * g.Tx, ye = g.Cy + xi * g.Ty;
   return rcp(xx * ye - xe * yx);
 }
 

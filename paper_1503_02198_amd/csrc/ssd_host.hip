@@ -407,7 +407,7 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
 
   // ---- elements: flags, geometry checks, cubic tables
   std::vector<int> eflag(E);
-  std::vector<double> corners(8L * E);
+  std::vector<float> geo(8L * E);   // bilinear map p0, A, C, T per cell
   std::vector<int> cslot(E, -1);
   int C = 0;
   for (int e = 0; e < E; ++e) {
@@ -421,10 +421,16 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
     if (g == SSD_GEOM_CUBIC) cslot[e] = C++;
     eflag[e] = (g == SSD_GEOM_CUBIC ? EF_CUBIC : 0) | (z == 1 ? EF_ROT : 0) |
                (g == SSD_GEOM_CUBIC ? (cslot[e] << 8) : 0);
-    const int cn[4] = {0, 3, 6, 9};
-    for (int a = 0; a < 4; ++a) {
-      corners[(2 * a) * long(E) + e] = d->elem_xy[24L * e + 2 * cn[a]] - cx;
-      corners[(2 * a + 1) * long(E) + e] = d->elem_xy[24L * e + 2 * cn[a] + 1] - cy;
+    // x(xi, eta) = p0 + xi A + eta C + xi eta T relative to the rotation
+    // centre; differences in FP64, stored in FP32
+    const double *xy = d->elem_xy + 24L * e;
+    for (int c = 0; c < 2; ++c) {
+      const double x0 = xy[0 * 2 + c] - (c ? cy : cx), x3 = xy[3 * 2 + c] - (c ? cy : cx);
+      const double x6 = xy[6 * 2 + c] - (c ? cy : cx), x9 = xy[9 * 2 + c] - (c ? cy : cx);
+      geo[(0 + c) * long(E) + e] = float(x0);
+      geo[(2 + c) * long(E) + e] = float(x3 - x0);
+      geo[(4 + c) * long(E) + e] = float(x9 - x0);
+      geo[(6 + c) * long(E) + e] = float((x6 - x3) - (x9 - x0));
     }
   }
   if (C >= (1 << 23)) return fail(SSD_ERR_MESH, "too many cubic elements");
@@ -616,15 +622,16 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
   }
 
   // ---- upload
-  double *dcorn, *dcmet;
+  float *dgeo;
+  double *dcmet;
   int *deflag;
   uint32_t *dface;
-  SSD_HIP(dev_alloc(m, &dcorn, 8L * E), "alloc corners");
+  SSD_HIP(dev_alloc(m, &dgeo, 8L * E), "alloc cell geometry");
   SSD_HIP(dev_alloc(m, &deflag, E), "alloc flags");
   SSD_HIP(dev_alloc(m, &dface, 4L * E), "alloc faces");
   SSD_HIP(dev_alloc(m, &dcmet, cmet.size()), "alloc cubic metrics");
-  SSD_HIP(hipMemcpy(dcorn, corners.data(), corners.size() * sizeof(double), hipMemcpyHostToDevice),
-          "upload corners");
+  SSD_HIP(hipMemcpy(dgeo, geo.data(), geo.size() * sizeof(float), hipMemcpyHostToDevice),
+          "upload cell geometry");
   SSD_HIP(hipMemcpy(deflag, eflag.data(), E * sizeof(int), hipMemcpyHostToDevice), "upload flags");
   SSD_HIP(hipMemcpy(dface, face.data(), face.size() * sizeof(uint32_t), hipMemcpyHostToDevice),
           "upload faces");
@@ -645,7 +652,7 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
   D.K = m->K;
   D.C = C;
   D.N = N;
-  D.corners = dcorn;
+  D.geo = dgeo;
   D.eflag = deflag;
   D.face = dface;
   D.cmet = dcmet;

@@ -78,7 +78,7 @@ struct DevMesh {
   int K;           // faces per interface side (0: no interface)
   int C;           // cubic elements
   int N;
-  const double *corners;   // [8][E]: corners 0,3,6,9 (x, y), relative to rot centre
+  const float *geo;        // [8][E]: bilinear map p0, A, C, T (x, y each), see load_geo
   const int *eflag;        // [E]
   const uint32_t *face;    // [4][E]
   const double *cmet;      // cubic-cell metrics, see cubic_index()
