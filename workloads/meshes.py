@@ -91,10 +91,18 @@ def _block(P, curves=None, zone=0, tile=None):
                zone=np.full(ni * nj, zone, np.int32))
     if tile is not None:
         tj, ti = tile
-        if ni % ti or nj % tj:
-            raise ValueError("block size is not a multiple of the tile")
+        # full bands of ti rows use tj x ti tiles; a last band of r < ti rows
+        # uses (tj ti / r) x r tiles, so every tile keeps tj ti elements
+        r = ni % ti
+        tjr = (tj * ti) // r if r else tj
+        if nj % tj or (r and ((tj * ti) % r or nj % tjr)):
+            raise ValueError("block size does not split into whole tiles")
         ii, jj = np.meshgrid(np.arange(ni), np.arange(nj), indexing="ij")
-        key = (((ii // ti) * (nj // tj) + jj // tj) * ti + ii % ti) * tj + jj % tj
+        band, il = ii // ti, ii % ti
+        last = (ni - r) if r else ni
+        w = np.where(ii >= last, tjr, tj)       # tile width along j
+        h = np.where(ii >= last, r if r else ti, ti)
+        key = ((band * (nj // w) + jj // w) * h + il) * w + jj % w
         order = np.argsort(key.ravel(), kind="stable")
         out = {k: v[order] for k, v in out.items()}
     return out
