@@ -206,6 +206,51 @@ ssd_status ssd_check(ssd_mesh *m, void *stream);
 const char *ssd_last_error(void);
 
 /*
+ * Batches: many meshes of one device stepped together.  A batch groups its
+ * meshes by (N, viscous); per RK stage every group runs one mortar launch,
+ * (viscous) one gradient and one viscous-mortar launch, and one stage
+ * launch, each walking a device table of (mesh, 64-cell tile or interface
+ * chunk) pairs with a persistent grid.  The stage kernel's grid is chosen by
+ * timing candidate grids on the first call (an autotuner keyed by N,
+ * viscous and the group's tile count, shared by the process).  With
+ * use_graph, one and two steps are captured as HIP graphs on the first call
+ * for a scheme and replayed; the stage time is read from a device step
+ * counter, so the graphs do not depend on t.
+ *
+ * The batch references the meshes: they must outlive it, and no other call
+ * may use them while a batch call runs.
+ */
+typedef struct ssd_batch ssd_batch;
+
+typedef struct {
+  int32_t n_groups;     /* groups in the batch                                 */
+  int32_t N;            /* solution points per direction of this group         */
+  int32_t viscous;
+  int32_t tiles;        /* 64-cell tiles over all meshes of the group          */
+  int32_t stage_grid;   /* persistent blocks of its stage kernel               */
+  int32_t tuned;        /* 1 once the autotuner has chosen stage_grid          */
+} ssd_batch_group;
+
+/* n >= 1 distinct meshes, all on one device.  Errors: SSD_ERR_INVALID_ARG. */
+ssd_status ssd_batch_create(ssd_mesh *const *meshes, int32_t n, ssd_batch **out);
+ssd_status ssd_batch_destroy(ssd_batch *b);
+
+/*
+ * nsteps steps of `scheme` for every mesh c of the batch, mesh c from t[c]
+ * with step dt[c], in place on q[c] (device, its state_len floats) with
+ * work[c] (device, its work_len floats).  Same arithmetic as ssd_rk_steps
+ * per mesh; the rotor angle is formed on the device from t[c] + (n + c_k)
+ * dt[c], so results agree with ssd_rk_steps to rounding.  Host arrays q,
+ * work, t, dt have one entry per mesh in creation order.
+ */
+ssd_status ssd_batch_rk_steps(ssd_batch *b, float *const *q, float *const *work, const double *t,
+                              const double *dt, int32_t nsteps, ssd_rk scheme, int32_t use_graph,
+                              void *stream);
+
+/* Shape of group `group` (0 <= group < n_groups). */
+ssd_status ssd_batch_query(const ssd_batch *b, int32_t group, ssd_batch_group *info);
+
+/*
  * Kernel timing.  ssd_timing_enable selects the kernel classes whose
  * launches are bracketed by HIP events on their stream: `classes` is a bit
  * mask, bit SSD_KERNEL_x for class x (SSD_TIMING_ALL: every class, 0: off).

@@ -5,6 +5,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -967,6 +970,402 @@ ssd_status ssd_timing_read(ssd_mesh *m, int kernel, double *total_ms, int64_t *l
   }
   *total_ms = sum;
   *launches = int64_t(t.used / 2);
+  return SSD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches: many meshes stepped together
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct ssd_batch {
+  int device = 0;
+  int ncu = 1;
+  std::vector<ssd_mesh *> meshes;
+  struct Group {
+    int N = 0;
+    bool visc = false;
+    OpTables T{};
+    MortarTables MT{};
+    uint2 *stage_work = nullptr, *mortar_work = nullptr, *trace_work = nullptr;
+    int nstage = 0, nmortar = 0, ntrace = 0;
+    int stage_grid = 0;    // persistent blocks of the stage kernel (autotuned)
+    int stage_per_cu = 0;  // resident stage blocks per compute unit
+    bool tuned = false;
+  };
+  std::vector<Group> groups;
+  uint2 *comb_work = nullptr;
+  int ncomb = 0;
+  std::vector<BatchCase> cases;
+  BatchCase *dcases = nullptr;
+  double *step = nullptr;
+  std::vector<void *> allocs;
+  hipStream_t cap = nullptr;            // capture stream for the step graphs
+  hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [scheme][2 steps?]
+};
+
+namespace {
+
+template <class T>
+hipError_t batch_alloc(ssd_batch *b, T **p, size_t count) {
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+  if (e == hipSuccess) {
+    b->allocs.push_back(q);
+    *p = static_cast<T *>(q);
+  }
+  return e;
+}
+
+void batch_free(ssd_batch *b) {
+  for (auto &gs : b->graph)
+    for (auto &g : gs)
+      if (g) (void)hipGraphExecDestroy(g);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (void *p : b->allocs) (void)hipFree(p);
+  b->allocs.clear();
+}
+
+// Autotuned launch shape of the batched stage kernel, shared by all batches
+// of the process: resident blocks per compute unit of the persistent grid,
+// keyed by (N, viscous, log2 of the group's 64-cell tiles).
+std::mutex g_tune_mutex;
+std::map<std::tuple<int, int, int>, int> g_tune;
+
+int tile_bucket(int ntiles) {
+  int b = 0;
+  while ((1 << (b + 1)) <= ntiles) ++b;
+  return b;
+}
+
+// One RK stage of every group, eager launches on stream st.
+ssd_status batch_stage(ssd_batch *b, const BatchStage &S, hipStream_t st) {
+  for (auto &g : b->groups) {
+    const int mgrid = std::min(g.nmortar, 4 * b->ncu);
+    if (g.nmortar)
+      SSD_HIP(launch_batch_mortar(g.N, g.visc, b->dcases, g.mortar_work, g.nmortar, g.T, g.MT, S.cur,
+                                  S.c, b->step, mgrid, st),
+              "batched mortar launch");
+    if (g.visc) {
+      SSD_HIP(launch_batch_grad(g.N, b->dcases, g.stage_work, g.nstage, g.T, S.in, S.cur, S.c,
+                                b->step, g.stage_grid, st),
+              "batched gradient launch");
+      if (g.nmortar)
+        SSD_HIP(launch_batch_mortar_visc(g.N, b->dcases, g.mortar_work, g.nmortar, g.T, S.cur,
+                                         mgrid, st),
+                "batched viscous mortar launch");
+    }
+    SSD_HIP(launch_batch_stage(g.N, g.visc, b->dcases, g.stage_work, g.nstage, g.T, S, b->step,
+                               g.stage_grid, st),
+            "batched stage launch");
+  }
+  return SSD_OK;
+}
+
+// One step of `scheme` for every case, eager launches; *cur is the face
+// buffer parity of the step's input and is advanced stage by stage.
+ssd_status batch_step(ssd_batch *b, ssd_rk scheme, int *cur, hipStream_t st) {
+  if (scheme == SSD_RK3_SSP) {
+    const float B3[3] = {1.0f, 0.25f, 2.0f / 3.0f};
+    const double C3[3] = {0.0, 1.0, 0.5};
+    const int in[3] = {0, 1, 2}, qn[3] = {-1, 0, 0}, out[3] = {1, 2, 0};
+    for (int k = 0; k < 3; ++k) {
+      if (ssd_status e = batch_stage(b, BatchStage{in[k], qn[k], out[k], -1, *cur, B3[k], B3[k],
+                                                   C3[k]}, st))
+        return e;
+      *cur ^= 1;
+    }
+  } else {
+    double tau[5] = {0.0, RK54_A[0][2], 0.0, 0.0, 0.0};
+    for (int k = 1; k < 4; ++k) tau[k + 1] = RK54_A[k][1] * tau[k] + RK54_A[k][2];
+    const int in[4] = {0, 1, 2, 1}, out[4] = {1, 2, 1, 3};
+    for (int k = 0; k < 4; ++k) {
+      if (ssd_status e = batch_stage(b, BatchStage{in[k], k ? 0 : -1, out[k], -1, *cur,
+                                                   float(RK54_A[k][1]), float(RK54_A[k][2]),
+                                                   tau[k]}, st))
+        return e;
+      *cur ^= 1;
+    }
+    const double g4 = RK54_A[3][2];
+    SSD_HIP(launch_batch_combine(b->dcases, b->comb_work, b->ncomb, float(RK54_C[0]),
+                                 float(RK54_C[1] - RK54_C[2] * RK54_A[3][1] / g4),
+                                 float(RK54_C[2] / g4), std::min(b->ncomb, 8 * b->ncu), st),
+            "batched stage combination launch");
+    if (ssd_status e = batch_stage(b, BatchStage{3, 0, 0, 2, *cur, float(RK54_C[3]),
+                                                 float(RK54_C[4]), tau[4]}, st))
+      return e;
+    *cur ^= 1;
+  }
+  SSD_HIP(launch_step_count(b->step, st), "step counter launch");
+  return SSD_OK;
+}
+
+// Picks the persistent grid of each group's stage kernel by timing a few
+// launches of each candidate on the real data.  Trial launches write only
+// scratch (work array 3 and the face buffer of parity 1).
+ssd_status batch_tune(ssd_batch *b, hipStream_t st) {
+  hipEvent_t e0, e1;
+  SSD_HIP(hipEventCreate(&e0), "event");
+  SSD_HIP(hipEventCreate(&e1), "event");
+  ssd_status result = SSD_OK;
+  for (auto &g : b->groups) {
+    if (g.tuned) continue;
+    const auto key = std::make_tuple(g.N, int(g.visc), tile_bucket(g.nstage));
+    {
+      std::lock_guard<std::mutex> lock(g_tune_mutex);
+      auto it = g_tune.find(key);
+      if (it != g_tune.end()) {
+        g.stage_grid = std::min(g.nstage, it->second * b->ncu);
+        g.tuned = true;
+        continue;
+      }
+    }
+    // the trial stage reads the mortar (and viscous) inputs of face buffer 0
+    const int mgrid = std::min(g.nmortar, 4 * b->ncu);
+    if (g.nmortar &&
+        launch_batch_mortar(g.N, g.visc, b->dcases, g.mortar_work, g.nmortar, g.T, g.MT, 0, 0.0,
+                            b->step, mgrid, st) != hipSuccess)
+      result = fail(SSD_ERR_DEVICE, "stage kernel tuning failed");
+    if (!result && g.visc &&
+        (launch_batch_grad(g.N, b->dcases, g.stage_work, g.nstage, g.T, 0, 0, 0.0, b->step,
+                           g.stage_grid, st) != hipSuccess ||
+         (g.nmortar && launch_batch_mortar_visc(g.N, b->dcases, g.mortar_work, g.nmortar, g.T, 0,
+                                                mgrid, st) != hipSuccess)))
+      result = fail(SSD_ERR_DEVICE, "stage kernel tuning failed");
+    if (result) break;
+    const BatchStage S{0, -1, 3, -1, 0, 1.0f, 0.0f, 0.0};
+    int best_pc = g.stage_per_cu;
+    float best = 1e30f;
+    for (int pc = 1; pc <= g.stage_per_cu; ++pc) {
+      const int grid = std::min(g.nstage, pc * b->ncu);
+      float ms = 0.0f;
+      for (int rep = 0; rep < 2; ++rep) {   // first repetition warms up
+        if (hipEventRecord(e0, st) != hipSuccess ||
+            launch_batch_stage(g.N, g.visc, b->dcases, g.stage_work, g.nstage, g.T, S, b->step,
+                               grid, st) != hipSuccess ||
+            hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          result = fail(SSD_ERR_DEVICE, "stage kernel tuning failed");
+          break;
+        }
+      }
+      if (result) break;
+      if (ms < best) {
+        best = ms;
+        best_pc = pc;
+      }
+      if (grid == g.nstage) break;   // more blocks than tiles changes nothing
+    }
+    if (result) break;
+    g.stage_grid = std::min(g.nstage, best_pc * b->ncu);
+    g.tuned = true;
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    g_tune[key] = best_pc;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return result;
+}
+
+}  // namespace
+
+extern "C" {
+
+ssd_status ssd_batch_create(ssd_mesh *const *meshes, int32_t n, ssd_batch **out) {
+  if (!meshes || !out || n < 1) return fail(SSD_ERR_INVALID_ARG, "need n >= 1 meshes and an output");
+  *out = nullptr;
+  for (int c = 0; c < n; ++c) {
+    if (!meshes[c]) return fail(SSD_ERR_INVALID_ARG, "null mesh handle in the batch");
+    if (meshes[c]->device != meshes[0]->device)
+      return fail(SSD_ERR_INVALID_ARG, "all meshes of a batch must be on one device");
+    for (int d = 0; d < c; ++d)
+      if (meshes[d] == meshes[c]) return fail(SSD_ERR_INVALID_ARG, "a mesh appears twice in the batch");
+  }
+  ssd_batch *b = new (std::nothrow) ssd_batch();
+  if (!b) return fail(SSD_ERR_NOMEM, "host allocation failed");
+  b->device = meshes[0]->device;
+  DeviceGuard guard(b->device);
+  auto bail = [&](ssd_status st) {
+    batch_free(b);
+    delete b;
+    return st;
+  };
+  try {
+    b->meshes.assign(meshes, meshes + n);
+    if (hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, b->device) !=
+        hipSuccess)
+      return bail(fail(SSD_ERR_DEVICE, "query compute units"));
+    b->ncu = std::max(b->ncu, 1);
+    // groups of equal (N, viscous)
+    std::vector<std::vector<uint2>> sw, mw, tw;
+    std::vector<uint2> cw;
+    for (int c = 0; c < n; ++c) {
+      const ssd_mesh *m = meshes[c];
+      int gi = -1;
+      for (size_t k = 0; k < b->groups.size(); ++k)
+        if (b->groups[k].N == m->N && b->groups[k].visc == m->viscous) gi = int(k);
+      if (gi < 0) {
+        ssd_batch::Group g;
+        g.N = m->N;
+        g.visc = m->viscous;
+        g.T = m->T;
+        g.MT = m->MT;
+        b->groups.push_back(g);
+        sw.emplace_back();
+        mw.emplace_back();
+        tw.emplace_back();
+        gi = int(b->groups.size()) - 1;
+      }
+      for (int t = 0; t < (m->E + EB - 1) / EB; ++t) sw[gi].push_back(make_uint2(c, t));
+      const int fpb = 256 / m->N;
+      for (int k = 0; k < (2 * m->K + fpb - 1) / fpb; ++k) mw[gi].push_back(make_uint2(c, k));
+      for (int k = 0; k < (m->E + 255) / 256; ++k) tw[gi].push_back(make_uint2(c, k));
+      const long len = 4L * m->N * m->N * m->E;
+      for (long k = 0; k < (len + 255) / 256; ++k) cw.push_back(make_uint2(c, unsigned(k)));
+    }
+    auto upload = [&](const std::vector<uint2> &v, uint2 **p) -> hipError_t {
+      hipError_t e = batch_alloc(b, p, v.size());
+      if (e == hipSuccess && !v.empty())
+        e = hipMemcpy(*p, v.data(), v.size() * sizeof(uint2), hipMemcpyHostToDevice);
+      return e;
+    };
+    for (size_t k = 0; k < b->groups.size(); ++k) {
+      auto &g = b->groups[k];
+      if (upload(sw[k], &g.stage_work) != hipSuccess || upload(mw[k], &g.mortar_work) != hipSuccess ||
+          upload(tw[k], &g.trace_work) != hipSuccess)
+        return bail(fail(SSD_ERR_NOMEM, "batch work tables"));
+      g.nstage = int(sw[k].size());
+      g.nmortar = int(mw[k].size());
+      g.ntrace = int(tw[k].size());
+      if (batch_stage_blocks_per_cu(g.N, g.visc, &g.stage_per_cu) != hipSuccess || g.stage_per_cu < 1)
+        return bail(fail(SSD_ERR_DEVICE, "batched stage occupancy"));
+      g.stage_grid = std::min(g.nstage, g.stage_per_cu * b->ncu);
+    }
+    if (cw.size() > size_t(0x7fffffff)) return bail(fail(SSD_ERR_INVALID_ARG, "batch too large"));
+    if (upload(cw, &b->comb_work) != hipSuccess) return bail(fail(SSD_ERR_NOMEM, "batch tables"));
+    b->ncomb = int(cw.size());
+    b->cases.resize(n);
+    for (int c = 0; c < n; ++c) {
+      const ssd_mesh *m = meshes[c];
+      BatchCase &B = b->cases[c];
+      B = BatchCase{};
+      B.M = m->D;
+      B.theta0 = m->theta0;
+      B.omega = m->omega0;
+      B.ms = m->ms;
+      B.face[0] = m->tr[0];
+      B.face[1] = m->tr[1];
+      B.V = m->V;
+    }
+    if (batch_alloc(b, &b->dcases, size_t(n)) != hipSuccess ||
+        batch_alloc(b, &b->step, size_t(1)) != hipSuccess)
+      return bail(fail(SSD_ERR_NOMEM, "batch descriptors"));
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(SSD_ERR_DEVICE, "batch capture stream"));
+  } catch (const std::bad_alloc &) {
+    return bail(fail(SSD_ERR_NOMEM, "host allocation failed"));
+  }
+  *out = b;
+  return SSD_OK;
+}
+
+ssd_status ssd_batch_destroy(ssd_batch *b) {
+  if (!b) return SSD_OK;
+  DeviceGuard guard(b->device);
+  (void)hipDeviceSynchronize();
+  batch_free(b);
+  delete b;
+  return SSD_OK;
+}
+
+ssd_status ssd_batch_rk_steps(ssd_batch *b, float *const *q, float *const *work, const double *t,
+                              const double *dt, int32_t nsteps, ssd_rk scheme, int32_t use_graph,
+                              void *stream) {
+  if (!b) return fail(SSD_ERR_INVALID_ARG, "null batch handle");
+  if (!q || !work || !t || !dt) return fail(SSD_ERR_INVALID_ARG, "null argument array");
+  if (nsteps < 1) return fail(SSD_ERR_INVALID_ARG, "nsteps must be >= 1");
+  if (scheme != SSD_RK3_SSP && scheme != SSD_RK54_SSP)
+    return fail(SSD_ERR_INVALID_ARG, "unknown Runge-Kutta scheme");
+  const int n = int(b->meshes.size());
+  for (int c = 0; c < n; ++c) {
+    const ssd_mesh *m = b->meshes[c];
+    if (!q[c] || !work[c]) return fail(SSD_ERR_INVALID_ARG, "null state or work pointer");
+    if (!std::isfinite(t[c]) || !std::isfinite(dt[c]) || !(dt[c] > 0.0))
+      return fail(SSD_ERR_INVALID_ARG, "need finite t and dt > 0 for every case");
+    const long len = 4L * m->N * m->N * m->E;
+    if (overlap(q[c], len * sizeof(float), work[c], 3 * len * sizeof(float)))
+      return fail(SSD_ERR_INVALID_ARG, "q and work overlap");
+  }
+  DeviceGuard guard(b->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int c = 0; c < n; ++c) {
+    const ssd_mesh *m = b->meshes[c];
+    const long len = 4L * m->N * m->N * m->E;
+    BatchCase &B = b->cases[c];
+    B.t0 = t[c];
+    B.dt = dt[c];
+    B.buf[0] = q[c];
+    for (int k = 1; k < 4; ++k) B.buf[k] = work[c] + (k - 1) * len;
+  }
+  // descriptors and the step counter, ordered before the work on `st`
+  SSD_HIP(hipStreamSynchronize(st), "stream synchronize");
+  SSD_HIP(hipMemcpy(b->dcases, b->cases.data(), n * sizeof(BatchCase), hipMemcpyHostToDevice),
+          "upload batch descriptors");
+  SSD_HIP(hipMemset(b->step, 0, sizeof(double)), "clear step counter");
+  for (auto &g : b->groups)
+    SSD_HIP(launch_batch_traces(g.N, b->dcases, g.trace_work, g.ntrace, g.T,
+                                std::min(g.ntrace, 8 * b->ncu), st),
+            "batched trace launch");
+  if (ssd_status e = batch_tune(b, st)) return e;
+  int cur = 0;
+  if (!use_graph) {
+    for (int s = 0; s < nsteps; ++s)
+      if (ssd_status e = batch_step(b, scheme, &cur, st)) return e;
+  } else {
+    // graphs of two steps and of one step, each starting at face parity 0;
+    // a step has an odd number of stages, so two steps return to parity 0
+    const int si = scheme == SSD_RK3_SSP ? 0 : 1;
+    for (int k = 0; k < 2; ++k) {
+      if (b->graph[si][k]) continue;
+      hipGraph_t gr = nullptr;
+      SSD_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+      int c0 = 0;
+      ssd_status e = SSD_OK;
+      for (int s = 0; s < (k ? 2 : 1) && !e; ++s) e = batch_step(b, scheme, &c0, b->cap);
+      hipError_t he = hipStreamEndCapture(b->cap, &gr);
+      if (e) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return e;
+      }
+      SSD_HIP(he, "end capture");
+      he = hipGraphInstantiate(&b->graph[si][k], gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      SSD_HIP(he, "graph instantiate");
+    }
+    for (int s = 0; s + 1 < nsteps; s += 2)
+      SSD_HIP(hipGraphLaunch(b->graph[si][1], st), "graph launch");
+    if (nsteps % 2) SSD_HIP(hipGraphLaunch(b->graph[si][0], st), "graph launch");
+  }
+  for (int c = 0; c < n; ++c) {
+    ssd_mesh *m = b->meshes[c];
+    m->theta = m->theta0 + m->omega0 * (t[c] + nsteps * dt[c]);
+    m->omega = m->omega0;
+    m->mortar_fresh = m->K == 0;
+  }
+  return SSD_OK;
+}
+
+ssd_status ssd_batch_query(const ssd_batch *b, int32_t group, ssd_batch_group *info) {
+  if (!b || !info) return fail(SSD_ERR_INVALID_ARG, "null batch or output");
+  if (group < 0 || group >= int(b->groups.size()))
+    return fail(SSD_ERR_INVALID_ARG, "group out of range");
+  const auto &g = b->groups[group];
+  info->n_groups = int32_t(b->groups.size());
+  info->N = g.N;
+  info->viscous = g.visc;
+  info->tiles = g.nstage;
+  info->stage_grid = g.stage_grid;
+  info->tuned = g.tuned;
   return SSD_OK;
 }
 

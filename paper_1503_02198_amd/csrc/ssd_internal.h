@@ -161,6 +161,51 @@ struct RKCoef {
 hipError_t launch_stage(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
                         const float *qn, float *out, const float *facein, float *trout,
                         const ViscIO *visc, const RKCoef &C, bool rk, hipStream_t s);
+// ---------------------------------------------------------------------------
+// batched execution of many meshes (same device): per-case descriptors and
+// work tables live in device memory; every batched kernel walks a table of
+// (case, tile or chunk) pairs with a grid-stride loop.
+// ---------------------------------------------------------------------------
+struct BatchCase {
+  DevMesh M;
+  double theta0, omega;   // rotor motion: theta = theta0 + omega t
+  double t0, dt;          // step n starts at t0 + n dt
+  MortarState *ms;
+  float *buf[4];          // stage arrays: 0 the state, 1..3 the work arrays
+  float *face[2];         // face data buffers
+  ViscIO V;
+};
+
+// Which stage arrays a batched stage reads and writes (indices into
+// BatchCase::buf, -1: none), the face buffer parity and the stage time
+// offset c (theta at t0 + (n + c) dt, n read from the step counter).
+struct BatchStage {
+  int in, qn, out, add;
+  int cur;
+  float beta, gamma;
+  double c;
+};
+
+// Grid-stride batched launchers; `work` tables hold (case, tile/chunk).
+hipError_t launch_batch_traces(int N, const BatchCase *cases, const uint2 *work, int nwork,
+                               const OpTables &T, int grid, hipStream_t s);
+hipError_t launch_batch_mortar(int N, bool visc, const BatchCase *cases, const uint2 *work,
+                               int nwork, const OpTables &T, const MortarTables &MT, int cur,
+                               double c, const double *step, int grid, hipStream_t s);
+hipError_t launch_batch_grad(int N, const BatchCase *cases, const uint2 *work, int nwork,
+                             const OpTables &T, int in, int cur, double c, const double *step,
+                             int grid, hipStream_t s);
+hipError_t launch_batch_mortar_visc(int N, const BatchCase *cases, const uint2 *work, int nwork,
+                                    const OpTables &T, int cur, int grid, hipStream_t s);
+hipError_t launch_batch_stage(int N, bool visc, const BatchCase *cases, const uint2 *work,
+                              int nwork, const OpTables &T, const BatchStage &S,
+                              const double *step, int grid, hipStream_t s);
+hipError_t launch_batch_combine(const BatchCase *cases, const uint2 *work, int nwork, float w2,
+                                float w3, float w4, int grid, hipStream_t s);
+hipError_t launch_step_count(double *step, hipStream_t s);
+// Resident blocks per compute unit of the batched stage kernel.
+hipError_t batch_stage_blocks_per_cu(int N, bool visc, int *blocks);
+
 // W = w2 (u2 - un) + w3 (u3 - un) + w4 (u4 - un) over n floats.
 hipError_t launch_rk_combine(long n, const float *un, const float *u2, const float *u3,
                              const float *u4, float w2, float w3, float w4, float *W,

@@ -15,13 +15,16 @@
 
 namespace ssd {
 
+constexpr int TRACE_BLOCK = 256;
+
 // ---------------------------------------------------------------------------
 // face traces of a state, for the faces some other block reads
 // ---------------------------------------------------------------------------
 template <int N>
-__global__ __launch_bounds__(256) void k_traces(DevMesh M, OpTables T, const float *__restrict__ q,
-                                                float *__restrict__ tr) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void traces_block(const DevMesh &M, const OpTables &T,
+                                             const float *__restrict__ q, float *__restrict__ tr,
+                                             int block) {
+  const int e = block * TRACE_BLOCK + int(threadIdx.x);
   if (e >= M.E) return;
   const uint32_t E4 = uint32_t(M.E) * 4u;
   const rsrc_t rq = make_rsrc(q, 4u * N * N * E4), rt = make_rsrc(tr, 16u * N * E4);
@@ -57,6 +60,13 @@ __global__ __launch_bounds__(256) void k_traces(DevMesh M, OpTables T, const flo
     if (ex[2]) bstore4(f2, rt, vo, 2 * fs);
     if (ex[3]) bstore4(f3, rt, vo, 3 * fs);
   }
+}
+
+template <int N>
+__global__ __launch_bounds__(TRACE_BLOCK) void k_traces(DevMesh M, OpTables T,
+                                                        const float *__restrict__ q,
+                                                        float *__restrict__ tr) {
+  traces_block<N>(M, T, q, tr, blockIdx.x);
 }
 
 // Viscous inputs of the stage kernel (null on inviscid meshes).
@@ -146,10 +156,10 @@ __device__ __forceinline__ void common_visc(const DevMesh &M, const ViscParams &
 // Global accesses of a wave are contiguous 256-byte rows.
 // ---------------------------------------------------------------------------
 template <int N, bool RK, bool VISC, bool ADD>
-__global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotation R,
-                                                  const float *q, const float *qn, float *out,
-                                                  const float *facein, float *trout, ViscBufs V,
-                                                  RKCoef C) {
+__device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, const Rotation &R,
+                                           const float *q, const float *qn, float *out,
+                                           const float *facein, float *trout, const ViscBufs &V,
+                                           const RKCoef &C, int tile) {
   __shared__ float S[4][N][N][EB];     // state of the block's elements
   __shared__ float SR[4][N][N][EB];    // xi part of the residual, then the new state
   __shared__ uint8_t XL[4][EB];        // exporting lanes per face
@@ -158,7 +168,7 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
   // the wave index is uniform across the wave (blocks are 64 N lanes): say so,
   // so that offsets derived from it live in SGPRs
   const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / EB);
-  const int e0 = blockIdx.x * EB + l;
+  const int e0 = tile * EB + l;
   const bool valid = e0 < M.E;
   const int e = valid ? e0 : M.E - 1;
   const float gm1 = M.gamma - 1.0f;
@@ -434,7 +444,7 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
   // and one store instruction covers the records of 64 / N elements:
   // consecutive exporting elements give one contiguous span.
   constexpr int EPC = EB / N;   // elements per chunk
-  const uint32_t tile0 = uint32_t(blockIdx.x) * EB;
+  const uint32_t tile0 = uint32_t(tile) * EB;
   for (int f = w; f < 4; f += N) {
     const int cnt = __builtin_popcountll(xm[f]);
     for (int c0 = 0; c0 < cnt; c0 += EPC) {
@@ -463,6 +473,14 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
   }
 }
 
+template <int N, bool RK, bool VISC, bool ADD>
+__global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotation R,
+                                                  const float *q, const float *qn, float *out,
+                                                  const float *facein, float *trout, ViscBufs V,
+                                                  RKCoef C) {
+  stage_tile<N, RK, VISC, ADD>(M, T, R, q, qn, out, facein, trout, V, C, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // viscous gradient pass (Sec. 3.1, BR1 reading)
 //   Q_xi and Q_eta at the SPs are the derivatives of the degree-N
@@ -474,9 +492,9 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
 // Same block and wave organisation as k_stage.
 // ---------------------------------------------------------------------------
 template <int N>
-__global__ __launch_bounds__(64 * N) void k_grad(DevMesh M, OpTables T, Rotation R,
-                                                 const float *q, const float *facein, float *Gout,
-                                                 float *gtr) {
+__device__ __forceinline__ void grad_tile(const DevMesh &M, const OpTables &T, const Rotation &R,
+                                          const float *q, const float *facein, float *Gout,
+                                          float *gtr, int tile) {
   // LDS: the state and Q_xi while the derivatives are formed, then the
   // gradient of the whole block
   __shared__ float L[8][N][N][EB];
@@ -485,7 +503,7 @@ __global__ __launch_bounds__(64 * N) void k_grad(DevMesh M, OpTables T, Rotation
   const float *Sf = &L[0][0][0][0];
   const int l = threadIdx.x & (EB - 1);
   const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / EB);
-  const int e0 = blockIdx.x * EB + l;
+  const int e0 = tile * EB + l;
   const bool valid = e0 < M.E;
   const int e = valid ? e0 : M.E - 1;
   const uint32_t E4 = uint32_t(M.E) * 4u;
@@ -679,6 +697,13 @@ __global__ __launch_bounds__(64 * N) void k_grad(DevMesh M, OpTables T, Rotation
   }
 }
 
+template <int N>
+__global__ __launch_bounds__(64 * N) void k_grad(DevMesh M, OpTables T, Rotation R,
+                                                 const float *q, const float *facein, float *Gout,
+                                                 float *gtr) {
+  grad_tile<N>(M, T, R, q, facein, Gout, gtr, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // sliding interface (Sec. 3.2)
 // ---------------------------------------------------------------------------
@@ -790,21 +815,21 @@ __device__ __forceinline__ void load_canon(const DevMesh &M, const float *__rest
 constexpr int MORTAR_BLOCK = 256;
 
 template <int N, bool VISC>
-__global__ __launch_bounds__(MORTAR_BLOCK) void k_mortar(DevMesh M, OpTables T, MortarTables MT,
-                                                         double theta, MortarState *ms_out,
-                                                         const float *__restrict__ tr,
-                                                         float *__restrict__ mflux,
-                                                         float *__restrict__ mqc) {
+__device__ __forceinline__ void mortar_chunk(const DevMesh &M, const OpTables &T,
+                                             const MortarTables &MT, double theta,
+                                             MortarState *ms_out, const float *__restrict__ tr,
+                                             float *__restrict__ mflux, float *__restrict__ mqc,
+                                             int chunk) {
   constexpr int FPB = MORTAR_BLOCK / N;   // faces per workgroup
   __shared__ MortarState S;
   __shared__ double A[4][N][N];
   __shared__ double FM[FPB][2][N][4];     // mortar fluxes at the mortar points
   __shared__ double QM[VISC ? FPB : 1][2][N][4];
   build_mortar<N>(M, MT, theta, S, A);
-  if (blockIdx.x == 0) store_mortar(S, ms_out);
+  if (chunk == 0) store_mortar(S, ms_out);
   const int K = M.K;
   const int fl = threadIdx.x / N, a = threadIdx.x % N;
-  const int t = blockIdx.x * FPB + fl;
+  const int t = chunk * FPB + fl;
   const bool act = fl < FPB && t < 2 * K;
   const bool right = t >= K;
   const int j = right ? t - K : t;
@@ -868,6 +893,15 @@ __global__ __launch_bounds__(MORTAR_BLOCK) void k_mortar(DevMesh M, OpTables T, 
   }
 }
 
+template <int N, bool VISC>
+__global__ __launch_bounds__(MORTAR_BLOCK) void k_mortar(DevMesh M, OpTables T, MortarTables MT,
+                                                         double theta, MortarState *ms_out,
+                                                         const float *__restrict__ tr,
+                                                         float *__restrict__ mflux,
+                                                         float *__restrict__ mqc) {
+  mortar_chunk<N, VISC>(M, T, MT, theta, ms_out, tr, mflux, mqc, blockIdx.x);
+}
+
 // Canonical point a of ring slot `slot`: C values from a [face][E][point][C]
 // trace array, or 4 values from a per-slot record array [slot][point][4].
 template <int N, int C>
@@ -895,17 +929,17 @@ __device__ __forceinline__ void load_slot_point(const DevMesh &M, const float *_
 // mean is projected back to the lane's face point.  Output: outward viscous
 // flux, mvflux[slot][point][var].
 template <int N>
-__global__ __launch_bounds__(MORTAR_BLOCK) void k_mortar_visc(DevMesh M, OpTables T,
-                                                              const MortarState *__restrict__ ms,
-                                                              const float *__restrict__ mqc,
-                                                              const float *__restrict__ gtr,
-                                                              float *__restrict__ mvflux) {
+__device__ __forceinline__ void mortar_visc_chunk(const DevMesh &M, const OpTables &T,
+                                                  const MortarState *__restrict__ ms,
+                                                  const float *__restrict__ mqc,
+                                                  const float *__restrict__ gtr,
+                                                  float *__restrict__ mvflux, int chunk) {
   constexpr int FPB = MORTAR_BLOCK / N;
   __shared__ double VF[FPB][2][2][N][4];   // [mortar][side][face point][var]
   __shared__ double VM[FPB][2][N][4];      // averaged flux at the mortar points
   const int K = M.K;
   const int fl = threadIdx.x / N, a = threadIdx.x % N;
-  const int t = blockIdx.x * FPB + fl;
+  const int t = chunk * FPB + fl;
   const bool act = fl < FPB && t < 2 * K;
   const bool right = t >= K;
   const int j = right ? t - K : t;
@@ -969,6 +1003,15 @@ __global__ __launch_bounds__(MORTAR_BLOCK) void k_mortar_visc(DevMesh M, OpTable
   for (int v = 0; v < 4; ++v) mvflux[(long(t) * N + pa) * 4 + v] = float(sign * acc[v]);
 }
 
+template <int N>
+__global__ __launch_bounds__(MORTAR_BLOCK) void k_mortar_visc(DevMesh M, OpTables T,
+                                                              const MortarState *__restrict__ ms,
+                                                              const float *__restrict__ mqc,
+                                                              const float *__restrict__ gtr,
+                                                              float *__restrict__ mvflux) {
+  mortar_visc_chunk<N>(M, T, ms, mqc, gtr, mvflux, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -982,7 +1025,6 @@ __global__ __launch_bounds__(MORTAR_BLOCK) void k_mortar_visc(DevMesh M, OpTable
     default: return hipErrorInvalidValue;                \
   }
 
-constexpr int TRACE_BLOCK = 256;
 
 hipError_t launch_traces(const DevMesh &M, const OpTables &T, const float *q, float *tr,
                          hipStream_t s) {
@@ -1084,6 +1126,193 @@ hipError_t launch_rk_combine(long n, const float *un, const float *u2, const flo
   hipLaunchKernelGGL(k_rk_combine, dim3(unsigned(grid)), dim3(256), 0, s, n, un, u2, u3, u4, w2,
                      w3, w4, W);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// batched kernels: the same tile and chunk bodies over a (case, index) table
+// ---------------------------------------------------------------------------
+// Rotation of a case at stage time offset c of step *step.
+__device__ __forceinline__ Rotation batch_rotation(const BatchCase &B, const double *step,
+                                                   double c) {
+  const double th = B.theta0 + B.omega * (B.t0 + (step[0] + c) * B.dt);
+  double sn, cs;
+  sincos(th, &sn, &cs);
+  return Rotation{cs, sn, B.omega};
+}
+
+__device__ __forceinline__ uint2 batch_item(const uint2 *work, int k) {
+  const uint2 w = work[k];
+  return make_uint2(__builtin_amdgcn_readfirstlane(w.x), __builtin_amdgcn_readfirstlane(w.y));
+}
+
+template <int N>
+__global__ __launch_bounds__(TRACE_BLOCK) void kb_traces(const BatchCase *cases, const uint2 *work,
+                                                         int nwork, OpTables T) {
+  for (int k = blockIdx.x; k < nwork; k += gridDim.x) {
+    const uint2 it = batch_item(work, k);
+    const BatchCase &B = cases[it.x];
+    traces_block<N>(B.M, T, B.buf[0], B.face[0], int(it.y));
+  }
+}
+
+template <int N, bool VISC>
+__global__ __launch_bounds__(MORTAR_BLOCK) void kb_mortar(const BatchCase *cases, const uint2 *work,
+                                                          int nwork, OpTables T, MortarTables MT,
+                                                          int cur, double c, const double *step) {
+  for (int k = blockIdx.x; k < nwork; k += gridDim.x) {
+    const uint2 it = batch_item(work, k);
+    const BatchCase &B = cases[it.x];
+    const double theta = B.theta0 + B.omega * (B.t0 + (step[0] + c) * B.dt);
+    float *fb = B.face[cur];
+    const long nt = 16L * N * B.M.E, nr = 8L * B.M.K * N;
+    mortar_chunk<N, VISC>(B.M, T, MT, theta, B.ms, fb, fb + nt, VISC ? fb + nt + nr : nullptr,
+                          int(it.y));
+    __syncthreads();
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(64 * N) void kb_grad(const BatchCase *cases, const uint2 *work,
+                                                  int nwork, OpTables T, int in, int cur,
+                                                  double c, const double *step) {
+  for (int k = blockIdx.x; k < nwork; k += gridDim.x) {
+    const uint2 it = batch_item(work, k);
+    const BatchCase &B = cases[it.x];
+    const Rotation R = batch_rotation(B, step, c);
+    grad_tile<N>(B.M, T, R, B.buf[in], B.face[cur], B.V.G, B.V.gtr, int(it.y));
+    __syncthreads();
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(MORTAR_BLOCK) void kb_mortar_visc(const BatchCase *cases,
+                                                               const uint2 *work, int nwork,
+                                                               OpTables T, int cur) {
+  for (int k = blockIdx.x; k < nwork; k += gridDim.x) {
+    const uint2 it = batch_item(work, k);
+    const BatchCase &B = cases[it.x];
+    const float *fb = B.face[cur];
+    const long nt = 16L * N * B.M.E, nr = 8L * B.M.K * N;
+    mortar_visc_chunk<N>(B.M, T, B.ms, fb + nt + nr, B.V.gtr, B.V.mvflux, int(it.y));
+    __syncthreads();
+  }
+}
+
+template <int N, bool VISC, bool ADD>
+__global__ __launch_bounds__(64 * N) void kb_stage(const BatchCase *cases, const uint2 *work,
+                                                   int nwork, OpTables T, BatchStage S,
+                                                   const double *step) {
+  for (int k = blockIdx.x; k < nwork; k += gridDim.x) {
+    const uint2 it = batch_item(work, k);
+    const BatchCase &B = cases[it.x];
+    const Rotation R = batch_rotation(B, step, S.c);
+    const ViscBufs V{B.V.G, B.V.gtr, B.V.mvflux};
+    const RKCoef C{S.beta, S.gamma, float(B.dt), ADD ? B.buf[S.add] : nullptr};
+    stage_tile<N, true, VISC, ADD>(B.M, T, R, B.buf[S.in], S.qn >= 0 ? B.buf[S.qn] : nullptr,
+                                   B.buf[S.out], B.face[S.cur], B.face[S.cur ^ 1], V, C,
+                                   int(it.y));
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void kb_rk_combine(const BatchCase *cases, const uint2 *work,
+                                                     int nwork, float w2, float w3, float w4) {
+  for (int k = blockIdx.x; k < nwork; k += gridDim.x) {
+    const uint2 it = batch_item(work, k);
+    const BatchCase &B = cases[it.x];
+    const long n = 4L * B.M.N * B.M.N * B.M.E;
+    const long i = long(it.y) * 256 + threadIdx.x;
+    if (i < n) {
+      const float u = B.buf[0][i];
+      B.buf[2][i] = w2 * (B.buf[2][i] - u) + w3 * (B.buf[1][i] - u) + w4 * (B.buf[3][i] - u);
+    }
+  }
+}
+
+__global__ void k_step_count(double *step) {
+  if (threadIdx.x == 0) step[0] += 1.0;
+}
+
+hipError_t launch_batch_traces(int N, const BatchCase *cases, const uint2 *work, int nwork,
+                               const OpTables &T, int grid, hipStream_t s) {
+  SSD_DISPATCH_N(N, hipLaunchKernelGGL(kb_traces<NN>, dim3(grid), dim3(TRACE_BLOCK), 0, s, cases,
+                                       work, nwork, T));
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_mortar(int N, bool visc, const BatchCase *cases, const uint2 *work,
+                               int nwork, const OpTables &T, const MortarTables &MT, int cur,
+                               double c, const double *step, int grid, hipStream_t s) {
+  if (visc) {
+    SSD_DISPATCH_N(N, hipLaunchKernelGGL((kb_mortar<NN, true>), dim3(grid), dim3(MORTAR_BLOCK), 0,
+                                         s, cases, work, nwork, T, MT, cur, c, step));
+  } else {
+    SSD_DISPATCH_N(N, hipLaunchKernelGGL((kb_mortar<NN, false>), dim3(grid), dim3(MORTAR_BLOCK),
+                                         0, s, cases, work, nwork, T, MT, cur, c, step));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_grad(int N, const BatchCase *cases, const uint2 *work, int nwork,
+                             const OpTables &T, int in, int cur, double c, const double *step,
+                             int grid, hipStream_t s) {
+  SSD_DISPATCH_N(N, hipLaunchKernelGGL(kb_grad<NN>, dim3(grid), dim3(EB * NN), 0, s, cases, work,
+                                       nwork, T, in, cur, c, step));
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_mortar_visc(int N, const BatchCase *cases, const uint2 *work, int nwork,
+                                    const OpTables &T, int cur, int grid, hipStream_t s) {
+  SSD_DISPATCH_N(N, hipLaunchKernelGGL(kb_mortar_visc<NN>, dim3(grid), dim3(MORTAR_BLOCK), 0, s,
+                                       cases, work, nwork, T, cur));
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_stage(int N, bool visc, const BatchCase *cases, const uint2 *work,
+                              int nwork, const OpTables &T, const BatchStage &S,
+                              const double *step, int grid, hipStream_t s) {
+#define SSD_BSTAGE(VV, AV)                                                                     \
+  SSD_DISPATCH_N(N, hipLaunchKernelGGL((kb_stage<NN, VV, AV>), dim3(grid), dim3(EB * NN), 0, s, \
+                                       cases, work, nwork, T, S, step))
+  const bool add = S.add >= 0;
+  if (visc) {
+    if (add) {
+      SSD_BSTAGE(true, true);
+    } else {
+      SSD_BSTAGE(true, false);
+    }
+  } else {
+    if (add) {
+      SSD_BSTAGE(false, true);
+    } else {
+      SSD_BSTAGE(false, false);
+    }
+  }
+#undef SSD_BSTAGE
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_combine(const BatchCase *cases, const uint2 *work, int nwork, float w2,
+                                float w3, float w4, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(kb_rk_combine, dim3(grid), dim3(256), 0, s, cases, work, nwork, w2, w3, w4);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_count(double *step, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_count, dim3(1), dim3(64), 0, s, step);
+  return hipGetLastError();
+}
+
+hipError_t batch_stage_blocks_per_cu(int N, bool visc, int *blocks) {
+  *blocks = 0;
+  if (visc) {
+    SSD_DISPATCH_N(N, return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                       blocks, kb_stage<NN, true, false>, EB * NN, 0));
+  } else {
+    SSD_DISPATCH_N(N, return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                       blocks, kb_stage<NN, false, false>, EB * NN, 0));
+  }
+  return hipSuccess;
 }
 
 }  // namespace ssd

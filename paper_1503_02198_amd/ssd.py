@@ -20,7 +20,8 @@ KERNELS = {"stage": 0, "traces": 1, "mortar": 2, "rebuild": 3, "grad": 4}
 SCHEMES = {"rk3": 0, "rk54": 1}   # ssd_rk
 EXPORTS = ["ssd_create_mesh", "ssd_destroy_mesh", "ssd_query", "ssd_set_rotation",
            "ssd_mortar_rebuild", "ssd_residual", "ssd_rk_step", "ssd_rk_steps", "ssd_check",
-           "ssd_last_error", "ssd_timing_enable", "ssd_timing_reset", "ssd_timing_read"]
+           "ssd_last_error", "ssd_timing_enable", "ssd_timing_reset", "ssd_timing_read",
+           "ssd_batch_create", "ssd_batch_destroy", "ssd_batch_rk_steps", "ssd_batch_query"]
 
 
 class SSDError(RuntimeError):
@@ -42,6 +43,11 @@ class MeshDesc(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("gas_R", ctypes.c_double), ("mu", ctypes.c_double),
                 ("prandtl", ctypes.c_double), ("T_wall", ctypes.c_double),
                 ("farfield", ctypes.c_double * 4)]
+
+
+class BatchGroup(ctypes.Structure):
+    _fields_ = [("n_groups", ctypes.c_int32), ("N", ctypes.c_int32), ("viscous", ctypes.c_int32),
+                ("tiles", ctypes.c_int32), ("stage_grid", ctypes.c_int32), ("tuned", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -77,6 +83,12 @@ def lib():
             "ssd_timing_enable": (i32, [vp, ctypes.c_int]),
             "ssd_timing_reset": (i32, [vp]),
             "ssd_timing_read": (i32, [vp, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
+            "ssd_batch_create": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]),
+            "ssd_batch_destroy": (i32, [vp]),
+            "ssd_batch_rk_steps": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                         ctypes.POINTER(dbl), ctypes.POINTER(dbl), i32,
+                                         ctypes.c_int, i32, vp]),
+            "ssd_batch_query": (i32, [vp, i32, ctypes.POINTER(BatchGroup)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -222,3 +234,51 @@ class Mesh:
         n = ctypes.c_int64()
         _check(lib().ssd_timing_read(self._h, KERNELS[kernel], ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+class Batch:
+    """Several meshes of one GPU stepped together (ssd_batch_*).  The meshes
+    must outlive the batch."""
+
+    def __init__(self, meshes):
+        self.meshes = list(meshes)
+        n = len(self.meshes)
+        arr = (ctypes.c_void_p * n)(*[m._h.value for m in self.meshes])
+        h = ctypes.c_void_p()
+        _check(lib().ssd_batch_create(arr, n, ctypes.byref(h)))
+        self._h = h
+        self.device = self.meshes[0].device
+
+    def rk_steps(self, qs, works, ts, dts, nsteps, scheme="rk3", graph=True, stream=None):
+        n = len(self.meshes)
+        if not (len(qs) == len(works) == len(ts) == len(dts) == n):
+            raise ValueError("one state, work array, t and dt per mesh")
+        q = (ctypes.c_void_p * n)(*[m._tensor(x, m.info["state_len"], "q").value
+                                    for m, x in zip(self.meshes, qs)])
+        w = (ctypes.c_void_p * n)(*[m._tensor(x, m.info["work_len"], "work").value
+                                    for m, x in zip(self.meshes, works)])
+        t = (ctypes.c_double * n)(*[float(x) for x in ts])
+        d = (ctypes.c_double * n)(*[float(x) for x in dts])
+        _check(lib().ssd_batch_rk_steps(self._h, q, w, t, d, int(nsteps), SCHEMES[scheme],
+                                        int(bool(graph)), _stream_ptr(stream, self.device)))
+
+    def groups(self):
+        out, g = [], 0
+        while True:
+            inf = BatchGroup()
+            _check(lib().ssd_batch_query(self._h, g, ctypes.byref(inf)))
+            out.append({f: getattr(inf, f) for f, _ in BatchGroup._fields_ if f != "n_groups"})
+            g += 1
+            if g >= inf.n_groups:
+                return out
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ssd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

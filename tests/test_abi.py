@@ -37,6 +37,7 @@ def test_struct_layout_matches_header():
     # ssd_mesh_desc: 2 ints, 6 pointers, 14 doubles (incl. arrays) on LP64
     assert ctypes.sizeof(ssd.MeshDesc) == 8 + 6 * 8 + 14 * 8
     assert ctypes.sizeof(ssd.Info) == 6 * 4 + 2 * 8
+    assert ctypes.sizeof(ssd.BatchGroup) == 6 * 4
 
 
 def test_argument_errors_without_device(L):
@@ -56,3 +57,13 @@ def test_argument_errors_without_device(L):
     assert L.ssd_residual(None, None, None, None) == -1
     assert L.ssd_rk_step(None, None, None, 0.0, 1.0, 0, None) == -1
     assert L.ssd_destroy_mesh(None) == 0
+    # batches
+    b = ctypes.c_void_p()
+    assert L.ssd_batch_create(None, 1, ctypes.byref(b)) == -1
+    arr = (ctypes.c_void_p * 1)(None)
+    assert L.ssd_batch_create(arr, 1, ctypes.byref(b)) == -1
+    assert b"null mesh" in L.ssd_last_error()
+    assert L.ssd_batch_create(arr, 0, ctypes.byref(b)) == -1
+    assert L.ssd_batch_rk_steps(None, None, None, None, None, 1, 0, 0, None) == -1
+    assert L.ssd_batch_query(None, 0, None) == -1
+    assert L.ssd_batch_destroy(None) == 0
