@@ -60,6 +60,90 @@ def workload(args):
     return mesh, case, N, E, Q0, dt
 
 
+def batch_workload(seed=20150307, n=64):
+    """The many-case workload: n instances, Taylor-Couette or vortex with
+    equal odds, cell count log-uniform in [1k, 50k] (nearest mesh of the
+    family), N uniform in 2..5, omega uniform in [0.1, 2], all drawn from one
+    seed.  Initial states are the far field with a seeded 1% density
+    perturbation; each case steps at its own CFL 0.1 time step."""
+    from workloads import cases as C
+    from workloads import meshes as M
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in range(n):
+        kind = "couette" if rng.random() < 0.5 else "vortex"
+        E_target = float(np.exp(rng.uniform(np.log(1000.0), np.log(50000.0))))
+        N = int(rng.integers(2, 6))
+        omega = float(rng.uniform(0.1, 2.0))
+        if kind == "vortex":
+            f = int(min(11, max(2, round(np.sqrt(E_target / 384.0)))))
+            mesh = M.vortex_mesh(f)
+            case = C.vortex_case(omega=omega)
+        else:
+            nr = int(min(112, max(16, 2 * round(np.sqrt(E_target / 4.0) / 2.0))))
+            mesh = M.couette_mesh(nr, 4 * nr, phi_offset=0.37 * 2 * np.pi / (4 * nr))
+            case = C.couette_case(omega=omega)
+        E = len(mesh["zone"])
+        Q0 = C.perturbed_farfield_state(case, N, E, seed=seed + c).astype(np.float32)
+        xy = mesh["xy"][:, [0, 3, 6, 9]]
+        h = np.linalg.norm(xy - np.roll(xy, 1, axis=1), axis=-1).min()
+        rho, u, v, p = case["farfield"]
+        r_max = float(np.abs(mesh["xy"]).max())
+        lam = np.hypot(u, v) + np.sqrt(case["gamma"] * p / rho) + abs(omega) * r_max
+        out.append(dict(kind=kind, mesh=mesh, case=case, N=N, E=E, Q0=Q0,
+                        dt=0.1 * h / (lam * N * N)))
+    return out
+
+
+def batched_main(args):
+    """Aggregate throughput of the many-case workload: one batch (graphs,
+    then eager launches) against stepping every case on its own."""
+    import torch
+    from paper_1503_02198_amd import Batch, Mesh
+    ws = batch_workload()
+    meshes = [Mesh(w["mesh"], w["case"], w["N"], device=0) for w in ws]
+    qs = [torch.from_numpy(w["Q0"].ravel()).to("cuda:0") for w in ws]
+    works = [torch.empty(m.info["work_len"], dtype=torch.float32, device="cuda:0") for m in meshes]
+    dts = [w["dt"] for w in ws]
+    dof = sum(4 * w["N"] ** 2 * w["E"] for w in ws)
+    steps = args.steps
+    batch = Batch(meshes)
+    res = {}
+    for mode in ("graph", "eager"):
+        graph = mode == "graph"
+        batch.rk_steps(qs, works, [0.0] * len(ws), dts, args.warmup, graph=graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.rk_steps(qs, works, [0.0] * len(ws), dts, steps, graph=graph)
+        torch.cuda.synchronize()
+        res[mode] = time.perf_counter() - t0
+    # every case on its own, one after the other on the same stream
+    for m, q, wk, w in zip(meshes, qs, works, ws):
+        m.rk_steps(q, wk, 0.0, w["dt"], args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for m, q, wk, w in zip(meshes, qs, works, ws):
+        m.rk_steps(q, wk, 0.0, w["dt"], steps)
+    torch.cuda.synchronize()
+    res["separate"] = time.perf_counter() - t0
+    for m in meshes:
+        m.check()
+    groups = batch.groups()
+    rate = {k: dof * 3 * steps / v for k, v in res.items()}
+    print(json.dumps({
+        "metric": "aggregate DOF-updates/s per RK stage, 64-case batch",
+        "value": rate["graph"], "unit": "DOF-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "64 Taylor-Couette and vortex instances, cells log-uniform in "
+                               "[1k, 50k], N in 2..5, omega in [0.1, 2], seed 20150307, SSP-RK3",
+                   "cells": sum(w["E"] for w in ws), "dof": dof,
+                   "kinds": {k: sum(w["kind"] == k for w in ws) for k in ("vortex", "couette")},
+                   "groups": groups},
+        "batched_graph": rate["graph"], "batched_eager": rate["eager"],
+        "separate": rate["separate"], "speedup_vs_separate": rate["graph"] / rate["separate"],
+        "seconds": res}), flush=True)
+
+
 def traffic_for(kind_hash, E, N):
     """HBM bytes per stage launch from the committed rocprofv3 counter runs,
     or None when the kernels changed since the counters were taken."""
@@ -166,6 +250,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true")
+    ap.add_argument("--batched", action="store_true",
+                    help="the 64-case batch workload instead of the headline run")
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV",
                                                           "CALIB_FETCH_CSV", "CALIB_WRITE_CSV"))
     args = ap.parse_args()
@@ -183,6 +269,9 @@ def main():
         sys.exit(2)
     if args.calib_copy:
         calib_copy()
+        return
+    if args.batched:
+        batched_main(args)
         return
 
     from paper_1503_02198_amd import Mesh

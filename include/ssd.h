@@ -209,26 +209,34 @@ const char *ssd_last_error(void);
  * Batches: many meshes of one device stepped together.  A batch groups its
  * meshes by (N, viscous); per RK stage every group runs one mortar launch,
  * (viscous) one gradient and one viscous-mortar launch, and one stage
- * launch, each walking a device table of (mesh, 64-cell tile or interface
- * chunk) pairs with a persistent grid.  The stage kernel's grid is chosen by
- * timing candidate grids on the first call (an autotuner keyed by N,
- * viscous and the group's tile count, shared by the process).  With
+ * launch, each with one block per item of a device table of (mesh, 64-cell
+ * tile or interface chunk) pairs.  Groups share no data, so each group's
+ * whole chain of launches runs on one of up to SSD_BATCH_MAX_STREAMS
+ * streams, forked from and joined back to the caller's stream.  On the
+ * first call an autotuner times every group's stage alone, then the
+ * stage of the whole batch with 1, 2, ... streams (groups dealt to streams
+ * longest first by their measured times), and keeps the fastest.  With
  * use_graph, one and two steps are captured as HIP graphs on the first call
  * for a scheme and replayed; the stage time is read from a device step
- * counter, so the graphs do not depend on t.
+ * counter per group, so the graphs do not depend on t.
  *
  * The batch references the meshes: they must outlive it, and no other call
- * may use them while a batch call runs.
+ * may use them while a batch call runs.  Calls on one batch must not
+ * overlap.
  */
 typedef struct ssd_batch ssd_batch;
+
+#define SSD_BATCH_MAX_STREAMS 4
 
 typedef struct {
   int32_t n_groups;     /* groups in the batch                                 */
   int32_t N;            /* solution points per direction of this group         */
   int32_t viscous;
   int32_t tiles;        /* 64-cell tiles over all meshes of the group          */
-  int32_t stage_grid;   /* persistent blocks of its stage kernel               */
-  int32_t tuned;        /* 1 once the autotuner has chosen stage_grid          */
+  int32_t stream;       /* stream index of the group's launches                */
+  int32_t n_streams;    /* streams the batch uses (1..SSD_BATCH_MAX_STREAMS)   */
+  int32_t tuned;        /* 1 once the autotuner has run                        */
+  float stage_us;       /* the group's stage alone, as timed by the autotuner  */
 } ssd_batch_group;
 
 /* n >= 1 distinct meshes, all on one device.  Errors: SSD_ERR_INVALID_ARG. */

@@ -5,9 +5,6 @@
 
 #include <algorithm>
 #include <cmath>
-#include <map>
-#include <mutex>
-#include <tuple>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -980,7 +977,6 @@ ssd_status ssd_timing_read(ssd_mesh *m, int kernel, double *total_ms, int64_t *l
 
 struct ssd_batch {
   int device = 0;
-  int ncu = 1;
   std::vector<ssd_mesh *> meshes;
   struct Group {
     int N = 0;
@@ -988,18 +984,22 @@ struct ssd_batch {
     OpTables T{};
     MortarTables MT{};
     uint2 *stage_work = nullptr, *mortar_work = nullptr, *trace_work = nullptr;
-    int nstage = 0, nmortar = 0, ntrace = 0;
-    int stage_grid = 0;    // persistent blocks of the stage kernel (autotuned)
-    int stage_per_cu = 0;  // resident stage blocks per compute unit
-    bool tuned = false;
+    uint2 *comb_work = nullptr;
+    int nstage = 0, nmortar = 0, ntrace = 0, ncomb = 0;
+    double *step = nullptr;   // device step counter of the group
+    int stream = 0;           // index into ssd_batch::streams
+    float stage_ms = 0.0f;    // the group's stage alone (autotuner)
   };
   std::vector<Group> groups;
-  uint2 *comb_work = nullptr;
-  int ncomb = 0;
   std::vector<BatchCase> cases;
   BatchCase *dcases = nullptr;
-  double *step = nullptr;
+  double *steps = nullptr;   // one counter per group
   std::vector<void *> allocs;
+  hipStream_t streams[SSD_BATCH_MAX_STREAMS] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[SSD_BATCH_MAX_STREAMS] = {};
+  int nstreams = 1;
+  bool tuned = false;
   hipStream_t cap = nullptr;            // capture stream for the step graphs
   hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [scheme][2 steps?]
 };
@@ -1017,61 +1017,56 @@ hipError_t batch_alloc(ssd_batch *b, T **p, size_t count) {
   return e;
 }
 
-void batch_free(ssd_batch *b) {
+void batch_drop_graphs(ssd_batch *b) {
   for (auto &gs : b->graph)
     for (auto &g : gs)
-      if (g) (void)hipGraphExecDestroy(g);
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+}
+
+void batch_free(ssd_batch *b) {
+  batch_drop_graphs(b);
   if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (auto &s : b->streams)
+    if (s) (void)hipStreamDestroy(s);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (auto &e : b->join)
+    if (e) (void)hipEventDestroy(e);
   for (void *p : b->allocs) (void)hipFree(p);
   b->allocs.clear();
 }
 
-// Autotuned launch shape of the batched stage kernel, shared by all batches
-// of the process: resident blocks per compute unit of the persistent grid,
-// keyed by (N, viscous, log2 of the group's 64-cell tiles).
-std::mutex g_tune_mutex;
-std::map<std::tuple<int, int, int>, int> g_tune;
-
-int tile_bucket(int ntiles) {
-  int b = 0;
-  while ((1 << (b + 1)) <= ntiles) ++b;
-  return b;
-}
-
-// One RK stage of every group, eager launches on stream st.
-ssd_status batch_stage(ssd_batch *b, const BatchStage &S, hipStream_t st) {
-  for (auto &g : b->groups) {
-    const int mgrid = std::min(g.nmortar, 4 * b->ncu);
-    if (g.nmortar)
-      SSD_HIP(launch_batch_mortar(g.N, g.visc, b->dcases, g.mortar_work, g.nmortar, g.T, g.MT, S.cur,
-                                  S.c, b->step, mgrid, st),
-              "batched mortar launch");
-    if (g.visc) {
-      SSD_HIP(launch_batch_grad(g.N, b->dcases, g.stage_work, g.nstage, g.T, S.in, S.cur, S.c,
-                                b->step, g.stage_grid, st),
-              "batched gradient launch");
-      if (g.nmortar)
-        SSD_HIP(launch_batch_mortar_visc(g.N, b->dcases, g.mortar_work, g.nmortar, g.T, S.cur,
-                                         mgrid, st),
-                "batched viscous mortar launch");
-    }
-    SSD_HIP(launch_batch_stage(g.N, g.visc, b->dcases, g.stage_work, g.nstage, g.T, S, b->step,
-                               g.stage_grid, st),
-            "batched stage launch");
+// One RK stage of group g, launched on stream st.
+ssd_status group_stage(ssd_batch *b, const ssd_batch::Group &g, const BatchStage &S,
+                       hipStream_t st) {
+  SSD_HIP(launch_batch_mortar(g.N, g.visc, b->dcases, g.mortar_work, g.nmortar, g.T, g.MT, S.cur,
+                              S.c, g.step, st),
+          "batched mortar launch");
+  if (g.visc) {
+    SSD_HIP(launch_batch_grad(g.N, b->dcases, g.stage_work, g.nstage, g.T, S.in, S.cur, S.c,
+                              g.step, st),
+            "batched gradient launch");
+    SSD_HIP(launch_batch_mortar_visc(g.N, b->dcases, g.mortar_work, g.nmortar, g.T, S.cur, st),
+            "batched viscous mortar launch");
   }
+  SSD_HIP(launch_batch_stage(g.N, g.visc, b->dcases, g.stage_work, g.nstage, g.T, S, g.step, st),
+          "batched stage launch");
   return SSD_OK;
 }
 
-// One step of `scheme` for every case, eager launches; *cur is the face
-// buffer parity of the step's input and is advanced stage by stage.
-ssd_status batch_step(ssd_batch *b, ssd_rk scheme, int *cur, hipStream_t st) {
+// One step of `scheme` for group g on stream st; *cur is the face buffer
+// parity of the step's input and is advanced stage by stage.
+ssd_status group_step(ssd_batch *b, const ssd_batch::Group &g, ssd_rk scheme, int *cur,
+                      hipStream_t st) {
   if (scheme == SSD_RK3_SSP) {
     const float B3[3] = {1.0f, 0.25f, 2.0f / 3.0f};
     const double C3[3] = {0.0, 1.0, 0.5};
     const int in[3] = {0, 1, 2}, qn[3] = {-1, 0, 0}, out[3] = {1, 2, 0};
     for (int k = 0; k < 3; ++k) {
-      if (ssd_status e = batch_stage(b, BatchStage{in[k], qn[k], out[k], -1, *cur, B3[k], B3[k],
-                                                   C3[k]}, st))
+      if (ssd_status e = group_stage(b, g, BatchStage{in[k], qn[k], out[k], -1, *cur, B3[k], B3[k],
+                                                      C3[k]}, st))
         return e;
       *cur ^= 1;
     }
@@ -1080,91 +1075,134 @@ ssd_status batch_step(ssd_batch *b, ssd_rk scheme, int *cur, hipStream_t st) {
     for (int k = 1; k < 4; ++k) tau[k + 1] = RK54_A[k][1] * tau[k] + RK54_A[k][2];
     const int in[4] = {0, 1, 2, 1}, out[4] = {1, 2, 1, 3};
     for (int k = 0; k < 4; ++k) {
-      if (ssd_status e = batch_stage(b, BatchStage{in[k], k ? 0 : -1, out[k], -1, *cur,
-                                                   float(RK54_A[k][1]), float(RK54_A[k][2]),
-                                                   tau[k]}, st))
+      if (ssd_status e = group_stage(b, g, BatchStage{in[k], k ? 0 : -1, out[k], -1, *cur,
+                                                      float(RK54_A[k][1]), float(RK54_A[k][2]),
+                                                      tau[k]}, st))
         return e;
       *cur ^= 1;
     }
     const double g4 = RK54_A[3][2];
-    SSD_HIP(launch_batch_combine(b->dcases, b->comb_work, b->ncomb, float(RK54_C[0]),
+    SSD_HIP(launch_batch_combine(b->dcases, g.comb_work, g.ncomb, float(RK54_C[0]),
                                  float(RK54_C[1] - RK54_C[2] * RK54_A[3][1] / g4),
-                                 float(RK54_C[2] / g4), std::min(b->ncomb, 8 * b->ncu), st),
+                                 float(RK54_C[2] / g4), st),
             "batched stage combination launch");
-    if (ssd_status e = batch_stage(b, BatchStage{3, 0, 0, 2, *cur, float(RK54_C[3]),
-                                                 float(RK54_C[4]), tau[4]}, st))
+    if (ssd_status e = group_stage(b, g, BatchStage{3, 0, 0, 2, *cur, float(RK54_C[3]),
+                                                    float(RK54_C[4]), tau[4]}, st))
       return e;
     *cur ^= 1;
   }
-  SSD_HIP(launch_step_count(b->step, st), "step counter launch");
+  SSD_HIP(launch_step_count(g.step, st), "step counter launch");
   return SSD_OK;
 }
 
-// Picks the persistent grid of each group's stage kernel by timing a few
-// launches of each candidate on the real data.  Trial launches write only
-// scratch (work array 3 and the face buffer of parity 1).
+// Fork: the batch streams in use wait for what is queued on `st`.
+ssd_status batch_fork(ssd_batch *b, hipStream_t st) {
+  SSD_HIP(hipEventRecord(b->fork, st), "fork event");
+  for (int k = 0; k < b->nstreams; ++k)
+    SSD_HIP(hipStreamWaitEvent(b->streams[k], b->fork, 0), "fork wait");
+  return SSD_OK;
+}
+
+// Join: `st` waits for everything queued on the batch streams in use.
+ssd_status batch_join(ssd_batch *b, hipStream_t st) {
+  for (int k = 0; k < b->nstreams; ++k) {
+    SSD_HIP(hipEventRecord(b->join[k], b->streams[k]), "join event");
+    SSD_HIP(hipStreamWaitEvent(st, b->join[k], 0), "join wait");
+  }
+  return SSD_OK;
+}
+
+// nsteps steps of every group, each group on its stream, between a fork
+// from and a join to `st`; the face parity starts and ends at `*cur`
+// (updated).
+ssd_status batch_steps(ssd_batch *b, ssd_rk scheme, int nsteps, int *cur, hipStream_t st) {
+  if (ssd_status e = batch_fork(b, st)) return e;
+  int c_end = *cur;
+  for (const auto &g : b->groups) {
+    int c = *cur;
+    for (int s = 0; s < nsteps; ++s)
+      if (ssd_status e = group_step(b, g, scheme, &c, b->streams[g.stream])) return e;
+    c_end = c;
+  }
+  *cur = c_end;
+  return batch_join(b, st);
+}
+
+// Deals the groups to n streams, longest measured stage first, each to the
+// stream with the least work so far.
+void assign_streams(ssd_batch *b, int n) {
+  std::vector<int> order(b->groups.size());
+  for (size_t k = 0; k < order.size(); ++k) order[k] = int(k);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return b->groups[x].stage_ms > b->groups[y].stage_ms;
+  });
+  std::vector<double> load(n, 0.0);
+  for (int k : order) {
+    const int s = int(std::min_element(load.begin(), load.end()) - load.begin());
+    b->groups[k].stream = s;
+    load[s] += b->groups[k].stage_ms;
+  }
+  b->nstreams = n;
+}
+
+// Autotuner: times each group's stage alone, then one stage of the whole
+// batch on 1, 2, ... streams, and keeps the fastest stream count.  The
+// trial stage reads the state and face buffer 0 (traces already formed)
+// and writes only what the first real stage rewrites before reading: the
+// mortar records and viscous buffers of face buffer 0, work array 3 and
+// face buffer 1.
 ssd_status batch_tune(ssd_batch *b, hipStream_t st) {
-  hipEvent_t e0, e1;
+  if (b->tuned) return SSD_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   SSD_HIP(hipEventCreate(&e0), "event");
-  SSD_HIP(hipEventCreate(&e1), "event");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(SSD_ERR_DEVICE, "event");
+  }
+  const BatchStage S{0, -1, 3, -1, 0, 1.0f, 0.0f, 0.0};
+  auto timed = [&](auto &&body, float *ms) -> ssd_status {
+    *ms = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {   // best of three after the first
+      float t = 0.0f;
+      if (hipEventRecord(e0, st) != hipSuccess) return fail(SSD_ERR_DEVICE, "tuning event");
+      if (ssd_status e = body()) return e;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+        return fail(SSD_ERR_DEVICE, "tuning timing");
+      if (rep) *ms = std::min(*ms, t);
+    }
+    return SSD_OK;
+  };
   ssd_status result = SSD_OK;
   for (auto &g : b->groups) {
-    if (g.tuned) continue;
-    const auto key = std::make_tuple(g.N, int(g.visc), tile_bucket(g.nstage));
-    {
-      std::lock_guard<std::mutex> lock(g_tune_mutex);
-      auto it = g_tune.find(key);
-      if (it != g_tune.end()) {
-        g.stage_grid = std::min(g.nstage, it->second * b->ncu);
-        g.tuned = true;
-        continue;
-      }
-    }
-    // the trial stage reads the mortar (and viscous) inputs of face buffer 0
-    const int mgrid = std::min(g.nmortar, 4 * b->ncu);
-    if (g.nmortar &&
-        launch_batch_mortar(g.N, g.visc, b->dcases, g.mortar_work, g.nmortar, g.T, g.MT, 0, 0.0,
-                            b->step, mgrid, st) != hipSuccess)
-      result = fail(SSD_ERR_DEVICE, "stage kernel tuning failed");
-    if (!result && g.visc &&
-        (launch_batch_grad(g.N, b->dcases, g.stage_work, g.nstage, g.T, 0, 0, 0.0, b->step,
-                           g.stage_grid, st) != hipSuccess ||
-         (g.nmortar && launch_batch_mortar_visc(g.N, b->dcases, g.mortar_work, g.nmortar, g.T, 0,
-                                                mgrid, st) != hipSuccess)))
-      result = fail(SSD_ERR_DEVICE, "stage kernel tuning failed");
+    result = timed([&]() { return group_stage(b, g, S, st); }, &g.stage_ms);
     if (result) break;
-    const BatchStage S{0, -1, 3, -1, 0, 1.0f, 0.0f, 0.0};
-    int best_pc = g.stage_per_cu;
-    float best = 1e30f;
-    for (int pc = 1; pc <= g.stage_per_cu; ++pc) {
-      const int grid = std::min(g.nstage, pc * b->ncu);
-      float ms = 0.0f;
-      for (int rep = 0; rep < 2; ++rep) {   // first repetition warms up
-        if (hipEventRecord(e0, st) != hipSuccess ||
-            launch_batch_stage(g.N, g.visc, b->dcases, g.stage_work, g.nstage, g.T, S, b->step,
-                               grid, st) != hipSuccess ||
-            hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-          result = fail(SSD_ERR_DEVICE, "stage kernel tuning failed");
-          break;
-        }
-      }
-      if (result) break;
-      if (ms < best) {
-        best = ms;
-        best_pc = pc;
-      }
-      if (grid == g.nstage) break;   // more blocks than tiles changes nothing
+  }
+  const int maxs = std::min<int>(SSD_BATCH_MAX_STREAMS, int(b->groups.size()));
+  int best_n = 1;
+  float best = 1e30f;
+  for (int n = 1; n <= maxs && !result; ++n) {
+    assign_streams(b, n);
+    float ms = 0.0f;
+    result = timed(
+        [&]() -> ssd_status {
+          if (ssd_status e = batch_fork(b, st)) return e;
+          for (const auto &g : b->groups)
+            if (ssd_status e = group_stage(b, g, S, b->streams[g.stream])) return e;
+          return batch_join(b, st);
+        },
+        &ms);
+    if (!result && ms < best) {
+      best = ms;
+      best_n = n;
     }
-    if (result) break;
-    g.stage_grid = std::min(g.nstage, best_pc * b->ncu);
-    g.tuned = true;
-    std::lock_guard<std::mutex> lock(g_tune_mutex);
-    g_tune[key] = best_pc;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  return result;
+  if (result) return result;
+  assign_streams(b, best_n);
+  b->tuned = true;
+  return SSD_OK;
 }
 
 }  // namespace
@@ -1192,13 +1230,8 @@ ssd_status ssd_batch_create(ssd_mesh *const *meshes, int32_t n, ssd_batch **out)
   };
   try {
     b->meshes.assign(meshes, meshes + n);
-    if (hipDeviceGetAttribute(&b->ncu, hipDeviceAttributeMultiprocessorCount, b->device) !=
-        hipSuccess)
-      return bail(fail(SSD_ERR_DEVICE, "query compute units"));
-    b->ncu = std::max(b->ncu, 1);
-    // groups of equal (N, viscous)
-    std::vector<std::vector<uint2>> sw, mw, tw;
-    std::vector<uint2> cw;
+    // groups of equal (N, viscous) and their work tables
+    std::vector<std::vector<uint2>> sw, mw, tw, cw;
     for (int c = 0; c < n; ++c) {
       const ssd_mesh *m = meshes[c];
       int gi = -1;
@@ -1214,16 +1247,20 @@ ssd_status ssd_batch_create(ssd_mesh *const *meshes, int32_t n, ssd_batch **out)
         sw.emplace_back();
         mw.emplace_back();
         tw.emplace_back();
+        cw.emplace_back();
         gi = int(b->groups.size()) - 1;
       }
       for (int t = 0; t < (m->E + EB - 1) / EB; ++t) sw[gi].push_back(make_uint2(c, t));
       const int fpb = 256 / m->N;
       for (int k = 0; k < (2 * m->K + fpb - 1) / fpb; ++k) mw[gi].push_back(make_uint2(c, k));
-      for (int k = 0; k < (m->E + 255) / 256; ++k) tw[gi].push_back(make_uint2(c, k));
+      for (int k = 0; k < (m->E + TRACE_BLOCK - 1) / TRACE_BLOCK; ++k)
+        tw[gi].push_back(make_uint2(c, k));
       const long len = 4L * m->N * m->N * m->E;
-      for (long k = 0; k < (len + 255) / 256; ++k) cw.push_back(make_uint2(c, unsigned(k)));
+      for (long k = 0; k < (len + 255) / 256; ++k) cw[gi].push_back(make_uint2(c, unsigned(k)));
     }
-    auto upload = [&](const std::vector<uint2> &v, uint2 **p) -> hipError_t {
+    auto upload = [&](const std::vector<uint2> &v, uint2 **p, int *count) -> hipError_t {
+      if (v.size() > size_t(0x7fffffff)) return hipErrorInvalidValue;
+      *count = int(v.size());
       hipError_t e = batch_alloc(b, p, v.size());
       if (e == hipSuccess && !v.empty())
         e = hipMemcpy(*p, v.data(), v.size() * sizeof(uint2), hipMemcpyHostToDevice);
@@ -1231,19 +1268,12 @@ ssd_status ssd_batch_create(ssd_mesh *const *meshes, int32_t n, ssd_batch **out)
     };
     for (size_t k = 0; k < b->groups.size(); ++k) {
       auto &g = b->groups[k];
-      if (upload(sw[k], &g.stage_work) != hipSuccess || upload(mw[k], &g.mortar_work) != hipSuccess ||
-          upload(tw[k], &g.trace_work) != hipSuccess)
+      if (upload(sw[k], &g.stage_work, &g.nstage) != hipSuccess ||
+          upload(mw[k], &g.mortar_work, &g.nmortar) != hipSuccess ||
+          upload(tw[k], &g.trace_work, &g.ntrace) != hipSuccess ||
+          upload(cw[k], &g.comb_work, &g.ncomb) != hipSuccess)
         return bail(fail(SSD_ERR_NOMEM, "batch work tables"));
-      g.nstage = int(sw[k].size());
-      g.nmortar = int(mw[k].size());
-      g.ntrace = int(tw[k].size());
-      if (batch_stage_blocks_per_cu(g.N, g.visc, &g.stage_per_cu) != hipSuccess || g.stage_per_cu < 1)
-        return bail(fail(SSD_ERR_DEVICE, "batched stage occupancy"));
-      g.stage_grid = std::min(g.nstage, g.stage_per_cu * b->ncu);
     }
-    if (cw.size() > size_t(0x7fffffff)) return bail(fail(SSD_ERR_INVALID_ARG, "batch too large"));
-    if (upload(cw, &b->comb_work) != hipSuccess) return bail(fail(SSD_ERR_NOMEM, "batch tables"));
-    b->ncomb = int(cw.size());
     b->cases.resize(n);
     for (int c = 0; c < n; ++c) {
       const ssd_mesh *m = meshes[c];
@@ -1258,10 +1288,19 @@ ssd_status ssd_batch_create(ssd_mesh *const *meshes, int32_t n, ssd_batch **out)
       B.V = m->V;
     }
     if (batch_alloc(b, &b->dcases, size_t(n)) != hipSuccess ||
-        batch_alloc(b, &b->step, size_t(1)) != hipSuccess)
+        batch_alloc(b, &b->steps, b->groups.size()) != hipSuccess)
       return bail(fail(SSD_ERR_NOMEM, "batch descriptors"));
+    for (size_t k = 0; k < b->groups.size(); ++k) b->groups[k].step = b->steps + k;
     if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
       return bail(fail(SSD_ERR_DEVICE, "batch capture stream"));
+    for (auto &s : b->streams)
+      if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(SSD_ERR_DEVICE, "batch streams"));
+    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
+      return bail(fail(SSD_ERR_DEVICE, "batch events"));
+    for (auto &e : b->join)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(SSD_ERR_DEVICE, "batch events"));
   } catch (const std::bad_alloc &) {
     return bail(fail(SSD_ERR_NOMEM, "host allocation failed"));
   }
@@ -1307,45 +1346,42 @@ ssd_status ssd_batch_rk_steps(ssd_batch *b, float *const *q, float *const *work,
     B.buf[0] = q[c];
     for (int k = 1; k < 4; ++k) B.buf[k] = work[c] + (k - 1) * len;
   }
-  // descriptors and the step counter, ordered before the work on `st`
+  // descriptors and the step counters, ordered before the work on `st`
   SSD_HIP(hipStreamSynchronize(st), "stream synchronize");
   SSD_HIP(hipMemcpy(b->dcases, b->cases.data(), n * sizeof(BatchCase), hipMemcpyHostToDevice),
           "upload batch descriptors");
-  SSD_HIP(hipMemset(b->step, 0, sizeof(double)), "clear step counter");
-  for (auto &g : b->groups)
-    SSD_HIP(launch_batch_traces(g.N, b->dcases, g.trace_work, g.ntrace, g.T,
-                                std::min(g.ntrace, 8 * b->ncu), st),
+  SSD_HIP(hipMemset(b->steps, 0, b->groups.size() * sizeof(double)), "clear step counters");
+  for (const auto &g : b->groups)
+    SSD_HIP(launch_batch_traces(g.N, b->dcases, g.trace_work, g.ntrace, g.T, st),
             "batched trace launch");
-  if (ssd_status e = batch_tune(b, st)) return e;
-  int cur = 0;
-  if (!use_graph) {
-    for (int s = 0; s < nsteps; ++s)
-      if (ssd_status e = batch_step(b, scheme, &cur, st)) return e;
-  } else {
-    // graphs of two steps and of one step, each starting at face parity 0;
-    // a step has an odd number of stages, so two steps return to parity 0
-    const int si = scheme == SSD_RK3_SSP ? 0 : 1;
-    for (int k = 0; k < 2; ++k) {
-      if (b->graph[si][k]) continue;
-      hipGraph_t gr = nullptr;
-      SSD_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
-      int c0 = 0;
-      ssd_status e = SSD_OK;
-      for (int s = 0; s < (k ? 2 : 1) && !e; ++s) e = batch_step(b, scheme, &c0, b->cap);
-      hipError_t he = hipStreamEndCapture(b->cap, &gr);
-      if (e) {
-        if (gr) (void)hipGraphDestroy(gr);
-        return e;
-      }
-      SSD_HIP(he, "end capture");
-      he = hipGraphInstantiate(&b->graph[si][k], gr, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(gr);
-      SSD_HIP(he, "graph instantiate");
-    }
-    for (int s = 0; s + 1 < nsteps; s += 2)
-      SSD_HIP(hipGraphLaunch(b->graph[si][1], st), "graph launch");
-    if (nsteps % 2) SSD_HIP(hipGraphLaunch(b->graph[si][0], st), "graph launch");
+  if (!b->tuned) {
+    if (ssd_status e = batch_tune(b, st)) return e;
+    batch_drop_graphs(b);   // captured before the stream assignment was final
   }
+  int cur = 0;
+  if (!use_graph) return batch_steps(b, scheme, nsteps, &cur, st);
+  // graphs of two steps and of one step, each starting at face parity 0;
+  // a step has an odd number of stages, so two steps return to parity 0
+  const int si = scheme == SSD_RK3_SSP ? 0 : 1;
+  for (int k = 0; k < 2; ++k) {
+    if (b->graph[si][k]) continue;
+    hipGraph_t gr = nullptr;
+    SSD_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+    int c0 = 0;
+    ssd_status e = batch_steps(b, scheme, k ? 2 : 1, &c0, b->cap);
+    hipError_t he = hipStreamEndCapture(b->cap, &gr);
+    if (e) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return e;
+    }
+    SSD_HIP(he, "end capture");
+    he = hipGraphInstantiate(&b->graph[si][k], gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    SSD_HIP(he, "graph instantiate");
+  }
+  for (int s = 0; s + 1 < nsteps; s += 2)
+    SSD_HIP(hipGraphLaunch(b->graph[si][1], st), "graph launch");
+  if (nsteps % 2) SSD_HIP(hipGraphLaunch(b->graph[si][0], st), "graph launch");
   for (int c = 0; c < n; ++c) {
     ssd_mesh *m = b->meshes[c];
     m->theta = m->theta0 + m->omega0 * (t[c] + nsteps * dt[c]);
@@ -1364,8 +1400,10 @@ ssd_status ssd_batch_query(const ssd_batch *b, int32_t group, ssd_batch_group *i
   info->N = g.N;
   info->viscous = g.visc;
   info->tiles = g.nstage;
-  info->stage_grid = g.stage_grid;
-  info->tuned = g.tuned;
+  info->stream = g.stream;
+  info->n_streams = b->nstreams;
+  info->tuned = b->tuned;
+  info->stage_us = 1000.0f * g.stage_ms;
   return SSD_OK;
 }
 

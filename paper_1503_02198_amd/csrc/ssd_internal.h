@@ -35,6 +35,7 @@ __host__ __device__ inline bool face_exported(uint32_t w) {
          ((k == SSD_FACE_INTERIOR || k == SSD_FACE_PERIODIC) && !face_inblock_of(w));
 }
 constexpr int MAX_ELEMS = 1 << 25;
+constexpr int TRACE_BLOCK = 256;   // elements per block of the trace kernel
 
 // Element flag word: bit 0 cubic map, bit 1 rotating zone, bits 8.. cubic slot.
 constexpr int EF_CUBIC = 1;
@@ -186,25 +187,24 @@ struct BatchStage {
   double c;
 };
 
-// Grid-stride batched launchers; `work` tables hold (case, tile/chunk).
+// Batched launchers: one block per item of `work`, a table of (case, tile
+// or chunk) pairs; `step` points at the group's step counter.
 hipError_t launch_batch_traces(int N, const BatchCase *cases, const uint2 *work, int nwork,
-                               const OpTables &T, int grid, hipStream_t s);
+                               const OpTables &T, hipStream_t s);
 hipError_t launch_batch_mortar(int N, bool visc, const BatchCase *cases, const uint2 *work,
                                int nwork, const OpTables &T, const MortarTables &MT, int cur,
-                               double c, const double *step, int grid, hipStream_t s);
+                               double c, const double *step, hipStream_t s);
 hipError_t launch_batch_grad(int N, const BatchCase *cases, const uint2 *work, int nwork,
                              const OpTables &T, int in, int cur, double c, const double *step,
-                             int grid, hipStream_t s);
+                             hipStream_t s);
 hipError_t launch_batch_mortar_visc(int N, const BatchCase *cases, const uint2 *work, int nwork,
-                                    const OpTables &T, int cur, int grid, hipStream_t s);
+                                    const OpTables &T, int cur, hipStream_t s);
 hipError_t launch_batch_stage(int N, bool visc, const BatchCase *cases, const uint2 *work,
                               int nwork, const OpTables &T, const BatchStage &S,
-                              const double *step, int grid, hipStream_t s);
+                              const double *step, hipStream_t s);
 hipError_t launch_batch_combine(const BatchCase *cases, const uint2 *work, int nwork, float w2,
-                                float w3, float w4, int grid, hipStream_t s);
+                                float w3, float w4, hipStream_t s);
 hipError_t launch_step_count(double *step, hipStream_t s);
-// Resident blocks per compute unit of the batched stage kernel.
-hipError_t batch_stage_blocks_per_cu(int N, bool visc, int *blocks);
 
 // W = w2 (u2 - un) + w3 (u3 - un) + w4 (u4 - un) over n floats.
 hipError_t launch_rk_combine(long n, const float *un, const float *u2, const float *u3,

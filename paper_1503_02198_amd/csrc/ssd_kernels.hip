@@ -15,8 +15,6 @@
 
 namespace ssd {
 
-constexpr int TRACE_BLOCK = 256;
-
 // ---------------------------------------------------------------------------
 // face traces of a state, for the faces some other block reads
 // ---------------------------------------------------------------------------
@@ -1129,7 +1127,10 @@ hipError_t launch_rk_combine(long n, const float *un, const float *u2, const flo
 }
 
 // ---------------------------------------------------------------------------
-// batched kernels: the same tile and chunk bodies over a (case, index) table
+// batched kernels: the same tile and chunk bodies over a table of
+// (case, tile or chunk) items, one item per block.  A persistent grid-stride
+// loop over the items was measured slower: the compiler hoists per-tile
+// values out of the loop and the stage kernel loses half its occupancy.
 // ---------------------------------------------------------------------------
 // Rotation of a case at stage time offset c of step *step.
 __device__ __forceinline__ Rotation batch_rotation(const BatchCase &B, const double *step,
@@ -1140,92 +1141,76 @@ __device__ __forceinline__ Rotation batch_rotation(const BatchCase &B, const dou
   return Rotation{cs, sn, B.omega};
 }
 
-__device__ __forceinline__ uint2 batch_item(const uint2 *work, int k) {
-  const uint2 w = work[k];
+__device__ __forceinline__ uint2 batch_item(const uint2 *work) {
+  const uint2 w = work[blockIdx.x];
   return make_uint2(__builtin_amdgcn_readfirstlane(w.x), __builtin_amdgcn_readfirstlane(w.y));
 }
 
 template <int N>
 __global__ __launch_bounds__(TRACE_BLOCK) void kb_traces(const BatchCase *cases, const uint2 *work,
-                                                         int nwork, OpTables T) {
-  for (int k = blockIdx.x; k < nwork; k += gridDim.x) {
-    const uint2 it = batch_item(work, k);
-    const BatchCase &B = cases[it.x];
-    traces_block<N>(B.M, T, B.buf[0], B.face[0], int(it.y));
-  }
+                                                         OpTables T) {
+  const uint2 it = batch_item(work);
+  const BatchCase &B = cases[it.x];
+  traces_block<N>(B.M, T, B.buf[0], B.face[0], int(it.y));
 }
 
 template <int N, bool VISC>
 __global__ __launch_bounds__(MORTAR_BLOCK) void kb_mortar(const BatchCase *cases, const uint2 *work,
-                                                          int nwork, OpTables T, MortarTables MT,
-                                                          int cur, double c, const double *step) {
-  for (int k = blockIdx.x; k < nwork; k += gridDim.x) {
-    const uint2 it = batch_item(work, k);
-    const BatchCase &B = cases[it.x];
-    const double theta = B.theta0 + B.omega * (B.t0 + (step[0] + c) * B.dt);
-    float *fb = B.face[cur];
-    const long nt = 16L * N * B.M.E, nr = 8L * B.M.K * N;
-    mortar_chunk<N, VISC>(B.M, T, MT, theta, B.ms, fb, fb + nt, VISC ? fb + nt + nr : nullptr,
-                          int(it.y));
-    __syncthreads();
-  }
+                                                          OpTables T, MortarTables MT, int cur,
+                                                          double c, const double *step) {
+  const uint2 it = batch_item(work);
+  const BatchCase &B = cases[it.x];
+  const double theta = B.theta0 + B.omega * (B.t0 + (step[0] + c) * B.dt);
+  float *fb = B.face[cur];
+  const long nt = 16L * N * B.M.E, nr = 8L * B.M.K * N;
+  mortar_chunk<N, VISC>(B.M, T, MT, theta, B.ms, fb, fb + nt, VISC ? fb + nt + nr : nullptr,
+                        int(it.y));
 }
 
 template <int N>
 __global__ __launch_bounds__(64 * N) void kb_grad(const BatchCase *cases, const uint2 *work,
-                                                  int nwork, OpTables T, int in, int cur,
-                                                  double c, const double *step) {
-  for (int k = blockIdx.x; k < nwork; k += gridDim.x) {
-    const uint2 it = batch_item(work, k);
-    const BatchCase &B = cases[it.x];
-    const Rotation R = batch_rotation(B, step, c);
-    grad_tile<N>(B.M, T, R, B.buf[in], B.face[cur], B.V.G, B.V.gtr, int(it.y));
-    __syncthreads();
-  }
+                                                  OpTables T, int in, int cur, double c,
+                                                  const double *step) {
+  const uint2 it = batch_item(work);
+  const BatchCase &B = cases[it.x];
+  const Rotation R = batch_rotation(B, step, c);
+  grad_tile<N>(B.M, T, R, B.buf[in], B.face[cur], B.V.G, B.V.gtr, int(it.y));
 }
 
 template <int N>
 __global__ __launch_bounds__(MORTAR_BLOCK) void kb_mortar_visc(const BatchCase *cases,
-                                                               const uint2 *work, int nwork,
-                                                               OpTables T, int cur) {
-  for (int k = blockIdx.x; k < nwork; k += gridDim.x) {
-    const uint2 it = batch_item(work, k);
-    const BatchCase &B = cases[it.x];
-    const float *fb = B.face[cur];
-    const long nt = 16L * N * B.M.E, nr = 8L * B.M.K * N;
-    mortar_visc_chunk<N>(B.M, T, B.ms, fb + nt + nr, B.V.gtr, B.V.mvflux, int(it.y));
-    __syncthreads();
-  }
+                                                               const uint2 *work, OpTables T,
+                                                               int cur) {
+  const uint2 it = batch_item(work);
+  const BatchCase &B = cases[it.x];
+  const float *fb = B.face[cur];
+  const long nt = 16L * N * B.M.E, nr = 8L * B.M.K * N;
+  mortar_visc_chunk<N>(B.M, T, B.ms, fb + nt + nr, B.V.gtr, B.V.mvflux, int(it.y));
 }
 
 template <int N, bool VISC, bool ADD>
 __global__ __launch_bounds__(64 * N) void kb_stage(const BatchCase *cases, const uint2 *work,
-                                                   int nwork, OpTables T, BatchStage S,
-                                                   const double *step) {
-  for (int k = blockIdx.x; k < nwork; k += gridDim.x) {
-    const uint2 it = batch_item(work, k);
-    const BatchCase &B = cases[it.x];
-    const Rotation R = batch_rotation(B, step, S.c);
-    const ViscBufs V{B.V.G, B.V.gtr, B.V.mvflux};
-    const RKCoef C{S.beta, S.gamma, float(B.dt), ADD ? B.buf[S.add] : nullptr};
-    stage_tile<N, true, VISC, ADD>(B.M, T, R, B.buf[S.in], S.qn >= 0 ? B.buf[S.qn] : nullptr,
-                                   B.buf[S.out], B.face[S.cur], B.face[S.cur ^ 1], V, C,
-                                   int(it.y));
-    __syncthreads();
-  }
+                                                   OpTables T, BatchStage S, const double *step) {
+  const uint2 it = batch_item(work);
+  const BatchCase &B = cases[it.x];
+  const Rotation R = batch_rotation(B, step, S.c);
+  const ViscBufs V{B.V.G, B.V.gtr, B.V.mvflux};
+  const RKCoef C{S.beta, S.gamma, float(B.dt), ADD ? B.buf[S.add] : nullptr};
+  stage_tile<N, true, VISC, ADD>(B.M, T, R, B.buf[S.in], S.qn >= 0 ? B.buf[S.qn] : nullptr,
+                                 B.buf[S.out], B.face[S.cur], B.face[S.cur ^ 1], V, C, int(it.y));
 }
 
+// W = w2 (u2 - un) + w3 (u3 - un) + w4 (u4 - un) with un, u2, u3, u4 and W
+// the case's stage arrays 0, 2, 1, 3 and 2.
 __global__ __launch_bounds__(256) void kb_rk_combine(const BatchCase *cases, const uint2 *work,
-                                                     int nwork, float w2, float w3, float w4) {
-  for (int k = blockIdx.x; k < nwork; k += gridDim.x) {
-    const uint2 it = batch_item(work, k);
-    const BatchCase &B = cases[it.x];
-    const long n = 4L * B.M.N * B.M.N * B.M.E;
-    const long i = long(it.y) * 256 + threadIdx.x;
-    if (i < n) {
-      const float u = B.buf[0][i];
-      B.buf[2][i] = w2 * (B.buf[2][i] - u) + w3 * (B.buf[1][i] - u) + w4 * (B.buf[3][i] - u);
-    }
+                                                     float w2, float w3, float w4) {
+  const uint2 it = batch_item(work);
+  const BatchCase &B = cases[it.x];
+  const long n = 4L * B.M.N * B.M.N * B.M.E;
+  const long i = long(it.y) * 256 + threadIdx.x;
+  if (i < n) {
+    const float u = B.buf[0][i];
+    B.buf[2][i] = w2 * (B.buf[2][i] - u) + w3 * (B.buf[1][i] - u) + w4 * (B.buf[3][i] - u);
   }
 }
 
@@ -1234,46 +1219,51 @@ __global__ void k_step_count(double *step) {
 }
 
 hipError_t launch_batch_traces(int N, const BatchCase *cases, const uint2 *work, int nwork,
-                               const OpTables &T, int grid, hipStream_t s) {
-  SSD_DISPATCH_N(N, hipLaunchKernelGGL(kb_traces<NN>, dim3(grid), dim3(TRACE_BLOCK), 0, s, cases,
-                                       work, nwork, T));
+                               const OpTables &T, hipStream_t s) {
+  if (nwork < 1) return hipSuccess;
+  SSD_DISPATCH_N(N, hipLaunchKernelGGL(kb_traces<NN>, dim3(nwork), dim3(TRACE_BLOCK), 0, s, cases,
+                                       work, T));
   return hipGetLastError();
 }
 
 hipError_t launch_batch_mortar(int N, bool visc, const BatchCase *cases, const uint2 *work,
                                int nwork, const OpTables &T, const MortarTables &MT, int cur,
-                               double c, const double *step, int grid, hipStream_t s) {
+                               double c, const double *step, hipStream_t s) {
+  if (nwork < 1) return hipSuccess;
   if (visc) {
-    SSD_DISPATCH_N(N, hipLaunchKernelGGL((kb_mortar<NN, true>), dim3(grid), dim3(MORTAR_BLOCK), 0,
-                                         s, cases, work, nwork, T, MT, cur, c, step));
+    SSD_DISPATCH_N(N, hipLaunchKernelGGL((kb_mortar<NN, true>), dim3(nwork), dim3(MORTAR_BLOCK),
+                                         0, s, cases, work, T, MT, cur, c, step));
   } else {
-    SSD_DISPATCH_N(N, hipLaunchKernelGGL((kb_mortar<NN, false>), dim3(grid), dim3(MORTAR_BLOCK),
-                                         0, s, cases, work, nwork, T, MT, cur, c, step));
+    SSD_DISPATCH_N(N, hipLaunchKernelGGL((kb_mortar<NN, false>), dim3(nwork), dim3(MORTAR_BLOCK),
+                                         0, s, cases, work, T, MT, cur, c, step));
   }
   return hipGetLastError();
 }
 
 hipError_t launch_batch_grad(int N, const BatchCase *cases, const uint2 *work, int nwork,
                              const OpTables &T, int in, int cur, double c, const double *step,
-                             int grid, hipStream_t s) {
-  SSD_DISPATCH_N(N, hipLaunchKernelGGL(kb_grad<NN>, dim3(grid), dim3(EB * NN), 0, s, cases, work,
-                                       nwork, T, in, cur, c, step));
+                             hipStream_t s) {
+  if (nwork < 1) return hipSuccess;
+  SSD_DISPATCH_N(N, hipLaunchKernelGGL(kb_grad<NN>, dim3(nwork), dim3(EB * NN), 0, s, cases, work,
+                                       T, in, cur, c, step));
   return hipGetLastError();
 }
 
 hipError_t launch_batch_mortar_visc(int N, const BatchCase *cases, const uint2 *work, int nwork,
-                                    const OpTables &T, int cur, int grid, hipStream_t s) {
-  SSD_DISPATCH_N(N, hipLaunchKernelGGL(kb_mortar_visc<NN>, dim3(grid), dim3(MORTAR_BLOCK), 0, s,
-                                       cases, work, nwork, T, cur));
+                                    const OpTables &T, int cur, hipStream_t s) {
+  if (nwork < 1) return hipSuccess;
+  SSD_DISPATCH_N(N, hipLaunchKernelGGL(kb_mortar_visc<NN>, dim3(nwork), dim3(MORTAR_BLOCK), 0, s,
+                                       cases, work, T, cur));
   return hipGetLastError();
 }
 
 hipError_t launch_batch_stage(int N, bool visc, const BatchCase *cases, const uint2 *work,
                               int nwork, const OpTables &T, const BatchStage &S,
-                              const double *step, int grid, hipStream_t s) {
-#define SSD_BSTAGE(VV, AV)                                                                     \
-  SSD_DISPATCH_N(N, hipLaunchKernelGGL((kb_stage<NN, VV, AV>), dim3(grid), dim3(EB * NN), 0, s, \
-                                       cases, work, nwork, T, S, step))
+                              const double *step, hipStream_t s) {
+  if (nwork < 1) return hipSuccess;
+#define SSD_BSTAGE(VV, AV)                                                                      \
+  SSD_DISPATCH_N(N, hipLaunchKernelGGL((kb_stage<NN, VV, AV>), dim3(nwork), dim3(EB * NN), 0, s, \
+                                       cases, work, T, S, step))
   const bool add = S.add >= 0;
   if (visc) {
     if (add) {
@@ -1293,26 +1283,15 @@ hipError_t launch_batch_stage(int N, bool visc, const BatchCase *cases, const ui
 }
 
 hipError_t launch_batch_combine(const BatchCase *cases, const uint2 *work, int nwork, float w2,
-                                float w3, float w4, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(kb_rk_combine, dim3(grid), dim3(256), 0, s, cases, work, nwork, w2, w3, w4);
+                                float w3, float w4, hipStream_t s) {
+  if (nwork < 1) return hipSuccess;
+  hipLaunchKernelGGL(kb_rk_combine, dim3(nwork), dim3(256), 0, s, cases, work, w2, w3, w4);
   return hipGetLastError();
 }
 
 hipError_t launch_step_count(double *step, hipStream_t s) {
   hipLaunchKernelGGL(k_step_count, dim3(1), dim3(64), 0, s, step);
   return hipGetLastError();
-}
-
-hipError_t batch_stage_blocks_per_cu(int N, bool visc, int *blocks) {
-  *blocks = 0;
-  if (visc) {
-    SSD_DISPATCH_N(N, return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                       blocks, kb_stage<NN, true, false>, EB * NN, 0));
-  } else {
-    SSD_DISPATCH_N(N, return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                       blocks, kb_stage<NN, false, false>, EB * NN, 0));
-  }
-  return hipSuccess;
 }
 
 }  // namespace ssd

@@ -47,7 +47,8 @@ class MeshDesc(ctypes.Structure):
 
 class BatchGroup(ctypes.Structure):
     _fields_ = [("n_groups", ctypes.c_int32), ("N", ctypes.c_int32), ("viscous", ctypes.c_int32),
-                ("tiles", ctypes.c_int32), ("stage_grid", ctypes.c_int32), ("tuned", ctypes.c_int32)]
+                ("tiles", ctypes.c_int32), ("stream", ctypes.c_int32), ("n_streams", ctypes.c_int32),
+                ("tuned", ctypes.c_int32), ("stage_us", ctypes.c_float)]
 
 
 class Info(ctypes.Structure):

@@ -75,7 +75,8 @@ def test_batch_matches_single_meshes(torch_cuda, scheme, graph):
     groups = batch.groups()
     print("groups", groups, flush=True)
     assert sorted((g["N"], g["viscous"]) for g in groups) == [(2, 1), (3, 0), (3, 1), (4, 0), (5, 0)]
-    assert all(g["tuned"] and 1 <= g["stage_grid"] <= g["tiles"] for g in groups)
+    assert all(g["tuned"] and 0 <= g["stream"] < g["n_streams"] <= 4 and g["stage_us"] > 0
+               for g in groups)
     for k, (gm, (m, c, N, Q, t0, dt)) in enumerate(zip(meshes, cs)):
         got = from_gpu(qs[k], N, gm.info["n_elem"])
         err = state_error(got, ref[k])
