@@ -30,7 +30,7 @@ METRIC = "DOF-updates/s per RK stage at stated L2 error; learned-coarse vs plain
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_ellipse_n4.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1503_02198_amd", "csrc", f)
-                  for f in ("ssd_kernels.hip", "ssd_device.h", "ssd_internal.h")]
+                  for f in ("ssd_kernels.hip", "ssd_tiles.h", "ssd_device.h", "ssd_internal.h")]
 
 
 def kernel_hash():

@@ -133,7 +133,7 @@ struct ViscIO {
   float *mvflux;   // viscous mortar flux [slot][point][4]
 };
 
-// Kernel launchers (defined in ssd_kernels.hip).
+// Kernel launchers (single mesh: ssd_kernels.hip; batched: ssd_batch.hip).
 hipError_t launch_traces(const DevMesh &M, const OpTables &T, const float *q, float *tr,
                          hipStream_t s);
 hipError_t launch_rebuild(const DevMesh &M, const MortarTables &MT, double theta, MortarState *ms,
