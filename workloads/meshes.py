@@ -88,7 +88,7 @@ def _block(P, curves=None, zone=0, tile=None):
             xy[line - 1, :, 5] = fn(jj, 2.0 / 3.0)
             geom[line - 1, :] = GEOM_CUBIC
     out = dict(xy=xy.reshape(-1, 12, 2), geom=geom.reshape(-1),
-               zone=np.full(ni * nj, zone, np.int32))
+               zone=np.full(ni * nj, zone, np.int32), sid=np.arange(ni * nj))
     if tile is not None:
         tj, ti = tile
         # full bands of ti rows use tj x ti tiles; a last band of r < ti rows
@@ -106,6 +106,73 @@ def _block(P, curves=None, zone=0, tile=None):
         order = np.argsort(key.ravel(), kind="stable")
         out = {k: v[order] for k, v in out.items()}
     return out
+
+
+def _refine_block(P, curves=None):
+    """Nodes and curves of the block whose cells are the 2 x 2 children of
+    the cells of block (P, curves), each child an exact piece of its
+    parent's map.  A parent with a curved edge is its bilinear map plus the
+    curve's deviation from the chord blended linearly across the cell, so
+    the line through the parent's middle is a curve too: the average of the
+    curved edge and the opposite chord.  Returns (Pf, curves_f)."""
+    curves = curves or {}
+    ni, nj = P.shape[0] - 1, P.shape[1] - 1
+    Pf = np.empty((2 * ni + 1, 2 * nj + 1, 2))
+    Pf[0::2, 0::2] = P
+    Pf[1::2, 0::2] = 0.5 * (P[:-1] + P[1:])
+    Pf[0::2, 1::2] = 0.5 * (P[:, :-1] + P[:, 1:])
+    Pf[1::2, 1::2] = 0.25 * (P[:-1, :-1] + P[1:, :-1] + P[:-1, 1:] + P[1:, 1:])
+
+    def chord(line, j, t):
+        j = np.asarray(j)
+        t = np.asarray(t, dtype=float)[..., None]
+        return (1.0 - t) * P[line, j] + t * P[line, j + 1]
+
+    def fine_fn(fn):
+        def g(jf, t):
+            jf = np.asarray(jf)
+            return fn(jf // 2, (jf % 2 + np.asarray(t, dtype=float)) / 2.0)
+        return g
+
+    def mid_fn(fn, opposite):
+        def g(jf, t):
+            jf = np.asarray(jf)
+            eta = (jf % 2 + np.asarray(t, dtype=float)) / 2.0
+            j = jf // 2
+            return 0.5 * (fn(j, eta) + chord(opposite, j, eta))
+        return g
+
+    curves_f = {}
+    jj = np.arange(nj)
+    for line, fn in curves.items():
+        curves_f[2 * line] = fine_fn(fn)
+        Pf[2 * line, 1::2] = fn(jj, 0.5)
+        for mid, opp in ((2 * line + 1, line + 1), (2 * line - 1, line - 1)):
+            if 0 < mid < 2 * ni:
+                if mid in curves_f:
+                    raise ValueError("a cell with two curved edges cannot be refined")
+                curves_f[mid] = mid_fn(fn, opp)
+                Pf[mid, 1::2] = curves_f[mid](2 * jj, 1.0)
+    return Pf, curves_f
+
+
+def _children(coarse_blocks, fine_blocks):
+    """children[c, a + 2 b]: the fine element of child (a, b) of coarse
+    element c, for blocks refined by _refine_block and concatenated in the
+    same order (a along xi = the block's i, b along eta = its j)."""
+    out, off_c, off_f = [], 0, 0
+    for (bc, nj), bf in zip(coarse_blocks, fine_blocks):
+        pos = np.empty(len(bf["sid"]), np.int64)
+        pos[bf["sid"]] = np.arange(len(bf["sid"]))
+        i, j = bc["sid"] // nj, bc["sid"] % nj
+        ch = np.empty((len(bc["sid"]), 4), np.int64)
+        for b in range(2):
+            for a in range(2):
+                ch[:, a + 2 * b] = pos[(2 * i + a) * (2 * nj) + 2 * j + b] + off_f
+        out.append(ch)
+        off_c += len(bc["sid"])
+        off_f += len(bf["sid"])
+    return np.concatenate(out).astype(np.int32)
 
 
 def _concat(blocks):
@@ -348,12 +415,16 @@ def _geometric(n, first):
 
 
 def ellipse_mesh(K=4096, n_in=64, n_out=180, semi=(0.5, 0.1), radius=3.0,
-                 box_half=30.0, first_in=2e-3, first_out=4e-3, tile=(16, 4)):
-    """Slip-wall ellipse in a rotating disk r < radius inside a stationary
-    box [-B,B]^2 with far-field sides.  K azimuthal cells, n_in rotating and
-    n_out stationary layers (defaults: 4096 x (64 + 180) = 999,424 cells),
-    numbered in tiles of 16 azimuthal x 4 radial cells (tile=None: ring by
-    ring)."""
+                 box_half=30.0, first_in=2e-3, first_out=4e-3, tile=(16, 4),
+                 wall=FACE_WALL_SLIP, nested=False):
+    """Ellipse wall (slip, or `wall`) in a rotating disk r < radius inside a
+    stationary box [-B,B]^2 with far-field sides.  K azimuthal cells, n_in
+    rotating and n_out stationary layers (defaults: 4096 x (64 + 180) =
+    999,424 cells), numbered in tiles of 16 azimuthal x 4 radial cells
+    (tile=None: ring by ring).  nested=True returns (coarse, fine, children):
+    the fine mesh splits every cell 2 x 2 in its reference square (2K
+    faces per interface side) and children[c, a + 2 b] is the fine element
+    of child (a, b) of coarse element c."""
     if K % 4:
         raise ValueError("K must be a multiple of 4")
     c = np.zeros(2)
@@ -370,8 +441,9 @@ def ellipse_mesh(K=4096, n_in=64, n_out=180, semi=(0.5, 0.1), radius=3.0,
         ang = (np.asarray(j) + t) * dphi
         return np.column_stack([a * np.cos(ang), b * np.sin(ang)])
 
-    inner = _block(_wrap(Pin), curves={0: ell_fn, n_in: _circle_fn(c, radius, 0.0, dphi)}, zone=1,
-                   tile=tile)
+    inner_P = _wrap(Pin)
+    inner_curves = {0: ell_fn, n_in: _circle_fn(c, radius, 0.0, dphi)}
+    inner = _block(inner_P, curves=inner_curves, zone=1, tile=tile)
 
     phi = -np.pi / 4 + dphi * np.arange(K)
     Cout = np.column_stack([radius * np.cos(phi), radius * np.sin(phi)])
@@ -380,12 +452,9 @@ def ellipse_mesh(K=4096, n_in=64, n_out=180, semi=(0.5, 0.1), radius=3.0,
     g = _geometric(n_out, first_out)
     Pout = (1 - g)[:, None, None] * Cout[None] + g[:, None, None] * Bx[None]
     Pout[0], Pout[-1] = Cout, Bx
-    outer = _block(_wrap(Pout), curves={0: _circle_fn(c, radius, -np.pi / 4, dphi)}, zone=0,
-                   tile=tile)
-
-    mesh = _concat([inner, outer])
-    mesh["center"] = c
-    mesh["radius"] = float(radius)
+    outer_P = _wrap(Pout)
+    outer_curves = {0: _circle_fn(c, radius, -np.pi / 4, dphi)}
+    outer = _block(outer_P, curves=outer_curves, zone=0, tile=tile)
     tol = 1e-9 * box_half
 
     def classify(ends, z):
@@ -395,10 +464,25 @@ def ellipse_mesh(K=4096, n_in=64, n_out=180, semi=(0.5, 0.1), radius=3.0,
                         | (np.abs(np.abs(ends[..., 1]) - box_half) <= tol), axis=-1)
         k[on_box] = FACE_FARFIELD
         r2 = (ends[..., 0] / a) ** 2 + (ends[..., 1] / b) ** 2
-        k[np.all(np.abs(r2 - 1.0) < 1e-9, axis=-1)] = FACE_WALL_SLIP
+        k[np.all(np.abs(r2 - 1.0) < 1e-9, axis=-1)] = wall
         return k
 
-    return connect(mesh, classify)
+    def finish(blocks):
+        mesh = _concat(blocks)
+        mesh["center"] = c
+        mesh["radius"] = float(radius)
+        return connect(mesh, classify)
+
+    coarse = finish([inner, outer])
+    if not nested:
+        return coarse
+    fine_blocks = []
+    for P, cv, z in ((inner_P, inner_curves, 1), (outer_P, outer_curves, 0)):
+        Pf, cf = _refine_block(P, cv)
+        fine_blocks.append(_block(Pf, curves=cf, zone=z, tile=tile))
+    fine = finish(fine_blocks)
+    children = _children([(inner, K), (outer, K)], fine_blocks)
+    return coarse, fine, children
 
 
 # ----------------------------------------------------------------------------
