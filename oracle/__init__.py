@@ -17,6 +17,8 @@ coupled rotating and stationary domains" (arXiv:1503.02198):
   ssd.py       the residual, the dynamic mortars and SSP-RK3 (Sec. 3)
   exact.py     the isentropic vortex (Sec. 4.1) and Taylor-Couette (Sec. 4.2)
                exact solutions
+  subgrid.py   the learned per-element correction (an extension, not in the
+               paper): features, restriction of nested meshes, the MLP
 
 Everything is vectorised numpy over elements in float64; numpy routines
 (einsum, polynomial algebra, solve) serve as the library primitives.
