@@ -278,6 +278,117 @@ ssd_status ssd_timing_enable(ssd_mesh *m, int classes);
 ssd_status ssd_timing_reset(ssd_mesh *m);
 ssd_status ssd_timing_read(ssd_mesh *m, int kernel, double *total_ms, int64_t *launches);
 
+/*
+ * Learned per-element subgrid correction (an extension of the method; not
+ * in the paper).  A coarse run of N = 2..4 solution points per direction
+ * adds, in every SSP-RK3 stage, a correction C(Q) to dQ/dt: per element, a
+ * small MLP maps the element's 4 N^2 solution-point values and its
+ * neighbours' face traces (16 N values) to 4 N^2 corrections.  The network
+ * is trained on fine runs of the solver: a nested fine mesh (every coarse
+ * cell split 2 x 2 in its reference square) is restricted to the coarse
+ * one, and the target is the restricted fine dQ/dt minus the coarse
+ * residual of the restricted state.
+ *
+ * Network: xn = (x - mu_x) / sig_x, h1 = tanh(W1 xn + b1), h2 = tanh(W2 h1
+ * + b2), yn = W3 h2 + b3, y = yn sig_y + mu_y; hidden width
+ * SSD_MLP_HIDDEN.  Products run on the BF16 matrix cores (operands rounded
+ * to bfloat16, FP32 accumulation); biases, tanh and the update are FP32.
+ *
+ * Feature layout of element e, n_in = 4 N^2 + 16 N values per row:
+ *   [v N^2 + j N + i]            Q[v][j][i] of the element (state layout)
+ *   [4 N^2 + (f N + p) 4 + v]    variable v of the neighbour's trace at
+ *                                point p of local face f (in the face's own
+ *                                parameter order); boundary and sliding
+ *                                faces use the element's own trace.
+ * Outputs (n_out = 4 N^2 per row) follow the state layout of one element.
+ */
+#define SSD_MLP_HIDDEN 64
+
+typedef struct ssd_mlp ssd_mlp;
+
+/* A network for meshes of N = 2..4 solution points per direction, on
+ * `device`, all parameters zero and the normalisation the identity.
+ * Errors: SSD_ERR_INVALID_ARG, SSD_ERR_NOMEM, SSD_ERR_DEVICE. */
+ssd_status ssd_mlp_create(int32_t N, int32_t device, ssd_mlp **out);
+ssd_status ssd_mlp_destroy(ssd_mlp *net);
+/* n_in and n_out of the network. */
+ssd_status ssd_mlp_dims(const ssd_mlp *net, int32_t *n_in, int32_t *n_out);
+
+/*
+ * Parameters as host FP32 arrays, row-major: W1 [H][n_in], b1 [H],
+ * W2 [H][H], b2 [H], W3 [n_out][H], b3 [n_out] (H = SSD_MLP_HIDDEN).
+ * Setting them also clears the optimiser state.  Both calls synchronise
+ * the device.
+ */
+ssd_status ssd_mlp_set_params(ssd_mlp *net, const float *W1, const float *b1, const float *W2,
+                              const float *b2, const float *W3, const float *b3);
+ssd_status ssd_mlp_get_params(const ssd_mlp *net, float *W1, float *b1, float *W2, float *b2,
+                              float *W3, float *b3);
+
+/* Normalisation as host FP32 arrays mu_x, sig_x [n_in], mu_y, sig_y [n_out];
+ * every sig > 0.  Errors: SSD_ERR_INVALID_ARG. */
+ssd_status ssd_mlp_set_normalization(ssd_mlp *net, const float *mu_x, const float *sig_x,
+                                     const float *mu_y, const float *sig_y);
+/* Fits the normalisation to n >= 2 rows of X [n][n_in] and T [n][n_out]
+ * (device): per-column mean and standard deviation; a column whose
+ * deviation is below 1e-6 (|mean| + 1e-30) gets sig = 1.  Synchronises. */
+ssd_status ssd_mlp_fit_normalization(ssd_mlp *net, const float *X, const float *T, int64_t n,
+                                     void *stream);
+
+/* Y [n][n_out] = the network of the rows X [n][n_in] (device, n >= 0). */
+ssd_status ssd_mlp_forward(ssd_mlp *net, const float *X, int64_t n, float *Y, void *stream);
+
+/*
+ * Loss gradient of the minibatch of rows idx[0..batch) of X [n_rows][n_in]
+ * and T [n_rows][n_out] (device; idx device int32, batch >= 1; an index
+ * outside [0, n_rows) contributes nothing).  The loss is the mean
+ * over the batch and the outputs of (yn - (t - mu_y) / sig_y)^2.  The
+ * gradient goes to host arrays laid out as ssd_mlp_get_params, the loss to
+ * *loss.  Parameters are not changed.  Synchronises.
+ */
+ssd_status ssd_mlp_gradient(ssd_mlp *net, const float *X, const float *T, int64_t n_rows,
+                            const int32_t *idx, int32_t batch, float *gW1, float *gb1, float *gW2,
+                            float *gb2, float *gW3, float *gb3, double *loss, void *stream);
+/*
+ * One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the
+ * loss of the minibatch idx[0..batch).  The minibatch losses are summed on
+ * the device; ssd_mlp_loss returns the sum and the number of steps since
+ * the last call (and synchronises).
+ */
+ssd_status ssd_mlp_train_step(ssd_mlp *net, const float *X, const float *T, int64_t n_rows,
+                              const int32_t *idx, int32_t batch, float lr, void *stream);
+ssd_status ssd_mlp_loss(ssd_mlp *net, double *loss_sum, int64_t *steps);
+
+/* Features of every element of state q (device, state layout) into the rows
+ * X [E][n_in] (device). */
+ssd_status ssd_subgrid_features(ssd_mesh *m, const float *q, float *X, void *stream);
+
+/*
+ * Restriction of a state qf of the nested fine mesh `fine` to its coarse
+ * parent mesh `coarse`: the L2 projection, in each coarse cell's reference
+ * square, of the fine piecewise polynomial onto the coarse polynomials,
+ * at the coarse solution points.  children [E_coarse][4] (device int32):
+ * the fine element of child (a, b) at index a + 2 b, child (a, b) covering
+ * [a/2, (a+1)/2] x [b/2, (b+1)/2] of the parent's reference square.
+ * qc is in the coarse state layout.  Supported (N coarse, N fine): (2, 2),
+ * (2, 4), (2, 6), (3, 3), (3, 6), (4, 6).  The child table is read back
+ * and checked (every entry in [0, E_fine)) before the launch, so the call
+ * synchronises with the device.
+ */
+ssd_status ssd_restrict(const ssd_mesh *fine, const ssd_mesh *coarse, const int32_t *children,
+                        const float *qf, float *qc, void *stream);
+/* Training targets T [E_coarse][4 N^2] = restriction of Rf (a fine dQ/dt)
+ * minus Rc (a coarse dQ/dt, state layout). */
+ssd_status ssd_subgrid_targets(const ssd_mesh *fine, const ssd_mesh *coarse,
+                               const int32_t *children, const float *Rf, const float *Rc, float *T,
+                               void *stream);
+
+/* Attaches `net` (same N and device) to mesh m: from then on ssd_rk_step(s)
+ * with SSD_RK3_SSP adds the correction in every stage (other schemes return
+ * SSD_ERR_INVALID_ARG).  net = NULL detaches (plain SSD).  The network must
+ * outlive the attachment. */
+ssd_status ssd_subgrid_attach(ssd_mesh *m, ssd_mlp *net);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libssd.so")
 SOURCES = [os.path.join(HERE, "csrc", f)
-           for f in ("ssd_host.hip", "ssd_kernels.hip", "ssd_batch.hip")]
+           for f in ("ssd_host.hip", "ssd_kernels.hip", "ssd_batch.hip", "ssd_mlp.hip")]
 HEADERS = [os.path.join(ROOT, "include", "ssd.h")] + [
     os.path.join(HERE, "csrc", f) for f in ("ssd_internal.h", "ssd_device.h", "ssd_tiles.h")]
 

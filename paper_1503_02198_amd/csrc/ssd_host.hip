@@ -301,6 +301,22 @@ struct ssd_mesh {
     std::vector<hipEvent_t> ev;   // start/stop pairs
     size_t used = 0;
   } timers[SSD_KERNEL_COUNT];
+  ssd_mlp *model = nullptr;            // learned correction added by ssd_rk_steps
+  float *addbuf = nullptr;             // its per-stage increment (state layout)
+};
+
+// A network of the learned subgrid correction.  FP32 parameters laid out
+// flat as [W1 | b1 | W2 | b2 | W3 | b3] with padded widths (see MlpDev).
+struct ssd_mlp {
+  int device = 0, N = 0, nin = 0, nout = 0, kin = 0, kout = 0;
+  long o_b1 = 0, o_W2 = 0, o_b2 = 0, o_W3 = 0, o_b3 = 0, plen = 0;
+  float *P = nullptr, *G = nullptr, *M = nullptr, *V = nullptr;
+  __bf16 *Wb = nullptr;     // W1 | W2 | W3 | W2t | W3t in bf16
+  float *norm = nullptr;    // mu_x [kin] | isig_x [kin] | mu_y [kout] | sig_y [kout]
+  double *acc = nullptr;    // summed minibatch losses, then moment sums
+  long steps = 0;           // Adam steps since the parameters were set
+  long loss_steps = 0;      // steps since the last ssd_mlp_loss
+  std::vector<void *> allocs;
 };
 
 namespace {
@@ -681,6 +697,25 @@ ssd_status check_handle(const ssd_mesh *m) {
   return SSD_OK;
 }
 
+MlpDev mlp_dev(const ssd_mlp *n) {
+  constexpr int H = MLP_HIDDEN;
+  const __bf16 *w = n->Wb;
+  MlpDev D;
+  D.W1 = w;
+  D.W2 = w + long(H) * n->kin;
+  D.W3 = D.W2 + H * H;
+  D.W2t = D.W3 + long(n->kout) * H;
+  D.W3t = D.W2t + H * H;
+  D.b1 = n->P + n->o_b1;
+  D.b2 = n->P + n->o_b2;
+  D.b3 = n->P + n->o_b3;
+  D.mu_x = n->norm;
+  D.isig_x = n->norm + n->kin;
+  D.mu_y = n->norm + 2 * n->kin;
+  D.sig_y = n->norm + 2 * n->kin + n->kout;
+  return D;
+}
+
 // One evaluation of the residual of `in` (face data in facein) at rotor
 // angle th: the mortar rebuild for th fused with the inviscid mortar; on
 // viscous meshes the gradient pass and the viscous mortar; then the stage
@@ -855,6 +890,8 @@ ssd_status ssd_rk_steps(ssd_mesh *m, float *q, float *work, double t, double dt,
   if (nsteps < 1) return fail(SSD_ERR_INVALID_ARG, "nsteps must be >= 1");
   if (scheme != SSD_RK3_SSP && scheme != SSD_RK54_SSP)
     return fail(SSD_ERR_INVALID_ARG, "unknown Runge-Kutta scheme");
+  if (m->model && scheme != SSD_RK3_SSP)
+    return fail(SSD_ERR_INVALID_ARG, "the learned correction is applied with SSP-RK3 only");
   const long len = 4L * m->N * m->N * m->E;
   const int nwork = scheme == SSD_RK3_SSP ? 2 : 3;
   if (overlap(q, len * sizeof(float), work, nwork * len * sizeof(float)))
@@ -885,9 +922,15 @@ ssd_status ssd_rk_steps(ssd_mesh *m, float *q, float *work, double t, double dt,
       const double Cs[3] = {0.0, 1.0, 0.5};
       const float *in[3] = {q, w1, w2};
       float *outp[3] = {w1, w2, q};
-      for (int k = 0; k < 3; ++k)
-        if (ssd_status e = stage(tn, Cs[k], in[k], k ? q : nullptr, outp[k], B[k], B[k], nullptr))
+      for (int k = 0; k < 3; ++k) {
+        if (m->model)   // learned correction: add = b_k dt C(Q_k), added by the stage
+          SSD_HIP(launch_subgrid(m->D, m->T, mlp_dev(m->model), in[k], m->addbuf,
+                                 float(B[k] * dt), st),
+                  "subgrid correction launch");
+        if (ssd_status e = stage(tn, Cs[k], in[k], k ? q : nullptr, outp[k], B[k], B[k],
+                                 m->model ? m->addbuf : nullptr))
           return e;
+      }
     } else {
       // SSPRK54 with U1, U3 in w1, U2 then the last stage's increment in w2,
       // U4 in w3; stage times follow the stage values
@@ -1404,6 +1447,413 @@ ssd_status ssd_batch_query(const ssd_batch *b, int32_t group, ssd_batch_group *i
   info->n_streams = b->nstreams;
   info->tuned = b->tuned;
   info->stage_us = 1000.0f * g.stage_ms;
+  return SSD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// learned per-element subgrid correction
+// ---------------------------------------------------------------------------
+namespace {
+
+template <class T>
+hipError_t mlp_alloc(ssd_mlp *n, T **p, size_t count) {
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+  if (e == hipSuccess) {
+    n->allocs.push_back(q);
+    *p = static_cast<T *>(q);
+    e = hipMemset(q, 0, std::max<size_t>(count, 1) * sizeof(T));
+  }
+  return e;
+}
+
+void mlp_free(ssd_mlp *n) {
+  for (void *p : n->allocs) (void)hipFree(p);
+  n->allocs.clear();
+}
+
+MlpGrad mlp_grad(const ssd_mlp *n) {
+  return MlpGrad{n->G, n->G + n->o_W2, n->G + n->o_W3, n->G + n->o_b1, n->G + n->o_b2,
+                 n->G + n->o_b3, n->acc};
+}
+
+MlpStore mlp_store(const ssd_mlp *n) {
+  const MlpDev D = mlp_dev(n);
+  MlpStore S;
+  S.P = n->P;
+  S.G = n->G;
+  S.M = n->M;
+  S.V = n->V;
+  S.W1b = const_cast<__bf16 *>(D.W1);
+  S.W2b = const_cast<__bf16 *>(D.W2);
+  S.W3b = const_cast<__bf16 *>(D.W3);
+  S.W2tb = const_cast<__bf16 *>(D.W2t);
+  S.W3tb = const_cast<__bf16 *>(D.W3t);
+  S.o_b1 = n->o_b1;
+  S.o_W2 = n->o_W2;
+  S.o_b2 = n->o_b2;
+  S.o_W3 = n->o_W3;
+  S.o_b3 = n->o_b3;
+  S.kin = n->kin;
+  S.kout = n->kout;
+  return S;
+}
+
+// host arrays (unpadded) <-> the flat padded layout
+void mlp_pack(const ssd_mlp *n, const float *W1, const float *b1, const float *W2, const float *b2,
+              const float *W3, const float *b3, std::vector<float> &flat) {
+  constexpr int H = MLP_HIDDEN;
+  flat.assign(n->plen, 0.0f);
+  for (int o = 0; o < H; ++o)
+    for (int i = 0; i < n->nin; ++i) flat[long(o) * n->kin + i] = W1[long(o) * n->nin + i];
+  for (int o = 0; o < H; ++o) flat[n->o_b1 + o] = b1[o];
+  for (int k = 0; k < H * H; ++k) flat[n->o_W2 + k] = W2[k];
+  for (int o = 0; o < H; ++o) flat[n->o_b2 + o] = b2[o];
+  for (int k = 0; k < n->nout * H; ++k) flat[n->o_W3 + k] = W3[k];
+  for (int o = 0; o < n->nout; ++o) flat[n->o_b3 + o] = b3[o];
+}
+
+void mlp_unpack(const ssd_mlp *n, const std::vector<float> &flat, float *W1, float *b1, float *W2,
+                float *b2, float *W3, float *b3) {
+  constexpr int H = MLP_HIDDEN;
+  for (int o = 0; o < H; ++o)
+    for (int i = 0; i < n->nin; ++i) W1[long(o) * n->nin + i] = flat[long(o) * n->kin + i];
+  for (int o = 0; o < H; ++o) b1[o] = flat[n->o_b1 + o];
+  for (int k = 0; k < H * H; ++k) W2[k] = flat[n->o_W2 + k];
+  for (int o = 0; o < H; ++o) b2[o] = flat[n->o_b2 + o];
+  for (int k = 0; k < n->nout * H; ++k) W3[k] = flat[n->o_W3 + k];
+  for (int o = 0; o < n->nout; ++o) b3[o] = flat[n->o_b3 + o];
+}
+
+ssd_status mlp_upload_norm(ssd_mlp *n, const float *mu_x, const float *sig_x, const float *mu_y,
+                           const float *sig_y) {
+  for (int i = 0; i < n->nin; ++i)
+    if (!std::isfinite(mu_x[i]) || !std::isfinite(sig_x[i]) || !(sig_x[i] > 0.0f))
+      return fail(SSD_ERR_INVALID_ARG, "input normalisation needs finite mu and sig > 0");
+  for (int o = 0; o < n->nout; ++o)
+    if (!std::isfinite(mu_y[o]) || !std::isfinite(sig_y[o]) || !(sig_y[o] > 0.0f))
+      return fail(SSD_ERR_INVALID_ARG, "output normalisation needs finite mu and sig > 0");
+  std::vector<float> h(2 * n->kin + 2 * n->kout, 0.0f);
+  for (int i = 0; i < n->nin; ++i) {
+    h[i] = mu_x[i];
+    h[n->kin + i] = 1.0f / sig_x[i];
+  }
+  for (int o = 0; o < n->kout; ++o) {
+    h[2 * n->kin + o] = o < n->nout ? mu_y[o] : 0.0f;
+    h[2 * n->kin + n->kout + o] = o < n->nout ? sig_y[o] : 1.0f;
+  }
+  DeviceGuard guard(n->device);
+  SSD_HIP(hipMemcpy(n->norm, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice),
+          "upload normalisation");
+  return SSD_OK;
+}
+
+// R[a][ic][if]: coarse SP values of the L2 projection on [0, 1] of the fine
+// basis function if of child half a, by Gauss-Legendre quadrature (exact
+// for these polynomial degrees).
+bool restriction_table(int Nc, int Nf, Restrict1D &R) {
+  const std::vector<double> Xc = solution_points(Nc), Xf = solution_points(Nf);
+  const std::vector<double> bc = bary_weights(Xc), bf = bary_weights(Xf);
+  std::vector<double> g, w;
+  gauss_legendre(Nc + Nf, g, w);
+  const int nq = int(g.size());
+  std::vector<double> Mm(Nc * Nc, 0.0), Mi;
+  for (int q = 0; q < nq; ++q) {
+    const double z = 0.5 * (g[q] + 1.0), wq = 0.5 * w[q];
+    const std::vector<double> h = cardinal(Xc, bc, z);
+    for (int k = 0; k < Nc; ++k)
+      for (int l = 0; l < Nc; ++l) Mm[k * Nc + l] += wq * h[k] * h[l];
+  }
+  if (!invert(Nc, Mm, Mi)) return false;
+  R = Restrict1D{};
+  for (int a = 0; a < 2; ++a) {
+    std::vector<double> b(Nc * Nf, 0.0);
+    for (int q = 0; q < nq; ++q) {
+      const double z = 0.5 * (g[q] + 1.0), wq = 0.5 * w[q];
+      const std::vector<double> hc = cardinal(Xc, bc, 0.5 * (a + z)), hf = cardinal(Xf, bf, z);
+      for (int k = 0; k < Nc; ++k)
+        for (int m = 0; m < Nf; ++m) b[k * Nf + m] += 0.5 * wq * hc[k] * hf[m];
+    }
+    for (int i = 0; i < Nc; ++i)
+      for (int m = 0; m < Nf; ++m) {
+        double s = 0.0;
+        for (int k = 0; k < Nc; ++k) s += Mi[i * Nc + k] * b[k * Nf + m];
+        R.r[a][i][m] = float(s);
+      }
+  }
+  return true;
+}
+
+ssd_status check_pair(const ssd_mesh *fine, const ssd_mesh *coarse, const int32_t *children) {
+  if (!fine || !coarse || !children) return fail(SSD_ERR_INVALID_ARG, "null mesh or child table");
+  if (fine->device != coarse->device)
+    return fail(SSD_ERR_INVALID_ARG, "fine and coarse meshes on different devices");
+  if (long(fine->E) != 4L * coarse->E)
+    return fail(SSD_ERR_INVALID_ARG, "the fine mesh must have 4 elements per coarse element");
+  // the kernels index the fine state by the table: check it here
+  std::vector<int32_t> ch(size_t(4) * coarse->E);
+  DeviceGuard guard(coarse->device);
+  SSD_HIP(hipMemcpy(ch.data(), children, ch.size() * sizeof(int32_t), hipMemcpyDeviceToHost),
+          "read child table");
+  for (int32_t c : ch)
+    if (c < 0 || c >= fine->E) return fail(SSD_ERR_INVALID_ARG, "child index out of range");
+  return SSD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ssd_status ssd_mlp_create(int32_t N, int32_t device, ssd_mlp **out) {
+  if (!out) return fail(SSD_ERR_INVALID_ARG, "null output pointer");
+  *out = nullptr;
+  if (N < 2 || N > 4) return fail(SSD_ERR_INVALID_ARG, "the learned correction supports N = 2..4");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(SSD_ERR_INVALID_ARG, "no such device");
+  ssd_mlp *n = new (std::nothrow) ssd_mlp();
+  if (!n) return fail(SSD_ERR_NOMEM, "host allocation failed");
+  constexpr int H = MLP_HIDDEN;
+  n->device = device;
+  n->N = N;
+  n->nin = 4 * N * N + 16 * N;
+  n->nout = 4 * N * N;
+  n->kin = (n->nin + 31) / 32 * 32;
+  n->kout = (n->nout + 31) / 32 * 32;
+  n->o_b1 = long(H) * n->kin;
+  n->o_W2 = n->o_b1 + H;
+  n->o_b2 = n->o_W2 + H * H;
+  n->o_W3 = n->o_b2 + H;
+  n->o_b3 = n->o_W3 + long(n->kout) * H;
+  n->plen = n->o_b3 + n->kout;
+  DeviceGuard guard(device);
+  const long nb = long(H) * n->kin + 2L * H * H + 2L * n->kout * H;
+  if (mlp_alloc(n, &n->P, n->plen) != hipSuccess || mlp_alloc(n, &n->G, n->plen) != hipSuccess ||
+      mlp_alloc(n, &n->M, n->plen) != hipSuccess || mlp_alloc(n, &n->V, n->plen) != hipSuccess ||
+      mlp_alloc(n, &n->Wb, nb) != hipSuccess ||
+      mlp_alloc(n, &n->norm, 2 * n->kin + 2 * n->kout) != hipSuccess ||
+      mlp_alloc(n, &n->acc, 1 + 2 * (n->nin + n->nout)) != hipSuccess) {
+    mlp_free(n);
+    delete n;
+    return fail(SSD_ERR_NOMEM, "network allocation failed");
+  }
+  std::vector<float> mu_x(n->nin, 0.0f), sx(n->nin, 1.0f), mu_y(n->nout, 0.0f), sy(n->nout, 1.0f);
+  if (ssd_status e = mlp_upload_norm(n, mu_x.data(), sx.data(), mu_y.data(), sy.data())) {
+    mlp_free(n);
+    delete n;
+    return e;
+  }
+  *out = n;
+  return SSD_OK;
+}
+
+ssd_status ssd_mlp_destroy(ssd_mlp *n) {
+  if (!n) return SSD_OK;
+  DeviceGuard guard(n->device);
+  (void)hipDeviceSynchronize();
+  mlp_free(n);
+  delete n;
+  return SSD_OK;
+}
+
+ssd_status ssd_mlp_dims(const ssd_mlp *n, int32_t *n_in, int32_t *n_out) {
+  if (!n || !n_in || !n_out) return fail(SSD_ERR_INVALID_ARG, "null argument");
+  *n_in = n->nin;
+  *n_out = n->nout;
+  return SSD_OK;
+}
+
+ssd_status ssd_mlp_set_params(ssd_mlp *n, const float *W1, const float *b1, const float *W2,
+                              const float *b2, const float *W3, const float *b3) {
+  if (!n || !W1 || !b1 || !W2 || !b2 || !W3 || !b3) return fail(SSD_ERR_INVALID_ARG, "null argument");
+  std::vector<float> flat;
+  mlp_pack(n, W1, b1, W2, b2, W3, b3, flat);
+  for (float x : flat)
+    if (!std::isfinite(x)) return fail(SSD_ERR_INVALID_ARG, "non-finite parameter");
+  DeviceGuard guard(n->device);
+  SSD_HIP(hipDeviceSynchronize(), "synchronize");
+  SSD_HIP(hipMemcpy(n->P, flat.data(), flat.size() * sizeof(float), hipMemcpyHostToDevice),
+          "upload parameters");
+  SSD_HIP(hipMemset(n->G, 0, n->plen * sizeof(float)), "clear gradient");
+  SSD_HIP(hipMemset(n->M, 0, n->plen * sizeof(float)), "clear moments");
+  SSD_HIP(hipMemset(n->V, 0, n->plen * sizeof(float)), "clear moments");
+  SSD_HIP(launch_mlp_sync(mlp_store(n), n->plen, nullptr), "weight copy launch");
+  SSD_HIP(hipDeviceSynchronize(), "synchronize");
+  n->steps = 0;
+  return SSD_OK;
+}
+
+ssd_status ssd_mlp_get_params(const ssd_mlp *n, float *W1, float *b1, float *W2, float *b2,
+                              float *W3, float *b3) {
+  if (!n || !W1 || !b1 || !W2 || !b2 || !W3 || !b3) return fail(SSD_ERR_INVALID_ARG, "null argument");
+  std::vector<float> flat(n->plen);
+  DeviceGuard guard(n->device);
+  SSD_HIP(hipDeviceSynchronize(), "synchronize");
+  SSD_HIP(hipMemcpy(flat.data(), n->P, flat.size() * sizeof(float), hipMemcpyDeviceToHost),
+          "read parameters");
+  mlp_unpack(n, flat, W1, b1, W2, b2, W3, b3);
+  return SSD_OK;
+}
+
+ssd_status ssd_mlp_set_normalization(ssd_mlp *n, const float *mu_x, const float *sig_x,
+                                     const float *mu_y, const float *sig_y) {
+  if (!n || !mu_x || !sig_x || !mu_y || !sig_y) return fail(SSD_ERR_INVALID_ARG, "null argument");
+  return mlp_upload_norm(n, mu_x, sig_x, mu_y, sig_y);
+}
+
+ssd_status ssd_mlp_fit_normalization(ssd_mlp *n, const float *X, const float *T, int64_t rows,
+                                     void *stream) {
+  if (!n || !X || !T) return fail(SSD_ERR_INVALID_ARG, "null argument");
+  if (rows < 2) return fail(SSD_ERR_INVALID_ARG, "need at least two rows");
+  DeviceGuard guard(n->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int nm = 2 * (n->nin + n->nout);
+  double *mom = n->acc + 1;
+  SSD_HIP(hipStreamSynchronize(st), "stream synchronize");
+  SSD_HIP(hipMemset(mom, 0, nm * sizeof(double)), "clear moments");
+  SSD_HIP(launch_moments(X, rows, n->nin, mom, st), "moment launch");
+  SSD_HIP(launch_moments(T, rows, n->nout, mom + 2 * n->nin, st), "moment launch");
+  SSD_HIP(hipStreamSynchronize(st), "stream synchronize");
+  std::vector<double> h(nm);
+  SSD_HIP(hipMemcpy(h.data(), mom, nm * sizeof(double), hipMemcpyDeviceToHost), "read moments");
+  auto fit = [&](const double *s, int cols, std::vector<float> &mu, std::vector<float> &sig) {
+    mu.resize(cols);
+    sig.resize(cols);
+    for (int c = 0; c < cols; ++c) {
+      const double m = s[c] / double(rows);
+      const double var = std::max(s[cols + c] / double(rows) - m * m, 0.0);
+      double sd = std::sqrt(var);
+      if (!(sd >= 1e-6 * (std::fabs(m) + 1e-30))) sd = 1.0;
+      mu[c] = float(m);
+      sig[c] = float(sd);
+    }
+  };
+  std::vector<float> mx, sx, my, sy;
+  fit(h.data(), n->nin, mx, sx);
+  fit(h.data() + 2 * n->nin, n->nout, my, sy);
+  return mlp_upload_norm(n, mx.data(), sx.data(), my.data(), sy.data());
+}
+
+ssd_status ssd_mlp_forward(ssd_mlp *n, const float *X, int64_t rows, float *Y, void *stream) {
+  if (!n || (rows > 0 && (!X || !Y))) return fail(SSD_ERR_INVALID_ARG, "null argument");
+  if (rows < 0) return fail(SSD_ERR_INVALID_ARG, "negative row count");
+  DeviceGuard guard(n->device);
+  SSD_HIP(launch_mlp_forward(n->N, mlp_dev(n), X, rows, Y, static_cast<hipStream_t>(stream)),
+          "network launch");
+  return SSD_OK;
+}
+
+ssd_status ssd_mlp_gradient(ssd_mlp *n, const float *X, const float *T, int64_t n_rows,
+                            const int32_t *idx, int32_t batch, float *gW1, float *gb1, float *gW2,
+                            float *gb2, float *gW3, float *gb3, double *loss, void *stream) {
+  if (!n || !X || !T || !idx || !gW1 || !gb1 || !gW2 || !gb2 || !gW3 || !gb3 || !loss)
+    return fail(SSD_ERR_INVALID_ARG, "null argument");
+  if (batch < 1 || n_rows < 1) return fail(SSD_ERR_INVALID_ARG, "need batch >= 1 and rows");
+  DeviceGuard guard(n->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SSD_HIP(hipStreamSynchronize(st), "stream synchronize");
+  SSD_HIP(hipMemset(n->G, 0, n->plen * sizeof(float)), "clear gradient");
+  SSD_HIP(hipMemset(n->acc, 0, sizeof(double)), "clear loss");
+  SSD_HIP(launch_mlp_grad(n->N, mlp_dev(n), mlp_grad(n), X, T, n_rows, idx, batch, st),
+          "gradient launch");
+  SSD_HIP(hipStreamSynchronize(st), "stream synchronize");
+  std::vector<float> flat(n->plen);
+  SSD_HIP(hipMemcpy(flat.data(), n->G, flat.size() * sizeof(float), hipMemcpyDeviceToHost),
+          "read gradient");
+  SSD_HIP(hipMemcpy(loss, n->acc, sizeof(double), hipMemcpyDeviceToHost), "read loss");
+  SSD_HIP(hipMemset(n->G, 0, n->plen * sizeof(float)), "clear gradient");
+  SSD_HIP(hipMemset(n->acc, 0, sizeof(double)), "clear loss");
+  n->loss_steps = 0;
+  mlp_unpack(n, flat, gW1, gb1, gW2, gb2, gW3, gb3);
+  return SSD_OK;
+}
+
+ssd_status ssd_mlp_train_step(ssd_mlp *n, const float *X, const float *T, int64_t n_rows,
+                              const int32_t *idx, int32_t batch, float lr, void *stream) {
+  if (!n || !X || !T || !idx) return fail(SSD_ERR_INVALID_ARG, "null argument");
+  if (batch < 1 || n_rows < 1) return fail(SSD_ERR_INVALID_ARG, "need batch >= 1 and rows");
+  if (!std::isfinite(lr) || lr < 0.0f) return fail(SSD_ERR_INVALID_ARG, "need a finite lr >= 0");
+  DeviceGuard guard(n->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SSD_HIP(launch_mlp_grad(n->N, mlp_dev(n), mlp_grad(n), X, T, n_rows, idx, batch, st),
+          "gradient launch");
+  ++n->steps;
+  ++n->loss_steps;
+  const double b1 = 0.9, b2 = 0.999;
+  SSD_HIP(launch_adam(mlp_store(n), n->plen, lr, float(b1), float(b2), 1e-8f,
+                      float(1.0 - std::pow(b1, double(n->steps))),
+                      float(1.0 - std::pow(b2, double(n->steps))), st),
+          "optimiser launch");
+  return SSD_OK;
+}
+
+ssd_status ssd_mlp_loss(ssd_mlp *n, double *loss_sum, int64_t *steps) {
+  if (!n || !loss_sum || !steps) return fail(SSD_ERR_INVALID_ARG, "null argument");
+  DeviceGuard guard(n->device);
+  SSD_HIP(hipDeviceSynchronize(), "synchronize");
+  SSD_HIP(hipMemcpy(loss_sum, n->acc, sizeof(double), hipMemcpyDeviceToHost), "read loss");
+  SSD_HIP(hipMemset(n->acc, 0, sizeof(double)), "clear loss");
+  *steps = n->loss_steps;
+  n->loss_steps = 0;
+  return SSD_OK;
+}
+
+ssd_status ssd_subgrid_features(ssd_mesh *m, const float *q, float *X, void *stream) {
+  if (ssd_status s = check_handle(m)) return s;
+  if (!q || !X) return fail(SSD_ERR_INVALID_ARG, "null state or output");
+  if (m->N > 4) return fail(SSD_ERR_INVALID_ARG, "the learned correction supports N = 2..4");
+  DeviceGuard guard(m->device);
+  SSD_HIP(launch_features(m->D, m->T, q, X, static_cast<hipStream_t>(stream)), "feature launch");
+  return SSD_OK;
+}
+
+ssd_status ssd_restrict(const ssd_mesh *fine, const ssd_mesh *coarse, const int32_t *children,
+                        const float *qf, float *qc, void *stream) {
+  if (ssd_status s = check_pair(fine, coarse, children)) return s;
+  if (!qf || !qc) return fail(SSD_ERR_INVALID_ARG, "null state");
+  Restrict1D R;
+  if (!restriction_table(coarse->N, fine->N, R))
+    return fail(SSD_ERR_INVALID_ARG, "restriction table");
+  DeviceGuard guard(coarse->device);
+  const hipError_t e = launch_restrict(coarse->N, fine->N, qf, fine->E, children, coarse->E, R,
+                                       nullptr, qc, false, static_cast<hipStream_t>(stream));
+  if (e == hipErrorInvalidValue)
+    return fail(SSD_ERR_INVALID_ARG, "unsupported pair of coarse and fine N");
+  SSD_HIP(e, "restriction launch");
+  return SSD_OK;
+}
+
+ssd_status ssd_subgrid_targets(const ssd_mesh *fine, const ssd_mesh *coarse,
+                               const int32_t *children, const float *Rf, const float *Rc, float *T,
+                               void *stream) {
+  if (ssd_status s = check_pair(fine, coarse, children)) return s;
+  if (!Rf || !Rc || !T) return fail(SSD_ERR_INVALID_ARG, "null array");
+  Restrict1D R;
+  if (!restriction_table(coarse->N, fine->N, R))
+    return fail(SSD_ERR_INVALID_ARG, "restriction table");
+  DeviceGuard guard(coarse->device);
+  const hipError_t e = launch_restrict(coarse->N, fine->N, Rf, fine->E, children, coarse->E, R, Rc,
+                                       T, true, static_cast<hipStream_t>(stream));
+  if (e == hipErrorInvalidValue)
+    return fail(SSD_ERR_INVALID_ARG, "unsupported pair of coarse and fine N");
+  SSD_HIP(e, "target launch");
+  return SSD_OK;
+}
+
+ssd_status ssd_subgrid_attach(ssd_mesh *m, ssd_mlp *net) {
+  if (ssd_status s = check_handle(m)) return s;
+  if (!net) {
+    m->model = nullptr;
+    return SSD_OK;
+  }
+  if (net->N != m->N) return fail(SSD_ERR_INVALID_ARG, "network and mesh have different N");
+  if (net->device != m->device) return fail(SSD_ERR_INVALID_ARG, "network on another device");
+  DeviceGuard guard(m->device);
+  if (!m->addbuf && dev_alloc(m, &m->addbuf, size_t(4) * m->N * m->N * m->E) != hipSuccess)
+    return fail(SSD_ERR_NOMEM, "correction buffer");
+  m->model = net;
   return SSD_OK;
 }
 

@@ -206,6 +206,65 @@ hipError_t launch_batch_combine(const BatchCase *cases, const uint2 *work, int n
                                 float w3, float w4, hipStream_t s);
 hipError_t launch_step_count(double *step, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// learned per-element subgrid correction (ssd_mlp.hip)
+// ---------------------------------------------------------------------------
+constexpr int MLP_HIDDEN = SSD_MLP_HIDDEN;
+
+// Read-only view of a network for the kernels.  bf16 weights, row-major with
+// padded widths KIN = 32 ceil(n_in / 32), KOUT = 32 ceil(n_out / 32):
+// W1 [H][KIN], W2 [H][H], W3 [KOUT][H], and the transposed W2t [H][H]
+// (W2t[i][o] = W2[o][i]) and W3t [H][KOUT].  FP32 biases and the
+// normalisation (padding entries 0, isig 0).
+struct MlpDev {
+  const __bf16 *W1, *W2, *W3, *W2t, *W3t;
+  const float *b1, *b2, *b3;
+  const float *mu_x, *isig_x;   // [KIN]
+  const float *mu_y, *sig_y;    // [KOUT]
+};
+
+// Gradient accumulators (FP32, same padded shapes) and the loss sum.
+struct MlpGrad {
+  float *W1, *W2, *W3, *b1, *b2, *b3;
+  double *loss;
+};
+
+// Flat FP32 parameters [W1 | b1 | W2 | b2 | W3 | b3] with their gradient and
+// Adam moments, and where the bf16 copies go.
+struct MlpStore {
+  float *P, *G, *M, *V;
+  __bf16 *W1b, *W2b, *W3b, *W2tb, *W3tb;
+  long o_b1, o_W2, o_b2, o_W3, o_b3;
+  int kin, kout;
+};
+
+// 1-D restriction operators r[a][ic][if] of the two child halves.
+struct Restrict1D {
+  float r[2][NMAX][NMAX];
+};
+
+hipError_t launch_features(const DevMesh &M, const OpTables &T, const float *q, float *X,
+                           hipStream_t s);
+// add[o][e] = scale * (MLP correction of element e), o in the state layout
+hipError_t launch_subgrid(const DevMesh &M, const OpTables &T, const MlpDev &P, const float *q,
+                          float *add, float scale, hipStream_t s);
+hipError_t launch_mlp_forward(int N, const MlpDev &P, const float *X, long n, float *Y,
+                              hipStream_t s);
+// adds the minibatch's loss gradient to G and its mean loss to *G.loss;
+// rows idx[s] outside [0, n_rows) are skipped
+hipError_t launch_mlp_grad(int N, const MlpDev &P, const MlpGrad &G, const float *X,
+                           const float *Tg, long n_rows, const int *idx, int batch,
+                           hipStream_t s);
+hipError_t launch_adam(const MlpStore &S, long n, float lr, float b1, float b2, float eps,
+                       float bc1, float bc2, hipStream_t s);
+hipError_t launch_mlp_sync(const MlpStore &S, long n, hipStream_t s);
+hipError_t launch_moments(const float *A, long n, int cols, double *acc, hipStream_t s);
+// out = restriction of qf (nested fine state) - sub (null: nothing); rows:
+// out[c][o], else the state layout out[o][c]
+hipError_t launch_restrict(int Nc, int Nf, const float *qf, long Ef, const int *children, long Ec,
+                           const Restrict1D &R, const float *sub, float *out, bool rows,
+                           hipStream_t s);
+
 // W = w2 (u2 - un) + w3 (u3 - un) + w4 (u4 - un) over n floats.
 hipError_t launch_rk_combine(long n, const float *un, const float *u2, const float *u3,
                              const float *u4, float w2, float w3, float w4, float *W,

@@ -21,7 +21,11 @@ SCHEMES = {"rk3": 0, "rk54": 1}   # ssd_rk
 EXPORTS = ["ssd_create_mesh", "ssd_destroy_mesh", "ssd_query", "ssd_set_rotation",
            "ssd_mortar_rebuild", "ssd_residual", "ssd_rk_step", "ssd_rk_steps", "ssd_check",
            "ssd_last_error", "ssd_timing_enable", "ssd_timing_reset", "ssd_timing_read",
-           "ssd_batch_create", "ssd_batch_destroy", "ssd_batch_rk_steps", "ssd_batch_query"]
+           "ssd_batch_create", "ssd_batch_destroy", "ssd_batch_rk_steps", "ssd_batch_query",
+           "ssd_mlp_create", "ssd_mlp_destroy", "ssd_mlp_dims", "ssd_mlp_set_params",
+           "ssd_mlp_get_params", "ssd_mlp_set_normalization", "ssd_mlp_fit_normalization",
+           "ssd_mlp_forward", "ssd_mlp_gradient", "ssd_mlp_train_step", "ssd_mlp_loss",
+           "ssd_subgrid_features", "ssd_restrict", "ssd_subgrid_targets", "ssd_subgrid_attach"]
 
 
 class SSDError(RuntimeError):
@@ -90,6 +94,23 @@ def lib():
                                          ctypes.POINTER(dbl), ctypes.POINTER(dbl), i32,
                                          ctypes.c_int, i32, vp]),
             "ssd_batch_query": (i32, [vp, i32, ctypes.POINTER(BatchGroup)]),
+            "ssd_mlp_create": (i32, [i32, i32, ctypes.POINTER(vp)]),
+            "ssd_mlp_destroy": (i32, [vp]),
+            "ssd_mlp_dims": (i32, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+            "ssd_mlp_set_params": (i32, [vp] + [ctypes.POINTER(ctypes.c_float)] * 6),
+            "ssd_mlp_get_params": (i32, [vp] + [ctypes.POINTER(ctypes.c_float)] * 6),
+            "ssd_mlp_set_normalization": (i32, [vp] + [ctypes.POINTER(ctypes.c_float)] * 4),
+            "ssd_mlp_fit_normalization": (i32, [vp, vp, vp, i64, vp]),
+            "ssd_mlp_forward": (i32, [vp, vp, i64, vp, vp]),
+            "ssd_mlp_gradient": (i32, [vp, vp, vp, i64, vp, i32]
+                                 + [ctypes.POINTER(ctypes.c_float)] * 6
+                                 + [ctypes.POINTER(dbl), vp]),
+            "ssd_mlp_train_step": (i32, [vp, vp, vp, i64, vp, i32, ctypes.c_float, vp]),
+            "ssd_mlp_loss": (i32, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
+            "ssd_subgrid_features": (i32, [vp, vp, vp, vp]),
+            "ssd_restrict": (i32, [vp, vp, vp, vp, vp, vp]),
+            "ssd_subgrid_targets": (i32, [vp, vp, vp, vp, vp, vp, vp]),
+            "ssd_subgrid_attach": (i32, [vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -214,6 +235,19 @@ class Mesh:
     def check(self, stream=None):
         _check(lib().ssd_check(self._h, _stream_ptr(stream, self.device)))
 
+    def features(self, q, X, stream=None):
+        """Rows X [E][4N^2 + 16N] of the learned correction's features of q."""
+        n_in = 4 * self.info["N"] ** 2 + 16 * self.info["N"]
+        _check(lib().ssd_subgrid_features(self._h, self._tensor(q, self.info["state_len"], "q"),
+                                          self._tensor(X, self.info["n_elem"] * n_in, "X"),
+                                          _stream_ptr(stream, self.device)))
+
+    def attach(self, net):
+        """Add the learned correction of `net` in every SSP-RK3 stage (None:
+        plain SSD).  The network must outlive the attachment."""
+        _check(lib().ssd_subgrid_attach(self._h, net._h if net is not None else None))
+        self._net = net
+
     def timing_enable(self, on=True, kernels=None):
         """Bracket launches with HIP events: every kernel class, or only
         `kernels` (names from KERNELS), or none (on=False)."""
@@ -283,3 +317,132 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def _f32(a, n, name):
+    a = np.ascontiguousarray(a, dtype=np.float32).reshape(-1)
+    if a.size != n:
+        raise ValueError(f"{name} must hold {n} values")
+    return a
+
+
+def _dev(t, n, name, dtype="float32", device=None):
+    import torch
+    want = getattr(torch, dtype)
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != want or not t.is_contiguous() or (n is not None and t.numel() != n):
+        raise ValueError(f"{name} must be contiguous {dtype}"
+                         + (f" with {n} elements" if n is not None else ""))
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{name} lives on device {t.device.index}, expected {device}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class MLP:
+    """Network of the learned per-element correction (a handle of the C
+    library): n_in = 4N^2 + 16N features, two tanh layers of HIDDEN, n_out =
+    4N^2 outputs, BF16 matrix products with FP32 accumulation."""
+
+    HIDDEN = 64
+
+    def __init__(self, N, device=0):
+        h = ctypes.c_void_p()
+        _check(lib().ssd_mlp_create(int(N), int(device), ctypes.byref(h)))
+        self._h = h
+        self.N = int(N)
+        self.device = int(device)
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().ssd_mlp_dims(self._h, ctypes.byref(a), ctypes.byref(b)))
+        self.n_in, self.n_out = a.value, b.value
+
+    def shapes(self):
+        H = self.HIDDEN
+        return dict(W1=(H, self.n_in), b1=(H,), W2=(H, H), b2=(H,), W3=(self.n_out, H),
+                    b3=(self.n_out,))
+
+    def set_params(self, p):
+        arrs = [_f32(p[k], int(np.prod(sh)), k) for k, sh in self.shapes().items()]
+        _check(lib().ssd_mlp_set_params(self._h, *[_ptr(a, ctypes.c_float) for a in arrs]))
+
+    def get_params(self):
+        out = {k: np.empty(sh, np.float32) for k, sh in self.shapes().items()}
+        _check(lib().ssd_mlp_get_params(self._h, *[_ptr(out[k], ctypes.c_float) for k in out]))
+        return out
+
+    def set_normalization(self, mu_x, sig_x, mu_y, sig_y):
+        a = [_f32(mu_x, self.n_in, "mu_x"), _f32(sig_x, self.n_in, "sig_x"),
+             _f32(mu_y, self.n_out, "mu_y"), _f32(sig_y, self.n_out, "sig_y")]
+        _check(lib().ssd_mlp_set_normalization(self._h, *[_ptr(x, ctypes.c_float) for x in a]))
+
+    def fit_normalization(self, X, T, stream=None):
+        n = X.numel() // self.n_in
+        _check(lib().ssd_mlp_fit_normalization(
+            self._h, _dev(X, n * self.n_in, "X", device=self.device),
+            _dev(T, n * self.n_out, "T", device=self.device), int(n),
+            _stream_ptr(stream, self.device)))
+
+    def forward(self, X, Y, stream=None):
+        n = X.numel() // self.n_in
+        _check(lib().ssd_mlp_forward(self._h, _dev(X, n * self.n_in, "X", device=self.device),
+                                     int(n), _dev(Y, n * self.n_out, "Y", device=self.device),
+                                     _stream_ptr(stream, self.device)))
+
+    def gradient(self, X, T, idx, stream=None):
+        """Loss and its gradient (host arrays) on the rows idx of X, T."""
+        n = X.numel() // self.n_in
+        out = {k: np.empty(sh, np.float32) for k, sh in self.shapes().items()}
+        loss = ctypes.c_double()
+        _check(lib().ssd_mlp_gradient(
+            self._h, _dev(X, n * self.n_in, "X", device=self.device),
+            _dev(T, n * self.n_out, "T", device=self.device), int(n),
+            _dev(idx, None, "idx", "int32", self.device), int(idx.numel()),
+            *[_ptr(out[k], ctypes.c_float) for k in out], ctypes.byref(loss),
+            _stream_ptr(stream, self.device)))
+        return loss.value, out
+
+    def train_step(self, X, T, idx, lr, stream=None):
+        n = X.numel() // self.n_in
+        _check(lib().ssd_mlp_train_step(
+            self._h, _dev(X, n * self.n_in, "X", device=self.device),
+            _dev(T, n * self.n_out, "T", device=self.device), int(n),
+            _dev(idx, None, "idx", "int32", self.device), int(idx.numel()), float(lr),
+            _stream_ptr(stream, self.device)))
+
+    def loss(self):
+        """Mean loss of the steps since the last call, and their count."""
+        s, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().ssd_mlp_loss(self._h, ctypes.byref(s), ctypes.byref(n)))
+        return (s.value / n.value if n.value else float("nan")), n.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ssd_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def restrict(fine, coarse, children, qf, qc, stream=None):
+    """qc = restriction of the fine state qf to the coarse parent mesh."""
+    _check(lib().ssd_restrict(fine._h, coarse._h,
+                              _dev(children, 4 * coarse.info["n_elem"], "children", "int32",
+                                   coarse.device),
+                              fine._tensor(qf, fine.info["state_len"], "qf"),
+                              coarse._tensor(qc, coarse.info["state_len"], "qc"),
+                              _stream_ptr(stream, coarse.device)))
+
+
+def subgrid_targets(fine, coarse, children, Rf, Rc, T, stream=None):
+    """T rows = restriction of the fine dQ/dt Rf minus the coarse Rc."""
+    _check(lib().ssd_subgrid_targets(fine._h, coarse._h,
+                                     _dev(children, 4 * coarse.info["n_elem"], "children",
+                                          "int32", coarse.device),
+                                     fine._tensor(Rf, fine.info["state_len"], "Rf"),
+                                     coarse._tensor(Rc, coarse.info["state_len"], "Rc"),
+                                     coarse._tensor(T, coarse.info["state_len"], "T"),
+                                     _stream_ptr(stream, coarse.device)))

@@ -43,6 +43,15 @@ def ellipse_case(mach=0.3, omega=1.0):
                 farfield=(1.0, mach, 0.0, 1.0 / GAMMA), omega=float(omega), theta0=0.0)
 
 
+def ellipse_viscous_case(mach=0.2, reynolds=1000.0, omega=1.0, prandtl=0.72):
+    """Viscous flow past the rotating ellipse: far field (1, mach, 0, 1/gamma),
+    so that the speed of sound is 1; Re based on the major axis (length 1)
+    and the free-stream speed; isothermal walls at the free-stream
+    temperature."""
+    return dict(gamma=GAMMA, gas_R=1.0 / GAMMA, mu=mach / reynolds, prandtl=prandtl, T_wall=1.0,
+                farfield=(1.0, mach, 0.0, 1.0 / GAMMA), omega=float(omega), theta0=0.0)
+
+
 def perturbed_farfield_state(case, N, E, seed=20150307, amplitude=0.01):
     """Conservative state [4][N][N][E] (float64): the far-field state with
     density scaled by (1 + amplitude * u), u uniform on [-1, 1) drawn by
