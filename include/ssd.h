@@ -330,10 +330,11 @@ ssd_status ssd_mlp_get_params(const ssd_mlp *net, float *W1, float *b1, float *W
 ssd_status ssd_mlp_set_normalization(ssd_mlp *net, const float *mu_x, const float *sig_x,
                                      const float *mu_y, const float *sig_y);
 /* Fits the normalisation to n >= 2 rows of X [n][n_in] and T [n][n_out]
- * (device): per-column mean and standard deviation; a column whose
- * deviation is below 1e-6 (|mean| + 1e-30) gets sig = 1.  Synchronises. */
+ * (device): per-column mean and standard deviation, the deviation floored
+ * at min_rel times the column's root mean square (min_rel >= 0); a column
+ * that is zero throughout gets sig = 1.  Synchronises. */
 ssd_status ssd_mlp_fit_normalization(ssd_mlp *net, const float *X, const float *T, int64_t n,
-                                     void *stream);
+                                     float min_rel, void *stream);
 
 /* Y [n][n_out] = the network of the rows X [n][n_in] (device, n >= 0). */
 ssd_status ssd_mlp_forward(ssd_mlp *net, const float *X, int64_t n, float *Y, void *stream);
@@ -345,10 +346,18 @@ ssd_status ssd_mlp_forward(ssd_mlp *net, const float *X, int64_t n, float *Y, vo
  * over the batch and the outputs of (yn - (t - mu_y) / sig_y)^2.  The
  * gradient goes to host arrays laid out as ssd_mlp_get_params, the loss to
  * *loss.  Parameters are not changed.  Synchronises.
+ *
+ * Input noise (noise > 0, training only): the normalised input i of
+ * minibatch position s gets noise * eps added before the first layer, eps
+ * = (2u - 1) sqrt(3) with u the top 24 bits (times 2^-24) of the SplitMix64
+ * output of stream noise_seed at counter (step << 32) + s n_in + i, where
+ * step is the number of Adam steps taken since the parameters were set,
+ * plus one.
  */
 ssd_status ssd_mlp_gradient(ssd_mlp *net, const float *X, const float *T, int64_t n_rows,
-                            const int32_t *idx, int32_t batch, float *gW1, float *gb1, float *gW2,
-                            float *gb2, float *gW3, float *gb3, double *loss, void *stream);
+                            const int32_t *idx, int32_t batch, float noise, uint64_t noise_seed,
+                            float *gW1, float *gb1, float *gW2, float *gb2, float *gW3, float *gb3,
+                            double *loss, void *stream);
 /*
  * One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the
  * loss of the minibatch idx[0..batch).  The minibatch losses are summed on
@@ -356,7 +365,8 @@ ssd_status ssd_mlp_gradient(ssd_mlp *net, const float *X, const float *T, int64_
  * the last call (and synchronises).
  */
 ssd_status ssd_mlp_train_step(ssd_mlp *net, const float *X, const float *T, int64_t n_rows,
-                              const int32_t *idx, int32_t batch, float lr, void *stream);
+                              const int32_t *idx, int32_t batch, float lr, float noise,
+                              uint64_t noise_seed, void *stream);
 ssd_status ssd_mlp_loss(ssd_mlp *net, double *loss_sum, int64_t *steps);
 
 /* Features of every element of state q (device, state layout) into the rows
@@ -371,9 +381,13 @@ ssd_status ssd_subgrid_features(ssd_mesh *m, const float *q, float *X, void *str
  * the fine element of child (a, b) at index a + 2 b, child (a, b) covering
  * [a/2, (a+1)/2] x [b/2, (b+1)/2] of the parent's reference square.
  * qc is in the coarse state layout.  Supported (N coarse, N fine): (2, 2),
- * (2, 4), (2, 6), (3, 3), (3, 6), (4, 6).  The child table is read back
- * and checked (every entry in [0, E_fine)) before the launch, so the call
- * synchronises with the device.
+ * (2, 4), (2, 6), (3, 3), (3, 4), (3, 5), (3, 6), (4, 6).  The child table
+ * is read back and checked (every entry in [0, E_fine)) before the launch,
+ * so the call synchronises with the device.
+ *
+ * children = NULL: `fine` and `coarse` are the same mesh and qc is the L2
+ * projection of qf onto the lower order of `coarse`, element by element
+ * (N pairs with 2 <= N coarse < N fine <= 6).
  */
 ssd_status ssd_restrict(const ssd_mesh *fine, const ssd_mesh *coarse, const int32_t *children,
                         const float *qf, float *qc, void *stream);
@@ -383,11 +397,11 @@ ssd_status ssd_subgrid_targets(const ssd_mesh *fine, const ssd_mesh *coarse,
                                const int32_t *children, const float *Rf, const float *Rc, float *T,
                                void *stream);
 
-/* Attaches `net` (same N and device) to mesh m: from then on ssd_rk_step(s)
- * with SSD_RK3_SSP adds the correction in every stage (other schemes return
- * SSD_ERR_INVALID_ARG).  net = NULL detaches (plain SSD).  The network must
- * outlive the attachment. */
-ssd_status ssd_subgrid_attach(ssd_mesh *m, ssd_mlp *net);
+/* Attaches `net` (same N and device) to mesh m with weight w (finite): from
+ * then on ssd_rk_step(s) with SSD_RK3_SSP adds w C(Q) to dQ/dt in every
+ * stage (other schemes return SSD_ERR_INVALID_ARG).  net = NULL detaches
+ * (plain SSD).  The network must outlive the attachment. */
+ssd_status ssd_subgrid_attach(ssd_mesh *m, ssd_mlp *net, float w);
 
 #ifdef __cplusplus
 }

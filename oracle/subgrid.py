@@ -93,11 +93,27 @@ def restriction_1d(Nc, Nf):
     return R
 
 
+def projection_1d(Nc, Nf):
+    """P (Nc x Nf): coarse SP values of the L2 projection onto degree Nc-1
+    polynomials on [0, 1] of the basis function m of Nf points on the same
+    interval (lowering the order on one mesh)."""
+    Xc, Xf = solution_points(Nc), solution_points(Nf)
+    g, w = np.polynomial.legendre.leggauss(Nc + Nf)
+    z, w = 0.5 * (g + 1.0), 0.5 * w
+    hc = np.array([lagrange(Xc, k, z) for k in range(Nc)])
+    hf = np.array([lagrange(Xf, m, z) for m in range(Nf)])
+    return np.linalg.solve((hc * w) @ hc.T, (hc * w) @ hf.T)
+
+
 def restrict(Qf, children, Nc):
     """Coarse state Qc[v, j, i, c] from the fine state Qf[v, j, i, e] of the
-    nested mesh; children[c, a + 2 b] is the fine element of child (a, b)."""
+    nested mesh; children[c, a + 2 b] is the fine element of child (a, b).
+    children None: the same mesh at a lower order (projection per element)."""
     Qf = np.asarray(Qf, dtype=float)
     Nf = Qf.shape[1]
+    if children is None:
+        P = projection_1d(Nc, Nf)
+        return np.einsum("JF,IG,vFGc->vJIc", P, P, Qf)
     R = restriction_1d(Nc, Nf)
     ch = np.asarray(children)
     out = np.zeros((Qf.shape[0], Nc, Nc, len(ch)))
@@ -135,20 +151,24 @@ class MLP:
         self.mu_y = np.zeros(n_out) if mu_y is None else np.asarray(mu_y, dtype=float)
         self.sig_y = np.ones(n_out) if sig_y is None else np.asarray(sig_y, dtype=float)
 
-    def _in(self, X, bf):
+    def _in(self, X, bf, noise=None):
         X = np.asarray(X, dtype=float)
         if not bf:
-            return (X - self.mu_x) / self.sig_x
+            xn = (X - self.mu_x) / self.sig_x
+            return xn if noise is None else xn + noise
         # as a kernel does it: FP32 difference times the FP32 reciprocal
         f32 = np.float32
         xn = (X.astype(f32) - self.mu_x.astype(f32)) * (f32(1.0) / self.sig_x.astype(f32))
+        if noise is not None:
+            xn = xn + np.asarray(noise, dtype=f32)
         return bf16(xn)
 
-    def forward(self, X, bf=False):
-        """Normalised outputs yn and the activations (a1, h1, a2, h2, a3)."""
+    def forward(self, X, bf=False, noise=None):
+        """Normalised outputs yn and the activations (a1, h1, a2, h2, a3);
+        `noise` (rows x n_in) is added to the normalised inputs."""
         p = self.p
         r = bf16 if bf else (lambda v: v)
-        a1 = self._in(X, bf)
+        a1 = self._in(X, bf, noise)
         h1 = np.tanh(a1 @ r(p["W1"]).T + p["b1"])
         a2 = r(h1)
         h2 = np.tanh(a2 @ r(p["W2"]).T + p["b2"])
@@ -160,11 +180,12 @@ class MLP:
         yn, _ = self.forward(X, bf)
         return yn * self.sig_y + self.mu_y
 
-    def loss_grads(self, X, T, bf=False):
-        """Loss and its gradient with respect to every parameter."""
+    def loss_grads(self, X, T, bf=False, noise=None):
+        """Loss and its gradient with respect to every parameter (inputs
+        perturbed by `noise` in normalised units, if given)."""
         p = self.p
         r = bf16 if bf else (lambda v: v)
-        yn, (a1, h1, a2, h2, a3) = self.forward(X, bf)
+        yn, (a1, h1, a2, h2, a3) = self.forward(X, bf, noise)
         tn = (np.asarray(T, dtype=float) - self.mu_y) / self.sig_y
         B, n_out = yn.shape
         d = yn - tn
@@ -211,3 +232,18 @@ def corrected_rk3(ssd, mlp, Q, t, dt, nsteps, bf=False):
         U2 = 0.75 * U + 0.25 * (U1 + dt * rhs(U1, tn + dt))
         U = U / 3.0 + 2.0 / 3.0 * (U2 + dt * rhs(U2, tn + 0.5 * dt))
     return U
+
+
+def training_noise(seed, step, batch, n_in, std):
+    """Input noise of one training step: std * (2u - 1) sqrt(3) for
+    minibatch position s and input i, u the top 24 bits (times 2^-24) of
+    SplitMix64 of stream `seed` at counter (step << 32) + s n_in + i; in FP32
+    as the kernels form it."""
+    from workloads.rng import splitmix64
+    s = np.arange(batch, dtype=np.uint64)[:, None]
+    i = np.arange(n_in, dtype=np.uint64)[None, :]
+    z = splitmix64(seed, (np.uint64(step) << np.uint64(32)) + s * np.uint64(n_in) + i)
+    f32 = np.float32
+    u = (z >> np.uint64(40)).astype(f32) * f32(2.0 ** -24)
+    eps = (f32(2.0) * u - f32(1.0)) * f32(1.7320508075688772)
+    return f32(std) * eps

@@ -1,5 +1,6 @@
 // Batched execution of many meshes: the tile and chunk bodies of
 // ssd_tiles.h driven by device tables of (case, tile or chunk) items.
+#include "ssd_launch.h"
 #include "ssd_tiles.h"
 
 namespace ssd {

@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "ssd_internal.h"
+#include "ssd_launch.h"
 
 using namespace ssd;
 
@@ -303,6 +303,7 @@ struct ssd_mesh {
   } timers[SSD_KERNEL_COUNT];
   ssd_mlp *model = nullptr;            // learned correction added by ssd_rk_steps
   float *addbuf = nullptr;             // its per-stage increment (state layout)
+  float model_weight = 1.0f;           // weight of the correction
 };
 
 // A network of the learned subgrid correction.  FP32 parameters laid out
@@ -923,9 +924,9 @@ ssd_status ssd_rk_steps(ssd_mesh *m, float *q, float *work, double t, double dt,
       const float *in[3] = {q, w1, w2};
       float *outp[3] = {w1, w2, q};
       for (int k = 0; k < 3; ++k) {
-        if (m->model)   // learned correction: add = b_k dt C(Q_k), added by the stage
+        if (m->model)   // learned correction: add = w b_k dt C(Q_k), added by the stage
           SSD_HIP(launch_subgrid(m->D, m->T, mlp_dev(m->model), in[k], m->addbuf,
-                                 float(B[k] * dt), st),
+                                 float(m->model_weight * B[k] * dt), st),
                   "subgrid correction launch");
         if (ssd_status e = stage(tn, Cs[k], in[k], k ? q : nullptr, outp[k], B[k], B[k],
                                  m->model ? m->addbuf : nullptr))
@@ -1553,7 +1554,7 @@ ssd_status mlp_upload_norm(ssd_mlp *n, const float *mu_x, const float *sig_x, co
 // R[a][ic][if]: coarse SP values of the L2 projection on [0, 1] of the fine
 // basis function if of child half a, by Gauss-Legendre quadrature (exact
 // for these polynomial degrees).
-bool restriction_table(int Nc, int Nf, Restrict1D &R) {
+bool restriction_table(int Nc, int Nf, bool split, Restrict1D &R) {
   const std::vector<double> Xc = solution_points(Nc), Xf = solution_points(Nf);
   const std::vector<double> bc = bary_weights(Xc), bf = bary_weights(Xf);
   std::vector<double> g, w;
@@ -1568,13 +1569,16 @@ bool restriction_table(int Nc, int Nf, Restrict1D &R) {
   }
   if (!invert(Nc, Mm, Mi)) return false;
   R = Restrict1D{};
-  for (int a = 0; a < 2; ++a) {
+  for (int a = 0; a < (split ? 2 : 1); ++a) {
+    // split: the fine basis of child half a, h^f(2 xi - a) on [a/2, (a+1)/2];
+    // otherwise the fine basis on the whole of [0, 1]
     std::vector<double> b(Nc * Nf, 0.0);
     for (int q = 0; q < nq; ++q) {
       const double z = 0.5 * (g[q] + 1.0), wq = 0.5 * w[q];
-      const std::vector<double> hc = cardinal(Xc, bc, 0.5 * (a + z)), hf = cardinal(Xf, bf, z);
+      const double xi = split ? 0.5 * (a + z) : z, jac = split ? 0.5 : 1.0;
+      const std::vector<double> hc = cardinal(Xc, bc, xi), hf = cardinal(Xf, bf, z);
       for (int k = 0; k < Nc; ++k)
-        for (int m = 0; m < Nf; ++m) b[k * Nf + m] += 0.5 * wq * hc[k] * hf[m];
+        for (int m = 0; m < Nf; ++m) b[k * Nf + m] += jac * wq * hc[k] * hf[m];
     }
     for (int i = 0; i < Nc; ++i)
       for (int m = 0; m < Nf; ++m) {
@@ -1587,9 +1591,15 @@ bool restriction_table(int Nc, int Nf, Restrict1D &R) {
 }
 
 ssd_status check_pair(const ssd_mesh *fine, const ssd_mesh *coarse, const int32_t *children) {
-  if (!fine || !coarse || !children) return fail(SSD_ERR_INVALID_ARG, "null mesh or child table");
+  if (!fine || !coarse) return fail(SSD_ERR_INVALID_ARG, "null mesh");
   if (fine->device != coarse->device)
     return fail(SSD_ERR_INVALID_ARG, "fine and coarse meshes on different devices");
+  if (!children) {
+    if (fine->E != coarse->E || fine->N < coarse->N)
+      return fail(SSD_ERR_INVALID_ARG,
+                  "without a child table the meshes must match, the second of lower order");
+    return SSD_OK;
+  }
   if (long(fine->E) != 4L * coarse->E)
     return fail(SSD_ERR_INVALID_ARG, "the fine mesh must have 4 elements per coarse element");
   // the kernels index the fine state by the table: check it here
@@ -1704,9 +1714,10 @@ ssd_status ssd_mlp_set_normalization(ssd_mlp *n, const float *mu_x, const float 
 }
 
 ssd_status ssd_mlp_fit_normalization(ssd_mlp *n, const float *X, const float *T, int64_t rows,
-                                     void *stream) {
+                                     float min_rel, void *stream) {
   if (!n || !X || !T) return fail(SSD_ERR_INVALID_ARG, "null argument");
   if (rows < 2) return fail(SSD_ERR_INVALID_ARG, "need at least two rows");
+  if (!std::isfinite(min_rel) || min_rel < 0.0f) return fail(SSD_ERR_INVALID_ARG, "need min_rel >= 0");
   DeviceGuard guard(n->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int nm = 2 * (n->nin + n->nout);
@@ -1723,9 +1734,9 @@ ssd_status ssd_mlp_fit_normalization(ssd_mlp *n, const float *X, const float *T,
     sig.resize(cols);
     for (int c = 0; c < cols; ++c) {
       const double m = s[c] / double(rows);
-      const double var = std::max(s[cols + c] / double(rows) - m * m, 0.0);
-      double sd = std::sqrt(var);
-      if (!(sd >= 1e-6 * (std::fabs(m) + 1e-30))) sd = 1.0;
+      const double ms = s[cols + c] / double(rows);
+      double sd = std::max(std::sqrt(std::max(ms - m * m, 0.0)), double(min_rel) * std::sqrt(ms));
+      if (!(sd > 0.0)) sd = 1.0;
       mu[c] = float(m);
       sig[c] = float(sd);
     }
@@ -1746,8 +1757,9 @@ ssd_status ssd_mlp_forward(ssd_mlp *n, const float *X, int64_t rows, float *Y, v
 }
 
 ssd_status ssd_mlp_gradient(ssd_mlp *n, const float *X, const float *T, int64_t n_rows,
-                            const int32_t *idx, int32_t batch, float *gW1, float *gb1, float *gW2,
-                            float *gb2, float *gW3, float *gb3, double *loss, void *stream) {
+                            const int32_t *idx, int32_t batch, float noise, uint64_t noise_seed,
+                            float *gW1, float *gb1, float *gW2, float *gb2, float *gW3, float *gb3,
+                            double *loss, void *stream) {
   if (!n || !X || !T || !idx || !gW1 || !gb1 || !gW2 || !gb2 || !gW3 || !gb3 || !loss)
     return fail(SSD_ERR_INVALID_ARG, "null argument");
   if (batch < 1 || n_rows < 1) return fail(SSD_ERR_INVALID_ARG, "need batch >= 1 and rows");
@@ -1756,7 +1768,9 @@ ssd_status ssd_mlp_gradient(ssd_mlp *n, const float *X, const float *T, int64_t 
   SSD_HIP(hipStreamSynchronize(st), "stream synchronize");
   SSD_HIP(hipMemset(n->G, 0, n->plen * sizeof(float)), "clear gradient");
   SSD_HIP(hipMemset(n->acc, 0, sizeof(double)), "clear loss");
-  SSD_HIP(launch_mlp_grad(n->N, mlp_dev(n), mlp_grad(n), X, T, n_rows, idx, batch, st),
+  if (!std::isfinite(noise) || noise < 0.0f) return fail(SSD_ERR_INVALID_ARG, "need noise >= 0");
+  SSD_HIP(launch_mlp_grad(n->N, mlp_dev(n), mlp_grad(n), X, T, n_rows, idx, batch, noise,
+                          noise_seed, uint64_t(n->steps + 1), st),
           "gradient launch");
   SSD_HIP(hipStreamSynchronize(st), "stream synchronize");
   std::vector<float> flat(n->plen);
@@ -1771,13 +1785,16 @@ ssd_status ssd_mlp_gradient(ssd_mlp *n, const float *X, const float *T, int64_t 
 }
 
 ssd_status ssd_mlp_train_step(ssd_mlp *n, const float *X, const float *T, int64_t n_rows,
-                              const int32_t *idx, int32_t batch, float lr, void *stream) {
+                              const int32_t *idx, int32_t batch, float lr, float noise,
+                              uint64_t noise_seed, void *stream) {
   if (!n || !X || !T || !idx) return fail(SSD_ERR_INVALID_ARG, "null argument");
   if (batch < 1 || n_rows < 1) return fail(SSD_ERR_INVALID_ARG, "need batch >= 1 and rows");
   if (!std::isfinite(lr) || lr < 0.0f) return fail(SSD_ERR_INVALID_ARG, "need a finite lr >= 0");
+  if (!std::isfinite(noise) || noise < 0.0f) return fail(SSD_ERR_INVALID_ARG, "need noise >= 0");
   DeviceGuard guard(n->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  SSD_HIP(launch_mlp_grad(n->N, mlp_dev(n), mlp_grad(n), X, T, n_rows, idx, batch, st),
+  SSD_HIP(launch_mlp_grad(n->N, mlp_dev(n), mlp_grad(n), X, T, n_rows, idx, batch, noise,
+                          noise_seed, uint64_t(n->steps + 1), st),
           "gradient launch");
   ++n->steps;
   ++n->loss_steps;
@@ -1814,7 +1831,7 @@ ssd_status ssd_restrict(const ssd_mesh *fine, const ssd_mesh *coarse, const int3
   if (ssd_status s = check_pair(fine, coarse, children)) return s;
   if (!qf || !qc) return fail(SSD_ERR_INVALID_ARG, "null state");
   Restrict1D R;
-  if (!restriction_table(coarse->N, fine->N, R))
+  if (!restriction_table(coarse->N, fine->N, children != nullptr, R))
     return fail(SSD_ERR_INVALID_ARG, "restriction table");
   DeviceGuard guard(coarse->device);
   const hipError_t e = launch_restrict(coarse->N, fine->N, qf, fine->E, children, coarse->E, R,
@@ -1831,7 +1848,7 @@ ssd_status ssd_subgrid_targets(const ssd_mesh *fine, const ssd_mesh *coarse,
   if (ssd_status s = check_pair(fine, coarse, children)) return s;
   if (!Rf || !Rc || !T) return fail(SSD_ERR_INVALID_ARG, "null array");
   Restrict1D R;
-  if (!restriction_table(coarse->N, fine->N, R))
+  if (!restriction_table(coarse->N, fine->N, children != nullptr, R))
     return fail(SSD_ERR_INVALID_ARG, "restriction table");
   DeviceGuard guard(coarse->device);
   const hipError_t e = launch_restrict(coarse->N, fine->N, Rf, fine->E, children, coarse->E, R, Rc,
@@ -1842,18 +1859,21 @@ ssd_status ssd_subgrid_targets(const ssd_mesh *fine, const ssd_mesh *coarse,
   return SSD_OK;
 }
 
-ssd_status ssd_subgrid_attach(ssd_mesh *m, ssd_mlp *net) {
+ssd_status ssd_subgrid_attach(ssd_mesh *m, ssd_mlp *net, float w) {
   if (ssd_status s = check_handle(m)) return s;
   if (!net) {
     m->model = nullptr;
     return SSD_OK;
   }
+  if (!std::isfinite(w)) return fail(SSD_ERR_INVALID_ARG, "need a finite weight");
   if (net->N != m->N) return fail(SSD_ERR_INVALID_ARG, "network and mesh have different N");
   if (net->device != m->device) return fail(SSD_ERR_INVALID_ARG, "network on another device");
   DeviceGuard guard(m->device);
   if (!m->addbuf && dev_alloc(m, &m->addbuf, size_t(4) * m->N * m->N * m->E) != hipSuccess)
     return fail(SSD_ERR_NOMEM, "correction buffer");
+
   m->model = net;
+  m->model_weight = w;
   return SSD_OK;
 }
 

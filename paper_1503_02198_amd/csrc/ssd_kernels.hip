@@ -1,4 +1,5 @@
 // Launchers of the single-mesh SSD kernels (device bodies in ssd_tiles.h).
+#include "ssd_launch.h"
 #include "ssd_tiles.h"
 
 namespace ssd {

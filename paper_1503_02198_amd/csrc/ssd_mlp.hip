@@ -16,6 +16,7 @@
 //   B (32 x 16): lane l holds B[8 (l / 16) + e][l % 16]
 //   D (16 x 16): lane l holds D[4 (l / 16) + r][l % 16], r = 0..3
 #include "ssd_device.h"
+#include "ssd_launch.h"
 
 namespace ssd {
 
@@ -31,6 +32,19 @@ __device__ __forceinline__ __bf16 to_bf16(float x) {
 }
 __device__ __forceinline__ float from_bf16(__bf16 h) {
   return __uint_as_float(uint32_t(__builtin_bit_cast(unsigned short, h)) << 16);
+}
+
+// Training noise: SplitMix64 (Steele, Lea and Flood, 2014) output for
+// counter c of stream `seed` (the mix of seed + (c + 1) 0x9E3779B97F4A7C15),
+// its top 24 bits as u in [0, 1), and eps = (2u - 1) sqrt(3), uniform with
+// unit variance; every step is exact in FP32.
+__device__ __forceinline__ float noise_eps(uint64_t seed, uint64_t c) {
+  uint64_t z = seed + (c + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  const float u = float(uint32_t(z >> 40)) * 0x1p-24f;
+  return (2.0f * u - 1.0f) * 1.7320508075688772f;
 }
 
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
@@ -305,7 +319,8 @@ __global__ __launch_bounds__(256) void k_mlp_forward(MlpDev P, const float *X, l
 template <int N>
 __global__ __launch_bounds__(256) void k_mlp_grad(MlpDev P, MlpGrad G, const float *X,
                                                   const float *Tg, long n_rows, const int *idx,
-                                                  int batch) {
+                                                  int batch, float noise, uint64_t seed,
+                                                  uint64_t step) {
   using D = MlpDims<N>;
   constexpr int KO = D::KOUT, H = D::H;
   __shared__ MlpLds<N> S;
@@ -327,7 +342,11 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpDev P, MlpGrad G, const flo
     const int s = c / D::KIN, i = c % D::KIN;
     const int r = rowi[s];
     const float x = r >= 0 && i < D::NIN ? X[long(r) * D::NIN + i] : 0.f;
-    S.A1[s][i] = to_bf16((x - P.mu_x[i]) * P.isig_x[i]);
+    float xn = (x - P.mu_x[i]) * P.isig_x[i];
+    // input noise of minibatch position s0 + s, feature i, at this step
+    if (noise != 0.f && r >= 0 && i < D::NIN)
+      xn += noise * noise_eps(seed, (step << 32) + uint64_t(s0 + s) * D::NIN + i);
+    S.A1[s][i] = to_bf16(xn);
   }
   for (int c = threadIdx.x; c < 64 * KO; c += 256) {
     const int s = c / KO, o = c % KO;
@@ -490,22 +509,25 @@ __global__ __launch_bounds__(256) void k_moments(const float *A, long n, int col
 //   out = P qf - sub (sub may be null); rows: out[c][o] instead of the state
 //   layout out[o][c]
 // ---------------------------------------------------------------------------
-template <int NC, int NF>
+// SPLIT: each coarse element has 4 children; otherwise the same mesh at a
+// lower order (one "child", the element itself, operator r[0]).
+template <int NC, int NF, bool SPLIT>
 __global__ __launch_bounds__(256) void k_restrict(const float *qf, long Ef, const int *children,
                                                   long Ec, Restrict1D R, const float *sub,
                                                   float *out, int rows) {
+  constexpr int NS = SPLIT ? 2 : 1;
   const long c = long(blockIdx.x) * 256 + threadIdx.x;
   if (c >= Ec) return;
   int ch[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) ch[k] = children[c * 4 + k];
+  for (int k = 0; k < 4; ++k) ch[k] = SPLIT ? children[c * 4 + k] : int(c);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     float acc[NC][NC] = {};
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < NS; ++b)
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
+      for (int a = 0; a < NS; ++a) {
         const long fe = ch[a + 2 * b];
 #pragma unroll
         for (int jf = 0; jf < NF; ++jf) {
@@ -574,11 +596,11 @@ hipError_t launch_mlp_forward(int N, const MlpDev &P, const float *X, long n, fl
 }
 
 hipError_t launch_mlp_grad(int N, const MlpDev &P, const MlpGrad &G, const float *X,
-                           const float *Tg, long n_rows, const int *idx, int batch,
-                           hipStream_t s) {
+                           const float *Tg, long n_rows, const int *idx, int batch, float noise,
+                           uint64_t seed, uint64_t step, hipStream_t s) {
   const int grid = (batch + 63) / 64;
   SSD_MLP_DISPATCH(N, hipLaunchKernelGGL(k_mlp_grad<NN>, dim3(grid), dim3(256), 0, s, P, G, X,
-                                         Tg, n_rows, idx, batch));
+                                         Tg, n_rows, idx, batch, noise, seed, step));
   return hipGetLastError();
 }
 
@@ -606,18 +628,33 @@ hipError_t launch_restrict(int Nc, int Nf, const float *qf, long Ef, const int *
                            const Restrict1D &R, const float *sub, float *out, bool rows,
                            hipStream_t s) {
   const long grid = (Ec + 255) / 256;
-#define SSD_RESTRICT(NCV, NFV)                                                                   \
-  if (Nc == NCV && Nf == NFV) {                                                                  \
-    hipLaunchKernelGGL((k_restrict<NCV, NFV>), dim3(grid), dim3(256), 0, s, qf, Ef, children,    \
-                       Ec, R, sub, out, int(rows));                                              \
+  const bool split = children != nullptr;
+#define SSD_RESTRICT(NCV, NFV, SP)                                                               \
+  if (Nc == NCV && Nf == NFV && split == SP) {                                                   \
+    hipLaunchKernelGGL((k_restrict<NCV, NFV, SP>), dim3(grid), dim3(256), 0, s, qf, Ef,          \
+                       children, Ec, R, sub, out, int(rows));                                    \
     return hipGetLastError();                                                                    \
   }
-  SSD_RESTRICT(2, 4)
-  SSD_RESTRICT(2, 6)
-  SSD_RESTRICT(3, 6)
-  SSD_RESTRICT(3, 3)
-  SSD_RESTRICT(2, 2)
-  SSD_RESTRICT(4, 6)
+  // nested meshes
+  SSD_RESTRICT(2, 2, true)
+  SSD_RESTRICT(2, 4, true)
+  SSD_RESTRICT(2, 6, true)
+  SSD_RESTRICT(3, 3, true)
+  SSD_RESTRICT(3, 4, true)
+  SSD_RESTRICT(3, 5, true)
+  SSD_RESTRICT(3, 6, true)
+  SSD_RESTRICT(4, 6, true)
+  // one mesh, lower order
+  SSD_RESTRICT(2, 3, false)
+  SSD_RESTRICT(2, 4, false)
+  SSD_RESTRICT(2, 5, false)
+  SSD_RESTRICT(2, 6, false)
+  SSD_RESTRICT(3, 4, false)
+  SSD_RESTRICT(3, 5, false)
+  SSD_RESTRICT(3, 6, false)
+  SSD_RESTRICT(4, 5, false)
+  SSD_RESTRICT(4, 6, false)
+  SSD_RESTRICT(5, 6, false)
 #undef SSD_RESTRICT
   return hipErrorInvalidValue;
 }

@@ -100,17 +100,18 @@ def lib():
             "ssd_mlp_set_params": (i32, [vp] + [ctypes.POINTER(ctypes.c_float)] * 6),
             "ssd_mlp_get_params": (i32, [vp] + [ctypes.POINTER(ctypes.c_float)] * 6),
             "ssd_mlp_set_normalization": (i32, [vp] + [ctypes.POINTER(ctypes.c_float)] * 4),
-            "ssd_mlp_fit_normalization": (i32, [vp, vp, vp, i64, vp]),
+            "ssd_mlp_fit_normalization": (i32, [vp, vp, vp, i64, ctypes.c_float, vp]),
             "ssd_mlp_forward": (i32, [vp, vp, i64, vp, vp]),
-            "ssd_mlp_gradient": (i32, [vp, vp, vp, i64, vp, i32]
+            "ssd_mlp_gradient": (i32, [vp, vp, vp, i64, vp, i32, ctypes.c_float, ctypes.c_uint64]
                                  + [ctypes.POINTER(ctypes.c_float)] * 6
                                  + [ctypes.POINTER(dbl), vp]),
-            "ssd_mlp_train_step": (i32, [vp, vp, vp, i64, vp, i32, ctypes.c_float, vp]),
+            "ssd_mlp_train_step": (i32, [vp, vp, vp, i64, vp, i32, ctypes.c_float,
+                                         ctypes.c_float, ctypes.c_uint64, vp]),
             "ssd_mlp_loss": (i32, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
             "ssd_subgrid_features": (i32, [vp, vp, vp, vp]),
             "ssd_restrict": (i32, [vp, vp, vp, vp, vp, vp]),
             "ssd_subgrid_targets": (i32, [vp, vp, vp, vp, vp, vp, vp]),
-            "ssd_subgrid_attach": (i32, [vp, vp]),
+            "ssd_subgrid_attach": (i32, [vp, vp, ctypes.c_float]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -242,10 +243,12 @@ class Mesh:
                                           self._tensor(X, self.info["n_elem"] * n_in, "X"),
                                           _stream_ptr(stream, self.device)))
 
-    def attach(self, net):
-        """Add the learned correction of `net` in every SSP-RK3 stage (None:
-        plain SSD).  The network must outlive the attachment."""
-        _check(lib().ssd_subgrid_attach(self._h, net._h if net is not None else None))
+    def attach(self, net, weight=1.0):
+        """Add weight x the learned correction of `net` to dQ/dt in every
+        SSP-RK3 stage (None: plain SSD).  The network must outlive the
+        attachment."""
+        _check(lib().ssd_subgrid_attach(self._h, net._h if net is not None else None,
+                                        float(weight)))
         self._net = net
 
     def timing_enable(self, on=True, kernels=None):
@@ -375,11 +378,11 @@ class MLP:
              _f32(mu_y, self.n_out, "mu_y"), _f32(sig_y, self.n_out, "sig_y")]
         _check(lib().ssd_mlp_set_normalization(self._h, *[_ptr(x, ctypes.c_float) for x in a]))
 
-    def fit_normalization(self, X, T, stream=None):
+    def fit_normalization(self, X, T, min_rel=0.0, stream=None):
         n = X.numel() // self.n_in
         _check(lib().ssd_mlp_fit_normalization(
             self._h, _dev(X, n * self.n_in, "X", device=self.device),
-            _dev(T, n * self.n_out, "T", device=self.device), int(n),
+            _dev(T, n * self.n_out, "T", device=self.device), int(n), float(min_rel),
             _stream_ptr(stream, self.device)))
 
     def forward(self, X, Y, stream=None):
@@ -388,7 +391,7 @@ class MLP:
                                      int(n), _dev(Y, n * self.n_out, "Y", device=self.device),
                                      _stream_ptr(stream, self.device)))
 
-    def gradient(self, X, T, idx, stream=None):
+    def gradient(self, X, T, idx, noise=0.0, seed=0, stream=None):
         """Loss and its gradient (host arrays) on the rows idx of X, T."""
         n = X.numel() // self.n_in
         out = {k: np.empty(sh, np.float32) for k, sh in self.shapes().items()}
@@ -396,18 +399,18 @@ class MLP:
         _check(lib().ssd_mlp_gradient(
             self._h, _dev(X, n * self.n_in, "X", device=self.device),
             _dev(T, n * self.n_out, "T", device=self.device), int(n),
-            _dev(idx, None, "idx", "int32", self.device), int(idx.numel()),
-            *[_ptr(out[k], ctypes.c_float) for k in out], ctypes.byref(loss),
+            _dev(idx, None, "idx", "int32", self.device), int(idx.numel()), float(noise),
+            int(seed), *[_ptr(out[k], ctypes.c_float) for k in out], ctypes.byref(loss),
             _stream_ptr(stream, self.device)))
         return loss.value, out
 
-    def train_step(self, X, T, idx, lr, stream=None):
+    def train_step(self, X, T, idx, lr, noise=0.0, seed=0, stream=None):
         n = X.numel() // self.n_in
         _check(lib().ssd_mlp_train_step(
             self._h, _dev(X, n * self.n_in, "X", device=self.device),
             _dev(T, n * self.n_out, "T", device=self.device), int(n),
             _dev(idx, None, "idx", "int32", self.device), int(idx.numel()), float(lr),
-            _stream_ptr(stream, self.device)))
+            float(noise), int(seed), _stream_ptr(stream, self.device)))
 
     def loss(self):
         """Mean loss of the steps since the last call, and their count."""
@@ -428,8 +431,10 @@ class MLP:
 
 
 def restrict(fine, coarse, children, qf, qc, stream=None):
-    """qc = restriction of the fine state qf to the coarse parent mesh."""
+    """qc = restriction of the fine state qf to the coarse parent mesh
+    (children None: the same mesh at the lower order of `coarse`)."""
     _check(lib().ssd_restrict(fine._h, coarse._h,
+                              None if children is None else
                               _dev(children, 4 * coarse.info["n_elem"], "children", "int32",
                                    coarse.device),
                               fine._tensor(qf, fine.info["state_len"], "qf"),

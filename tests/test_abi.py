@@ -75,10 +75,11 @@ def test_argument_errors_without_device(L):
     assert L.ssd_mlp_destroy(None) == 0
     assert L.ssd_mlp_dims(None, None, None) == -1
     assert L.ssd_mlp_forward(None, None, 0, None, None) == -1
-    assert L.ssd_mlp_train_step(None, None, None, 1, None, 1, ctypes.c_float(1e-3), None) == -1
+    assert L.ssd_mlp_train_step(None, None, None, 1, None, 1, ctypes.c_float(1e-3),
+                                ctypes.c_float(0.0), 0, None) == -1
     assert L.ssd_mlp_loss(None, None, None) == -1
     assert L.ssd_subgrid_features(None, None, None, None) == -1
     assert L.ssd_restrict(None, None, None, None, None, None) == -1
     assert b"null mesh" in L.ssd_last_error()
     assert L.ssd_subgrid_targets(None, None, None, None, None, None, None) == -1
-    assert L.ssd_subgrid_attach(None, None) == -1
+    assert L.ssd_subgrid_attach(None, None, ctypes.c_float(1.0)) == -1

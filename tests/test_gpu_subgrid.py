@@ -120,19 +120,24 @@ def test_features(torch_cuda, nested):
         _close(Xg, S.features(ora, Q), 1e-6, f"features N={N}")
 
 
-@pytest.mark.parametrize("Nc,Nf", [(3, 6), (2, 4)])
-def test_restrict(torch_cuda, nested, Nc, Nf):
+@pytest.mark.parametrize("Nc,Nf,split", [(3, 6, True), (2, 4, True), (3, 5, True),
+                                         (3, 6, False), (5, 6, False), (2, 3, False)])
+def test_restrict(torch_cuda, nested, Nc, Nf, split):
+    """Nested fine mesh to the coarse one, or one mesh to a lower order."""
     from paper_1503_02198_amd import Mesh, restrict
-    print(f"case: restriction N {Nf} -> {Nc}", flush=True)
+    print(f"case: restriction N {Nf} -> {Nc}, nested {split}", flush=True)
     coarse, fine, ch = nested
     case = C.ellipse_viscous_case()
     of = SSD(fine, case, Nf)
     Qf = _smooth_state(of, case) * (1 + 0.01 * np.random.default_rng(1).normal(
         size=(4, Nf, Nf, of.E)))
-    gf, gc = Mesh(fine, case, Nf), Mesh(coarse, case, Nc)
+    gf = Mesh(fine, case, Nf)
+    gc = Mesh(coarse if split else fine, case, Nc)
     qc = torch_cuda.empty(gc.info["state_len"], dtype=torch_cuda.float32, device="cuda:0")
-    restrict(gf, gc, torch_cuda.tensor(ch.ravel(), device="cuda:0"), to_gpu(Qf), qc)
-    _close(from_gpu(qc, Nc, gc.info["n_elem"]), S.restrict(Qf, ch, Nc), 1e-6, "restriction")
+    chd = torch_cuda.tensor(ch.ravel(), device="cuda:0") if split else None
+    restrict(gf, gc, chd, to_gpu(Qf), qc)
+    want = S.restrict(Qf, ch if split else None, Nc)
+    _close(from_gpu(qc, Nc, gc.info["n_elem"]), want, 1e-6, "restriction")
 
 
 def test_targets(torch_cuda, nested):
@@ -197,6 +202,15 @@ def test_mlp_gradient(torch_cuda, N, batch):
         rel = np.linalg.norm(G[k] - G_ora[k]) / np.linalg.norm(G_ora[k])
         print("gradient", k, "relative error", rel, flush=True)
         assert rel <= 2e-3, k
+    # with input noise (step 1 after the parameters were set)
+    loss_n, G_n = net.gradient(Xd, Td, torch_cuda.tensor(idx, device="cuda:0"), noise=0.3,
+                               seed=99)
+    nz = S.training_noise(99, 1, batch, net.n_in, 0.3)
+    L_n, G_no = _oracle_net(p, norm).loss_grads(X[idx], T[idx], bf=True, noise=nz)
+    print("loss with noise", loss_n, L_n, flush=True)
+    assert abs(loss_n - L_n) <= 1e-5 * abs(L_n) and abs(L_n - L_ora) > 1e-3 * L_ora
+    for k in G_no:
+        assert np.linalg.norm(G_n[k] - G_no[k]) <= 2e-3 * np.linalg.norm(G_no[k]), k
     # an index outside the rows contributes nothing; the mean is still
     # taken over the whole minibatch
     bad = idx.copy()

@@ -230,3 +230,38 @@ def test_targets_vanish_on_free_stream(nested):
     lin = coarse["geom"] == M.GEOM_LINEAR
     assert lin.sum() > len(lin) // 2
     assert np.abs(T[lin]).max() < 1e-10
+
+
+def test_training_noise_is_uniform_unit_variance():
+    """The training noise is uniform on [-sqrt(3), sqrt(3)) std, so it has
+    mean 0 and standard deviation std; distinct steps give distinct noise."""
+    z = S.training_noise(7, 3, 256, 84, 0.5).astype(np.float64)
+    assert z.shape == (256, 84)
+    assert np.all(np.abs(z) <= 0.5 * np.sqrt(3.0))
+    assert abs(z.mean()) < 0.01 and abs(z.std() - 0.5) < 0.01
+    h, _ = np.histogram(z, bins=8, range=(-0.5 * np.sqrt(3), 0.5 * np.sqrt(3)))
+    assert h.min() > 0.9 * h.mean()
+    assert not np.array_equal(z, S.training_noise(7, 4, 256, 84, 0.5))
+    assert np.array_equal(z, S.training_noise(7, 3, 256, 84, 0.5))
+
+
+@pytest.mark.parametrize("Nc,Nf", [(3, 6), (5, 6), (4, 4)])
+def test_projection_reproduces_and_is_orthogonal(Nc, Nf):
+    """Same-mesh order lowering: polynomials of degree < Nc are kept, and the
+    remainder is orthogonal to the coarse polynomials (Gauss-Legendre)."""
+    P = S.projection_1d(Nc, Nf)
+    Xc, Xf = solution_points(Nc), solution_points(Nf)
+    rng = np.random.default_rng(Nc + 7 * Nf)
+    c = rng.normal(size=Nc)
+    assert np.allclose(P @ np.polyval(c, Xf), np.polyval(c, Xc), atol=1e-12)
+    vals = rng.normal(size=Nf)
+    coarse = P @ vals
+    g, w = nleg.leggauss(Nf + 2)
+    z, w = 0.5 * (g + 1.0), 0.5 * w
+    from oracle.basis import lagrange
+    u = sum(vals[m] * lagrange(Xf, m, z) for m in range(Nf))
+    pu = sum(coarse[k] * lagrange(Xc, k, z) for k in range(Nc))
+    for k in range(Nc):
+        assert abs(np.sum(w * lagrange(Xc, k, z) * (u - pu))) < 1e-14
+    if Nc == Nf:
+        assert np.allclose(P, np.eye(Nc), atol=1e-13)
