@@ -172,11 +172,143 @@ class Interface:
               + np.einsum("ab,vjb->vja", PbR[1], mort[1][:, (r - m - 1) % K, :]))
         return FL, FR
 
+    def common_flux(self, T, theta, gam):
+        """Interface fluxes per unit face coordinate, canonical (4, K, N) for
+        the L and R faces, from the face traces T (4, E, 4, N)."""
+        m, dlt, thL, thR = self.placement(theta)
+        osL, PfL, PbL, PfR, PbR = self.operators(dlt)
+        TL, TR = self.canon(self.L, T), self.canon(self.Rt, T)
+        proj = self.to_mortars(TL, TR, m, PfL, PfR)
+        ang = self.mortar_angles(thL, osL)
+        scale = self.R * self.delta
+        fm = []
+        for (aL, aR), phi in zip(proj, ang):
+            nx, ny = np.cos(phi) * scale, np.sin(phi) * scale
+            fm.append(ph.rusanov(aL, aR, nx, ny, 0.0, gam))
+        return self.to_faces(fm, m, PbL, PbR)
+
+
+class GeneralInterface:
+    """A sliding interface whose two rings need not have the same number of
+    faces nor uniform faces (more than two mortars per face; the extension
+    named at the end of Sec. 3.2 and in the conclusions).
+
+    Each side's faces are sorted counter-clockwise, face i spanning the
+    angles start_i + theta_side + [0, width_i].  At a rotor angle the two
+    sides' face end points, merged in angular order, cut the circle into
+    mortars; each mortar lies on exactly one L face and one R face, at face
+    coordinate offset o and length s on each (eqs. xz, prjQ2, prjF2 with a
+    separate (o, s) per mortar).  Fluxes: Rusanov on the exact circle at
+    each mortar's solution points, as flux per unit angle times R, projected
+    back to a face with s M^-1 A^T and scaled by the face's width (flux per
+    unit face coordinate).
+    """
+
+    def __init__(self, mesh, ops):
+        self.ops = ops
+        self.c = np.asarray(mesh["center"], dtype=float)
+        self.R = float(mesh["radius"])
+        xy = mesh["xy"]
+        e, f = np.nonzero(mesh["face_kind"] == FACE_SLIDING)
+        st = xy[e, FACE_CORNERS[f, 0]] - self.c
+        en = xy[e, FACE_CORNERS[f, 1]] - self.c
+        a0 = np.arctan2(st[:, 1], st[:, 0])
+        a1 = np.arctan2(en[:, 1], en[:, 0])
+        d = _wrap_pi(a1 - a0)
+        flip = d < 0
+        start = np.where(flip, a1, a0) % (2 * np.pi)
+        cen = xy[e][:, [0, 3, 6, 9]].mean(axis=1) - self.c
+        inner = np.hypot(cen[:, 0], cen[:, 1]) < self.R
+        sides = []
+        for sel in (inner, ~inner):
+            order = np.argsort(start[sel])
+            s = dict(e=e[sel][order], f=f[sel][order], flip=flip[sel][order],
+                     start=start[sel][order], width=np.abs(d[sel][order]),
+                     zone=mesh["zone"][e[sel][order]])
+            nxt = np.concatenate([s["start"][1:], s["start"][:1] + 2 * np.pi])
+            if np.max(np.abs(nxt - s["start"] - s["width"])) > 1e-9:
+                raise ValueError("sliding interface faces do not tile the circle")
+            if len(set(s["zone"].tolist())) != 1:
+                raise ValueError("one side of the interface spans two zones")
+            sides.append(s)
+        self.L, self.Rt = sides
+        self.rotL = int(self.L["zone"][0]) == 1
+        self.rotR = int(self.Rt["zone"][0]) == 1
+
+    def mortars(self, theta):
+        """Per mortar: L face, R face, (o, s) on each, start angle, width."""
+        thL = theta if self.rotL else 0.0
+        thR = theta if self.rotR else 0.0
+        pts = []
+        for side, th, tag in ((self.L, thL, 0), (self.Rt, thR, 1)):
+            for i, a in enumerate(side["start"]):
+                pts.append(((a + th) % (2 * np.pi), tag, i))
+        pts.sort(key=lambda p: (p[0], p[1]))
+        out = []
+        M = len(pts)
+        cur = {}
+        # the face of each side in force at the first merged point
+        for tag, side, th in ((0, self.L, thL), (1, self.Rt, thR)):
+            a = (side["start"] + th) % (2 * np.pi)
+            before = np.nonzero(a <= pts[0][0])[0]
+            cur[tag] = int(before[np.argmax(a[before])]) if len(before) else int(np.argmax(a))
+        for k in range(M):
+            b0, tag, i = pts[k]
+            cur[tag] = i
+            b1 = pts[(k + 1) % M][0] + (2 * np.pi if k + 1 == M else 0.0)
+            w = b1 - b0
+            rec = dict(b0=b0, w=w, iL=cur[0], iR=cur[1])
+            for key, side, th, idx in (("L", self.L, thL, cur[0]), ("R", self.Rt, thR, cur[1])):
+                a = (side["start"][idx] + th) % (2 * np.pi)
+                off = (b0 - a) % (2 * np.pi)
+                rec["o" + key] = off / side["width"][idx]
+                rec["s" + key] = w / side["width"][idx]
+            out.append(rec)
+        return out
+
+    def canon(self, side, arr):
+        d = arr[:, side["e"], side["f"], :]
+        return np.where(side["flip"][None, :, None], d[:, :, ::-1], d)
+
+    def scatter(self, side, ring, out, sign):
+        d = np.where(side["flip"][None, :, None], ring[:, :, ::-1], ring)
+        out[:, side["e"], side["f"], :] = sign * d
+
+    def common_flux(self, T, theta, gam):
+        ops = self.ops
+        TL, TR = self.canon(self.L, T), self.canon(self.Rt, T)
+        FL = np.zeros_like(TL)
+        FR = np.zeros_like(TR)
+        for r in self.mortars(theta):
+            if r["w"] <= 0.0:
+                continue
+            aL = ops.forward(r["oL"], r["sL"]) @ TL[:, r["iL"], :].T          # (N, 4)
+            aR = ops.forward(r["oR"], r["sR"]) @ TR[:, r["iR"], :].T
+            phi = r["b0"] + r["w"] * ops.X
+            nx, ny = np.cos(phi) * self.R, np.sin(phi) * self.R
+            fm = ph.rusanov(aL.T, aR.T, nx, ny, 0.0, gam)                     # (4, N)
+            FL[:, r["iL"], :] += (ops.backward(r["oL"], r["sL"]) @ fm.T).T * self.L["width"][r["iL"]]
+            FR[:, r["iR"], :] += (ops.backward(r["oR"], r["sR"]) @ fm.T).T * self.Rt["width"][r["iR"]]
+        return FL, FR
+
+
+def make_interface(mesh, ops, general=None):
+    """The uniform interface (K equal faces per side) when the rings allow
+    it, else the general one; general=True forces the general one."""
+    if general:
+        return GeneralInterface(mesh, ops)
+    try:
+        return Interface(mesh, ops)
+    except ValueError:
+        if general is False:
+            raise
+        return GeneralInterface(mesh, ops)
+
 
 class SSD:
     """FP64 residual of the SSD method on one mesh (Sec. 3)."""
 
-    def __init__(self, mesh, case, N):
+    def __init__(self, mesh, case, N, general_interface=None):
         self.mesh = mesh
         self.case = case
         self.N = N
@@ -193,7 +325,10 @@ class SSD:
         nb = np.where(has, self.nbr, 0)
         nf = np.where(has, self.nbf, 0)
         self.rev = has & (np.einsum("efc,efc->ef", tang, tang[nb, nf]) < 0)
-        self.iface = Interface(mesh, self.ops) if np.any(self.kind == FACE_SLIDING) else None
+        self.iface = (make_interface(mesh, self.ops, general_interface)
+                      if np.any(self.kind == FACE_SLIDING) else None)
+        if isinstance(self.iface, GeneralInterface) and case["mu"] > 0:
+            raise ValueError("the general sliding interface is inviscid only")
         self.zone1 = np.asarray(mesh["zone"]) == 1
 
     # ------------------------------------------------------------------
@@ -270,17 +405,7 @@ class SSD:
 
         itf = self.iface
         if itf is not None:
-            m, dlt, thL, thR = itf.placement(theta)
-            osL, PfL, PbL, PfR, PbR = itf.operators(dlt)
-            TL, TR = itf.canon(itf.L, T), itf.canon(itf.Rt, T)
-            proj = itf.to_mortars(TL, TR, m, PfL, PfR)
-            ang = itf.mortar_angles(thL, osL)
-            scale = itf.R * itf.delta
-            fm = []
-            for (aL, aR), phi in zip(proj, ang):
-                nx, ny = np.cos(phi) * scale, np.sin(phi) * scale
-                fm.append(ph.rusanov(aL, aR, nx, ny, 0.0, gam))
-            FL, FR = itf.to_faces(fm, m, PbL, PbR)
+            FL, FR = itf.common_flux(T, theta, gam)
             itf.scatter(itf.L, FL, fs, 1.0)
             itf.scatter(itf.Rt, FR, fs, -1.0)
 

@@ -416,7 +416,7 @@ def _geometric(n, first):
 
 def ellipse_mesh(K=4096, n_in=64, n_out=180, semi=(0.5, 0.1), radius=3.0,
                  box_half=30.0, first_in=2e-3, first_out=4e-3, tile=(16, 4),
-                 wall=FACE_WALL_SLIP, nested=False):
+                 wall=FACE_WALL_SLIP, nested=False, K_out=None, warp=0.0):
     """Ellipse wall (slip, or `wall`) in a rotating disk r < radius inside a
     stationary box [-B,B]^2 with far-field sides.  K azimuthal cells, n_in
     rotating and n_out stationary layers (defaults: 4096 x (64 + 180) =
@@ -424,13 +424,25 @@ def ellipse_mesh(K=4096, n_in=64, n_out=180, semi=(0.5, 0.1), radius=3.0,
     (tile=None: ring by ring).  nested=True returns (coarse, fine, children):
     the fine mesh splits every cell 2 x 2 in its reference square (2K
     faces per interface side) and children[c, a + 2 b] is the fine element
-    of child (a, b) of coarse element c."""
-    if K % 4:
-        raise ValueError("K must be a multiple of 4")
+    of child (a, b) of coarse element c.
+
+    K_out (default K) sets the number of stationary azimuthal cells, so the
+    two sides of the sliding interface may have different face counts; warp
+    (|warp| < 1) spaces the rotating side's K faces non-uniformly, at angles
+    2 pi s + warp sin(2 pi s) for s = j / K."""
+    K_out = K if K_out is None else K_out
+    if K % 4 or K_out % 4:
+        raise ValueError("K and K_out must be multiples of 4")
+    if not abs(warp) < 1.0:
+        raise ValueError("need |warp| < 1")
     c = np.zeros(2)
     a, b = semi
-    dphi = 2 * np.pi / K
-    tt = dphi * np.arange(K)
+
+    def ang_in(s):
+        s = np.asarray(s, dtype=float)
+        return 2 * np.pi * s + warp * np.sin(2 * np.pi * s)
+
+    tt = ang_in(np.arange(K) / K)
     Ell = np.column_stack([a * np.cos(tt), b * np.sin(tt)])
     Cin = np.column_stack([radius * np.cos(tt), radius * np.sin(tt)])
     f = _geometric(n_in, first_in)
@@ -438,16 +450,21 @@ def ellipse_mesh(K=4096, n_in=64, n_out=180, semi=(0.5, 0.1), radius=3.0,
     Pin[0], Pin[-1] = Ell, Cin
 
     def ell_fn(j, t):
-        ang = (np.asarray(j) + t) * dphi
+        ang = ang_in((np.asarray(j) + t) / K)
         return np.column_stack([a * np.cos(ang), b * np.sin(ang)])
 
+    def circ_in(j, t):
+        ang = ang_in((np.asarray(j) + t) / K)
+        return np.column_stack([c[0] + radius * np.cos(ang), c[1] + radius * np.sin(ang)])
+
     inner_P = _wrap(Pin)
-    inner_curves = {0: ell_fn, n_in: _circle_fn(c, radius, 0.0, dphi)}
+    inner_curves = {0: ell_fn, n_in: circ_in}
     inner = _block(inner_P, curves=inner_curves, zone=1, tile=tile)
 
-    phi = -np.pi / 4 + dphi * np.arange(K)
+    dphi = 2 * np.pi / K_out
+    phi = -np.pi / 4 + dphi * np.arange(K_out)
     Cout = np.column_stack([radius * np.cos(phi), radius * np.sin(phi)])
-    s_box = np.linspace(-box_half, box_half, K // 4 + 1)
+    s_box = np.linspace(-box_half, box_half, K_out // 4 + 1)
     Bx = _square_perimeter(s_box)
     g = _geometric(n_out, first_out)
     Pout = (1 - g)[:, None, None] * Cout[None] + g[:, None, None] * Bx[None]
@@ -481,7 +498,7 @@ def ellipse_mesh(K=4096, n_in=64, n_out=180, semi=(0.5, 0.1), radius=3.0,
         Pf, cf = _refine_block(P, cv)
         fine_blocks.append(_block(Pf, curves=cf, zone=z, tile=tile))
     fine = finish(fine_blocks)
-    children = _children([(inner, K), (outer, K)], fine_blocks)
+    children = _children([(inner, K), (outer, K_out)], fine_blocks)
     return coarse, fine, children
 
 
