@@ -152,7 +152,7 @@ def subgrid_main(args):
     from paper_1503_02198_amd import MLP
     from paper_1503_02198_amd import subgrid as G
     log = lambda m: print("# " + m, file=sys.stderr, flush=True)
-    cfg = dict(K=64, n_in=8, n_out=16, runs=4, snapshots=200, window=(0.5, 1.0), epochs=40,
+    cfg = dict(K=64, n_in=8, n_out=16, runs=4, snapshots=500, window=(0.5, 1.0), epochs=40,
                batch=4096, lr=2e-3, noise=0.1, eval_window=(0.5, 0.6), seed=20150307)
     meshes = G.ellipse_pair(cfg["K"], cfg["n_in"], cfg["n_out"])
     rng = np.random.default_rng(cfg["seed"])

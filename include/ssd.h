@@ -122,7 +122,7 @@ typedef struct {
 typedef struct {
   int32_t N;          /* solution points per direction                  */
   int32_t n_elem;     /* elements                                       */
-  int32_t K;          /* faces per side of the sliding interface (0: none) */
+  int32_t K;          /* sliding-interface faces on the larger side (0: none) */
   int32_t n_cubic;    /* cubic elements                                 */
   int32_t viscous;    /* 1 when mu > 0                                  */
   int32_t device;     /* HIP device the handle lives on                 */
@@ -134,9 +134,15 @@ typedef struct {
  * Validates the description, builds FP64 geometry and operator tables and
  * uploads them to `device`.  Fails with SSD_ERR_MESH when a neighbour link is
  * not mutual, a face tag is unknown, |J| <= 0 at a solution or flux point,
- * the two sides of the sliding interface hold different numbers of faces,
- * or their faces are not uniform arcs of the circle (Sec. 3.2 assumes
- * uniformly meshed interface faces).  *out receives the handle.
+ * or the faces of a side of the sliding interface do not tile the circle.
+ *
+ * Sliding interface: when both sides hold K faces that are uniform arcs
+ * (Sec. 3.2), each face meets two mortars placed by (m, delta).  Otherwise
+ * (general rings: different face counts, non-uniform arcs; the extension
+ * named at the end of Sec. 3.2) the sides' face end points, merged in
+ * angular order at each rotor angle, bound the mortars, and a face meets as
+ * many as fall on it; general rings are inviscid only (SSD_ERR_MESH when
+ * mu > 0).  *out receives the handle.
  */
 ssd_status ssd_create_mesh(const ssd_mesh_desc *desc, int device, ssd_mesh **out);
 
@@ -222,7 +228,8 @@ const char *ssd_last_error(void);
  *
  * The batch references the meshes: they must outlive it, and no other call
  * may use them while a batch call runs.  Calls on one batch must not
- * overlap.
+ * overlap.  Meshes with general sliding rings (see ssd_create_mesh) cannot
+ * be batched.
  */
 typedef struct ssd_batch ssd_batch;
 

@@ -301,6 +301,8 @@ struct ssd_mesh {
     std::vector<hipEvent_t> ev;   // start/stop pairs
     size_t used = 0;
   } timers[SSD_KERNEL_COUNT];
+  bool general = false;                 // sliding interface of unequal or non-uniform rings
+  GenRing G{};
   ssd_mlp *model = nullptr;            // learned correction added by ssd_rk_steps
   float *addbuf = nullptr;             // its per-stage increment (state layout)
   float model_weight = 1.0f;           // weight of the correction
@@ -574,51 +576,65 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
   if (need_far && !(d->farfield[0] > 0.0 && d->farfield[3] > 0.0))
     return fail(SSD_ERR_MESH, "far-field faces need rho > 0 and p > 0");
 
-  // ---- sliding interface rings (Sec. 3.2: uniform faces, K per side)
+  // ---- sliding interface rings (Sec. 3.2): uniform rings of K faces per
+  // side take the (m, delta) mortars; rings of unequal face counts or
+  // non-uniform faces take the general merged mortars (inviscid only)
   if (!L.empty() || !R.empty()) {
-    if (L.size() != R.size())
-      return fail(SSD_ERR_MESH, "sliding interface: " + std::to_string(L.size()) + " inner vs " +
-                                    std::to_string(R.size()) + " outer faces");
-    const int K = int(L.size());
-    const double dphi = 2.0 * PI / K;
+    if (L.empty() || R.empty())
+      return fail(SSD_ERR_MESH, "sliding interface faces on one side only");
+    std::vector<double> width[2];
+    bool uniform = L.size() == R.size();
+    int side_i = 0;
     for (auto *side : {&L, &R}) {
       std::sort(side->begin(), side->end(),
                 [](const RingFace &a, const RingFace &b) { return a.start < b.start; });
+      const int Ks = int(side->size());
+      const double unif = 2.0 * PI / Ks;
       const int z0 = d->elem_zone[(*side)[0].e];
-      for (int j = 0; j < K; ++j) {
+      for (int j = 0; j < Ks; ++j) {
         const RingFace &rf = (*side)[j];
-        const double nxt = (j + 1 < K) ? (*side)[j + 1].start : (*side)[0].start + 2.0 * PI;
-        if (std::fabs(nxt - rf.start - dphi) > 1e-8 * dphi)
-          return fail(SSD_ERR_MESH, "sliding interface faces are not uniform");
+        const double nxt = (j + 1 < Ks) ? (*side)[j + 1].start : (*side)[0].start + 2.0 * PI;
         double ax, ay, bx, by;
         corner(rf.e, FACE_CORNERS[rf.f][0], ax, ay);
         corner(rf.e, FACE_CORNERS[rf.f][1], bx, by);
-        const double span = std::fabs(wrap_pi(std::atan2(by - cy, bx - cx) - std::atan2(ay - cy, ax - cx)));
-        if (std::fabs(span - dphi) > 1e-8 * dphi)
-          return fail(SSD_ERR_MESH, "sliding interface face spans the wrong angle");
+        const double span =
+            std::fabs(wrap_pi(std::atan2(by - cy, bx - cx) - std::atan2(ay - cy, ax - cx)));
+        if (!(span > 0.0) || std::fabs(nxt - rf.start - span) > 1e-8 * span)
+          return fail(SSD_ERR_MESH, "sliding interface faces do not tile the circle");
+        if (std::fabs(span - unif) > 1e-8 * unif) uniform = false;
         if (d->elem_zone[rf.e] != z0)
           return fail(SSD_ERR_MESH, "one side of the sliding interface spans two zones");
+        width[side_i].push_back(span);
       }
+      ++side_i;
     }
     if (d->elem_zone[L[0].e] == d->elem_zone[R[0].e])
       return fail(SSD_ERR_MESH, "both sides of the sliding interface are in the same zone");
+    if (!uniform && m->viscous)
+      return fail(SSD_ERR_MESH, "unequal or non-uniform sliding interface rings are inviscid only");
+    const int KL = int(L.size()), KR = int(R.size());
+    const int K = std::max(KL, KR);
     m->K = K;
+    m->general = !uniform;
     if (4.0 * double(face_buffer_floats(N, E, K)) >= 4294967295.0)
       return fail(SSD_ERR_INVALID_ARG, "mesh too large for one handle (face data buffer >= 4 GiB)");
-    std::vector<int> re(2 * K), rfv(2 * K), rfl(2 * K);
-    for (int j = 0; j < K; ++j) {
+    // ring slots: L faces 0..KL-1, R faces K..K+KR-1
+    std::vector<int> re(2 * K, 0), rfv(2 * K, 0), rfl(2 * K, 0);
+    for (int j = 0; j < KL; ++j) {
       re[j] = L[j].e;
       rfv[j] = L[j].f;
       rfl[j] = L[j].flip;
+      face[long(L[j].f) * E + L[j].e] = pack_face(SSD_FACE_SLIDING, j, 0, 0, 0);
+    }
+    for (int j = 0; j < KR; ++j) {
       re[K + j] = R[j].e;
       rfv[K + j] = R[j].f;
       rfl[K + j] = R[j].flip;
-      face[long(L[j].f) * E + L[j].e] = pack_face(SSD_FACE_SLIDING, j, 0, 0, 0);
       face[long(R[j].f) * E + R[j].e] = pack_face(SSD_FACE_SLIDING, K + j, 0, 0, 0);
     }
     m->D.phi0L = L[0].start;
     m->D.phi0R = R[0].start;
-    m->D.dphi = dphi;
+    m->D.dphi = 2.0 * PI / K;
     m->D.Rs = Rs;
     m->D.rotL = d->elem_zone[L[0].e] == 1;
     m->D.rotR = d->elem_zone[R[0].e] == 1;
@@ -632,6 +648,34 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
     m->D.ring_e = dre;
     m->D.ring_f = drf;
     m->D.ring_flip = drl;
+    if (m->general) {
+      std::vector<double> st(KL + KR), wd(KL + KR);
+      for (int j = 0; j < KL; ++j) {
+        st[j] = L[j].start;
+        wd[j] = width[0][j];
+      }
+      for (int j = 0; j < KR; ++j) {
+        st[KL + j] = R[j].start;
+        wd[KL + j] = width[1][j];
+      }
+      GenRing &G = m->G;
+      G.KL = KL;
+      G.KR = KR;
+      double *dst, *dwd;
+      SSD_HIP(dev_alloc(m, &dst, KL + KR), "alloc ring angles");
+      SSD_HIP(dev_alloc(m, &dwd, KL + KR), "alloc ring angles");
+      SSD_HIP(hipMemcpy(dst, st.data(), st.size() * sizeof(double), hipMemcpyHostToDevice),
+              "upload ring angles");
+      SSD_HIP(hipMemcpy(dwd, wd.data(), wd.size() * sizeof(double), hipMemcpyHostToDevice),
+              "upload ring angles");
+      G.start = dst;
+      G.width = dwd;
+      SSD_HIP(dev_alloc(m, &G.mb, KL + KR), "alloc mortar table");
+      SSD_HIP(dev_alloc(m, &G.msrc, KL + KR), "alloc mortar table");
+      SSD_HIP(dev_alloc(m, &G.posL, KL), "alloc mortar table");
+      SSD_HIP(dev_alloc(m, &G.posR, KR), "alloc mortar table");
+      SSD_HIP(dev_alloc(m, &G.mf, size_t(KL + KR) * N * 4), "alloc mortar flux");
+    }
     if (m->viscous)
       SSD_HIP(dev_alloc(m, &m->V.mvflux, 2L * K * 4 * N), "alloc viscous mortar flux");
     SSD_HIP(dev_alloc(m, &m->ms, 1), "alloc mortar state");
@@ -730,8 +774,12 @@ ssd_status residual_pass(ssd_mesh *m, double th, double omega, const float *in, 
   float *mqc = mflux + face_record_floats(m->N, m->K);
   if (m->K) {
     LaunchTimer lt(m, SSD_KERNEL_MORTAR, st);
-    SSD_HIP(launch_mortar(m->D, m->T, m->MT, th, m->ms, facein, mflux, V ? mqc : nullptr, st),
-            "mortar launch");
+    if (m->general)
+      SSD_HIP(launch_gen_mortar(m->D, m->T, m->MT, m->G, th, facein, mflux, st),
+              "general mortar launch");
+    else
+      SSD_HIP(launch_mortar(m->D, m->T, m->MT, th, m->ms, facein, mflux, V ? mqc : nullptr, st),
+              "mortar launch");
   }
   const Rotation rot{std::cos(th), std::sin(th), omega};
   if (V) {
@@ -846,7 +894,7 @@ ssd_status ssd_mortar_rebuild(ssd_mesh *m, void *stream) {
   }
   DeviceGuard guard(m->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  {
+  if (!m->general) {   // general rings merge their mortars in every residual evaluation
     LaunchTimer lt(m, SSD_KERNEL_REBUILD, st);
     SSD_HIP(launch_rebuild(m->D, m->MT, m->theta, m->ms, st), "mortar rebuild launch");
   }
@@ -1262,6 +1310,8 @@ ssd_status ssd_batch_create(ssd_mesh *const *meshes, int32_t n, ssd_batch **out)
       return fail(SSD_ERR_INVALID_ARG, "all meshes of a batch must be on one device");
     for (int d = 0; d < c; ++d)
       if (meshes[d] == meshes[c]) return fail(SSD_ERR_INVALID_ARG, "a mesh appears twice in the batch");
+    if (meshes[c]->general)
+      return fail(SSD_ERR_INVALID_ARG, "meshes with general sliding rings cannot be batched");
   }
   ssd_batch *b = new (std::nothrow) ssd_batch();
   if (!b) return fail(SSD_ERR_NOMEM, "host allocation failed");

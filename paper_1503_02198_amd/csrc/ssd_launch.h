@@ -134,6 +134,28 @@ hipError_t launch_restrict(int Nc, int Nf, const float *qf, long Ef, const int *
                            const Restrict1D &R, const float *sub, float *out, bool rows,
                            hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// general sliding interface (ssd_iface.hip): sides of KL and KR faces, any
+// widths.  L faces use ring slots 0..KL-1, R faces K..K+KR-1 (DevMesh::K =
+// max(KL, KR)).
+// ---------------------------------------------------------------------------
+struct GenRing {
+  int KL, KR;
+  const double *start;   // [KL] then [KR]: canonical (counter-clockwise) face start
+                         // angles in the body frame, ascending in [0, 2 pi)
+  const double *width;   // [KL] then [KR]: the faces' angular widths
+  double *mb;            // [KL + KR] merged rotated starts (the mortar start angles)
+  int *msrc;             // [KL + KR] side << 30 | sorted-rotated index of each
+  int *posL, *posR;      // [KL], [KR] merged position of each sorted-rotated start
+  double *mf;            // [KL + KR][N][4] mortar flux per unit angle times R
+};
+
+// Mortar merge, mortar fluxes and their projection back to the faces for
+// the rotor angle theta; inviscid.  tr: the face data buffer's traces.
+hipError_t launch_gen_mortar(const DevMesh &M, const OpTables &T, const MortarTables &MT,
+                             const GenRing &G, double theta, const float *tr, float *mflux,
+                             hipStream_t s);
+
 // W = w2 (u2 - un) + w3 (u3 - un) + w4 (u4 - un) over n floats.
 hipError_t launch_rk_combine(long n, const float *un, const float *u2, const float *u3,
                              const float *u4, float w2, float w3, float w4, float *W,
