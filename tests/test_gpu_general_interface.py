@@ -47,16 +47,17 @@ def test_residual(torch_cuda, K, K_out, warp, N):
 
 
 def test_rk3_steps(torch_cuda):
+    """40 steps at 0.8 of the CFL-0.1 step of the mesh (1.5e-4)."""
     from paper_1503_02198_amd import Mesh
-    print("case: general interface SSP-RK3 30 steps", flush=True)
+    print("case: general interface SSP-RK3 40 steps", flush=True)
     case = C.ellipse_case(omega=2.0)
     mesh = _mesh(16, 24, 0.3)
     N = 3
     ora = SSD(mesh, case, N)
     gm = Mesh(mesh, case, N)
     Q = C.perturbed_farfield_state(case, N, ora.E, amplitude=0.05)
-    Qg = gpu_run(gm, Q, 0.0, 2e-3, 30)
-    Qo = ora.run(Q, 0.0, 2e-3, 30)
+    Qg = gpu_run(gm, Q, 0.4, 1.2e-4, 40)
+    Qo = ora.run(Q, 0.4, 1.2e-4, 40)
     err = state_error(Qg, Qo)
     print("state error", err, flush=True)
     assert np.all(err <= TOL), err
