@@ -141,8 +141,7 @@ typedef struct {
  * (general rings: different face counts, non-uniform arcs; the extension
  * named at the end of Sec. 3.2) the sides' face end points, merged in
  * angular order at each rotor angle, bound the mortars, and a face meets as
- * many as fall on it; general rings are inviscid only (SSD_ERR_MESH when
- * mu > 0).  *out receives the handle.
+ * many as fall on it.  *out receives the handle.
  */
 ssd_status ssd_create_mesh(const ssd_mesh_desc *desc, int device, ssd_mesh **out);
 

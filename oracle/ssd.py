@@ -188,6 +188,34 @@ class Interface:
         return self.to_faces(fm, m, PbL, PbR)
 
 
+    def common_solution(self, T, theta):
+        """BR1 common solution on the interface faces, canonical (4, K, N):
+        the mean of both sides' projections on each mortar, projected back."""
+        m, dlt, thL, thR = self.placement(theta)
+        osL, PfL, PbL, PfR, PbR = self.operators(dlt)
+        TL, TR = self.canon(self.L, T), self.canon(self.Rt, T)
+        proj = self.to_mortars(TL, TR, m, PfL, PfR)
+        return self.to_faces([0.5 * (aL + aR) for aL, aR in proj], m, PbL, PbR)
+
+    def viscous_common_flux(self, Qc, GX, GY, theta, flux):
+        """Viscous interface flux per unit face coordinate, canonical: each
+        side's face viscous flux along the radial normal (from the faces'
+        common solution and own gradients; flux(q, gx, gy) -> (F, G)),
+        projected onto the mortars, averaged, projected back."""
+        m, dlt, thL, thR = self.placement(theta)
+        osL, PfL, PbL, PfR, PbR = self.operators(dlt)
+        scale = self.R * self.delta
+
+        def side_flux(side, th):
+            phi = self.face_angles(side, th)
+            nx, ny = np.cos(phi) * scale, np.sin(phi) * scale
+            Fs, Gs = flux(self.canon(side, Qc), self.canon(side, GX), self.canon(side, GY))
+            return Fs * nx + Gs * ny
+
+        proj = self.to_mortars(side_flux(self.L, thL), side_flux(self.Rt, thR), m, PfL, PfR)
+        return self.to_faces([0.5 * (aL + aR) for aL, aR in proj], m, PbL, PbR)
+
+
 class GeneralInterface:
     """A sliding interface whose two rings need not have the same number of
     faces nor uniform faces (more than two mortars per face; the extension
@@ -274,22 +302,47 @@ class GeneralInterface:
         d = np.where(side["flip"][None, :, None], ring[:, :, ::-1], ring)
         out[:, side["e"], side["f"], :] = sign * d
 
-    def common_flux(self, T, theta, gam):
+    def _per_mortar(self, VL, VR, theta, combine, widths):
+        """For every mortar: project side data VL, VR (4, K_side, N) onto it,
+        combine(aL, aR, rec) -> (4, N) mortar values, project back onto both
+        faces (times the face width when `widths`)."""
         ops = self.ops
-        TL, TR = self.canon(self.L, T), self.canon(self.Rt, T)
-        FL = np.zeros_like(TL)
-        FR = np.zeros_like(TR)
+        FL = np.zeros((VL.shape[0],) + VL.shape[1:])
+        FR = np.zeros((VR.shape[0],) + VR.shape[1:])
         for r in self.mortars(theta):
             if r["w"] <= 0.0:
                 continue
-            aL = ops.forward(r["oL"], r["sL"]) @ TL[:, r["iL"], :].T          # (N, 4)
-            aR = ops.forward(r["oR"], r["sR"]) @ TR[:, r["iR"], :].T
-            phi = r["b0"] + r["w"] * ops.X
-            nx, ny = np.cos(phi) * self.R, np.sin(phi) * self.R
-            fm = ph.rusanov(aL.T, aR.T, nx, ny, 0.0, gam)                     # (4, N)
-            FL[:, r["iL"], :] += (ops.backward(r["oL"], r["sL"]) @ fm.T).T * self.L["width"][r["iL"]]
-            FR[:, r["iR"], :] += (ops.backward(r["oR"], r["sR"]) @ fm.T).T * self.Rt["width"][r["iR"]]
+            aL = (ops.forward(r["oL"], r["sL"]) @ VL[:, r["iL"], :].T).T       # (4, N)
+            aR = (ops.forward(r["oR"], r["sR"]) @ VR[:, r["iR"], :].T).T
+            fm = combine(aL, aR, r)
+            wL = self.L["width"][r["iL"]] if widths else 1.0
+            wR = self.Rt["width"][r["iR"]] if widths else 1.0
+            FL[:, r["iL"], :] += (ops.backward(r["oL"], r["sL"]) @ fm.T).T * wL
+            FR[:, r["iR"], :] += (ops.backward(r["oR"], r["sR"]) @ fm.T).T * wR
         return FL, FR
+
+    def common_flux(self, T, theta, gam):
+        def rus(aL, aR, r):
+            phi = r["b0"] + r["w"] * self.ops.X
+            return ph.rusanov(aL, aR, np.cos(phi) * self.R, np.sin(phi) * self.R, 0.0, gam)
+        return self._per_mortar(self.canon(self.L, T), self.canon(self.Rt, T), theta, rus, True)
+
+    def common_solution(self, T, theta):
+        return self._per_mortar(self.canon(self.L, T), self.canon(self.Rt, T), theta,
+                                lambda aL, aR, r: 0.5 * (aL + aR), False)
+
+    def viscous_common_flux(self, Qc, GX, GY, theta, flux):
+        X = self.ops.X
+
+        def side_flux(side, rot):
+            th = theta if rot else 0.0
+            phi = side["start"][:, None] + th + side["width"][:, None] * X[None, :]
+            nx, ny = np.cos(phi) * self.R, np.sin(phi) * self.R          # per unit angle
+            Fs, Gs = flux(self.canon(side, Qc), self.canon(side, GX), self.canon(side, GY))
+            return Fs * nx + Gs * ny
+
+        return self._per_mortar(side_flux(self.L, self.rotL), side_flux(self.Rt, self.rotR), theta,
+                                lambda aL, aR, r: 0.5 * (aL + aR), True)
 
 
 def make_interface(mesh, ops, general=None):
@@ -327,8 +380,6 @@ class SSD:
         self.rev = has & (np.einsum("efc,efc->ef", tang, tang[nb, nf]) < 0)
         self.iface = (make_interface(mesh, self.ops, general_interface)
                       if np.any(self.kind == FACE_SLIDING) else None)
-        if isinstance(self.iface, GeneralInterface) and case["mu"] > 0:
-            raise ValueError("the general sliding interface is inviscid only")
         self.zone1 = np.asarray(mesh["zone"]) == 1
 
     # ------------------------------------------------------------------
@@ -463,12 +514,7 @@ class SSD:
 
         itf = self.iface
         if itf is not None:
-            m, dlt, thL, thR = itf.placement(theta)
-            osL, PfL, PbL, PfR, PbR = itf.operators(dlt)
-            TL, TR = itf.canon(itf.L, T), itf.canon(itf.Rt, T)
-            proj = itf.to_mortars(TL, TR, m, PfL, PfR)
-            avg = [0.5 * (aL + aR) for aL, aR in proj]
-            QcL, QcR = itf.to_faces(avg, m, PbL, PbR)
+            QcL, QcR = itf.common_solution(T, theta)
             itf.scatter(itf.L, QcL, Qc, 1.0)
             itf.scatter(itf.Rt, QcR, Qc, 1.0)
 
@@ -502,20 +548,8 @@ class SSD:
         fv = np.where(slip, 0.0, fv)
 
         if itf is not None:
-            scale = itf.R * itf.delta
-
-            def side_flux(side, th):
-                phi = itf.face_angles(side, th)
-                nx, ny = np.cos(phi) * scale, np.sin(phi) * scale
-                Fs, Gs = ph.viscous_flux(itf.canon(side, Qc), itf.canon(side, GX),
-                                         itf.canon(side, GY), gam, Rg, mu, Pr)
-                return Fs * nx + Gs * ny
-
-            vL = side_flux(itf.L, thL)
-            vR = side_flux(itf.Rt, thR)
-            proj = itf.to_mortars(vL, vR, m, PfL, PfR)
-            avg = [0.5 * (aL + aR) for aL, aR in proj]
-            FvL, FvR = itf.to_faces(avg, m, PbL, PbR)
+            FvL, FvR = itf.viscous_common_flux(
+                Qc, GX, GY, theta, lambda q, gx, gy: ph.viscous_flux(q, gx, gy, gam, Rg, mu, Pr))
             itf.scatter(itf.L, FvL, fv, 1.0)
             itf.scatter(itf.Rt, FvR, fv, -1.0)
 

@@ -578,7 +578,7 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
 
   // ---- sliding interface rings (Sec. 3.2): uniform rings of K faces per
   // side take the (m, delta) mortars; rings of unequal face counts or
-  // non-uniform faces take the general merged mortars (inviscid only)
+  // non-uniform faces take the general merged mortars
   if (!L.empty() || !R.empty()) {
     if (L.empty() || R.empty())
       return fail(SSD_ERR_MESH, "sliding interface faces on one side only");
@@ -610,8 +610,6 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
     }
     if (d->elem_zone[L[0].e] == d->elem_zone[R[0].e])
       return fail(SSD_ERR_MESH, "both sides of the sliding interface are in the same zone");
-    if (!uniform && m->viscous)
-      return fail(SSD_ERR_MESH, "unequal or non-uniform sliding interface rings are inviscid only");
     const int KL = int(L.size()), KR = int(R.size());
     const int K = std::max(KL, KR);
     m->K = K;
@@ -675,6 +673,8 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
       SSD_HIP(dev_alloc(m, &G.posL, KL), "alloc mortar table");
       SSD_HIP(dev_alloc(m, &G.posR, KR), "alloc mortar table");
       SSD_HIP(dev_alloc(m, &G.mf, size_t(KL + KR) * N * 4), "alloc mortar flux");
+      if (m->viscous)
+        SSD_HIP(dev_alloc(m, &G.mq, size_t(KL + KR) * N * 4), "alloc mortar solution");
     }
     if (m->viscous)
       SSD_HIP(dev_alloc(m, &m->V.mvflux, 2L * K * 4 * N), "alloc viscous mortar flux");
@@ -775,7 +775,7 @@ ssd_status residual_pass(ssd_mesh *m, double th, double omega, const float *in, 
   if (m->K) {
     LaunchTimer lt(m, SSD_KERNEL_MORTAR, st);
     if (m->general)
-      SSD_HIP(launch_gen_mortar(m->D, m->T, m->MT, m->G, th, facein, mflux, st),
+      SSD_HIP(launch_gen_mortar(m->D, m->T, m->MT, m->G, th, facein, mflux, V ? mqc : nullptr, st),
               "general mortar launch");
     else
       SSD_HIP(launch_mortar(m->D, m->T, m->MT, th, m->ms, facein, mflux, V ? mqc : nullptr, st),
@@ -789,8 +789,12 @@ ssd_status residual_pass(ssd_mesh *m, double th, double omega, const float *in, 
     }
     if (m->K) {
       LaunchTimer lt(m, SSD_KERNEL_MORTAR, st);
-      SSD_HIP(launch_mortar_visc(m->D, m->T, m->ms, mqc, V->gtr, V->mvflux, st),
-              "viscous mortar launch");
+      if (m->general)
+        SSD_HIP(launch_gen_mortar_visc(m->D, m->T, m->MT, m->G, th, mqc, V->gtr, V->mvflux, st),
+                "general viscous mortar launch");
+      else
+        SSD_HIP(launch_mortar_visc(m->D, m->T, m->ms, mqc, V->gtr, V->mvflux, st),
+                "viscous mortar launch");
     }
   }
   LaunchTimer lt(m, SSD_KERNEL_STAGE, st);

@@ -16,6 +16,10 @@
 //      merged order) are projected back (s M^-1 A^T, eq. prjF2) and scaled
 //      by the face's angular width, giving the outward flux per unit face
 //      parameter in the records the stage kernel reads.
+// Viscous meshes: k_gen_flux also keeps the mean of the two projections
+// (BR1 common solution), projected back into the common-solution records;
+// after the gradient pass k_gen_vflux averages the two sides' face viscous
+// fluxes on each mortar, and k_gen_back projects them back.
 #include "ssd_launch.h"
 #include "ssd_tiles.h"
 
@@ -138,7 +142,7 @@ __device__ __forceinline__ MortarRec mortar_at(const DevMesh &M, const GenRing &
   return r;
 }
 
-template <int N>
+template <int N, bool VISC>
 __global__ __launch_bounds__(256) void k_gen_flux(DevMesh M, OpTables T, MortarTables MT,
                                                   GenRing G, double theta,
                                                   const float *__restrict__ tr) {
@@ -172,12 +176,69 @@ __global__ __launch_bounds__(256) void k_gen_flux(DevMesh M, OpTables T, MortarT
   double f4[4];
   rusanov_d(q[0], q[1], cs * M.Rs, sn * M.Rs, double(M.gamma), f4);
 #pragma unroll
-  for (int v = 0; v < 4; ++v) G.mf[(long(k) * N + a) * 4 + v] = f4[v];
+  for (int v = 0; v < 4; ++v) {
+    G.mf[(long(k) * N + a) * 4 + v] = f4[v];
+    // BR1 common solution at the mortar point: the mean of both projections
+    if (VISC) G.mq[(long(k) * N + a) * 4 + v] = 0.5 * (q[0][v] + q[1][v]);
+  }
 }
 
+// Viscous mortar flux at mortar point a: each side's face viscous flux along
+// the radial normal per unit angle times R, at its face points from the
+// face's common solution (mqc) and own gradient trace (gtr), projected onto
+// the mortar; the two sides averaged.  Into G.mf.
+template <int N>
+__global__ __launch_bounds__(256) void k_gen_vflux(DevMesh M, OpTables T, MortarTables MT,
+                                                   GenRing G, double theta,
+                                                   const float *__restrict__ mqc,
+                                                   const float *__restrict__ gtr) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  const int Mn = G.KL + G.KR;
+  if (idx >= Mn * N) return;
+  const int k = idx / N, a = idx % N;
+  const MortarRec r = mortar_at(M, G, theta, k);
+  const double gam = M.gamma, Rg = M.gas_R, mu = M.mu;
+  const double kc = mu * gam * Rg / ((gam - 1.0) * double(M.prandtl));
+  double avg[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int slot = s ? M.K + r.f[s] : r.f[s];
+    const double *start = G.start + (s ? G.KL : 0), *width = G.width + (s ? G.KL : 0);
+    const double th = (s ? M.rotR : M.rotL) ? theta : 0.0;
+    double vf[4][N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      double sn, cs;
+      sincos(start[r.f[s]] + th + width[r.f[s]] * T.X[b], &sn, &cs);
+      double q4[4], g8[8], f[4];
+      load_slot_point<N>(M, mqc, slot, b, q4);
+      load_canon_point<N, 8>(M, gtr, slot, b, g8);
+      visc_flux_n<double>(q4, g8, g8 + 4, cs * M.Rs, sn * M.Rs, gam, Rg, mu, kc, f);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) vf[v][b] = f[v];
+    }
+    double A[N][N];
+    overlap<N>(MT, r.o[s], r.s[s], A);
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      double pf = 0.0;   // (M^-1 A)[a][b]
+#pragma unroll
+      for (int l = 0; l < N; ++l) pf += MT.Minv[a][l] * A[l][b];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) avg[v] += 0.5 * pf * vf[v][b];
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) G.mf[(long(k) * N + a) * 4 + v] = avg[v];
+}
+
+// Back-projection of mortar data src [M][N][4] to face records dst: for a
+// flux, outward and per unit face parameter (times the face width, R faces
+// negated); for the common solution, as it is.
 template <int N>
 __global__ __launch_bounds__(256) void k_gen_back(DevMesh M, MortarTables MT, GenRing G,
-                                                  double theta, float *__restrict__ mflux) {
+                                                  double theta, const double *__restrict__ src,
+                                                  float *__restrict__ dst, int flux) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= (G.KL + G.KR) * N) return;
   const int i = idx / N, a = idx % N;
@@ -202,26 +263,47 @@ __global__ __launch_bounds__(256) void k_gen_back(DevMesh M, MortarTables MT, Ge
       for (int l = 0; l < N; ++l) pb += MT.Minv[a][l] * A[b][l];
       pb *= r.s[side];
 #pragma unroll
-      for (int vv = 0; vv < 4; ++vv) acc[vv] += pb * G.mf[(long(k) * N + b) * 4 + vv];
+      for (int vv = 0; vv < 4; ++vv) acc[vv] += pb * src[(long(k) * N + b) * 4 + vv];
     }
   }
   const int slot = side ? M.K + face : face;
   const int pa = M.ring_flip[slot] ? N - 1 - a : a;
-  const double sc = (side ? -1.0 : 1.0) * v.width[face];
+  const double sc = flux ? (side ? -1.0 : 1.0) * v.width[face] : 1.0;
 #pragma unroll
-  for (int vv = 0; vv < 4; ++vv) mflux[(long(slot) * N + pa) * 4 + vv] = float(sc * acc[vv]);
+  for (int vv = 0; vv < 4; ++vv) dst[(long(slot) * N + pa) * 4 + vv] = float(sc * acc[vv]);
 }
 
 hipError_t launch_gen_mortar(const DevMesh &M, const OpTables &T, const MortarTables &MT,
                              const GenRing &G, double theta, const float *tr, float *mflux,
-                             hipStream_t s) {
+                             float *mqc, hipStream_t s) {
   const int nb = G.KL + G.KR;
   hipLaunchKernelGGL(k_gen_merge, dim3((nb + 255) / 256), dim3(256), 0, s, M, G, theta);
   const int np = nb * M.N;
-  SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_gen_flux<NN>, dim3((np + 255) / 256), dim3(256), 0, s,
-                                         M, T, MT, G, theta, tr));
-  SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_gen_back<NN>, dim3((np + 255) / 256), dim3(256), 0, s,
-                                         M, MT, G, theta, mflux));
+  const dim3 grid((np + 255) / 256);
+  if (mqc) {
+    SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_gen_flux<NN, true>), grid, dim3(256), 0, s, M, T,
+                                           MT, G, theta, tr));
+  } else {
+    SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_gen_flux<NN, false>), grid, dim3(256), 0, s, M, T,
+                                           MT, G, theta, tr));
+  }
+  SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_gen_back<NN>, grid, dim3(256), 0, s, M, MT, G, theta,
+                                         G.mf, mflux, 1));
+  if (mqc)
+    SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_gen_back<NN>, grid, dim3(256), 0, s, M, MT, G, theta,
+                                           G.mq, mqc, 0));
+  return hipGetLastError();
+}
+
+hipError_t launch_gen_mortar_visc(const DevMesh &M, const OpTables &T, const MortarTables &MT,
+                                  const GenRing &G, double theta, const float *mqc,
+                                  const float *gtr, float *mvflux, hipStream_t s) {
+  const int np = (G.KL + G.KR) * M.N;
+  const dim3 grid((np + 255) / 256);
+  SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_gen_vflux<NN>, grid, dim3(256), 0, s, M, T, MT, G,
+                                         theta, mqc, gtr));
+  SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_gen_back<NN>, grid, dim3(256), 0, s, M, MT, G, theta,
+                                         G.mf, mvflux, 1));
   return hipGetLastError();
 }
 

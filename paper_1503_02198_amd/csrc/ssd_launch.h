@@ -148,13 +148,20 @@ struct GenRing {
   int *msrc;             // [KL + KR] side << 30 | sorted-rotated index of each
   int *posL, *posR;      // [KL], [KR] merged position of each sorted-rotated start
   double *mf;            // [KL + KR][N][4] mortar flux per unit angle times R
+  double *mq;            // [KL + KR][N][4] mortar common solution (viscous meshes)
 };
 
 // Mortar merge, mortar fluxes and their projection back to the faces for
-// the rotor angle theta; inviscid.  tr: the face data buffer's traces.
+// the rotor angle theta (tr: the face data buffer's traces); with mqc also
+// the faces' common solution.
 hipError_t launch_gen_mortar(const DevMesh &M, const OpTables &T, const MortarTables &MT,
                              const GenRing &G, double theta, const float *tr, float *mflux,
-                             hipStream_t s);
+                             float *mqc, hipStream_t s);
+// Viscous mortar flux from the faces' common solution and gradient traces,
+// for the angle of the preceding launch_gen_mortar.
+hipError_t launch_gen_mortar_visc(const DevMesh &M, const OpTables &T, const MortarTables &MT,
+                                  const GenRing &G, double theta, const float *mqc,
+                                  const float *gtr, float *mvflux, hipStream_t s);
 
 // W = w2 (u2 - un) + w3 (u3 - un) + w4 (u4 - un) over n floats.
 hipError_t launch_rk_combine(long n, const float *un, const float *u2, const float *u3,

@@ -63,10 +63,28 @@ def test_rk3_steps(torch_cuda):
     assert np.all(err <= TOL), err
 
 
-def test_viscous_general_rings_rejected(torch_cuda):
-    from paper_1503_02198_amd import Mesh, SSDError
-    print("case: viscous general rings rejected", flush=True)
+@pytest.mark.parametrize("K,K_out,warp,N", [(16, 24, 0.3, 3), (24, 16, -0.4, 4)])
+def test_viscous_residual(torch_cuda, K, K_out, warp, N):
+    """BR1 common solution and viscous flux through the general mortars."""
+    from paper_1503_02198_amd import Mesh
+    print(f"case: general interface viscous residual K={K} K_out={K_out} N={N}", flush=True)
     case = C.ellipse_case()
-    case["mu"] = 0.01
+    case["mu"] = 0.02
+    mesh = _mesh(K, K_out, warp)
+    ora = SSD(mesh, case, N)
+    gm = Mesh(mesh, case, N)
+    Q = C.perturbed_farfield_state(case, N, ora.E, amplitude=0.05)
+    for th in (0.0, 0.81, -2.6):
+        Rg = gpu_residual(gm, Q, th, case["omega"])
+        Ro, diag = ora.residual(Q, th, case["omega"], diag=True)
+        err = residual_error(Rg, Ro, diag["flux_scale"])
+        print("theta", th, "residual error", err, flush=True)
+        assert np.all(err <= TOL), err
+
+
+def test_batch_rejects_general_rings(torch_cuda):
+    from paper_1503_02198_amd import Batch, Mesh, SSDError
+    print("case: batch rejects general rings", flush=True)
+    gm = Mesh(_mesh(16, 24, 0.3), C.ellipse_case(), 3)
     with pytest.raises(SSDError):
-        Mesh(_mesh(16, 24, 0.3), case, 3)
+        Batch([gm])

@@ -98,3 +98,39 @@ def test_face_flux_converges_to_the_normal_flux():
         errs.append(worst)
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert errs[-1] < 1e-4 and np.all(rates > 2.5), (errs, rates)
+
+
+def test_viscous_equals_uniform_construction_on_uniform_rings():
+    """BR1 common solution and viscous mortar flux through the general
+    interface equal the uniform construction's on uniform rings."""
+    case = C.ellipse_case()
+    case["mu"] = 0.02
+    mesh = _mesh(K_out=16, warp=0.0)
+    Q = C.perturbed_farfield_state(case, 3, len(mesh["zone"]), amplitude=0.05)
+    uni, gen = SSD(mesh, case, 3), SSD(mesh, case, 3, general_interface=True)
+    for th in (0.0, 0.43, -1.2):
+        Ru, Rg = uni.residual(Q, th, 1.0), gen.residual(Q, th, 1.0)
+        assert np.abs(Ru - Rg).max() <= 1e-12 * np.abs(Ru).max()
+
+
+def test_viscous_general_residual_conserves():
+    """On unequal, non-uniform rings the viscous residual's interface terms
+    still cancel: the total of |J| dQ/dt over the mesh equals the boundary
+    flux through the walls and the far field only, as on a conforming mesh;
+    checked as the change of the totals under a change of the state that is
+    zero away from the interface."""
+    case = C.ellipse_case()
+    case["mu"] = 0.02
+    ssd = SSD(_mesh(n=4), case, 3)   # BR1 reaches two cells: keep walls and far field 3 away
+    Q = C.perturbed_farfield_state(case, 3, ssd.E, amplitude=0.05)
+    R1 = ssd.residual(Q, 0.3, 1.0)
+    Q2 = Q.copy()
+    ring = np.unique(np.concatenate([ssd.iface.L["e"], ssd.iface.Rt["e"]]))
+    Q2[..., ring] *= 1.0 + 0.02 * np.random.default_rng(3).normal(size=(4, 3, 3, len(ring)))
+    R2 = ssd.residual(Q2, 0.3, 1.0)
+    w = ssd.ops.w
+    J = ssd.geo.detJ                                                   # (E, N, N) [e, j, i]
+    tot = lambda R: np.einsum("j,i,eji,vjie->v", w, w, J, R)
+    # the ring cells touch no wall and no far field, so the totals may only
+    # differ by roundoff
+    assert np.allclose(tot(R1), tot(R2), rtol=0, atol=1e-10 * np.abs(R1).max())
