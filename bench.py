@@ -11,8 +11,8 @@ One "step" is one SSP-RK3 step (three residual evaluations, each with its
 mortar rebuild and projection).  `value` is DOF-updates per second per RK
 stage: 4 N^2 E x 3 x steps / seconds, with the state resident in HBM.
 
-Prints one JSON line.  `--gpus` above 1 is refused: this build runs on one
-GPU.
+Prints one JSON line.  `--gpus` above 1 is refused: the library runs one
+mesh on one GPU.
 """
 import argparse
 import hashlib
@@ -306,8 +306,8 @@ def main():
         ingest_counters(*args.ingest_counters, E=E, N=args.N)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "sharding of the method is a design note, not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding the "
+              "method over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
