@@ -153,7 +153,8 @@ def subgrid_main(args):
     from paper_1503_02198_amd import subgrid as G
     log = lambda m: print("# " + m, file=sys.stderr, flush=True)
     cfg = dict(K=64, n_in=8, n_out=16, runs=4, snapshots=500, window=(0.5, 1.0), epochs=40,
-               batch=4096, lr=2e-3, noise=0.1, eval_window=(0.5, 0.6), seed=20150307)
+               batch=4096, lr=2e-3, noise=0.1, eval_window=(0.5, 0.6), seed=20150307,
+               per_step=True)
     meshes = G.ellipse_pair(cfg["K"], cfg["n_in"], cfg["n_out"])
     rng = np.random.default_rng(cfg["seed"])
     rates = rng.uniform(0.5, 2.0, cfg["runs"])
@@ -166,7 +167,7 @@ def subgrid_main(args):
                               noise=cfg["noise"])
     log(f"training loss {losses[0]:.4e} -> {losses[-1]:.4e} in {train_s:.2f} s")
     res = G.evaluate(meshes, net, G.convective_omega(rate_eval), *cfg["eval_window"],
-                     weights=(1.0,))
+                     weights=(1.0,), per_step=cfg["per_step"])
     sp = G.speedup_at_equal_error(res)[0]
     steps = cfg["epochs"] * (rows // cfg["batch"])
     print(json.dumps({

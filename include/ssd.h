@@ -405,9 +405,11 @@ ssd_status ssd_subgrid_targets(const ssd_mesh *fine, const ssd_mesh *coarse,
 
 /* Attaches `net` (same N and device) to mesh m with weight w (finite): from
  * then on ssd_rk_step(s) with SSD_RK3_SSP adds w C(Q) to dQ/dt in every
- * stage (other schemes return SSD_ERR_INVALID_ARG).  net = NULL detaches
- * (plain SSD).  The network must outlive the attachment. */
-ssd_status ssd_subgrid_attach(ssd_mesh *m, ssd_mlp *net, float w);
+ * stage (other schemes return SSD_ERR_INVALID_ARG), C evaluated at each
+ * stage's input, or, with per_step != 0, once per step at Q^n and held for
+ * the step's three stages (a third of the network's cost).  net = NULL
+ * detaches (plain SSD).  The network must outlive the attachment. */
+ssd_status ssd_subgrid_attach(ssd_mesh *m, ssd_mlp *net, float w, int32_t per_step);
 
 #ifdef __cplusplus
 }

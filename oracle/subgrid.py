@@ -215,19 +215,25 @@ def adam_step(params, grads, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return params
 
 
-def corrected_rk3(ssd, mlp, Q, t, dt, nsteps, bf=False):
-    """SSP-RK3 of dQ/dt = R(Q) + C(Q), C the MLP output laid back out as
-    [v, j, i, e] (the correction of the coarse run)."""
+def corrected_rk3(ssd, mlp, Q, t, dt, nsteps, bf=False, per_step=False):
+    """SSP-RK3 of dQ/dt = R(Q) + C, C the MLP output laid back out as
+    [v, j, i, e] (the correction of the coarse run): C(Q) of each stage's
+    input, or (per_step) C(Q^n) of the step's start for all its stages."""
     N = ssd.N
 
-    def rhs(U, tau):
+    def corr(U):
         C = mlp.predict(features(ssd, U), bf)                     # (E, 4 N^2)
-        Cq = C.reshape(ssd.E, 4, N, N).transpose(1, 2, 3, 0)
-        return ssd.residual(U, ssd.theta(tau), ssd.case["omega"]) + Cq
+        return C.reshape(ssd.E, 4, N, N).transpose(1, 2, 3, 0)
 
     U = np.asarray(Q, dtype=float).copy()
     for s in range(nsteps):
         tn = t + s * dt
+        Cn = corr(U) if per_step else None
+
+        def rhs(V, tau):
+            return ssd.residual(V, ssd.theta(tau), ssd.case["omega"]) + (
+                Cn if per_step else corr(V))
+
         U1 = U + dt * rhs(U, tn)
         U2 = 0.75 * U + 0.25 * (U1 + dt * rhs(U1, tn + dt))
         U = U / 3.0 + 2.0 / 3.0 * (U2 + dt * rhs(U2, tn + 0.5 * dt))

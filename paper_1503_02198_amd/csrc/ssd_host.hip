@@ -306,6 +306,7 @@ struct ssd_mesh {
   ssd_mlp *model = nullptr;            // learned correction added by ssd_rk_steps
   float *addbuf = nullptr;             // its per-stage increment (state layout)
   float model_weight = 1.0f;           // weight of the correction
+  bool model_per_step = false;         // the correction of Q^n serves all stages of a step
 };
 
 // A network of the learned subgrid correction.  FP32 parameters laid out
@@ -959,11 +960,11 @@ ssd_status ssd_rk_steps(ssd_mesh *m, float *q, float *work, double t, double dt,
   int cur = 0;   // face data buffer holding the traces of the current stage input
   // one stage: the residual of `in` at t + c dt, fused with the update
   auto stage = [&](double tn, double c, const float *in, const float *qn, float *out, float beta,
-                   float gamma, const float *add) -> ssd_status {
+                   float gamma, const float *add, float add_scale = 1.0f) -> ssd_status {
     const double th = m->theta0 + m->omega0 * (tn + c * dt);
     // the mortar kernel rebuilds the projections for th itself
     ssd_status e = residual_pass(m, th, m->omega0, in, qn, out, m->tr[cur], m->tr[cur ^ 1],
-                                 RKCoef{beta, gamma, float(dt), add}, true, st);
+                                 RKCoef{beta, gamma, float(dt), add, add_scale}, true, st);
     cur ^= 1;
     return e;
   };
@@ -976,12 +977,16 @@ ssd_status ssd_rk_steps(ssd_mesh *m, float *q, float *work, double t, double dt,
       const float *in[3] = {q, w1, w2};
       float *outp[3] = {w1, w2, q};
       for (int k = 0; k < 3; ++k) {
-        if (m->model)   // learned correction: add = w b_k dt C(Q_k), added by the stage
+        // learned correction: per stage, add = w b_k dt C(Q_k); once per step,
+        // add = w dt C(Q^n), scaled by b_k in every stage
+        if (m->model && (!m->model_per_step || k == 0))
           SSD_HIP(launch_subgrid(m->D, m->T, mlp_dev(m->model), in[k], m->addbuf,
-                                 float(m->model_weight * B[k] * dt), st),
+                                 float(m->model_weight * (m->model_per_step ? 1.0 : B[k]) * dt),
+                                 st),
                   "subgrid correction launch");
         if (ssd_status e = stage(tn, Cs[k], in[k], k ? q : nullptr, outp[k], B[k], B[k],
-                                 m->model ? m->addbuf : nullptr))
+                                 m->model ? m->addbuf : nullptr,
+                                 m->model && m->model_per_step ? B[k] : 1.0f))
           return e;
       }
     } else {
@@ -1913,7 +1918,7 @@ ssd_status ssd_subgrid_targets(const ssd_mesh *fine, const ssd_mesh *coarse,
   return SSD_OK;
 }
 
-ssd_status ssd_subgrid_attach(ssd_mesh *m, ssd_mlp *net, float w) {
+ssd_status ssd_subgrid_attach(ssd_mesh *m, ssd_mlp *net, float w, int32_t per_step) {
   if (ssd_status s = check_handle(m)) return s;
   if (!net) {
     m->model = nullptr;
@@ -1928,6 +1933,7 @@ ssd_status ssd_subgrid_attach(ssd_mesh *m, ssd_mlp *net, float w) {
 
   m->model = net;
   m->model_weight = w;
+  m->model_per_step = per_step != 0;
   return SSD_OK;
 }
 

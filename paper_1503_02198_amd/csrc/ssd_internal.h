@@ -134,10 +134,11 @@ struct ViscIO {
 };
 
 // Coefficients of one Runge-Kutta stage: out = qn + beta (q - qn) +
-// gamma dt dQ/dt [+ add] (qn null: qn = q).
+// gamma dt dQ/dt [+ add_scale add] (qn null: qn = q).
 struct RKCoef {
   float beta, gamma, dt;
-  const float *add;   // null: nothing added
+  const float *add;        // null: nothing added
+  float add_scale = 1.0f;
 };
 
 }  // namespace ssd

@@ -405,7 +405,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
   }
 
   // ---- SSP-RK stage on column w: Q <- Qn + beta (Q - Qn) + gamma dt R
-  // [+ add]; the new column goes to SR (no other lane reads column w of SR
+  // [+ add_scale add]; the new column goes to SR (no other lane reads column w of SR
   // after the column phase has started)
   bool bad = false;
 #pragma unroll
@@ -415,7 +415,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
     for (int v = 0; v < 4; ++v) {
       float x = with_qn ? qo[v][j] + (C.beta * (qc[v][j] - qo[v][j]) + gdt * rc[v][j])
                         : qc[v][j] + gdt * rc[v][j];
-      if (ADD) x += qa[v][j];
+      if (ADD) x += C.add_scale * qa[v][j];
       qc[v][j] = x;
       SR[v][j][w][l] = x;
     }

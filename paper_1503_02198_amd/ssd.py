@@ -111,7 +111,7 @@ def lib():
             "ssd_subgrid_features": (i32, [vp, vp, vp, vp]),
             "ssd_restrict": (i32, [vp, vp, vp, vp, vp, vp]),
             "ssd_subgrid_targets": (i32, [vp, vp, vp, vp, vp, vp, vp]),
-            "ssd_subgrid_attach": (i32, [vp, vp, ctypes.c_float]),
+            "ssd_subgrid_attach": (i32, [vp, vp, ctypes.c_float, i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -243,12 +243,13 @@ class Mesh:
                                           self._tensor(X, self.info["n_elem"] * n_in, "X"),
                                           _stream_ptr(stream, self.device)))
 
-    def attach(self, net, weight=1.0):
+    def attach(self, net, weight=1.0, per_step=False):
         """Add weight x the learned correction of `net` to dQ/dt in every
-        SSP-RK3 stage (None: plain SSD).  The network must outlive the
+        SSP-RK3 stage, evaluated per stage or (per_step) once per step at the
+        step's start (None: plain SSD).  The network must outlive the
         attachment."""
         _check(lib().ssd_subgrid_attach(self._h, net._h if net is not None else None,
-                                        float(weight)))
+                                        float(weight), int(bool(per_step))))
         self._net = net
 
     def timing_enable(self, on=True, kernels=None):

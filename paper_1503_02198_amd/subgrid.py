@@ -199,7 +199,7 @@ def train(net, X, T, epochs, batch, lr, seed, log=None, min_rel=1e-2, noise=0.0)
 
 
 def evaluate(meshes, net, omega, t0, t1, Nc=3, Nf=6, fine_orders=(5, 4, 3), weights=(1.0,),
-             chunks=10):
+             chunks=10, per_step=True):
     """Plain SSD runs and the corrected coarse run over [t0, t1], all from the
     state at t0 of a fine run (N = Nf) from the free stream at t = 0.
 
@@ -209,9 +209,11 @@ def evaluate(meshes, net, omega, t0, t1, Nc=3, Nf=6, fine_orders=(5, 4, 3), weig
         fine state onto that order;
       * the coarse mesh at N = Nc, plain, from the restriction of the fine
         state;
-      * the coarse mesh with the network attached, once per weight; checked
-        after each of `chunks` parts of the interval, and if it fails the
-        plain coarse run stands in (fallback) and the failure time is kept.
+      * the coarse mesh with the network attached, once per weight, its
+        correction evaluated once per step (per_step) or in every stage;
+        checked after each of `chunks` parts of the interval, and if it
+        fails the plain coarse run stands in (fallback) and the failure time
+        is kept.
     Error of a run: its state restricted to the coarse mesh at N = Nc minus
     the restricted reference, in L2 over all variables, relative to the
     restricted reference's departure from the free stream."""
@@ -264,7 +266,7 @@ def evaluate(meshes, net, omega, t0, t1, Nc=3, Nf=6, fine_orders=(5, 4, 3), weig
     def coarse_run(net_w):
         q = qc0.clone()
         if net_w:
-            P.coarse.attach(*net_w)
+            P.coarse.attach(*net_w, per_step=per_step)
         spent, t = 0.0, t0
         try:
             for te in edges[1:]:

@@ -82,4 +82,4 @@ def test_argument_errors_without_device(L):
     assert L.ssd_restrict(None, None, None, None, None, None) == -1
     assert b"null mesh" in L.ssd_last_error()
     assert L.ssd_subgrid_targets(None, None, None, None, None, None, None) == -1
-    assert L.ssd_subgrid_attach(None, None, ctypes.c_float(1.0)) == -1
+    assert L.ssd_subgrid_attach(None, None, ctypes.c_float(1.0), 0) == -1

@@ -304,6 +304,16 @@ def test_attached_correction_rk3(torch_cuda, nested):
     assert np.all(state_error(Qo, Qp) > 100 * err)
     with pytest.raises(Exception):
         gm.rk_steps(q, work, 0.0, dt, 1, scheme="rk54")
+    # the correction of Q^n held for the step's three stages
+    gm.attach(net, per_step=True)
+    q = to_gpu(Q)
+    gm.rk_steps(q, work, 0.0, dt, steps)
+    gm.check()
+    Qs = S.corrected_rk3(ora, _oracle_net(p, norm), Q, 0.0, dt, steps, bf=True, per_step=True)
+    err_s = state_error(from_gpu(q, N, ora.E), Qs)
+    print("per-step state error", err_s, "; per-step vs per-stage", state_error(Qs, Qo), flush=True)
+    assert np.all(err_s <= TOL)
+    assert np.all(state_error(Qs, Qo) > 10 * err_s)
     # detached: plain SSD, bitwise equal to a mesh that never had a network
     gm.attach(None)
     q1, q2 = to_gpu(Q), to_gpu(Q)
