@@ -99,10 +99,10 @@ def batched_main(args):
     """Aggregate throughput of the many-case workload: one batch (graphs,
     then eager launches) against stepping every case on its own."""
     import torch
-    from paper_1503_02198_amd import Batch, Mesh
+    from paper_1503_02198_amd import Batch, Mesh, pack_state
     ws = batch_workload()
     meshes = [Mesh(w["mesh"], w["case"], w["N"], device=0) for w in ws]
-    qs = [torch.from_numpy(w["Q0"].ravel()).to("cuda:0") for w in ws]
+    qs = [torch.from_numpy(pack_state(w["Q0"])).to("cuda:0") for w in ws]
     works = [torch.empty(m.info["work_len"], dtype=torch.float32, device="cuda:0") for m in meshes]
     dts = [w["dt"] for w in ws]
     dof = sum(4 * w["N"] ** 2 * w["E"] for w in ws)
@@ -325,11 +325,11 @@ def main():
         subgrid_main(args)
         return
 
-    from paper_1503_02198_amd import Mesh
+    from paper_1503_02198_amd import Mesh, pack_state, unpack_state
     t_setup = time.perf_counter()
     mesh, case, N, E, Q0, dt = workload(args)
     gm = Mesh(mesh, case, N, device=0)
-    q = torch.from_numpy(Q0.ravel()).to("cuda:0")
+    q = torch.from_numpy(pack_state(Q0)).to("cuda:0")
     work = torch.empty(gm.info["work_len"], dtype=torch.float32, device="cuda:0")
     setup_s = time.perf_counter() - t_setup
     print(f"# setup {setup_s:.1f} s: E={E} N={N} K={gm.info['K']} cubic={gm.info['n_cubic']} "
@@ -403,10 +403,10 @@ def main():
     }
     if not args.no_cpu_baseline:
         # one GPU step from the same initial state for the sampled parity check
-        q1 = torch.from_numpy(Q0.ravel()).to("cuda:0")
+        q1 = torch.from_numpy(pack_state(Q0)).to("cuda:0")
         gm.rk_step(q1, work, 0.0, dt)
         gm.check()
-        q1h = q1.cpu().numpy().astype(np.float64).reshape(4, N, N, E)
+        q1h = unpack_state(q1.cpu().numpy(), N, E).astype(np.float64)
         cb, err = cpu_baseline(mesh, case, N, Q0, dt, q1h, args.cpu_seconds)
         result["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
         result["l2_rel_vs_oracle"] = [float(x) for x in err]

@@ -14,9 +14,15 @@
  *  - A failing call has no side effect on the mesh handle.
  *  - Device arrays (q, r, work) are caller-owned device pointers of 32-bit
  *    floats; the library never frees or retains them beyond the call.
- *  - State layout: q[v][j][i][e], v = 0..3 the conservative variables
- *    rho, rho u, rho v, E (Sec. 2.1, eq. Q) at solution point (X_i, X_j) of
- *    element e; element index fastest.  state_len = 4 N^2 n_elem floats.
+ *  - State layout (cell-blocked): value (v, j, i) of element e is Q[v], v =
+ *    0..3 the conservative variables rho, rho u, rho v, E (Sec. 2.1, eq. Q),
+ *    at solution point (X_i, X_j); its plane is p = (v N + j) N + i.
+ *    Elements go in blocks of 64 consecutive elements, the last block holding
+ *    the remaining n_elem mod 64; block b = e / 64 stores plane after plane,
+ *    each plane as a row of its nb = min(64, n_elem - 64 b) elements:
+ *      index(e, p) = 64 * 4 N^2 * b + p * nb + (e - 64 b).
+ *    state_len = 4 N^2 n_elem floats (no padding).  For full blocks this is
+ *    q[b][v][j][i][e mod 64].
  *    The state holds the physical Q at the solution points; since the
  *    Jacobian of a fixed or rigidly rotating cell does not change in time,
  *    d(|J| Q)/dt = |J| dQ/dt and the residual is returned as dQ/dt.
@@ -301,12 +307,12 @@ ssd_status ssd_timing_read(ssd_mesh *m, int kernel, double *total_ms, int64_t *l
  * to bfloat16, FP32 accumulation); biases, tanh and the update are FP32.
  *
  * Feature layout of element e, n_in = 4 N^2 + 16 N values per row:
- *   [v N^2 + j N + i]            Q[v][j][i] of the element (state layout)
+ *   [v N^2 + j N + i]            Q[v][j][i] of the element
  *   [4 N^2 + (f N + p) 4 + v]    variable v of the neighbour's trace at
  *                                point p of local face f (in the face's own
  *                                parameter order); boundary and sliding
  *                                faces use the element's own trace.
- * Outputs (n_out = 4 N^2 per row) follow the state layout of one element.
+ * Outputs (n_out = 4 N^2 per row) are one element's values, index (v N + j) N + i.
  */
 #define SSD_MLP_HIDDEN 64
 

@@ -68,20 +68,24 @@ __device__ __forceinline__ void flux_n(const float q[4], float nx, float ny, flo
   f[3] = q[3] * rel + p * un;
 }
 
-// Rusanov common flux from the owner (l) towards the neighbour (r).
+// Rusanov common flux from the owner (l) towards the neighbour (r); *p_own
+// receives the owner's pressure.
 __device__ __forceinline__ void rusanov(const float ql[4], const float qr[4], float nx, float ny,
-                                        float vgn, float gam, float f[4]) {
+                                        float vgn, float gam, float f[4], float *p_own = nullptr) {
   const float gm1 = gam - 1.0f;
-  const float mag = __builtin_amdgcn_sqrtf(nx * nx + ny * ny);
+  const float n2 = nx * nx + ny * ny;
   const float irl = rcp(ql[0]), irr = rcp(qr[0]);
   const float ul = ql[1] * irl, vl = ql[2] * irl;
   const float ur = qr[1] * irr, vr = qr[2] * irr;
   const float pl = gm1 * (ql[3] - 0.5f * (ql[1] * ul + ql[2] * vl));
   const float pr = gm1 * (qr[3] - 0.5f * (qr[1] * ur + qr[2] * vr));
+  if (p_own) *p_own = pl;
   const float unl = ul * nx + vl * ny, unr = ur * nx + vr * ny;
   const float rl = unl - vgn, rr = unr - vgn;
-  const float cl = __builtin_amdgcn_sqrtf(gam * pl * irl), cr = __builtin_amdgcn_sqrtf(gam * pr * irr);
-  const float lam = fmaxf(fabsf(rl) + cl * mag, fabsf(rr) + cr * mag);
+  // c |n| of each side as one root: sqrt(gamma p / rho |n|^2)
+  const float cnl = __builtin_amdgcn_sqrtf(gam * pl * irl * n2);
+  const float cnr = __builtin_amdgcn_sqrtf(gam * pr * irr * n2);
+  const float lam = fmaxf(fabsf(rl) + cnl, fabsf(rr) + cnr);
   f[0] = 0.5f * (ql[0] * rl + qr[0] * rr) - 0.5f * lam * (qr[0] - ql[0]);
   f[1] = 0.5f * (ql[1] * rl + pl * nx + qr[1] * rr + pr * nx) - 0.5f * lam * (qr[1] - ql[1]);
   f[2] = 0.5f * (ql[2] * rl + pl * ny + qr[2] * rr + pr * ny) - 0.5f * lam * (qr[2] - ql[2]);
@@ -423,10 +427,9 @@ __device__ __forceinline__ void common_flux(const DevMesh &M, uint32_t fw, const
                                             const float qx[4], const float x[4], const FPGeo &G,
                                             float fs[4]) {
   const int kind = face_kind_of(fw);
-  float fr[4];
-  rusanov(qo, qx, G.nx, G.ny, G.vgn, M.gamma, fr);
+  float fr[4], pr;
+  rusanov(qo, qx, G.nx, G.ny, G.vgn, M.gamma, fr, &pr);
   // walls: no flux relative to the moving wall; pressure from the interior
-  const float pr = (M.gamma - 1.0f) * (qo[3] - 0.5f * (qo[1] * qo[1] + qo[2] * qo[2]) * rcp(qo[0]));
   const bool wall = kind == SSD_FACE_WALL_ISOTHERMAL || kind == SSD_FACE_WALL_SLIP;
   const bool sliding = kind == SSD_FACE_SLIDING;
   const float fw4[4] = {0.0f, pr * G.nx, pr * G.ny, pr * G.vgn};

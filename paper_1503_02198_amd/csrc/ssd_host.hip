@@ -291,6 +291,7 @@ struct ssd_mesh {
   double theta0 = 0.0, omega0 = 0.0;   // motion used by ssd_rk_step
   double theta = 0.0, omega = 0.0;     // angle/rate for ssd_residual
   bool mortar_fresh = false;
+  unsigned stage_launches = 0;        // parity picks the stage kernel's tile order
   std::vector<void *> allocs;
   float *tr[2] = {nullptr, nullptr};
   ViscIO V{};                          // viscous work buffers (mu > 0)
@@ -798,8 +799,10 @@ ssd_status residual_pass(ssd_mesh *m, double th, double omega, const float *in, 
                 "viscous mortar launch");
     }
   }
+  RKCoef Cs = C;
+  Cs.reverse = int(m->stage_launches++ & 1u);
   LaunchTimer lt(m, SSD_KERNEL_STAGE, st);
-  SSD_HIP(launch_stage(m->D, m->T, rot, in, qn, out, facein, trout, V, C, rk, st),
+  SSD_HIP(launch_stage(m->D, m->T, rot, in, qn, out, facein, trout, V, Cs, rk, st),
           rk ? "stage launch" : "residual launch");
   return SSD_OK;
 }

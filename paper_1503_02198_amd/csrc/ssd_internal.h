@@ -18,6 +18,20 @@ constexpr int NMAX = 6;
 //   bit  28      the neighbour's face parameter runs opposite to ours
 //   bits 29..31  SSD_FACE_* kind
 constexpr int EB = 64;   // elements per stage-kernel block
+
+// Cell-blocked layout of per-cell arrays of `planes` values each (a state:
+// planes = 4 N^2, plane (v N + j) N + i holds Q[v] at solution point
+// (X_i, X_j)).  Cells go in blocks of EB consecutive cells, the last block
+// holding the remaining E mod EB; block b stores its values plane after
+// plane, each plane as one row of its nb = min(EB, E - EB b) cells.  A
+// stage-kernel block therefore reads and writes one contiguous span.
+__host__ __device__ inline long cb_rows(long b, long E) {
+  return E - long(EB) * b < EB ? E - long(EB) * b : EB;
+}
+__host__ __device__ inline long cb_index(long e, long p, long planes, long E) {
+  const long b = e / EB;
+  return b * EB * planes + p * cb_rows(b, E) + (e - b * EB);
+}
 __host__ __device__ inline uint32_t pack_face(int kind, int idx, int nf, int rev, int inblock) {
   return (uint32_t(kind) << 29) | (uint32_t(rev & 1) << 28) | (uint32_t(nf & 3) << 26) |
          (uint32_t(inblock & 1) << 25) | (uint32_t(idx) & 0x1FFFFFFu);
@@ -139,6 +153,9 @@ struct RKCoef {
   float beta, gamma, dt;
   const float *add;        // null: nothing added
   float add_scale = 1.0f;
+  // nonzero: tiles taken in reverse block order, so that a launch starts on
+  // the cells the previous launch touched last (still in the memory-side cache)
+  int reverse = 0;
 };
 
 }  // namespace ssd

@@ -193,7 +193,8 @@ __device__ __forceinline__ void features_tile(const DevMesh &M, const OpTables &
 #pragma unroll
   for (int j = 0; j < N; ++j)
 #pragma unroll
-    for (int i = 0; i < N; ++i) F[l][w * N * N + j * N + i] = q[((long(w) * N + j) * N + i) * E + e];
+    for (int i = 0; i < N; ++i)
+      F[l][w * N * N + j * N + i] = q[cb_index(e, (long(w) * N + j) * N + i, 4 * N * N, E)];
   // face w
   const uint32_t fw = M.face[long(w) * E + e];
   const int kind = face_kind_of(fw);
@@ -218,7 +219,7 @@ __device__ __forceinline__ void features_tile(const DevMesh &M, const OpTables &
 #pragma unroll
       for (int k = 0; k < N; ++k) {
         const int jj = along_xi ? k : p, ii = along_xi ? p : k;
-        const float x = q[((long(v) * N + jj) * N + ii) * E + nb];
+        const float x = q[cb_index(nb, (long(v) * N + jj) * N + ii, 4 * N * N, E)];
         s += (high ? hi[k] : lo[k]) * x;
       }
       const int pp = rev ? N - 1 - p : p;
@@ -241,8 +242,9 @@ __global__ __launch_bounds__(256) void k_features(DevMesh M, OpTables T, const f
     X[base * D::NIN + c] = F[c / D::NIN][c % D::NIN];
 }
 
-// Correction of a stage: add[o][e] = scale (sig_y yn + mu_y) of the MLP of
-// element e's features, o = v N^2 + j N + i (the state layout).
+// Correction of a stage: value o = v N^2 + j N + i of element e in `add`
+// (cell-blocked state layout) = scale (sig_y yn + mu_y) of the MLP of
+// element e's features.
 template <int N>
 __global__ __launch_bounds__(256) void k_subgrid(DevMesh M, OpTables T, MlpDev P,
                                                  const float *q, float *add, float scale) {
@@ -260,7 +262,7 @@ __global__ __launch_bounds__(256) void k_subgrid(DevMesh M, OpTables T, MlpDev P
   hidden_layers<N>(P, S, nullptr, nullptr);
   f32x4 acc[D::KOUT / 16] = {};
   output_layer<N>(P, S, acc);
-  // y through LDS (reusing F) so that the state is written element-fastest
+  // y through LDS (reusing F) so that each plane row is written by consecutive lanes
   float(*Y)[D::NIN] = F;
   const int l = threadIdx.x & 63;
   const int rb = 16 * int(threadIdx.x >> 6) + 4 * (l >> 4);
@@ -276,7 +278,7 @@ __global__ __launch_bounds__(256) void k_subgrid(DevMesh M, OpTables T, MlpDev P
   __syncthreads();
   const long e = long(blockIdx.x) * 64 + l;
   if (e < M.E)
-    for (int o = int(threadIdx.x >> 6); o < D::NOUT; o += 4) add[long(o) * M.E + e] = Y[l][o];
+    for (int o = int(threadIdx.x >> 6); o < D::NOUT; o += 4) add[cb_index(e, o, D::NOUT, M.E)] = Y[l][o];
 }
 
 // Y [n][NOUT] = the network of the rows X [n][NIN].
@@ -506,8 +508,8 @@ __global__ __launch_bounds__(256) void k_moments(const float *A, long n, int col
 
 // ---------------------------------------------------------------------------
 // restriction of a nested fine state to the coarse mesh
-//   out = P qf - sub (sub may be null); rows: out[c][o] instead of the state
-//   layout out[o][c]
+//   out = P qf - sub (sub may be null); rows: out[c][o] instead of the
+//   cell-blocked state layout
 // ---------------------------------------------------------------------------
 // SPLIT: each coarse element has 4 children; otherwise the same mesh at a
 // lower order (one "child", the element itself, operator r[0]).
@@ -534,7 +536,7 @@ __global__ __launch_bounds__(256) void k_restrict(const float *qf, long Ef, cons
           float row[NC] = {};
 #pragma unroll
           for (int i_f = 0; i_f < NF; ++i_f) {
-            const float x = qf[((long(v) * NF + jf) * NF + i_f) * Ef + fe];
+            const float x = qf[cb_index(fe, (long(v) * NF + jf) * NF + i_f, 4 * NF * NF, Ef)];
 #pragma unroll
             for (int ic = 0; ic < NC; ++ic) row[ic] += R.r[a][ic][i_f] * x;
           }
@@ -550,11 +552,12 @@ __global__ __launch_bounds__(256) void k_restrict(const float *qf, long Ef, cons
       for (int ic = 0; ic < NC; ++ic) {
         const long o = (long(v) * NC + jc) * NC + ic;
         float y = acc[jc][ic];
-        if (sub) y -= sub[o * Ec + c];
+        const long co = cb_index(c, o, 4 * NC * NC, Ec);
+        if (sub) y -= sub[co];
         if (rows)
           out[c * (4L * NC * NC) + o] = y;
         else
-          out[o * Ec + c] = y;
+          out[co] = y;
       }
   }
 }

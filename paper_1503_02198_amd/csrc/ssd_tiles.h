@@ -30,7 +30,10 @@ __device__ __forceinline__ void traces_block(const DevMesh &M, const OpTables &T
   if (e >= M.E) return;
   const uint32_t E4 = uint32_t(M.E) * 4u;
   const rsrc_t rq = make_rsrc(q, 4u * N * N * E4), rt = make_rsrc(tr, 16u * N * E4);
-  const uint32_t ve = uint32_t(e) * 4u;
+  // cell-blocked state: plane 0 of cell e and the bytes of one plane row
+  const uint32_t b = uint32_t(e) / EB;
+  const uint32_t vq = (b * EB * 4u * N * N + (uint32_t(e) - b * EB)) * 4u;
+  const uint32_t rowb = uint32_t(cb_rows(b, M.E)) * 4u;
   bool ex[4];
 #pragma unroll
   for (int f = 0; f < 4; ++f) ex[f] = face_exported(M.face[long(f) * M.E + e]);
@@ -41,7 +44,7 @@ __device__ __forceinline__ void traces_block(const DevMesh &M, const OpTables &T
 #pragma unroll
     for (int j = 0; j < N; ++j)
 #pragma unroll
-      for (int i = 0; i < N; ++i) Q[v][j][i] = bload(rq, ve, ((v * N + j) * N + i) * E4);
+      for (int i = 0; i < N; ++i) Q[v][j][i] = bload(rq, vq + ((v * N + j) * N + i) * rowb, 0u);
 #pragma unroll
   for (int p = 0; p < N; ++p) {
     float f0[4], f1[4], f2[4], f3[4];
@@ -188,7 +191,13 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
   const rsrc_t rgtr = make_rsrc(V.gtr, VISC ? 2u * tbytes : 0u);
   const rsrc_t rmv = make_rsrc(V.mvflux, VISC ? mbytes : 0u);
   const ViscParams P = visc_params(M);
-  const uint32_t ve = uint32_t(e) * 4u;
+  // cell-blocked state and gradient arrays: plane 0 of the lane's cell, and
+  // the bytes of one plane row of this block (uniform)
+  const uint32_t nbt = uint32_t(__builtin_amdgcn_readfirstlane(int(cb_rows(tile, M.E))));
+  const uint32_t lc = valid ? uint32_t(l) : nbt - 1u;
+  const uint32_t vs = (uint32_t(tile) * (EB * 4u * N * N) + lc) * 4u;
+  const uint32_t vg = (uint32_t(tile) * (EB * 8u * N * N) + lc) * 4u;
+  const uint32_t rowb = nbt * 4u;
   const long E = M.E;
 
   // ---- everything the element needs from memory, issued up front
@@ -198,7 +207,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
-    for (int i = 0; i < N; ++i) qr[v][i] = bload(rq, ve, ((v * N + w) * N + i) * E4);
+    for (int i = 0; i < N; ++i) qr[v][i] = bload(rq, vs, ((v * N + w) * N + i) * rowb);
   const ElemGeo g = load_geo(M, e, R);
   float x0[4], x1[4], x2[4], x3[4];
   prefetch_face<N>(M, rtin, fbytes, tbytes, uint32_t(M.E), fw3, w, x3);   // row faces xi = 0, 1 at point w
@@ -211,7 +220,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int j = 0; j < N; ++j) qo[v][j] = bload(rqn, ve, ((v * N + j) * N + w) * E4);
+      for (int j = 0; j < N; ++j) qo[v][j] = bload(rqn, vs, ((v * N + j) * N + w) * rowb);
   }
   float qa[4][N];   // column w of the added increment (ADD)
   if (RK && ADD) {
@@ -219,7 +228,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int j = 0; j < N; ++j) qa[v][j] = bload(radd, ve, ((v * N + j) * N + w) * E4);
+      for (int j = 0; j < N; ++j) qa[v][j] = bload(radd, vs, ((v * N + j) * N + w) * rowb);
   }
 
   // ---- row phase
@@ -231,7 +240,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
 #pragma unroll
       for (int c = 0; c < 8; ++c)
 #pragma unroll
-        for (int i = 0; i < N; ++i) gr[c][i] = bload(rG, ve, ((c * N + w) * N + i) * E4);
+        for (int i = 0; i < N; ++i) gr[c][i] = bload(rG, vg, ((c * N + w) * N + i) * rowb);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v)
@@ -328,7 +337,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
 #pragma unroll
       for (int c = 0; c < 8; ++c)
 #pragma unroll
-        for (int j = 0; j < N; ++j) gc[c][j] = bload(rG, ve, ((c * N + j) * N + w) * E4);
+        for (int j = 0; j < N; ++j) gc[c][j] = bload(rG, vg, ((c * N + j) * N + w) * rowb);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v)
@@ -399,7 +408,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int j = 0; j < N; ++j) bstore(rc[v][j] * ij[j], rout, ve, ((v * N + j) * N + w) * E4);
+        for (int j = 0; j < N; ++j) bstore(rc[v][j] * ij[j], rout, vs, ((v * N + j) * N + w) * rowb);
     }
     return;
   }
@@ -419,15 +428,16 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
       qc[v][j] = x;
       SR[v][j][w][l] = x;
     }
+    // rho > 0 and p > 0, i.e. 2 rho E > |m|^2; false for any non-finite value
     const float rho = qc[0][j];
-    const float pr = gm1 * (qc[3][j] - 0.5f * (qc[1][j] * qc[1][j] + qc[2][j] * qc[2][j]) * rcp(rho));
-    bad |= !(rho > 0.0f) || !(pr > 0.0f) || !isfinite(qc[1][j]) || !isfinite(qc[2][j]);
+    bad |= !(rho > 0.0f) ||
+           !(2.0f * rho * qc[3][j] > qc[1][j] * qc[1][j] + qc[2][j] * qc[2][j]);
   }
   if (valid) {
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int j = 0; j < N; ++j) bstore(qc[v][j], rout, ve, ((v * N + j) * N + w) * E4);
+      for (int j = 0; j < N; ++j) bstore(qc[v][j], rout, vs, ((v * N + j) * N + w) * rowb);
     if (bad) M.flag[0] = 1;
   }
   // lanes whose face f is read by another block, in lane order (wave w lists
@@ -480,7 +490,8 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
                                                   const float *q, const float *qn, float *out,
                                                   const float *facein, float *trout, ViscBufs V,
                                                   RKCoef C) {
-  stage_tile<N, RK, VISC, ADD>(M, T, R, q, qn, out, facein, trout, V, C, blockIdx.x);
+  const int tile = C.reverse ? int(gridDim.x) - 1 - int(blockIdx.x) : int(blockIdx.x);
+  stage_tile<N, RK, VISC, ADD>(M, T, R, q, qn, out, facein, trout, V, C, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -518,7 +529,13 @@ __device__ __forceinline__ void grad_tile(const DevMesh &M, const OpTables &T, c
   const rsrc_t rtin = make_rsrc(facein, fbytes);
   const rsrc_t rG = make_rsrc(Gout, 2u * sbytes);
   const rsrc_t rgtr = make_rsrc(gtr, 2u * tbytes);
-  const uint32_t ve = uint32_t(e) * 4u;
+  // cell-blocked state and gradient arrays: plane 0 of the lane's cell, and
+  // the bytes of one plane row of this block (uniform)
+  const uint32_t nbt = uint32_t(__builtin_amdgcn_readfirstlane(int(cb_rows(tile, M.E))));
+  const uint32_t lc = valid ? uint32_t(l) : nbt - 1u;
+  const uint32_t vs = (uint32_t(tile) * (EB * 4u * N * N) + lc) * 4u;
+  const uint32_t vg = (uint32_t(tile) * (EB * 8u * N * N) + lc) * 4u;
+  const uint32_t rowb = nbt * 4u;
   const long E = M.E;
 
   const uint32_t fw0 = M.face[0 * E + e], fw1 = M.face[1 * E + e];
@@ -527,7 +544,7 @@ __device__ __forceinline__ void grad_tile(const DevMesh &M, const OpTables &T, c
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
-    for (int i = 0; i < N; ++i) qr[v][i] = bload(rq, ve, ((v * N + w) * N + i) * E4);
+    for (int i = 0; i < N; ++i) qr[v][i] = bload(rq, vs, ((v * N + w) * N + i) * rowb);
   const ElemGeo g = load_geo(M, e, R);
   float x0[4], x1[4], x2[4], x3[4];
   prefetch_face<N>(M, rtin, fbytes, tbytes + mbytes, uint32_t(M.E), fw3, w, x3);
@@ -653,7 +670,7 @@ __device__ __forceinline__ void grad_tile(const DevMesh &M, const OpTables &T, c
       f0[c] = f2[c] = 0.f;
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        bstore(gcol[c][j], rG, ve, ((c * N + j) * N + w) * E4);
+        bstore(gcol[c][j], rG, vg, ((c * N + j) * N + w) * rowb);
         f0[c] += T.I[0][j] * gcol[c][j];
         f2[c] += T.I[N][j] * gcol[c][j];
       }

@@ -28,6 +28,47 @@ EXPORTS = ["ssd_create_mesh", "ssd_destroy_mesh", "ssd_query", "ssd_set_rotation
            "ssd_subgrid_features", "ssd_restrict", "ssd_subgrid_targets", "ssd_subgrid_attach"]
 
 
+# -- cell-blocked state layout (include/ssd.h) ------------------------------
+# Elements in blocks of CB consecutive elements (the last holds the
+# remainder); block b stores plane after plane, each plane a row of its
+# elements.  These two helpers only reorder values (numpy arrays or torch
+# tensors, on any device); no step of the method is computed here.
+CB = 64
+
+
+def _swap01(a, shape):
+    a = a.reshape(shape)
+    return a.transpose(1, 0, 2) if isinstance(a, np.ndarray) else a.permute(1, 0, 2)
+
+
+def _cat(parts, axis):
+    if isinstance(parts[0], np.ndarray):
+        return np.concatenate(parts, axis=axis)
+    import torch
+    return torch.cat(parts, dim=axis)
+
+
+def pack_state(Q):
+    """Flat cell-blocked array of Q [..., n_elem] (the leading axes are the
+    planes: [4, N, N, n_elem] for a state)."""
+    E = Q.shape[-1]
+    P = int(np.prod(Q.shape[:-1]))
+    Q2 = Q.reshape(P, E)
+    nb = E // CB
+    head = _swap01(Q2[:, :nb * CB], (P, nb, CB)).reshape(-1)
+    tail = Q2[:, nb * CB:].reshape(-1)
+    return _cat([head, tail], 0)
+
+
+def unpack_state(q, N, n_elem, nvar=4):
+    """[nvar, N, N, n_elem] view of a flat cell-blocked array."""
+    E, P = n_elem, nvar * N * N
+    nb = E // CB
+    head = _swap01(q[:P * nb * CB], (nb, P, CB)).reshape(P, nb * CB)
+    tail = q[P * nb * CB:P * E].reshape(P, E - nb * CB)
+    return _cat([head, tail], 1).reshape(nvar, N, N, E)
+
+
 class SSDError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")

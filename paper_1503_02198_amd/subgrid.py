@@ -22,7 +22,7 @@ import time
 
 import numpy as np
 
-from .ssd import MLP, Mesh, restrict, subgrid_targets
+from .ssd import MLP, Mesh, pack_state, restrict, subgrid_targets, unpack_state
 
 
 def ellipse_pair(K=64, n_in=8, n_out=16, first_in=0.01, first_out=0.02):
@@ -71,7 +71,8 @@ class Pair:
         N, E = mesh.info["N"], mesh.info["n_elem"]
         rho, u, v, p = self.case["farfield"]
         q = np.array([rho, rho * u, rho * v, p / (self.case["gamma"] - 1) + 0.5 * rho * (u * u + v * v)])
-        return torch.tensor(np.repeat(q.astype(np.float32), N * N * E), device=f"cuda:{self.device}")
+        Q = np.broadcast_to(q.astype(np.float32)[:, None, None, None], (4, N, N, E))
+        return torch.tensor(pack_state(Q), device=f"cuda:{self.device}")
 
     def work(self, mesh):
         import torch
@@ -237,11 +238,12 @@ def evaluate(meshes, net, omega, t0, t1, Nc=3, Nf=6, fine_orders=(5, 4, 3), weig
     runs = []
     s_ref = timed(lambda: advance(P.fine, qf, wf, t0, P.dt_f, t1))
     P.fine.check()
-    ref = P.restrict(qf).cpu().numpy().astype(np.float64).reshape(4, -1)
+    Nc, Ec = P.Nc, P.Ec
+    ref = unpack_state(P.restrict(qf).cpu().numpy(), Nc, Ec).astype(np.float64).reshape(4, -1)
     dev = np.sum((ref - uniform_ref(P)) ** 2)
 
     def err(qc):
-        q = qc.cpu().numpy().astype(np.float64).reshape(4, -1)
+        q = unpack_state(qc.cpu().numpy(), Nc, Ec).astype(np.float64).reshape(4, -1)
         return float(np.sqrt(np.sum((q - ref) ** 2) / dev))
 
     runs.append(dict(run=f"fine mesh N={Nf} (reference)", s=s_ref, err=0.0, dt=P.dt_f,

@@ -32,13 +32,15 @@ def state_error(Q_gpu, Q_ora):
 
 def to_gpu(Q, device=0):
     import torch
-    return torch.tensor(np.ascontiguousarray(Q, dtype=np.float32).ravel(), device=f"cuda:{device}")
+    from paper_1503_02198_amd.ssd import pack_state
+    return torch.tensor(pack_state(np.asarray(Q, dtype=np.float32)), device=f"cuda:{device}")
 
 
 def from_gpu(t, N, E):
     import torch
     torch.cuda.synchronize()
-    return t.detach().cpu().numpy().astype(np.float64).reshape(4, N, N, E)
+    from paper_1503_02198_amd.ssd import unpack_state
+    return unpack_state(t.detach().cpu().numpy(), N, E).astype(np.float64)
 
 
 def gpu_residual(gm, Q, theta, omega):
