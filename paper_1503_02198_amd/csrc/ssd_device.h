@@ -173,7 +173,7 @@ __device__ __forceinline__ ElemGeo load_geo(const DevMesh &M, int e, const Rotat
   // that no load waits on the flag word
   float v[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) v[k] = M.geo[k * E + e];
+  for (int k = 0; k < 8; ++k) v[k] = M.geo[cb_index32(uint32_t(e), k, 8u, uint32_t(E))];
   const int fl = M.eflag[e];
   g.cubic = fl & EF_CUBIC;
   g.c = fl >> 8;

@@ -448,10 +448,10 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
     for (int c = 0; c < 2; ++c) {
       const double x0 = xy[0 * 2 + c] - (c ? cy : cx), x3 = xy[3 * 2 + c] - (c ? cy : cx);
       const double x6 = xy[6 * 2 + c] - (c ? cy : cx), x9 = xy[9 * 2 + c] - (c ? cy : cx);
-      geo[(0 + c) * long(E) + e] = float(x0);
-      geo[(2 + c) * long(E) + e] = float(x3 - x0);
-      geo[(4 + c) * long(E) + e] = float(x9 - x0);
-      geo[(6 + c) * long(E) + e] = float((x6 - x3) - (x9 - x0));
+      geo[cb_index(e, 0 + c, 8, E)] = float(x0);
+      geo[cb_index(e, 2 + c, 8, E)] = float(x3 - x0);
+      geo[cb_index(e, 4 + c, 8, E)] = float(x9 - x0);
+      geo[cb_index(e, 6 + c, 8, E)] = float((x6 - x3) - (x9 - x0));
     }
   }
   if (C >= (1 << 23)) return fail(SSD_ERR_MESH, "too many cubic elements");
@@ -539,7 +539,7 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
                                 : std::hypot(ax - cx2, ay - cy2) + std::hypot(bx - dx2, by - dy2);
           if (e1 > 1e-8 * len) return fail(SSD_ERR_MESH, where + ": neighbouring faces do not meet");
         }
-        face[long(f) * E + e] = pack_face(kind, nb, nf, rev, nb / EB == e / EB);
+        face[cb_index(e, f, 4, E)] = pack_face(kind, nb, nf, rev, nb / EB == e / EB);
       } else if (kind == SSD_FACE_SLIDING) {
         if (!(Rs > 0.0)) return fail(SSD_ERR_MESH, where + ": sliding face but iface_radius <= 0");
         const double ra = std::hypot(ax - cx, ay - cy), rb = std::hypot(bx - cx, by - cy);
@@ -563,13 +563,13 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
           gy += 0.25 * py;
         }
         (std::hypot(gx - cx, gy - cy) < Rs ? L : R).push_back(rf);
-        face[long(f) * E + e] = pack_face(kind, 0, 0, 0, 0);
+        face[cb_index(e, f, 4, E)] = pack_face(kind, 0, 0, 0, 0);
       } else if (kind == SSD_FACE_WALL_ISOTHERMAL || kind == SSD_FACE_WALL_SLIP) {
         need_wall |= kind == SSD_FACE_WALL_ISOTHERMAL;
-        face[long(f) * E + e] = pack_face(kind, 0, 0, 0, 0);
+        face[cb_index(e, f, 4, E)] = pack_face(kind, 0, 0, 0, 0);
       } else if (kind == SSD_FACE_FARFIELD) {
         need_far = true;
-        face[long(f) * E + e] = pack_face(kind, 0, 0, 0, 0);
+        face[cb_index(e, f, 4, E)] = pack_face(kind, 0, 0, 0, 0);
       } else {
         return fail(SSD_ERR_MESH, where + ": unknown face kind");
       }
@@ -624,13 +624,13 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
       re[j] = L[j].e;
       rfv[j] = L[j].f;
       rfl[j] = L[j].flip;
-      face[long(L[j].f) * E + L[j].e] = pack_face(SSD_FACE_SLIDING, j, 0, 0, 0);
+      face[cb_index(L[j].e, L[j].f, 4, E)] = pack_face(SSD_FACE_SLIDING, j, 0, 0, 0);
     }
     for (int j = 0; j < KR; ++j) {
       re[K + j] = R[j].e;
       rfv[K + j] = R[j].f;
       rfl[K + j] = R[j].flip;
-      face[long(R[j].f) * E + R[j].e] = pack_face(SSD_FACE_SLIDING, K + j, 0, 0, 0);
+      face[cb_index(R[j].e, R[j].f, 4, E)] = pack_face(SSD_FACE_SLIDING, K + j, 0, 0, 0);
     }
     m->D.phi0L = L[0].start;
     m->D.phi0R = R[0].start;

@@ -32,6 +32,12 @@ __host__ __device__ inline long cb_index(long e, long p, long planes, long E) {
   const long b = e / EB;
   return b * EB * planes + p * cb_rows(b, E) + (e - b * EB);
 }
+// the same in 32-bit arithmetic, for arrays of fewer than 2^32 values (the
+// per-cell geometry and face words, which use the same blocking)
+__host__ __device__ inline uint32_t cb_index32(uint32_t e, uint32_t p, uint32_t planes, uint32_t E) {
+  const uint32_t b = e / EB, r = E - EB * b;
+  return b * EB * planes + p * (r < uint32_t(EB) ? r : uint32_t(EB)) + (e - b * EB);
+}
 __host__ __device__ inline uint32_t pack_face(int kind, int idx, int nf, int rev, int inblock) {
   return (uint32_t(kind) << 29) | (uint32_t(rev & 1) << 28) | (uint32_t(nf & 3) << 26) |
          (uint32_t(inblock & 1) << 25) | (uint32_t(idx) & 0x1FFFFFFu);
@@ -93,9 +99,9 @@ struct DevMesh {
   int K;           // faces per interface side (0: no interface)
   int C;           // cubic elements
   int N;
-  const float *geo;        // [8][E]: bilinear map p0, A, C, T (x, y each), see load_geo
+  const float *geo;        // 8 planes, cell-blocked: bilinear map p0, A, C, T (x, y each), see load_geo
   const int *eflag;        // [E]
-  const uint32_t *face;    // [4][E]
+  const uint32_t *face;    // 4 planes (local faces), cell-blocked
   const double *cmet;      // cubic-cell metrics, see cubic_index()
   const int *ring_e;       // [2K] L slots 0..K-1, R slots K..2K-1 (CCW order)
   const int *ring_f;       // [2K]

@@ -196,7 +196,7 @@ __device__ __forceinline__ void features_tile(const DevMesh &M, const OpTables &
     for (int i = 0; i < N; ++i)
       F[l][w * N * N + j * N + i] = q[cb_index(e, (long(w) * N + j) * N + i, 4 * N * N, E)];
   // face w
-  const uint32_t fw = M.face[long(w) * E + e];
+  const uint32_t fw = M.face[cb_index32(uint32_t(e), uint32_t(w), 4u, uint32_t(E))];
   const int kind = face_kind_of(fw);
   const bool conf = kind == SSD_FACE_INTERIOR || kind == SSD_FACE_PERIODIC;
   const int nb = conf ? face_idx_of(fw) : e;

@@ -36,7 +36,7 @@ __device__ __forceinline__ void traces_block(const DevMesh &M, const OpTables &T
   const uint32_t rowb = uint32_t(cb_rows(b, M.E)) * 4u;
   bool ex[4];
 #pragma unroll
-  for (int f = 0; f < 4; ++f) ex[f] = face_exported(M.face[long(f) * M.E + e]);
+  for (int f = 0; f < 4; ++f) ex[f] = face_exported(M.face[cb_index32(uint32_t(e), f, 4u, uint32_t(M.E))]);
   if (!(ex[0] || ex[1] || ex[2] || ex[3])) return;
   float Q[4][N][N];
 #pragma unroll
@@ -201,8 +201,10 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
   const long E = M.E;
 
   // ---- everything the element needs from memory, issued up front
-  const uint32_t fw0 = M.face[0 * E + e], fw1 = M.face[1 * E + e];
-  const uint32_t fw2 = M.face[2 * E + e], fw3 = M.face[3 * E + e];
+  const uint32_t fw0 = M.face[cb_index32(uint32_t(e), 0u, 4u, uint32_t(E))];
+  const uint32_t fw1 = M.face[cb_index32(uint32_t(e), 1u, 4u, uint32_t(E))];
+  const uint32_t fw2 = M.face[cb_index32(uint32_t(e), 2u, 4u, uint32_t(E))];
+  const uint32_t fw3 = M.face[cb_index32(uint32_t(e), 3u, 4u, uint32_t(E))];
   float qr[4][N];
 #pragma unroll
   for (int v = 0; v < 4; ++v)
@@ -538,8 +540,10 @@ __device__ __forceinline__ void grad_tile(const DevMesh &M, const OpTables &T, c
   const uint32_t rowb = nbt * 4u;
   const long E = M.E;
 
-  const uint32_t fw0 = M.face[0 * E + e], fw1 = M.face[1 * E + e];
-  const uint32_t fw2 = M.face[2 * E + e], fw3 = M.face[3 * E + e];
+  const uint32_t fw0 = M.face[cb_index32(uint32_t(e), 0u, 4u, uint32_t(E))];
+  const uint32_t fw1 = M.face[cb_index32(uint32_t(e), 1u, 4u, uint32_t(E))];
+  const uint32_t fw2 = M.face[cb_index32(uint32_t(e), 2u, 4u, uint32_t(E))];
+  const uint32_t fw3 = M.face[cb_index32(uint32_t(e), 3u, 4u, uint32_t(E))];
   float qr[4][N];
 #pragma unroll
   for (int v = 0; v < 4; ++v)
