@@ -221,7 +221,10 @@ const char *ssd_last_error(void);
  * meshes by (N, viscous); per RK stage every group runs one mortar launch,
  * (viscous) one gradient and one viscous-mortar launch, and one stage
  * launch, each with one block per item of a device table of (mesh, 64-cell
- * tile or interface chunk) pairs.  Groups share no data, so each group's
+ * tile or interface chunk) pairs.  A mesh with general sliding rings (see
+ * ssd_create_mesh) has its own mortar merge, flux and back-projection
+ * launches inside its group's chain, its rotor angle likewise read from the
+ * group's step counter.  Groups share no data, so each group's
  * whole chain of launches runs on one of up to SSD_BATCH_MAX_STREAMS
  * streams, forked from and joined back to the caller's stream.  On the
  * first call an autotuner times every group's stage alone, then the
@@ -233,8 +236,7 @@ const char *ssd_last_error(void);
  *
  * The batch references the meshes: they must outlive it, and no other call
  * may use them while a batch call runs.  Calls on one batch must not
- * overlap.  Meshes with general sliding rings (see ssd_create_mesh) cannot
- * be batched.
+ * overlap.
  */
 typedef struct ssd_batch ssd_batch;
 

@@ -777,7 +777,8 @@ ssd_status residual_pass(ssd_mesh *m, double th, double omega, const float *in, 
   if (m->K) {
     LaunchTimer lt(m, SSD_KERNEL_MORTAR, st);
     if (m->general)
-      SSD_HIP(launch_gen_mortar(m->D, m->T, m->MT, m->G, th, facein, mflux, V ? mqc : nullptr, st),
+      SSD_HIP(launch_gen_mortar(m->D, m->T, m->MT, m->G, AngleArg{th, nullptr, 0.0, nullptr}, facein,
+                                mflux, V ? mqc : nullptr, st),
               "general mortar launch");
     else
       SSD_HIP(launch_mortar(m->D, m->T, m->MT, th, m->ms, facein, mflux, V ? mqc : nullptr, st),
@@ -792,7 +793,8 @@ ssd_status residual_pass(ssd_mesh *m, double th, double omega, const float *in, 
     if (m->K) {
       LaunchTimer lt(m, SSD_KERNEL_MORTAR, st);
       if (m->general)
-        SSD_HIP(launch_gen_mortar_visc(m->D, m->T, m->MT, m->G, th, mqc, V->gtr, V->mvflux, st),
+        SSD_HIP(launch_gen_mortar_visc(m->D, m->T, m->MT, m->G, AngleArg{th, nullptr, 0.0, nullptr},
+                                       mqc, V->gtr, V->mvflux, st),
                 "general viscous mortar launch");
       else
         SSD_HIP(launch_mortar_visc(m->D, m->T, m->ms, mqc, V->gtr, V->mvflux, st),
@@ -1091,6 +1093,7 @@ struct ssd_batch {
     uint2 *comb_work = nullptr;
     int nstage = 0, nmortar = 0, ntrace = 0, ncomb = 0;
     double *step = nullptr;   // device step counter of the group
+    std::vector<int> general; // cases with general rings: their mortars launched per case
     int stream = 0;           // index into ssd_batch::streams
     float stage_ms = 0.0f;    // the group's stage alone (autotuner)
   };
@@ -1142,18 +1145,46 @@ void batch_free(ssd_batch *b) {
   b->allocs.clear();
 }
 
-// One RK stage of group g, launched on stream st.
+// Face-data pointers of case c for face buffer parity cur: the mortar flux
+// records after the traces, then the mortar common solution records.
+void case_mortar_bufs(const ssd_batch *b, int c, int cur, float **mflux, float **mqc) {
+  const ssd_mesh *m = b->meshes[c];
+  *mflux = b->cases[c].face[cur] + face_trace_floats(m->N, m->E);
+  *mqc = *mflux + face_record_floats(m->N, m->K);
+}
+
+// One RK stage of group g, launched on stream st.  Cases with uniform rings
+// share the batched mortar launches; each case with general rings launches
+// its own merge, flux and back-projection, its angle read from the step
+// counter on the device.
 ssd_status group_stage(ssd_batch *b, const ssd_batch::Group &g, const BatchStage &S,
                        hipStream_t st) {
   SSD_HIP(launch_batch_mortar(g.N, g.visc, b->dcases, g.mortar_work, g.nmortar, g.T, g.MT, S.cur,
                               S.c, g.step, st),
           "batched mortar launch");
+  for (int c : g.general) {
+    const ssd_mesh *m = b->meshes[c];
+    float *mflux, *mqc;
+    case_mortar_bufs(b, c, S.cur, &mflux, &mqc);
+    SSD_HIP(launch_gen_mortar(m->D, m->T, m->MT, m->G, AngleArg{0.0, b->dcases + c, S.c, g.step},
+                              b->cases[c].face[S.cur], mflux, g.visc ? mqc : nullptr, st),
+            "general mortar launch");
+  }
   if (g.visc) {
     SSD_HIP(launch_batch_grad(g.N, b->dcases, g.stage_work, g.nstage, g.T, S.in, S.cur, S.c,
                               g.step, st),
             "batched gradient launch");
     SSD_HIP(launch_batch_mortar_visc(g.N, b->dcases, g.mortar_work, g.nmortar, g.T, S.cur, st),
             "batched viscous mortar launch");
+    for (int c : g.general) {
+      const ssd_mesh *m = b->meshes[c];
+      float *mflux, *mqc;
+      case_mortar_bufs(b, c, S.cur, &mflux, &mqc);
+      SSD_HIP(launch_gen_mortar_visc(m->D, m->T, m->MT, m->G,
+                                     AngleArg{0.0, b->dcases + c, S.c, g.step}, mqc, m->V.gtr,
+                                     m->V.mvflux, st),
+              "general viscous mortar launch");
+    }
   }
   SSD_HIP(launch_batch_stage(g.N, g.visc, b->dcases, g.stage_work, g.nstage, g.T, S, g.step, st),
           "batched stage launch");
@@ -1322,8 +1353,6 @@ ssd_status ssd_batch_create(ssd_mesh *const *meshes, int32_t n, ssd_batch **out)
       return fail(SSD_ERR_INVALID_ARG, "all meshes of a batch must be on one device");
     for (int d = 0; d < c; ++d)
       if (meshes[d] == meshes[c]) return fail(SSD_ERR_INVALID_ARG, "a mesh appears twice in the batch");
-    if (meshes[c]->general)
-      return fail(SSD_ERR_INVALID_ARG, "meshes with general sliding rings cannot be batched");
   }
   ssd_batch *b = new (std::nothrow) ssd_batch();
   if (!b) return fail(SSD_ERR_NOMEM, "host allocation failed");
@@ -1358,7 +1387,10 @@ ssd_status ssd_batch_create(ssd_mesh *const *meshes, int32_t n, ssd_batch **out)
       }
       for (int t = 0; t < (m->E + EB - 1) / EB; ++t) sw[gi].push_back(make_uint2(c, t));
       const int fpb = 256 / m->N;
-      for (int k = 0; k < (2 * m->K + fpb - 1) / fpb; ++k) mw[gi].push_back(make_uint2(c, k));
+      if (m->general)
+        b->groups[gi].general.push_back(c);
+      else
+        for (int k = 0; k < (2 * m->K + fpb - 1) / fpb; ++k) mw[gi].push_back(make_uint2(c, k));
       for (int k = 0; k < (m->E + TRACE_BLOCK - 1) / TRACE_BLOCK; ++k)
         tw[gi].push_back(make_uint2(c, k));
       const long len = 4L * m->N * m->N * m->E;

@@ -76,9 +76,10 @@ __device__ __forceinline__ int rank_in(const SideView &o, double x, bool strict)
   return lo;
 }
 
-__global__ __launch_bounds__(256) void k_gen_merge(DevMesh M, GenRing G, double theta) {
+__global__ __launch_bounds__(256) void k_gen_merge(DevMesh M, GenRing G, AngleArg A) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= G.KL + G.KR) return;
+  const double theta = angle_value(A);
   const int side = i < G.KL ? 0 : 1;
   const int t = side ? i - G.KL : i;
   const SideView own = side_view(G, side, theta, M), other = side_view(G, side ^ 1, theta, M);
@@ -144,11 +145,12 @@ __device__ __forceinline__ MortarRec mortar_at(const DevMesh &M, const GenRing &
 
 template <int N, bool VISC>
 __global__ __launch_bounds__(256) void k_gen_flux(DevMesh M, OpTables T, MortarTables MT,
-                                                  GenRing G, double theta,
+                                                  GenRing G, AngleArg Ang,
                                                   const float *__restrict__ tr) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
   const int Mn = G.KL + G.KR;
   if (idx >= Mn * N) return;
+  const double theta = angle_value(Ang);
   const int k = idx / N, a = idx % N;
   const MortarRec r = mortar_at(M, G, theta, k);
   double q[2][4];
@@ -189,12 +191,13 @@ __global__ __launch_bounds__(256) void k_gen_flux(DevMesh M, OpTables T, MortarT
 // the mortar; the two sides averaged.  Into G.mf.
 template <int N>
 __global__ __launch_bounds__(256) void k_gen_vflux(DevMesh M, OpTables T, MortarTables MT,
-                                                   GenRing G, double theta,
+                                                   GenRing G, AngleArg Ang,
                                                    const float *__restrict__ mqc,
                                                    const float *__restrict__ gtr) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
   const int Mn = G.KL + G.KR;
   if (idx >= Mn * N) return;
+  const double theta = angle_value(Ang);
   const int k = idx / N, a = idx % N;
   const MortarRec r = mortar_at(M, G, theta, k);
   const double gam = M.gamma, Rg = M.gas_R, mu = M.mu;
@@ -237,10 +240,11 @@ __global__ __launch_bounds__(256) void k_gen_vflux(DevMesh M, OpTables T, Mortar
 // negated); for the common solution, as it is.
 template <int N>
 __global__ __launch_bounds__(256) void k_gen_back(DevMesh M, MortarTables MT, GenRing G,
-                                                  double theta, const double *__restrict__ src,
+                                                  AngleArg Ang, const double *__restrict__ src,
                                                   float *__restrict__ dst, int flux) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= (G.KL + G.KR) * N) return;
+  const double theta = angle_value(Ang);
   const int i = idx / N, a = idx % N;
   const int side = i < G.KL ? 0 : 1;
   const int face = side ? i - G.KL : i;
@@ -274,35 +278,35 @@ __global__ __launch_bounds__(256) void k_gen_back(DevMesh M, MortarTables MT, Ge
 }
 
 hipError_t launch_gen_mortar(const DevMesh &M, const OpTables &T, const MortarTables &MT,
-                             const GenRing &G, double theta, const float *tr, float *mflux,
+                             const GenRing &G, const AngleArg &A, const float *tr, float *mflux,
                              float *mqc, hipStream_t s) {
   const int nb = G.KL + G.KR;
-  hipLaunchKernelGGL(k_gen_merge, dim3((nb + 255) / 256), dim3(256), 0, s, M, G, theta);
+  hipLaunchKernelGGL(k_gen_merge, dim3((nb + 255) / 256), dim3(256), 0, s, M, G, A);
   const int np = nb * M.N;
   const dim3 grid((np + 255) / 256);
   if (mqc) {
     SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_gen_flux<NN, true>), grid, dim3(256), 0, s, M, T,
-                                           MT, G, theta, tr));
+                                           MT, G, A, tr));
   } else {
     SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_gen_flux<NN, false>), grid, dim3(256), 0, s, M, T,
-                                           MT, G, theta, tr));
+                                           MT, G, A, tr));
   }
-  SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_gen_back<NN>, grid, dim3(256), 0, s, M, MT, G, theta,
+  SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_gen_back<NN>, grid, dim3(256), 0, s, M, MT, G, A,
                                          G.mf, mflux, 1));
   if (mqc)
-    SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_gen_back<NN>, grid, dim3(256), 0, s, M, MT, G, theta,
+    SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_gen_back<NN>, grid, dim3(256), 0, s, M, MT, G, A,
                                            G.mq, mqc, 0));
   return hipGetLastError();
 }
 
 hipError_t launch_gen_mortar_visc(const DevMesh &M, const OpTables &T, const MortarTables &MT,
-                                  const GenRing &G, double theta, const float *mqc,
+                                  const GenRing &G, const AngleArg &A, const float *mqc,
                                   const float *gtr, float *mvflux, hipStream_t s) {
   const int np = (G.KL + G.KR) * M.N;
   const dim3 grid((np + 255) / 256);
   SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_gen_vflux<NN>, grid, dim3(256), 0, s, M, T, MT, G,
-                                         theta, mqc, gtr));
-  SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_gen_back<NN>, grid, dim3(256), 0, s, M, MT, G, theta,
+                                         A, mqc, gtr));
+  SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_gen_back<NN>, grid, dim3(256), 0, s, M, MT, G, A,
                                          G.mf, mvflux, 1));
   return hipGetLastError();
 }

@@ -151,16 +151,31 @@ struct GenRing {
   double *mq;            // [KL + KR][N][4] mortar common solution (viscous meshes)
 };
 
+// Rotor angle of a general-ring launch: `theta`, or, with `bc` set, the
+// batched case's angle at stage offset c of step *step (read on the device,
+// so that a captured graph follows the step counter).
+struct AngleArg {
+  double theta;
+  const BatchCase *bc;
+  double c;
+  const double *step;
+};
+__device__ __forceinline__ double angle_value(const AngleArg &A) {
+  if (!A.bc) return A.theta;
+  const BatchCase &B = *A.bc;
+  return B.theta0 + B.omega * (B.t0 + (A.step[0] + A.c) * B.dt);
+}
+
 // Mortar merge, mortar fluxes and their projection back to the faces for
-// the rotor angle theta (tr: the face data buffer's traces); with mqc also
-// the faces' common solution.
+// the rotor angle A (tr: the face data buffer's traces); with mqc also the
+// faces' common solution.
 hipError_t launch_gen_mortar(const DevMesh &M, const OpTables &T, const MortarTables &MT,
-                             const GenRing &G, double theta, const float *tr, float *mflux,
+                             const GenRing &G, const AngleArg &A, const float *tr, float *mflux,
                              float *mqc, hipStream_t s);
 // Viscous mortar flux from the faces' common solution and gradient traces,
 // for the angle of the preceding launch_gen_mortar.
 hipError_t launch_gen_mortar_visc(const DevMesh &M, const OpTables &T, const MortarTables &MT,
-                                  const GenRing &G, double theta, const float *mqc,
+                                  const GenRing &G, const AngleArg &A, const float *mqc,
                                   const float *gtr, float *mvflux, hipStream_t s);
 
 // W = w2 (u2 - un) + w3 (u3 - un) + w4 (u4 - un) over n floats.

@@ -7,7 +7,8 @@ import numpy as np
 import pytest
 
 from oracle.ssd import SSD, GeneralInterface
-from tests.parity_utils import TOL, gpu_residual, gpu_run, residual_error, state_error
+from tests.parity_utils import (TOL, from_gpu, gpu_residual, gpu_run, residual_error,
+                                state_error, to_gpu)
 from workloads import cases as C
 from workloads import meshes as M
 
@@ -82,9 +83,41 @@ def test_viscous_residual(torch_cuda, K, K_out, warp, N):
         assert np.all(err <= TOL), err
 
 
-def test_batch_rejects_general_rings(torch_cuda):
-    from paper_1503_02198_amd import Batch, Mesh, SSDError
-    print("case: batch rejects general rings", flush=True)
-    gm = Mesh(_mesh(16, 24, 0.3), C.ellipse_case(), 3)
-    with pytest.raises(SSDError):
-        Batch([gm])
+@pytest.mark.parametrize("scheme", ["rk3", "rk54"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_with_general_rings(torch_cuda, scheme, graph):
+    """A batch mixing general-ring meshes (inviscid N = 3 and 4, viscous
+    N = 3) with a uniform-ring mesh of the same N steps like each mesh
+    alone.  The batch reads each stage's rotor angle from its device step
+    counter, the single mesh gets it from the host, so the two agree to
+    rounding (relative 1e-6), not bit for bit."""
+    import torch
+    from paper_1503_02198_amd import Batch, Mesh
+    print(f"case: batch with general rings, {scheme}, graph={graph}", flush=True)
+    cv = C.ellipse_case(omega=2.0)
+    cv["mu"] = 0.02
+    specs = [(_mesh(16, 24, 0.3), C.ellipse_case(omega=2.0), 3, 0.4),
+             (_mesh(24, 16, -0.4), C.ellipse_case(omega=-1.5), 4, 0.1),
+             (_mesh(16, 16, 0.0), C.ellipse_case(omega=1.0), 3, 0.0),   # uniform rings
+             (_mesh(16, 24, 0.3), cv, 3, 0.2)]
+    meshes = [Mesh(m, c, N) for m, c, N, _ in specs]
+    assert [g.info["K"] for g in meshes] == [24, 24, 16, 24]
+    dt, nsteps = 6.0e-5, 6
+    Qs = [C.perturbed_farfield_state(c, N, g.info["n_elem"], amplitude=0.05, seed=k)
+          for k, ((m, c, N, _), g) in enumerate(zip(specs, meshes))]
+    ref = []
+    for g, Q, (m, c, N, t0) in zip(meshes, Qs, specs):
+        ref.append(gpu_run(g, Q, t0, dt, nsteps, scheme=scheme))
+    batch = Batch(meshes)
+    qs = [to_gpu(Q) for Q in Qs]
+    ws = [torch.empty(g.info["work_len"], dtype=torch.float32, device="cuda:0") for g in meshes]
+    batch.rk_steps(qs, ws, [s[3] for s in specs], [dt] * len(specs), nsteps, scheme=scheme,
+                   graph=graph)
+    for g in meshes:
+        g.check()
+    assert sorted((g["N"], g["viscous"]) for g in batch.groups()) == [(3, 0), (3, 1), (4, 0)]
+    for k, (g, (m, c, N, t0)) in enumerate(zip(meshes, specs)):
+        err = state_error(from_gpu(qs[k], N, g.info["n_elem"]), ref[k])
+        print(k, "N", N, "relative difference", err, flush=True)
+        assert np.all(err < 1e-6), (k, err)
+    batch.close()
