@@ -144,6 +144,50 @@ def batched_main(args):
         "seconds": res}), flush=True)
 
 
+def mlp_kernels_main(args):
+    """Throughput of the learned-correction kernels alone, on seeded random
+    rows: the normalisation fit, 200 Adam steps on minibatches of 4096 rows
+    with input noise 0.1, one forward pass over all rows, then 200 SSP-RK3
+    steps of the coarse viscous ellipse mesh (64 x (8 + 16) cells, N = 3)
+    with the network attached.  Only library entry points are called."""
+    import torch
+    from paper_1503_02198_amd import MLP
+    from paper_1503_02198_amd import subgrid as G
+    from workloads import cases as C
+    meshes = G.ellipse_pair(64, 8, 16)
+    P = G.Pair(meshes, C.ellipse_viscous_case(omega=0.2))
+    net = MLP(3)
+    net.set_params(G.init_params(np.random.default_rng(1), net.n_in, net.n_out))
+    rows, batch, steps = P.Ec * 64, 4096, 200
+    g = torch.Generator().manual_seed(20150307)
+    X = torch.randn(rows * net.n_in, generator=g).to("cuda:0")
+    T = torch.randn(rows * net.n_out, generator=g).to("cuda:0")
+    net.fit_normalization(X, T, min_rel=1e-2)
+    rng = np.random.default_rng(2)
+    idx = [torch.tensor(rng.integers(0, rows, batch).astype(np.int32), device="cuda:0")
+           for _ in range(steps)]
+    Y = torch.empty(rows * net.n_out, device="cuda:0")
+    q, w = P.uniform(P.coarse), P.work(P.coarse)
+    P.coarse.attach(net)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    t_train = timed(lambda: [net.train_step(X, T, i, 1e-3, 0.1, 7) for i in idx])
+    t_fwd = timed(lambda: net.forward(X, Y))
+    t_rk = timed(lambda: P.coarse.rk_steps(q, w, 0.0, P.dt_c, steps))
+    P.coarse.check()
+    print(json.dumps({"metric": "learned-correction kernels", "rows": rows,
+                      "train_samples_per_s": steps * batch / t_train,
+                      "forward_samples_per_s": rows / t_fwd,
+                      "corrected_rk3_steps_per_s": steps / t_rk,
+                      "cells": P.Ec, "N": 3}), flush=True)
+
+
 def subgrid_main(args):
     """The learned-correction workload end to end: fine runs for training
     data, training, then plain SSD runs and the corrected coarse run over one
@@ -300,6 +344,8 @@ def main():
                     help="the 64-case batch workload instead of the headline run")
     ap.add_argument("--subgrid", action="store_true",
                     help="the learned-correction workload (training data, training, evaluation)")
+    ap.add_argument("--mlp-kernels", action="store_true",
+                    help="throughput of the learned-correction kernels on seeded random rows")
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV",
                                                           "CALIB_FETCH_CSV", "CALIB_WRITE_CSV"))
     args = ap.parse_args()
@@ -323,6 +369,9 @@ def main():
         return
     if args.subgrid:
         subgrid_main(args)
+        return
+    if args.mlp_kernels:
+        mlp_kernels_main(args)
         return
 
     from paper_1503_02198_amd import Mesh, pack_state, unpack_state
