@@ -2,9 +2,11 @@
 // per-chunk routines and the single-mesh __global__ wrappers, shared by the
 // single-mesh launchers (ssd_kernels.hip) and the batched ones (ssd_batch.hip).
 //
-// Layout: SoA with the element index fastest, so a wave that serves 64
-// consecutive elements reads and writes contiguous 256-byte rows per
-// (variable, point).  Face traces (the solution interpolated to the
+// Layout: per-cell arrays are cell-blocked (cb_index): blocks of 64
+// consecutive elements, each stored plane after plane with one row of its
+// elements per plane, so the wave that serves a block's 64 elements reads
+// and writes contiguous 256-byte rows per (variable, point) and a block's
+// state is one contiguous span.  Face traces (the solution interpolated to the
 // element-boundary flux points) travel between blocks through a trace buffer
 // laid out [face][element][point][var]: one lane moves the 4 variables of a
 // point as one 16-byte access, and the N waves of a block together touch
