@@ -274,10 +274,12 @@ ssd_status ssd_batch_query(const ssd_batch *b, int32_t group, ssd_batch_group *i
 
 /*
  * Kernel timing.  ssd_timing_enable selects the kernel classes whose
- * launches are bracketed by HIP events on their stream: `classes` is a bit
+ * launches are timed with HIP events on their stream: `classes` is a bit
  * mask, bit SSD_KERNEL_x for class x (SSD_TIMING_ALL: every class, 0: off).
- * Each bracket costs two event records in the stream, so time only the
- * classes of interest in a throughput run.  Classes: the stage kernel
+ * The stage kernel's events are attached to its dispatch and record the
+ * kernel's own start and end; the other classes are bracketed by two event
+ * records in the stream, which adds a few microseconds per launch, so time
+ * only the classes of interest in a throughput run.  Classes: the stage kernel
  * (residual or fused RK stage), the face-trace kernel, the mortar kernels
  * (the rebuild fused with the inviscid mortar, and with mu > 0 the viscous
  * mortar), the stand-alone mortar rebuild (ssd_mortar_rebuild), and the

@@ -348,12 +348,17 @@ void free_all(ssd_mesh *m) {
 }
 
 // Brackets one kernel launch with events when timing is on.
+// With by_dispatch, start and stop are handed to the launch itself
+// (hipExtLaunchKernelGGL), which records them at the kernel's own start and
+// end; otherwise they are recorded on the stream around the launch.
 struct LaunchTimer {
   ssd_mesh *m;
   int kind;
   hipStream_t s;
-  hipEvent_t stop = nullptr;
-  LaunchTimer(ssd_mesh *m_, int k, hipStream_t s_) : m(m_), kind(k), s(s_) {
+  hipEvent_t start = nullptr, stop = nullptr;
+  bool around = true;
+  LaunchTimer(ssd_mesh *m_, int k, hipStream_t s_, bool by_dispatch = false)
+      : m(m_), kind(k), s(s_) {
     if (!((m->timing >> kind) & 1)) return;
     auto &t = m->timers[kind];
     if (t.used + 2 > t.ev.size()) {
@@ -363,12 +368,14 @@ struct LaunchTimer {
         t.ev.push_back(e);
       }
     }
-    (void)hipEventRecord(t.ev[t.used], s);
+    start = t.ev[t.used];
     stop = t.ev[t.used + 1];
     t.used += 2;
+    around = !by_dispatch;
+    if (around) (void)hipEventRecord(start, s);
   }
   ~LaunchTimer() {
-    if (stop) (void)hipEventRecord(stop, s);
+    if (stop && around) (void)hipEventRecord(stop, s);
   }
 };
 
@@ -803,8 +810,8 @@ ssd_status residual_pass(ssd_mesh *m, double th, double omega, const float *in, 
   }
   RKCoef Cs = C;
   Cs.reverse = int(m->stage_launches++ & 1u);
-  LaunchTimer lt(m, SSD_KERNEL_STAGE, st);
-  SSD_HIP(launch_stage(m->D, m->T, rot, in, qn, out, facein, trout, V, Cs, rk, st),
+  LaunchTimer lt(m, SSD_KERNEL_STAGE, st, true);
+  SSD_HIP(launch_stage(m->D, m->T, rot, in, qn, out, facein, trout, V, Cs, rk, st, lt.start, lt.stop),
           rk ? "stage launch" : "residual launch");
   return SSD_OK;
 }

@@ -1,4 +1,6 @@
 // Launchers of the single-mesh SSD kernels (device bodies in ssd_tiles.h).
+#include <hip/hip_ext.h>
+
 #include "ssd_launch.h"
 #include "ssd_tiles.h"
 
@@ -54,13 +56,15 @@ hipError_t launch_grad(const DevMesh &M, const OpTables &T, Rotation rot, const 
 
 hipError_t launch_stage(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
                         const float *qn, float *out, const float *facein, float *trout,
-                        const ViscIO *visc, const RKCoef &C, bool rk, hipStream_t s) {
+                        const ViscIO *visc, const RKCoef &C, bool rk, hipStream_t s,
+                        hipEvent_t ev0, hipEvent_t ev1) {
   const int grid = (M.E + EB - 1) / EB;
   const ViscBufs V{visc ? visc->G : nullptr, visc ? visc->gtr : nullptr,
                    visc ? visc->mvflux : nullptr};
 #define SSD_STAGE(RKV, VV, AV)                                                               \
-  SSD_DISPATCH_N(M.N, hipLaunchKernelGGL((k_stage<NN, RKV, VV, AV>), dim3(grid), dim3(EB * NN), \
-                                         0, s, M, T, rot, q, qn, out, facein, trout, V, C))
+  SSD_DISPATCH_N(M.N, hipExtLaunchKernelGGL((k_stage<NN, RKV, VV, AV>), dim3(grid),             \
+                                            dim3(EB * NN), 0, s, ev0, ev1, 0, M, T, rot, q, qn, out, \
+                                            facein, trout, V, C))
   const bool add = rk && C.add != nullptr;
   if (rk && visc) {
     if (add) {

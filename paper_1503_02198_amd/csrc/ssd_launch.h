@@ -28,7 +28,8 @@ hipError_t launch_mortar_visc(const DevMesh &M, const OpTables &T, const MortarS
 // inviscid residual.
 hipError_t launch_stage(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
                         const float *qn, float *out, const float *facein, float *trout,
-                        const ViscIO *visc, const RKCoef &C, bool rk, hipStream_t s);
+                        const ViscIO *visc, const RKCoef &C, bool rk, hipStream_t s,
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // ---------------------------------------------------------------------------
 // batched execution of many meshes (same device): per-case descriptors and
 // work tables live in device memory; every batched kernel walks a table of
