@@ -169,7 +169,6 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
                                            const RKCoef &C, int tile) {
   __shared__ float S[4][N][N][EB];     // state of the block's elements
   __shared__ float SR[4][N][N][EB];    // xi part of the residual, then the new state
-  __shared__ uint8_t XL[4][EB];        // exporting lanes per face
   const float *Sf = &S[0][0][0][0];
   const int l = threadIdx.x & (EB - 1);
   // the wave index is uniform across the wave (blocks are 64 N lanes): say so,
@@ -444,15 +443,13 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
       for (int j = 0; j < N; ++j) bstore(qc[v][j], rout, vs, ((v * N + j) * N + w) * rowb);
     if (bad) M.flag[0] = 1;
   }
-  // lanes whose face f is read by another block, in lane order (wave w lists
-  // the faces it packs below)
+  // lanes whose face f is read by another block (every wave holds the
+  // same 64 elements, so every wave forms the same masks)
   const uint64_t xm[4] = {__builtin_amdgcn_ballot_w64(valid && face_exported(fw0)),
                           __builtin_amdgcn_ballot_w64(valid && face_exported(fw1)),
                           __builtin_amdgcn_ballot_w64(valid && face_exported(fw2)),
                           __builtin_amdgcn_ballot_w64(valid && face_exported(fw3))};
-  for (int f = w; f < 4; f += N)
-    if ((xm[f] >> l) & 1u) XL[f][lane_rank(xm[f])] = uint8_t(l);
-  __syncthreads();
+  __syncthreads();   // the new state of the whole block is in SR
 
   // ---- pack phase: wave w writes the face records of faces f = w, w + N,
   // ...  Lane k of a chunk takes point k % N of the (k / N)-th listed
@@ -462,11 +459,20 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
   constexpr int EPC = EB / N;   // elements per chunk
   const uint32_t tile0 = uint32_t(tile) * EB;
   for (int f = w; f < 4; f += N) {
-    const int cnt = __builtin_popcountll(xm[f]);
+    const uint64_t m = xm[f];
+    const int cnt = __builtin_popcountll(m);
+    // the list of exporting lanes in lane order, one entry per lane: a full
+    // permutation pushes exporter l to lane rank(l) and every other lane
+    // behind them, so lane k < cnt holds the k-th exporting lane
+    const bool ex = (m >> l) & 1u;
+    const int slot = ex ? lane_rank(m) : cnt + lane_rank(~m);
+    const int listed = __builtin_amdgcn_ds_permute(slot * 4, l);
     for (int c0 = 0; c0 < cnt; c0 += EPC) {
       const int j = c0 + l / N, p = l % N;
+      // all lanes take part in the pull; j < 64 always (c0 < cnt <= 64 and
+      // l / N < EPC), lanes with j >= cnt discard what they read
+      const int src = __builtin_amdgcn_ds_bpermute(min(j, EB - 1) * 4, listed);
       if (l < EPC * N && j < cnt) {
-        const int src = XL[f][j];
         float tv[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
