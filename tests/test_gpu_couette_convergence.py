@@ -8,7 +8,9 @@ form.  The state is FP32: at this Mach number (0.1 at the inner wall) the
 energy is about 180 times the kinetic energy, and the velocity error of an
 FP32 steady state levels off near 3e-6 (L2).  The levels used here keep the
 errors well above that floor: N = 2 on the 8 x 32 and 16 x 64 annuli,
-N = 3 on the 4 x 16 and 8 x 32 annuli.
+N = 3 and N = 4 on the 4 x 16 and 8 x 32 annuli (at N = 4 the 8 x 32 error,
+3e-5, is ten times the floor; the 2 x 8 annulus is not yet in the
+asymptotic range, order 2.8).
 """
 import json
 import os
@@ -65,7 +67,7 @@ def _couette_error(N, nr, nt, T=2.0, cfl=0.2):
     return (W * np.abs(e)).sum() / W.sum(), np.sqrt((W * e * e).sum() / W.sum())
 
 
-@pytest.mark.parametrize("N,nr,min_order", [(2, 8, 1.6), (3, 4, 2.6)])
+@pytest.mark.parametrize("N,nr,min_order", [(2, 8, 1.6), (3, 4, 2.6), (4, 4, 3.5)])
 def test_couette_steady_convergence(torch_cuda, N, nr, min_order):
     print(f"case: Couette steady state N={N}, {nr}x{4 * nr} and {2 * nr}x{8 * nr}", flush=True)
     e1 = _couette_error(N, nr, 4 * nr)
@@ -74,8 +76,8 @@ def test_couette_steady_convergence(torch_cuda, N, nr, min_order):
     print("L1, L2:", e1, e2, "orders", order, flush=True)
     assert np.all(order > min_order), order
     assert e2[1] > 1e-5          # above the FP32 floor: the order is the method's
-    if N == 3:
+    if N in (3, 4):
+        key = {3: "table5_couette_N3", 4: "table6_couette_N4"}[N]
         with open(GOLD) as fh:
-            paper = [r["L2_order"] for r in json.load(fh)["table5_couette_N3"]["rows"]
-                     if r["L2_order"] is not None]
+            paper = [r["L2_order"] for r in json.load(fh)[key]["rows"] if r["L2_order"] is not None]
         assert order[1] > min(paper) - 0.6, (order, paper)
