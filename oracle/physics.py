@@ -89,5 +89,17 @@ def viscous_flux(Q, Qx, Qy, gamma, gas_R, mu, prandtl):
     return F, G
 
 
+def slip_state(Q, nx, ny, ug, vg, gamma):
+    """Common solution of a slip wall (BR1 reading, Sec. 2): the trace Q
+    with the velocity component normal to the wall, relative to the wall's
+    own velocity (ug, vg), removed; density and pressure unchanged.  (nx,
+    ny) is any nonzero normal."""
+    rho, u, v, p = primitives(Q, gamma)
+    mag = np.sqrt(nx * nx + ny * ny)
+    nhx, nhy = nx / mag, ny / mag
+    urel = (u - ug) * nhx + (v - vg) * nhy
+    return conservative(rho, u - urel * nhx, v - urel * nhy, p, gamma)
+
+
 def conservative(rho, u, v, p, gamma):
     return np.stack([rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)])

@@ -504,11 +504,7 @@ class SSD:
         rb = p / (Rg * cs["T_wall"])
         Qiso = ph.conservative(rb, fug, fvg, p, gam)
         Qc = np.where(iso, Qiso, Qc)
-        mag = np.sqrt(fnx * fnx + fny * fny)
-        nhx, nhy = fnx / mag, fny / mag
-        urel = (u - fug) * nhx + (v - fvg) * nhy
-        Qslip = ph.conservative(rho, u - urel * nhx, v - urel * nhy, p, gam)
-        Qc = np.where(slip, Qslip, Qc)
+        Qc = np.where(slip, ph.slip_state(T, fnx, fny, fug, fvg, gam), Qc)
         Qinf = ph.conservative(*cs["farfield"], gam)[:, None, None, None] * np.ones_like(T)
         Qc = np.where(far, Qinf, Qc)
 

@@ -107,3 +107,33 @@ def test_free_stream_between_slip_walls_and_far_field(N, mu):
     Q = ph.conservative(rho0 * one, u0 * one, 0.0 * one, p0 * one, case["gamma"])
     R, diag = ora.residual(Q, 0.0, 0.0, diag=True)
     assert np.abs(R).max() < 1e-12 * max(1.0, np.abs(diag["flux_scale"]).max())
+
+
+def test_slip_state_properties():
+    """The slip common solution is fixed by what it must satisfy: zero
+    velocity normal to the wall relative to the wall, with density, pressure
+    and the tangential relative velocity unchanged.  It is idempotent, does
+    not depend on the normal's length or sign, and leaves a state that
+    already moves with the wall unchanged."""
+    rng = np.random.default_rng(11)
+    g = 1.4
+    n = 200
+    rho = rng.uniform(0.5, 2.0, n)
+    u, v = rng.normal(0, 1, n), rng.normal(0, 1, n)
+    p = rng.uniform(0.3, 3.0, n)
+    Q = ph.conservative(rho, u, v, p, g)
+    nx, ny = rng.normal(0, 1, n), rng.normal(0, 1, n)
+    ug, vg = rng.normal(0, 0.5, n), rng.normal(0, 0.5, n)
+    S = ph.slip_state(Q, nx, ny, ug, vg, g)
+    r2, u2, v2, p2 = ph.primitives(S, g)
+    mag = np.hypot(nx, ny)
+    tx, ty = -ny / mag, nx / mag
+    assert np.allclose(((u2 - ug) * nx + (v2 - vg) * ny) / mag, 0.0, atol=1e-13)
+    assert np.allclose(r2, rho, rtol=1e-14) and np.allclose(p2, p, rtol=1e-12)
+    assert np.allclose((u2 - ug) * tx + (v2 - vg) * ty, (u - ug) * tx + (v - vg) * ty, atol=1e-13)
+    assert np.allclose(ph.slip_state(S, nx, ny, ug, vg, g), S, atol=1e-13)
+    assert np.allclose(ph.slip_state(Q, -3.0 * nx, -3.0 * ny, ug, vg, g), S, atol=1e-13)
+    # a state moving with the wall plus any tangential velocity is unchanged
+    w = rng.normal(0, 1, n)
+    Qt = ph.conservative(rho, ug + w * tx, vg + w * ty, p, g)
+    assert np.allclose(ph.slip_state(Qt, nx, ny, ug, vg, g), Qt, atol=1e-13)
