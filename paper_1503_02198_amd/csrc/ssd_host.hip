@@ -972,11 +972,19 @@ ssd_status ssd_rk_steps(ssd_mesh *m, float *q, float *work, double t, double dt,
   int cur = 0;   // face data buffer holding the traces of the current stage input
   // one stage: the residual of `in` at t + c dt, fused with the update
   auto stage = [&](double tn, double c, const float *in, const float *qn, float *out, float beta,
-                   float gamma, const float *add, float add_scale = 1.0f) -> ssd_status {
+                   float gamma, const float *add, float add_scale = 1.0f,
+                   float *comb = nullptr, const double *cw = nullptr) -> ssd_status {
     const double th = m->theta0 + m->omega0 * (tn + c * dt);
+    RKCoef C{beta, gamma, float(dt), add, add_scale};
+    if (comb) {
+      C.comb = comb;
+      C.cw2 = float(cw[0]);
+      C.cw3 = float(cw[1]);
+      C.cw4 = float(cw[2]);
+    }
     // the mortar kernel rebuilds the projections for th itself
-    ssd_status e = residual_pass(m, th, m->omega0, in, qn, out, m->tr[cur], m->tr[cur ^ 1],
-                                 RKCoef{beta, gamma, float(dt), add, add_scale}, true, st);
+    ssd_status e = residual_pass(m, th, m->omega0, in, qn, out, m->tr[cur], m->tr[cur ^ 1], C,
+                                 true, st);
     cur ^= 1;
     return e;
   };
@@ -1008,19 +1016,17 @@ ssd_status ssd_rk_steps(ssd_mesh *m, float *q, float *work, double t, double dt,
       for (int k = 1; k < 4; ++k) tau[k + 1] = RK54_A[k][1] * tau[k] + RK54_A[k][2];
       const float *in[4] = {q, w1, w2, w1};
       float *outp[4] = {w1, w2, w1, w3};
-      for (int k = 0; k < 4; ++k)
-        if (ssd_status e = stage(tn, tau[k], in[k], k ? q : nullptr, outp[k], float(RK54_A[k][1]),
-                                 float(RK54_A[k][2]), nullptr))
-          return e;
       // U^{n+1} = U + W + C5[3] (U4 - U) + C5[4] dt L(U4), where
       // W = C5[0] (U2 - U) + C5[1] (U3 - U) + C5[2] dt L(U3) and dt L(U3) is
-      // recovered from stage 4: (U4 - U - A[3][1] (U3 - U)) / A[3][2]
+      // recovered from stage 4: (U4 - U - A[3][1] (U3 - U)) / A[3][2].  The
+      // fourth stage forms W itself, over U2 in w2.
       const double g4 = RK54_A[3][2];
-      const double w2c = RK54_C[0];
-      const double w3c = RK54_C[1] - RK54_C[2] * RK54_A[3][1] / g4;
-      const double w4c = RK54_C[2] / g4;
-      SSD_HIP(launch_rk_combine(len, q, w2, w1, w3, float(w2c), float(w3c), float(w4c), w2, st),
-              "stage combination launch");
+      const double cw[3] = {RK54_C[0], RK54_C[1] - RK54_C[2] * RK54_A[3][1] / g4,
+                            RK54_C[2] / g4};
+      for (int k = 0; k < 4; ++k)
+        if (ssd_status e = stage(tn, tau[k], in[k], k ? q : nullptr, outp[k], float(RK54_A[k][1]),
+                                 float(RK54_A[k][2]), nullptr, 1.0f, k == 3 ? w2 : nullptr, cw))
+          return e;
       if (ssd_status e = stage(tn, tau[4], w3, q, q, float(RK54_C[3]), float(RK54_C[4]), w2))
         return e;
     }

@@ -162,6 +162,11 @@ struct RKCoef {
   // nonzero: tiles taken in reverse block order, so that a launch starts on
   // the cells the previous launch touched last (still in the memory-side cache)
   int reverse = 0;
+  // SSPRK54, fourth stage: with comb set, the stage also forms the last
+  // stage's increment W = cw2 (U2 - Qn) + cw3 (Q - Qn) + cw4 (Q_new - Qn),
+  // reading U2 from comb and writing W over it
+  float *comb = nullptr;
+  float cw2 = 0.0f, cw3 = 0.0f, cw4 = 0.0f;
 };
 
 }  // namespace ssd

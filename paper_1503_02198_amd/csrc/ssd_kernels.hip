@@ -61,52 +61,36 @@ hipError_t launch_stage(const DevMesh &M, const OpTables &T, Rotation rot, const
   const int grid = (M.E + EB - 1) / EB;
   const ViscBufs V{visc ? visc->G : nullptr, visc ? visc->gtr : nullptr,
                    visc ? visc->mvflux : nullptr};
-#define SSD_STAGE(RKV, VV, AV)                                                               \
-  SSD_DISPATCH_N(M.N, hipExtLaunchKernelGGL((k_stage<NN, RKV, VV, AV>), dim3(grid),             \
+#define SSD_STAGE(RKV, VV, AV, CV)                                                           \
+  SSD_DISPATCH_N(M.N, hipExtLaunchKernelGGL((k_stage<NN, RKV, VV, AV, CV>), dim3(grid),         \
                                             dim3(EB * NN), 0, s, ev0, ev1, 0, M, T, rot, q, qn, out, \
                                             facein, trout, V, C))
   const bool add = rk && C.add != nullptr;
-  if (rk && visc) {
-    if (add) {
-      SSD_STAGE(true, true, true);
+  if (rk && C.comb) {   // SSPRK54 fourth stage with the increment (never with add)
+    if (add || !qn) return hipErrorInvalidValue;
+    if (visc) {
+      SSD_STAGE(true, true, false, true);
     } else {
-      SSD_STAGE(true, true, false);
+      SSD_STAGE(true, false, false, true);
+    }
+  } else if (rk && visc) {
+    if (add) {
+      SSD_STAGE(true, true, true, false);
+    } else {
+      SSD_STAGE(true, true, false, false);
     }
   } else if (rk) {
     if (add) {
-      SSD_STAGE(true, false, true);
+      SSD_STAGE(true, false, true, false);
     } else {
-      SSD_STAGE(true, false, false);
+      SSD_STAGE(true, false, false, false);
     }
   } else if (visc) {
-    SSD_STAGE(false, true, false);
+    SSD_STAGE(false, true, false, false);
   } else {
-    SSD_STAGE(false, false, false);
+    SSD_STAGE(false, false, false, false);
   }
 #undef SSD_STAGE
-  return hipGetLastError();
-}
-
-// SSPRK54 increment of the last stage (see the host stage loop):
-// W = w2 (u2 - un) + w3 (u3 - un) + w4 (u4 - un), elementwise.
-__global__ __launch_bounds__(256) void k_rk_combine(long n, const float *__restrict__ un,
-                                                    const float *__restrict__ u2,
-                                                    const float *__restrict__ u3,
-                                                    const float *__restrict__ u4, float w2,
-                                                    float w3, float w4, float *__restrict__ W) {
-  const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float b = un[i];
-  W[i] = w2 * (u2[i] - b) + w3 * (u3[i] - b) + w4 * (u4[i] - b);
-}
-
-hipError_t launch_rk_combine(long n, const float *un, const float *u2, const float *u3,
-                             const float *u4, float w2, float w3, float w4, float *W,
-                             hipStream_t s) {
-  const long grid = (n + 255) / 256;
-  if (grid > 0x7fffffffL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_rk_combine, dim3(unsigned(grid)), dim3(256), 0, s, n, un, u2, u3, u4, w2,
-                     w3, w4, W);
   return hipGetLastError();
 }
 

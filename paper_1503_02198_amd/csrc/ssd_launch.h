@@ -179,9 +179,4 @@ hipError_t launch_gen_mortar_visc(const DevMesh &M, const OpTables &T, const Mor
                                   const GenRing &G, const AngleArg &A, const float *mqc,
                                   const float *gtr, float *mvflux, hipStream_t s);
 
-// W = w2 (u2 - un) + w3 (u3 - un) + w4 (u4 - un) over n floats.
-hipError_t launch_rk_combine(long n, const float *un, const float *u2, const float *u3,
-                             const float *u4, float w2, float w3, float w4, float *W,
-                             hipStream_t s);
-
 }  // namespace ssd

@@ -162,7 +162,7 @@ __device__ __forceinline__ void common_visc(const DevMesh &M, const ViscParams &
 // LDS access of a wave to its own elements touches 64 distinct banks.
 // Global accesses of a wave are contiguous 256-byte rows.
 // ---------------------------------------------------------------------------
-template <int N, bool RK, bool VISC, bool ADD>
+template <int N, bool RK, bool VISC, bool ADD, bool COMB = false>
 __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, const Rotation &R,
                                            const float *q, const float *qn, float *out,
                                            const float *facein, float *trout, const ViscBufs &V,
@@ -191,6 +191,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
   const rsrc_t rG = make_rsrc(V.G, VISC ? 2u * sbytes : 0u);
   const rsrc_t rgtr = make_rsrc(V.gtr, VISC ? 2u * tbytes : 0u);
   const rsrc_t rmv = make_rsrc(V.mvflux, VISC ? mbytes : 0u);
+  const rsrc_t rcomb = make_rsrc(C.comb, (RK && COMB) ? sbytes : 0u);
   const ViscParams P = visc_params(M);
   // cell-blocked state and gradient arrays: plane 0 of the lane's cell, and
   // the bytes of one plane row of this block (uniform)
@@ -333,6 +334,13 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
 
   // ---- column phase
   float qc[4][N], rc[4][N];
+  float u2[4][N];   // (COMB) column w of U2, issued here for the column phase to hide
+  if (RK && COMB) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int j = 0; j < N; ++j) u2[v][j] = bload(rcomb, vs, ((v * N + j) * N + w) * rowb);
+  }
   {
     const LineGeo Lc = line_eta(g, float(T.X[w]));  // bilinear-cell metrics along column w
     float gc[8][N];   // gradient on column w
@@ -428,6 +436,9 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
       float x = with_qn ? qo[v][j] + (C.beta * (qc[v][j] - qo[v][j]) + gdt * rc[v][j])
                         : qc[v][j] + gdt * rc[v][j];
       if (ADD) x += C.add_scale * qa[v][j];
+      if (COMB)
+        u2[v][j] = C.cw2 * (u2[v][j] - qo[v][j]) + C.cw3 * (qc[v][j] - qo[v][j]) +
+                   C.cw4 * (x - qo[v][j]);
       qc[v][j] = x;
       SR[v][j][w][l] = x;
     }
@@ -441,6 +452,12 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
     for (int v = 0; v < 4; ++v)
 #pragma unroll
       for (int j = 0; j < N; ++j) bstore(qc[v][j], rout, vs, ((v * N + j) * N + w) * rowb);
+    if (COMB) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int j = 0; j < N; ++j) bstore(u2[v][j], rcomb, vs, ((v * N + j) * N + w) * rowb);
+    }
     if (bad) M.flag[0] = 1;
   }
   // lanes whose face f is read by another block (every wave holds the
@@ -495,13 +512,13 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
   }
 }
 
-template <int N, bool RK, bool VISC, bool ADD>
+template <int N, bool RK, bool VISC, bool ADD, bool COMB = false>
 __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotation R,
                                                   const float *q, const float *qn, float *out,
                                                   const float *facein, float *trout, ViscBufs V,
                                                   RKCoef C) {
   const int tile = C.reverse ? int(gridDim.x) - 1 - int(blockIdx.x) : int(blockIdx.x);
-  stage_tile<N, RK, VISC, ADD>(M, T, R, q, qn, out, facein, trout, V, C, tile);
+  stage_tile<N, RK, VISC, ADD, COMB>(M, T, R, q, qn, out, facein, trout, V, C, tile);
 }
 
 // ---------------------------------------------------------------------------
