@@ -67,30 +67,23 @@ __global__ __launch_bounds__(MORTAR_BLOCK) void kb_mortar_visc(const BatchCase *
   mortar_visc_chunk<N>(B.M, T, B.ms, fb + nt + nr, B.V.gtr, B.V.mvflux, int(it.y));
 }
 
-template <int N, bool VISC, bool ADD>
+template <int N, bool VISC, bool ADD, bool COMB = false>
 __global__ __launch_bounds__(64 * N) void kb_stage(const BatchCase *cases, const uint2 *work,
                                                    OpTables T, BatchStage S, const double *step) {
   const uint2 it = batch_item(work);
   const BatchCase &B = cases[it.x];
   const Rotation R = batch_rotation(B, step, S.c);
   const ViscBufs V{B.V.G, B.V.gtr, B.V.mvflux};
-  const RKCoef C{S.beta, S.gamma, float(B.dt), ADD ? B.buf[S.add] : nullptr};
-  stage_tile<N, true, VISC, ADD>(B.M, T, R, B.buf[S.in], S.qn >= 0 ? B.buf[S.qn] : nullptr,
-                                 B.buf[S.out], B.face[S.cur], B.face[S.cur ^ 1], V, C, int(it.y));
-}
-
-// W = w2 (u2 - un) + w3 (u3 - un) + w4 (u4 - un) with un, u2, u3, u4 and W
-// the case's stage arrays 0, 2, 1, 3 and 2.
-__global__ __launch_bounds__(256) void kb_rk_combine(const BatchCase *cases, const uint2 *work,
-                                                     float w2, float w3, float w4) {
-  const uint2 it = batch_item(work);
-  const BatchCase &B = cases[it.x];
-  const long n = 4L * B.M.N * B.M.N * B.M.E;
-  const long i = long(it.y) * 256 + threadIdx.x;
-  if (i < n) {
-    const float u = B.buf[0][i];
-    B.buf[2][i] = w2 * (B.buf[2][i] - u) + w3 * (B.buf[1][i] - u) + w4 * (B.buf[3][i] - u);
+  RKCoef C{S.beta, S.gamma, float(B.dt), ADD ? B.buf[S.add] : nullptr};
+  if (COMB) {
+    C.comb = B.buf[S.comb];
+    C.cw2 = S.cw2;
+    C.cw3 = S.cw3;
+    C.cw4 = S.cw4;
   }
+  stage_tile<N, true, VISC, ADD, COMB>(B.M, T, R, B.buf[S.in], S.qn >= 0 ? B.buf[S.qn] : nullptr,
+                                       B.buf[S.out], B.face[S.cur], B.face[S.cur ^ 1], V, C,
+                                       int(it.y));
 }
 
 __global__ void k_step_count(double *step) {
@@ -140,31 +133,31 @@ hipError_t launch_batch_stage(int N, bool visc, const BatchCase *cases, const ui
                               int nwork, const OpTables &T, const BatchStage &S,
                               const double *step, hipStream_t s) {
   if (nwork < 1) return hipSuccess;
-#define SSD_BSTAGE(VV, AV)                                                                      \
-  SSD_DISPATCH_N(N, hipLaunchKernelGGL((kb_stage<NN, VV, AV>), dim3(nwork), dim3(EB * NN), 0, s, \
-                                       cases, work, T, S, step))
+#define SSD_BSTAGE(VV, AV, CV)                                                                  \
+  SSD_DISPATCH_N(N, hipLaunchKernelGGL((kb_stage<NN, VV, AV, CV>), dim3(nwork), dim3(EB * NN), 0, \
+                                       s, cases, work, T, S, step))
   const bool add = S.add >= 0;
-  if (visc) {
-    if (add) {
-      SSD_BSTAGE(true, true);
+  if (S.comb >= 0) {   // SSPRK54's fourth stage with the increment (never with add)
+    if (add || S.qn < 0) return hipErrorInvalidValue;
+    if (visc) {
+      SSD_BSTAGE(true, false, true);
     } else {
-      SSD_BSTAGE(true, false);
+      SSD_BSTAGE(false, false, true);
+    }
+  } else if (visc) {
+    if (add) {
+      SSD_BSTAGE(true, true, false);
+    } else {
+      SSD_BSTAGE(true, false, false);
     }
   } else {
     if (add) {
-      SSD_BSTAGE(false, true);
+      SSD_BSTAGE(false, true, false);
     } else {
-      SSD_BSTAGE(false, false);
+      SSD_BSTAGE(false, false, false);
     }
   }
 #undef SSD_BSTAGE
-  return hipGetLastError();
-}
-
-hipError_t launch_batch_combine(const BatchCase *cases, const uint2 *work, int nwork, float w2,
-                                float w3, float w4, hipStream_t s) {
-  if (nwork < 1) return hipSuccess;
-  hipLaunchKernelGGL(kb_rk_combine, dim3(nwork), dim3(256), 0, s, cases, work, w2, w3, w4);
   return hipGetLastError();
 }
 

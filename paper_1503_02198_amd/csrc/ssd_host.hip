@@ -1103,8 +1103,7 @@ struct ssd_batch {
     OpTables T{};
     MortarTables MT{};
     uint2 *stage_work = nullptr, *mortar_work = nullptr, *trace_work = nullptr;
-    uint2 *comb_work = nullptr;
-    int nstage = 0, nmortar = 0, ntrace = 0, ncomb = 0;
+    int nstage = 0, nmortar = 0, ntrace = 0;
     double *step = nullptr;   // device step counter of the group
     std::vector<int> general; // cases with general rings: their mortars launched per case
     int stream = 0;           // index into ssd_batch::streams
@@ -1222,18 +1221,20 @@ ssd_status group_step(ssd_batch *b, const ssd_batch::Group &g, ssd_rk scheme, in
     double tau[5] = {0.0, RK54_A[0][2], 0.0, 0.0, 0.0};
     for (int k = 1; k < 4; ++k) tau[k + 1] = RK54_A[k][1] * tau[k] + RK54_A[k][2];
     const int in[4] = {0, 1, 2, 1}, out[4] = {1, 2, 1, 3};
+    // the fourth stage also forms the last stage's increment over U2 (array 2)
+    const double g4 = RK54_A[3][2];
     for (int k = 0; k < 4; ++k) {
-      if (ssd_status e = group_stage(b, g, BatchStage{in[k], k ? 0 : -1, out[k], -1, *cur,
-                                                      float(RK54_A[k][1]), float(RK54_A[k][2]),
-                                                      tau[k]}, st))
-        return e;
+      BatchStage S{in[k], k ? 0 : -1, out[k], -1, *cur, float(RK54_A[k][1]), float(RK54_A[k][2]),
+                   tau[k]};
+      if (k == 3) {
+        S.comb = 2;
+        S.cw2 = float(RK54_C[0]);
+        S.cw3 = float(RK54_C[1] - RK54_C[2] * RK54_A[3][1] / g4);
+        S.cw4 = float(RK54_C[2] / g4);
+      }
+      if (ssd_status e = group_stage(b, g, S, st)) return e;
       *cur ^= 1;
     }
-    const double g4 = RK54_A[3][2];
-    SSD_HIP(launch_batch_combine(b->dcases, g.comb_work, g.ncomb, float(RK54_C[0]),
-                                 float(RK54_C[1] - RK54_C[2] * RK54_A[3][1] / g4),
-                                 float(RK54_C[2] / g4), st),
-            "batched stage combination launch");
     if (ssd_status e = group_stage(b, g, BatchStage{3, 0, 0, 2, *cur, float(RK54_C[3]),
                                                     float(RK54_C[4]), tau[4]}, st))
       return e;
@@ -1379,7 +1380,7 @@ ssd_status ssd_batch_create(ssd_mesh *const *meshes, int32_t n, ssd_batch **out)
   try {
     b->meshes.assign(meshes, meshes + n);
     // groups of equal (N, viscous) and their work tables
-    std::vector<std::vector<uint2>> sw, mw, tw, cw;
+    std::vector<std::vector<uint2>> sw, mw, tw;
     for (int c = 0; c < n; ++c) {
       const ssd_mesh *m = meshes[c];
       int gi = -1;
@@ -1395,7 +1396,6 @@ ssd_status ssd_batch_create(ssd_mesh *const *meshes, int32_t n, ssd_batch **out)
         sw.emplace_back();
         mw.emplace_back();
         tw.emplace_back();
-        cw.emplace_back();
         gi = int(b->groups.size()) - 1;
       }
       for (int t = 0; t < (m->E + EB - 1) / EB; ++t) sw[gi].push_back(make_uint2(c, t));
@@ -1406,8 +1406,6 @@ ssd_status ssd_batch_create(ssd_mesh *const *meshes, int32_t n, ssd_batch **out)
         for (int k = 0; k < (2 * m->K + fpb - 1) / fpb; ++k) mw[gi].push_back(make_uint2(c, k));
       for (int k = 0; k < (m->E + TRACE_BLOCK - 1) / TRACE_BLOCK; ++k)
         tw[gi].push_back(make_uint2(c, k));
-      const long len = 4L * m->N * m->N * m->E;
-      for (long k = 0; k < (len + 255) / 256; ++k) cw[gi].push_back(make_uint2(c, unsigned(k)));
     }
     auto upload = [&](const std::vector<uint2> &v, uint2 **p, int *count) -> hipError_t {
       if (v.size() > size_t(0x7fffffff)) return hipErrorInvalidValue;
@@ -1421,8 +1419,7 @@ ssd_status ssd_batch_create(ssd_mesh *const *meshes, int32_t n, ssd_batch **out)
       auto &g = b->groups[k];
       if (upload(sw[k], &g.stage_work, &g.nstage) != hipSuccess ||
           upload(mw[k], &g.mortar_work, &g.nmortar) != hipSuccess ||
-          upload(tw[k], &g.trace_work, &g.ntrace) != hipSuccess ||
-          upload(cw[k], &g.comb_work, &g.ncomb) != hipSuccess)
+          upload(tw[k], &g.trace_work, &g.ntrace) != hipSuccess)
         return bail(fail(SSD_ERR_NOMEM, "batch work tables"));
     }
     b->cases.resize(n);

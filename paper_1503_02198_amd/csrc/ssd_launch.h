@@ -53,6 +53,10 @@ struct BatchStage {
   int cur;
   float beta, gamma;
   double c;
+  // SSPRK54's fourth stage: the stage array that holds U2 and receives the
+  // last stage's increment W = cw2 (U2 - Qn) + cw3 (Q - Qn) + cw4 (Q_new - Qn)
+  int comb = -1;
+  float cw2 = 0.0f, cw3 = 0.0f, cw4 = 0.0f;
 };
 
 // Batched launchers: one block per item of `work`, a table of (case, tile
@@ -70,8 +74,6 @@ hipError_t launch_batch_mortar_visc(int N, const BatchCase *cases, const uint2 *
 hipError_t launch_batch_stage(int N, bool visc, const BatchCase *cases, const uint2 *work,
                               int nwork, const OpTables &T, const BatchStage &S,
                               const double *step, hipStream_t s);
-hipError_t launch_batch_combine(const BatchCase *cases, const uint2 *work, int nwork, float w2,
-                                float w3, float w4, hipStream_t s);
 hipError_t launch_step_count(double *step, hipStream_t s);
 
 // ---------------------------------------------------------------------------
