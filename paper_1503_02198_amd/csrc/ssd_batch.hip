@@ -20,8 +20,8 @@ __device__ __forceinline__ Rotation batch_rotation(const BatchCase &B, const dou
   return Rotation{cs, sn, B.omega};
 }
 
-__device__ __forceinline__ uint2 batch_item(const uint2 *work) {
-  const uint2 w = work[blockIdx.x];
+__device__ __forceinline__ uint2 batch_item(const uint2 *work, bool reverse = false) {
+  const uint2 w = work[reverse ? gridDim.x - 1 - blockIdx.x : blockIdx.x];
   return make_uint2(__builtin_amdgcn_readfirstlane(w.x), __builtin_amdgcn_readfirstlane(w.y));
 }
 
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(MORTAR_BLOCK) void kb_mortar_visc(const BatchCase *
 template <int N, bool VISC, bool ADD, bool COMB = false>
 __global__ __launch_bounds__(64 * N) void kb_stage(const BatchCase *cases, const uint2 *work,
                                                    OpTables T, BatchStage S, const double *step) {
-  const uint2 it = batch_item(work);
+  const uint2 it = batch_item(work, S.reverse != 0);
   const BatchCase &B = cases[it.x];
   const Rotation R = batch_rotation(B, step, S.c);
   const ViscBufs V{B.V.G, B.V.gtr, B.V.mvflux};

@@ -1107,6 +1107,7 @@ struct ssd_batch {
     double *step = nullptr;   // device step counter of the group
     std::vector<int> general; // cases with general rings: their mortars launched per case
     int stream = 0;           // index into ssd_batch::streams
+    unsigned stages = 0;      // stage launches so far: parity picks the tile order
     float stage_ms = 0.0f;    // the group's stage alone (autotuner)
   };
   std::vector<Group> groups;
@@ -1165,12 +1166,13 @@ void case_mortar_bufs(const ssd_batch *b, int c, int cur, float **mflux, float *
   *mqc = *mflux + face_record_floats(m->N, m->K);
 }
 
-// One RK stage of group g, launched on stream st.  Cases with uniform rings
+// One RK stage of group g, launched on stream st (alternating the tile
+// order from stage to stage).  Cases with uniform rings
 // share the batched mortar launches; each case with general rings launches
 // its own merge, flux and back-projection, its angle read from the step
 // counter on the device.
-ssd_status group_stage(ssd_batch *b, const ssd_batch::Group &g, const BatchStage &S,
-                       hipStream_t st) {
+ssd_status group_stage(ssd_batch *b, ssd_batch::Group &g, BatchStage S, hipStream_t st) {
+  S.reverse = int(g.stages++ & 1u);
   SSD_HIP(launch_batch_mortar(g.N, g.visc, b->dcases, g.mortar_work, g.nmortar, g.T, g.MT, S.cur,
                               S.c, g.step, st),
           "batched mortar launch");
@@ -1205,7 +1207,7 @@ ssd_status group_stage(ssd_batch *b, const ssd_batch::Group &g, const BatchStage
 
 // One step of `scheme` for group g on stream st; *cur is the face buffer
 // parity of the step's input and is advanced stage by stage.
-ssd_status group_step(ssd_batch *b, const ssd_batch::Group &g, ssd_rk scheme, int *cur,
+ssd_status group_step(ssd_batch *b, ssd_batch::Group &g, ssd_rk scheme, int *cur,
                       hipStream_t st) {
   if (scheme == SSD_RK3_SSP) {
     const float B3[3] = {1.0f, 0.25f, 2.0f / 3.0f};
@@ -1267,7 +1269,7 @@ ssd_status batch_join(ssd_batch *b, hipStream_t st) {
 ssd_status batch_steps(ssd_batch *b, ssd_rk scheme, int nsteps, int *cur, hipStream_t st) {
   if (ssd_status e = batch_fork(b, st)) return e;
   int c_end = *cur;
-  for (const auto &g : b->groups) {
+  for (auto &g : b->groups) {
     int c = *cur;
     for (int s = 0; s < nsteps; ++s)
       if (ssd_status e = group_step(b, g, scheme, &c, b->streams[g.stream])) return e;
@@ -1309,6 +1311,10 @@ ssd_status batch_tune(ssd_batch *b, hipStream_t st) {
     return fail(SSD_ERR_DEVICE, "event");
   }
   const BatchStage S{0, -1, 3, -1, 0, 1.0f, 0.0f, 0.0};
+  // each trial enqueues kRep stages back to back, so that the GPU, not the
+  // host's launch rate, sets the time (the trial stage rewrites array 3 from
+  // array 0 every time)
+  constexpr int kRep = 4;
   auto timed = [&](auto &&body, float *ms) -> ssd_status {
     *ms = 1e30f;
     for (int rep = 0; rep < 3; ++rep) {   // best of three after the first
@@ -1318,13 +1324,19 @@ ssd_status batch_tune(ssd_batch *b, hipStream_t st) {
       if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
           hipEventElapsedTime(&t, e0, e1) != hipSuccess)
         return fail(SSD_ERR_DEVICE, "tuning timing");
-      if (rep) *ms = std::min(*ms, t);
+      if (rep) *ms = std::min(*ms, t / kRep);
     }
     return SSD_OK;
   };
   ssd_status result = SSD_OK;
   for (auto &g : b->groups) {
-    result = timed([&]() { return group_stage(b, g, S, st); }, &g.stage_ms);
+    result = timed(
+        [&]() -> ssd_status {
+          for (int r = 0; r < kRep; ++r)
+            if (ssd_status e = group_stage(b, g, S, st)) return e;
+          return SSD_OK;
+        },
+        &g.stage_ms);
     if (result) break;
   }
   const int maxs = std::min<int>(SSD_BATCH_MAX_STREAMS, int(b->groups.size()));
@@ -1336,8 +1348,9 @@ ssd_status batch_tune(ssd_batch *b, hipStream_t st) {
     result = timed(
         [&]() -> ssd_status {
           if (ssd_status e = batch_fork(b, st)) return e;
-          for (const auto &g : b->groups)
-            if (ssd_status e = group_stage(b, g, S, b->streams[g.stream])) return e;
+          for (auto &g : b->groups)
+            for (int r = 0; r < kRep; ++r)
+              if (ssd_status e = group_stage(b, g, S, b->streams[g.stream])) return e;
           return batch_join(b, st);
         },
         &ms);
