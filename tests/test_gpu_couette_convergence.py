@@ -8,9 +8,11 @@ form.  The state is FP32: at this Mach number (0.1 at the inner wall) the
 energy is about 180 times the kinetic energy, and the velocity error of an
 FP32 steady state levels off near 3e-6 (L2).  The levels used here keep the
 errors well above that floor: N = 2 on the 8 x 32 and 16 x 64 annuli,
-N = 3 and N = 4 on the 4 x 16 and 8 x 32 annuli (at N = 4 the 8 x 32 error,
-3e-5, is ten times the floor; the 2 x 8 annulus is not yet in the
-asymptotic range, order 2.8).
+N = 3, 4 and 5 on the 4 x 16 and 8 x 32 annuli (at N = 4 and 5 the 8 x 32
+errors, 2-3e-5, are ten times the floor; the 2 x 8 annulus is not yet in the
+asymptotic range, order 2.8-2.9).  At N = 5 the errors are close to N = 4's:
+the cubic (serendipity) wall and interface cells carry an O(h^4) geometric
+error, so the order stays near 4.5 rather than 5.
 """
 import json
 import os
@@ -67,7 +69,7 @@ def _couette_error(N, nr, nt, T=2.0, cfl=0.2):
     return (W * np.abs(e)).sum() / W.sum(), np.sqrt((W * e * e).sum() / W.sum())
 
 
-@pytest.mark.parametrize("N,nr,min_order", [(2, 8, 1.6), (3, 4, 2.6), (4, 4, 3.5)])
+@pytest.mark.parametrize("N,nr,min_order", [(2, 8, 1.6), (3, 4, 2.6), (4, 4, 3.5), (5, 4, 3.5)])
 def test_couette_steady_convergence(torch_cuda, N, nr, min_order):
     print(f"case: Couette steady state N={N}, {nr}x{4 * nr} and {2 * nr}x{8 * nr}", flush=True)
     e1 = _couette_error(N, nr, 4 * nr)
