@@ -51,6 +51,8 @@ def _cat(parts, axis):
 def pack_state(Q):
     """Flat cell-blocked array of Q [..., n_elem] (the leading axes are the
     planes: [4, N, N, n_elem] for a state)."""
+    if Q.ndim < 2:
+        raise ValueError("pack_state needs planes x elements (e.g. [4, N, N, n_elem])")
     E = Q.shape[-1]
     P = int(np.prod(Q.shape[:-1]))
     Q2 = Q.reshape(P, E)
@@ -63,6 +65,8 @@ def pack_state(Q):
 def unpack_state(q, N, n_elem, nvar=4):
     """[nvar, N, N, n_elem] view of a flat cell-blocked array."""
     E, P = n_elem, nvar * N * N
+    if q.ndim != 1 or q.shape[0] != P * E:
+        raise ValueError(f"expected a flat array of {P * E} values, got shape {tuple(q.shape)}")
     nb = E // CB
     head = _swap01(q[:P * nb * CB], (nb, P, CB)).reshape(P, nb * CB)
     tail = q[P * nb * CB:P * E].reshape(P, E - nb * CB)

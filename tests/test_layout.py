@@ -44,3 +44,12 @@ def test_torch_tensors():
     q = pack_state(Q)
     assert torch.equal(q, torch.from_numpy(pack_state(Q.numpy())))
     assert torch.equal(unpack_state(q, N, E), Q)
+
+
+def test_wrong_sizes_are_rejected():
+    with pytest.raises(ValueError):
+        unpack_state(np.zeros(4 * 2 * 2 * 10 - 1, np.float32), 2, 10)
+    with pytest.raises(ValueError):
+        unpack_state(np.zeros((4, 40), np.float32), 2, 10)
+    with pytest.raises(ValueError):
+        pack_state(np.zeros(7, np.float32))
