@@ -84,3 +84,28 @@ def test_fullsize_rk3_step_sampled(c3):
     rel_change = np.linalg.norm(dg - do) / np.linalg.norm(do)
     print("sampled state error", err, "error of the change", rel_change)
     assert np.all(err <= TOL), err
+
+
+def test_fullsize_ssprk54_step_sampled(c3):
+    """One SSPRK54 step (five residual evaluations, the fourth stage forming
+    the last stage's increment) on the full mesh, against the oracle on a
+    sub-mesh five neighbour layers deep around the sampled cells."""
+    import torch
+    mesh, case, N, E, Q0, dt, gm = c3
+    print(f"case: full-size SSPRK54 step E={E} dt={dt:.3e}", flush=True)
+    q = to_gpu(Q0)
+    work = torch.empty(gm.info["work_len"], dtype=torch.float32, device=q.device)
+    gm.rk_step(q, work, 0.0, dt, scheme="rk54")
+    gm.check()
+    Qg = from_gpu(q, N, E)
+    pick = _samples(E, np.random.default_rng(7))
+    sub, idx = submesh(mesh, pick, depth=5)
+    ora = SSD(sub, case, N)
+    Qo = ora.ssprk54_step(Q0[..., idx].astype(np.float64), 0.0, dt)
+    loc = np.searchsorted(idx, pick)
+    err = state_error(Qg[..., pick], Qo[..., loc])
+    dg = Qg[..., pick] - Q0[..., pick]
+    do = Qo[..., loc] - Q0[..., pick]
+    rel_change = np.linalg.norm(dg - do) / np.linalg.norm(do)
+    print("sampled state error", err, "error of the change", rel_change)
+    assert np.all(err <= TOL), err
