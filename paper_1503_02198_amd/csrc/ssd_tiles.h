@@ -216,11 +216,13 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
   float x0[4], x1[4], x2[4], x3[4];
   prefetch_face<N>(M, rtin, fbytes, tbytes, uint32_t(M.E), fw3, w, x3);   // row faces xi = 0, 1 at point w
   prefetch_face<N>(M, rtin, fbytes, tbytes, uint32_t(M.E), fw1, w, x1);
-  prefetch_face<N>(M, rtin, fbytes, tbytes, uint32_t(M.E), fw0, w, x0);   // column faces eta = 0, 1
-  prefetch_face<N>(M, rtin, fbytes, tbytes, uint32_t(M.E), fw2, w, x2);
+  if (!VISC) {   // column faces eta = 0, 1 (viscous stages: at the column phase)
+    prefetch_face<N>(M, rtin, fbytes, tbytes, uint32_t(M.E), fw0, w, x0);
+    prefetch_face<N>(M, rtin, fbytes, tbytes, uint32_t(M.E), fw2, w, x2);
+  }
   float qo[4][N];   // column w of Qn (RK stages after the first)
   const bool with_qn = RK && qn != nullptr;
-  if (with_qn) {
+  if (with_qn && !VISC) {   // viscous stages load these just before the update
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -334,12 +336,9 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
 
   // ---- column phase
   float qc[4][N], rc[4][N];
-  float u2[4][N];   // (COMB) column w of U2, issued here for the column phase to hide
-  if (RK && COMB) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-      for (int j = 0; j < N; ++j) u2[v][j] = bload(rcomb, vs, ((v * N + j) * N + w) * rowb);
+  if (VISC) {
+    prefetch_face<N>(M, rtin, fbytes, tbytes, uint32_t(M.E), fw0, w, x0);
+    prefetch_face<N>(M, rtin, fbytes, tbytes, uint32_t(M.E), fw2, w, x2);
   }
   {
     const LineGeo Lc = line_eta(g, float(T.X[w]));  // bilinear-cell metrics along column w
@@ -427,6 +426,19 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
   // ---- SSP-RK stage on column w: Q <- Qn + beta (Q - Qn) + gamma dt R
   // [+ add_scale add]; the new column goes to SR (no other lane reads column w of SR
   // after the column phase has started)
+  if (VISC && with_qn) {   // viscous stages: Qn only now, to keep the column phase's registers down
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int j = 0; j < N; ++j) qo[v][j] = bload(rqn, vs, ((v * N + j) * N + w) * rowb);
+  }
+  float u2[4][N];   // (COMB) column w of U2, loaded late for the same reason
+  if (COMB) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int j = 0; j < N; ++j) u2[v][j] = bload(rcomb, vs, ((v * N + j) * N + w) * rowb);
+  }
   bool bad = false;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
