@@ -792,10 +792,16 @@ ssd_status residual_pass(ssd_mesh *m, double th, double omega, const float *in, 
               "mortar launch");
   }
   const Rotation rot{std::cos(th), std::sin(th), omega};
+  // tile order: successive tile kernels alternate, so that each starts on
+  // the tiles the one before touched last.  Euler meshes alternate from stage
+  // to stage; on viscous meshes the gradient pass runs forward and the stage
+  // in reverse, every time.
+  const bool parity = (m->stage_launches++ & 1u) != 0;
   if (V) {
     {
       LaunchTimer lt(m, SSD_KERNEL_GRAD, st);
-      SSD_HIP(launch_grad(m->D, m->T, rot, in, facein, V->G, V->gtr, st), "gradient launch");
+      SSD_HIP(launch_grad(m->D, m->T, rot, in, facein, V->G, V->gtr, st, false),
+              "gradient launch");
     }
     if (m->K) {
       LaunchTimer lt(m, SSD_KERNEL_MORTAR, st);
@@ -809,7 +815,7 @@ ssd_status residual_pass(ssd_mesh *m, double th, double omega, const float *in, 
     }
   }
   RKCoef Cs = C;
-  Cs.reverse = int(m->stage_launches++ & 1u);
+  Cs.reverse = V ? 1 : int(parity);
   LaunchTimer lt(m, SSD_KERNEL_STAGE, st, true);
   SSD_HIP(launch_stage(m->D, m->T, rot, in, qn, out, facein, trout, V, Cs, rk, st, lt.start, lt.stop),
           rk ? "stage launch" : "residual launch");

@@ -47,10 +47,10 @@ hipError_t launch_mortar_visc(const DevMesh &M, const OpTables &T, const MortarS
 }
 
 hipError_t launch_grad(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
-                       const float *facein, float *G, float *gtr, hipStream_t s) {
+                       const float *facein, float *G, float *gtr, hipStream_t s, bool reverse) {
   const int grid = (M.E + EB - 1) / EB;
   SSD_DISPATCH_N(M.N, hipLaunchKernelGGL(k_grad<NN>, dim3(grid), dim3(EB * NN), 0, s, M, T, rot, q,
-                                         facein, G, gtr));
+                                         facein, G, gtr, int(reverse)));
   return hipGetLastError();
 }
 

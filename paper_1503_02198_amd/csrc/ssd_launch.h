@@ -19,8 +19,10 @@ hipError_t launch_mortar(const DevMesh &M, const OpTables &T, const MortarTables
                          double theta, MortarState *ms, const float *tr, float *mflux, float *mqc,
                          hipStream_t s);
 // facein: face data buffer of q with its traces and mortar common solution.
+// reverse: tiles taken in reverse block order.
 hipError_t launch_grad(const DevMesh &M, const OpTables &T, Rotation rot, const float *q,
-                       const float *facein, float *G, float *gtr, hipStream_t s);
+                       const float *facein, float *G, float *gtr, hipStream_t s,
+                       bool reverse = false);
 hipError_t launch_mortar_visc(const DevMesh &M, const OpTables &T, const MortarState *ms,
                               const float *mqc, const float *gtr, float *mvflux, hipStream_t s);
 // facein: face data buffer of q with its traces and mortar flux; trout:

@@ -760,8 +760,9 @@ __device__ __forceinline__ void grad_tile(const DevMesh &M, const OpTables &T, c
 template <int N>
 __global__ __launch_bounds__(64 * N) void k_grad(DevMesh M, OpTables T, Rotation R,
                                                  const float *q, const float *facein, float *Gout,
-                                                 float *gtr) {
-  grad_tile<N>(M, T, R, q, facein, Gout, gtr, blockIdx.x);
+                                                 float *gtr, int reverse) {
+  const int tile = reverse ? int(gridDim.x) - 1 - int(blockIdx.x) : int(blockIdx.x);
+  grad_tile<N>(M, T, R, q, facein, Gout, gtr, tile);
 }
 
 // ---------------------------------------------------------------------------
