@@ -109,3 +109,42 @@ def test_fullsize_ssprk54_step_sampled(c3):
     rel_change = np.linalg.norm(dg - do) / np.linalg.norm(do)
     print("sampled state error", err, "error of the change", rel_change)
     assert np.all(err <= TOL), err
+
+
+@pytest.fixture(scope="module")
+def c3_viscous():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import bench
+    from paper_1503_02198_amd import Mesh
+
+    class A:
+        N, K, n_in, n_out, viscous = 4, 4096, 64, 180, True
+    mesh, case, N, E, Q0, dt = bench.workload(A)
+    gm = Mesh(mesh, case, N, device=0)
+    return mesh, case, N, E, Q0, dt, gm
+
+
+def test_fullsize_viscous_residual_sampled(c3_viscous):
+    """The viscous residual on the full mesh of `bench.py --viscous`
+    (isothermal ellipse wall, Mach 0.3, Re 1000), against the oracle on a
+    sub-mesh two neighbour layers deep (BR1 gradients reach two layers)."""
+    import torch
+    mesh, case, N, E, Q0, dt, gm = c3_viscous
+    theta = 0.0371
+    print(f"case: full-size viscous residual E={E} N={N} theta={theta}", flush=True)
+    q = to_gpu(Q0)
+    r = torch.empty_like(q)
+    gm.set_rotation(theta, case["omega"])
+    gm.mortar_rebuild()
+    gm.residual(q, r)
+    Rg = from_gpu(r, N, E)
+    pick = _samples(E, np.random.default_rng(8))
+    sub, idx = submesh(mesh, pick, depth=2)
+    ora = SSD(sub, case, N)
+    Ro, diag = ora.residual(Q0[..., idx].astype(np.float64), theta, case["omega"], diag=True)
+    loc = np.searchsorted(idx, pick)
+    err = residual_error(Rg[..., pick], Ro[..., loc], diag["flux_scale"][..., loc])
+    print("sampled viscous residual error", err)
+    assert np.all(err <= TOL), err
