@@ -252,38 +252,106 @@ def traffic_for(kind_hash, E, N):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(mesh, case, N, Q0, dt, q_gpu_step, target_s):
-    """The FP64 oracle, single-threaded, on a bounded sub-mesh: one SSP-RK3
-    step on the first `n` cells (plus every interface cell and three layers
-    of neighbours, which the sub-mesh needs); returns the rate and the
-    oracle-vs-GPU error on the sampled cells."""
+def _usable_cores():
+    """Host cores this process may run on, at most 16 (the CPU share of one
+    GPU on the measurement machines)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_step_timed(mesh, case, N, Q0, dt, cells, depth=3):
+    """One SSP-RK3 step of the FP64 oracle on the sub-mesh around `cells`
+    (mesh build and set-up excluded from the time): (seconds, sub-mesh
+    cells, sub-mesh state after the step, global indices)."""
+    from oracle.ssd import SSD, submesh
+    sub, idx = submesh(mesh, cells, depth=depth)
+    ora = SSD(sub, case, N)
+    Qs = Q0[..., idx].astype(np.float64)
+    t0 = time.perf_counter()
+    Q1 = ora.ssprk3_step(Qs, 0.0, dt)
+    return time.perf_counter() - t0, len(idx), Q1, idx
+
+
+def _cpu_worker(rank, lo, hi, runs, viscous, barrier, out):
+    """One process of the all-cores oracle timing: rebuilds the workload,
+    then times `runs` oracle steps on the sub-mesh of cells [lo, hi), each
+    started together with the other processes."""
     from threadpoolctl import threadpool_limits
 
     from oracle.ssd import SSD, submesh
-    from tests.parity_utils import state_error
+
+    class A:
+        N, K, n_in, n_out = 4, 4096, 64, 180
+    A.viscous = viscous
+    mesh, case, N, E, Q0, dt = workload(A)
+    with threadpool_limits(1):
+        sub, idx = submesh(mesh, np.arange(lo, hi), depth=3)
+        ora = SSD(sub, case, N)
+        Qs = Q0[..., idx].astype(np.float64)
+        times = []
+        for _ in range(runs):
+            barrier.wait()
+            t0 = time.perf_counter()
+            ora.ssprk3_step(Qs, 0.0, dt)
+            times.append(time.perf_counter() - t0)
+    out.put((rank, len(idx), times))
+
+
+def cpu_baseline(mesh, case, N, Q0, dt, q_gpu_step, target_s, runs=3):
+    """The FP64 oracle timed on the host, on 1 core and on every usable core
+    (the median of `runs` steps each), on bounded samples of the workload;
+    also the oracle-vs-GPU errors of one step on the sampled cells."""
+    import multiprocessing as mp
+
+    from threadpoolctl import threadpool_limits
+
+    from tests.parity_utils import change_error, state_error
     E = len(mesh["zone"])
     n = 8192
     with threadpool_limits(1):
         while True:
             sample = np.arange(min(n, E))
-            sub, idx = submesh(mesh, sample, depth=3)
-            ora = SSD(sub, case, N)
-            Qs = Q0[..., idx].astype(np.float64)
-            t0 = time.perf_counter()
-            Q1 = ora.ssprk3_step(Qs, 0.0, dt)
-            el = time.perf_counter() - t0
-            # the measured step takes between 2/3 of the target and about the target
+            el, ncell, Q1, idx = _oracle_step_timed(mesh, case, N, Q0, dt, sample)
+            # one step of the sample takes between 2/3 of the target and about the target
             if el > target_s / 1.5 or n >= E:
                 break
             n = int(n * min(8.0, max(1.5, target_s / max(el, 1e-3))))
+        one = [el] + [_oracle_step_timed(mesh, case, N, Q0, dt, sample)[0]
+                      for _ in range(runs - 1)]
     loc = np.searchsorted(idx, sample)
     err = state_error(q_gpu_step[..., sample], Q1[..., loc])
-    dof_updates = 4 * N * N * len(idx) * 3
-    return dict(value=dof_updates / el, unit="DOF-updates/s", cores=1, kind="oracle",
-                sample=(f"one SSP-RK3 step (3 stages) of the FP64 numpy oracle on a "
-                        f"{len(idx)}-cell sub-mesh of the workload (cells 0..{len(sample) - 1}, "
-                        f"all interface cells and 3 neighbour layers), {el:.1f} s"),
-                seconds=el), err
+    ch, bound = change_error(q_gpu_step[..., sample], Q1[..., loc], Q0[..., sample])
+    t1 = float(np.median(one))
+    rate1 = 4 * N * N * ncell * 3 / t1
+
+    # all cores: one process per core, each on its own slice of the cells
+    P = _usable_cores()
+    per = min(len(sample), E // P)
+    ctx = mp.get_context("spawn")
+    barrier, out = ctx.Barrier(P), ctx.Queue()
+    procs = [ctx.Process(target=_cpu_worker, args=(r, r * per, (r + 1) * per, runs,
+                                                    case["mu"] > 0.0, barrier, out))
+             for r in range(P)]
+    for pr in procs:
+        pr.start()
+    res = sorted(out.get() for _ in range(P))
+    for pr in procs:
+        pr.join()
+    cells_all = sum(r[1] for r in res)
+    wall = [max(r[2][k] for r in res) for k in range(runs)]
+    tP = float(np.median(wall))
+    rateP = 4 * N * N * cells_all * 3 / tP
+    rec = dict(value=rateP, unit="DOF-updates/s", cores=P, kind="oracle",
+               sample=(f"FP64 numpy oracle, one SSP-RK3 step (3 stages), median of {runs}: "
+                       f"{P} processes, one per core, each on the sub-mesh of {per} cells of the "
+                       f"workload (with every interface cell and 3 neighbour layers; "
+                       f"{cells_all} cells in all), {tP:.2f} s; on 1 core the sub-mesh of cells "
+                       f"0..{len(sample) - 1} ({ncell} cells), {t1:.2f} s"),
+               value_1core=rate1, seconds_1core=one, seconds_all_cores=wall)
+    return rec, err, ch, bound
 
 
 def _counter_means(csv_path, counter):
@@ -351,7 +419,9 @@ def main():
     ap.add_argument("--scheme", choices=("rk3", "rk54"), default="rk3",
                     help="time integrator of the headline run (SSP-RK3, the benchmark "
                          "configuration; SSPRK54, the paper's scheme, reported alongside)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=4.0)
+    ap.add_argument("--settle-s", type=float, default=1.0,
+                    help="seconds of untimed steps before the warm-up steps (clock settling)")
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--batched", action="store_true",
                     help="the 64-case batch workload instead of the headline run")
@@ -399,6 +469,18 @@ def main():
 
     t = 0.0
     scheme = args.scheme
+    # Clock settling: after an idle spell the GPU's clocks and power state
+    # need a few hundred stage launches to settle (measured: launches 13-25
+    # of a cold start run 230-245 us, later ones 170-190 us).  The path is
+    # stepped for `--settle-s` seconds before the `--warmup` steps, so that
+    # the timed steps see the state a long run runs in.
+    settle_steps = 0
+    t_settle = time.perf_counter()
+    while time.perf_counter() - t_settle < args.settle_s:
+        gm.rk_steps(q, work, t, dt, 50, scheme=scheme)
+        torch.cuda.synchronize()
+        t += 50 * dt
+        settle_steps += 50
     if args.warmup:
         gm.rk_steps(q, work, t, dt, args.warmup, scheme=scheme)
         t += args.warmup * dt
@@ -414,7 +496,11 @@ def main():
     el = time.perf_counter() - t0
     t += args.steps * dt
     ms, n = gm.timing_read("stage")
-    kern = {"stage": dict(launches=n, avg_us=1e3 * ms / n, total_ms=ms)}
+    per = 1e3 * gm.timing_samples("stage")
+    kern = {"stage": dict(launches=n, avg_us=1e3 * ms / n, total_ms=ms,
+                          median_us=float(np.median(per)), p10_us=float(np.percentile(per, 10)),
+                          p90_us=float(np.percentile(per, 90)), min_us=float(per.min()),
+                          max_us=float(per.max()))}
     # the other kernels, from a short run after the timed region
     others = ("traces", "mortar") + (("grad",) if args.viscous else ())
     gm.timing_enable(kernels=list(others))
@@ -431,12 +517,16 @@ def main():
     stages = (3 if scheme == "rk3" else 5) * args.steps
     value = dof * stages / el
     # algorithmic bytes of one stage launch: the state it must read and
-    # write, on average per DOF, and the cell geometry (the bilinear map, 8
-    # floats = 32 bytes per cell).  SSP-RK3: Q_k and, in stages 2-3, Q^n,
-    # then Q_{k+1}: (8 + 12 + 12) / 3 bytes.  SSPRK54: stage 1 8, stages 2
-    # and 3 12, stage 4 20 (it also reads U2 and writes the last stage's
-    # increment over it), stage 5 16 (it reads that increment): 13.6 bytes.
-    alg_bytes = ((32.0 / 3.0) if scheme == "rk3" else 13.6) * dof + 32.0 * E
+    # write, on average per DOF, and the cell geometry as the FP64 node
+    # coordinates read once per cell (4 nodes, 64 bytes, for a bilinear
+    # cell; 12 nodes, 192 bytes, for a cubic one).  SSP-RK3: Q_k and, in
+    # stages 2-3, Q^n, then Q_{k+1}: (8 + 12 + 12) / 3 bytes.  SSPRK54:
+    # stage 1 8, stages 2 and 3 12, stage 4 20 (it also reads U2 and writes
+    # the last stage's increment over it), stage 5 16 (it reads that
+    # increment): 13.6 bytes.
+    n_cubic = gm.info["n_cubic"]
+    alg_bytes = (((32.0 / 3.0) if scheme == "rk3" else 13.6) * dof
+                 + 64.0 * (E - n_cubic) + 192.0 * n_cubic)
     if args.viscous:
         # the viscous stage also reads the SP gradients (8 values per point,
         # 8 B/DOF); the gradient pass is a kernel of its own
@@ -474,6 +564,7 @@ def main():
                      "alg_bytes_per_launch": alg_bytes, "avg_launch_us": stage_us},
         "kernels": kern,
         "kernel_hash": hsh,
+        "settle": {"steps": settle_steps, "seconds": args.settle_s},
     }
     if not args.no_cpu_baseline and scheme == "rk3" and not args.viscous:
         # one GPU step from the same initial state for the sampled parity check
@@ -481,9 +572,13 @@ def main():
         gm.rk_step(q1, work, 0.0, dt)
         gm.check()
         q1h = unpack_state(q1.cpu().numpy(), N, E).astype(np.float64)
-        cb, err = cpu_baseline(mesh, case, N, Q0, dt, q1h, args.cpu_seconds)
-        result["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        cb, err, ch, bound = cpu_baseline(mesh, case, N, Q0, dt, q1h, args.cpu_seconds)
+        result["cpu_baseline"] = cb
+        # one GPU step from the same state against the oracle's on the
+        # sampled cells: the state error, and the error of the step's change
+        # (the step moves the state by about 2e-5 of its norm)
         result["l2_rel_vs_oracle"] = [float(x) for x in err]
+        result["step_change_err_vs_oracle"] = {"value": float(ch), "bound": float(bound)}
     print(json.dumps(result), flush=True)
 
 

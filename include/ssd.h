@@ -253,7 +253,9 @@ typedef struct {
   float stage_us;       /* the group's stage alone, as timed by the autotuner  */
 } ssd_batch_group;
 
-/* n >= 1 distinct meshes, all on one device.  Errors: SSD_ERR_INVALID_ARG. */
+/* n >= 1 distinct meshes, all on one device, none with a learned correction
+ * attached (ssd_subgrid_attach): the batched stage has no correction input.
+ * Errors: SSD_ERR_INVALID_ARG. */
 ssd_status ssd_batch_create(ssd_mesh *const *meshes, int32_t n, ssd_batch **out);
 ssd_status ssd_batch_destroy(ssd_batch *b);
 
@@ -263,7 +265,11 @@ ssd_status ssd_batch_destroy(ssd_batch *b);
  * work[c] (device, its work_len floats).  Same arithmetic as ssd_rk_steps
  * per mesh; the rotor angle is formed on the device from t[c] + (n + c_k)
  * dt[c], so results agree with ssd_rk_steps to rounding.  Host arrays q,
- * work, t, dt have one entry per mesh in creation order.
+ * work, t, dt have one entry per mesh in creation order.  Afterwards each
+ * mesh is at the rotor angle of t[c] + nsteps dt[c] with stale mortars, as
+ * after ssd_rk_steps, with or without graphs.  A mesh that has had a learned
+ * correction attached since the batch was created gives
+ * SSD_ERR_INVALID_ARG, with no work enqueued.
  */
 ssd_status ssd_batch_rk_steps(ssd_batch *b, float *const *q, float *const *work, const double *t,
                               const double *dt, int32_t nsteps, ssd_rk scheme, int32_t use_graph,
@@ -293,6 +299,12 @@ enum { SSD_TIMING_ALL = (1 << SSD_KERNEL_COUNT) - 1 };
 ssd_status ssd_timing_enable(ssd_mesh *m, int classes);
 ssd_status ssd_timing_reset(ssd_mesh *m);
 ssd_status ssd_timing_read(ssd_mesh *m, int kernel, double *total_ms, int64_t *launches);
+/* The same launches one by one: ms[i] (host, cap entries) receives the
+ * duration of the i-th timed launch of class `kernel` since the last reset,
+ * in launch order, for i < min(cap, launches); *launches receives their
+ * count.  Synchronises the device.  Errors: SSD_ERR_INVALID_ARG for a bad
+ * class, cap < 0, or a null ms with cap > 0. */
+ssd_status ssd_timing_samples(ssd_mesh *m, int kernel, float *ms, int64_t cap, int64_t *launches);
 
 /*
  * Learned per-element subgrid correction (an extension of the method; not

@@ -1,11 +1,13 @@
 """Exact solutions used to pin the oracle (Sec. 4.1 and Sec. 4.2).
 
 Isentropic vortex (Sec. 4.1): the paper's formulas with strength epsilon,
-size r_c, freestream (U, rho, p, M) along direction theta_f, transported
-with the mean flow and wrapped to the nearest periodic image.  The vortex
-workload sets epsilon U = beta / (2 pi) with beta = 5, r_c = 1,
-rho = p = 1 and M = 0.5 along x; the exponent is read as (1 - r^2/r_c^2),
-which is what the printed formula gives for the r_c = 1 used here.
+size r_c, freestream (U, rho, p, M) along direction theta_f (the direction
+of the far-field velocity), transported with the mean flow and wrapped to
+the nearest periodic image.  The vortex workload sets epsilon U = beta /
+(2 pi) with beta = 5, r_c = 1, rho = p = 1 and M = 0.5 along x; the paper's
+own test gives epsilon directly (epsilon = 1, U = 1, M = 0.3, theta_f =
+arctan(1/2)).  The exponent is read as (1 - r^2/r_c^2), which is what the
+printed formula gives for the r_c = 1 used here.
 
 Taylor-Couette (Sec. 4.2): v_theta(r) = omega r_i (r_o/r - r/r_o)/(r_o/r_i -
 r_i/r_o).  With constant mu and k this azimuthal flow is an exact steady
@@ -25,15 +27,15 @@ def vortex_state(x, y, t, case):
     """Conservative state (4, ...) of the vortex at time t."""
     vx = case["vortex"]
     g = case["gamma"]
-    rho_inf, U, _, p_inf = case["farfield"]
+    rho_inf, u_inf, v_inf, p_inf = case["farfield"]
+    U = np.hypot(u_inf, v_inf)
+    th = np.arctan2(v_inf, u_inf)
     c_inf = np.sqrt(g * p_inf / rho_inf)
     M = U / c_inf
-    beta = vx["beta"]
-    eps = beta / (2 * np.pi * U)
+    eps = vx["epsilon"] if "epsilon" in vx else vx["beta"] / (2 * np.pi * U)
     rc = 1.0
     L = vx["period"]
     x0, y0 = vx["center"]
-    th = 0.0
     ub, vb = U * np.cos(th), U * np.sin(th)
     xr = x - x0 - ub * t
     yr = y - y0 - vb * t

@@ -1095,6 +1095,20 @@ ssd_status ssd_timing_read(ssd_mesh *m, int kernel, double *total_ms, int64_t *l
   return SSD_OK;
 }
 
+ssd_status ssd_timing_samples(ssd_mesh *m, int kernel, float *ms, int64_t cap, int64_t *launches) {
+  if (ssd_status s = check_handle(m)) return s;
+  if (kernel < 0 || kernel >= SSD_KERNEL_COUNT || !launches || cap < 0 || (cap > 0 && !ms))
+    return fail(SSD_ERR_INVALID_ARG, "bad kernel class, capacity or null output");
+  DeviceGuard guard(m->device);
+  SSD_HIP(hipDeviceSynchronize(), "synchronize");
+  auto &t = m->timers[kernel];
+  const int64_t n = int64_t(t.used / 2);
+  for (int64_t i = 0; i < n && i < cap; ++i)
+    SSD_HIP(hipEventElapsedTime(&ms[i], t.ev[2 * i], t.ev[2 * i + 1]), "event elapsed");
+  *launches = n;
+  return SSD_OK;
+}
+
 // ---------------------------------------------------------------------------
 // batches: many meshes stepped together
 // ---------------------------------------------------------------------------
@@ -1122,8 +1136,17 @@ struct ssd_batch {
   double *steps = nullptr;   // one counter per group
   std::vector<void *> allocs;
   hipStream_t streams[SSD_BATCH_MAX_STREAMS] = {};
-  hipEvent_t fork = nullptr;
-  hipEvent_t join[SSD_BATCH_MAX_STREAMS] = {};
+  // Fork and join events.  Eager launches use `eager`; every graph capture
+  // gets a set of its own, created for it and destroyed with its graph, so
+  // that no event object is ever recorded both outside and inside a
+  // capture, or inside two captures (HIP keeps the capture an event was
+  // last recorded in on the event object itself).
+  struct ForkJoin {
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[SSD_BATCH_MAX_STREAMS] = {};
+  };
+  ForkJoin eager;
+  ForkJoin captured[2][2];              // the events of graph[s][k]
   int nstreams = 1;
   bool tuned = false;
   hipStream_t cap = nullptr;            // capture stream for the step graphs
@@ -1143,13 +1166,36 @@ hipError_t batch_alloc(ssd_batch *b, T **p, size_t count) {
   return e;
 }
 
+void forkjoin_destroy(ssd_batch::ForkJoin &fj) {
+  if (fj.fork) (void)hipEventDestroy(fj.fork);
+  fj.fork = nullptr;
+  for (auto &e : fj.join) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
+}
+
+bool forkjoin_create(ssd_batch::ForkJoin &fj) {
+  if (hipEventCreateWithFlags(&fj.fork, hipEventDisableTiming) != hipSuccess) {
+    fj.fork = nullptr;
+    return false;
+  }
+  for (auto &e : fj.join)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      e = nullptr;
+      forkjoin_destroy(fj);
+      return false;
+    }
+  return true;
+}
+
 void batch_drop_graphs(ssd_batch *b) {
-  for (auto &gs : b->graph)
-    for (auto &g : gs)
-      if (g) {
-        (void)hipGraphExecDestroy(g);
-        g = nullptr;
-      }
+  for (int s = 0; s < 2; ++s)
+    for (int k = 0; k < 2; ++k) {
+      if (b->graph[s][k]) (void)hipGraphExecDestroy(b->graph[s][k]);
+      b->graph[s][k] = nullptr;
+      forkjoin_destroy(b->captured[s][k]);
+    }
 }
 
 void batch_free(ssd_batch *b) {
@@ -1157,9 +1203,7 @@ void batch_free(ssd_batch *b) {
   if (b->cap) (void)hipStreamDestroy(b->cap);
   for (auto &s : b->streams)
     if (s) (void)hipStreamDestroy(s);
-  if (b->fork) (void)hipEventDestroy(b->fork);
-  for (auto &e : b->join)
-    if (e) (void)hipEventDestroy(e);
+  forkjoin_destroy(b->eager);
   for (void *p : b->allocs) (void)hipFree(p);
   b->allocs.clear();
 }
@@ -1253,27 +1297,28 @@ ssd_status group_step(ssd_batch *b, ssd_batch::Group &g, ssd_rk scheme, int *cur
 }
 
 // Fork: the batch streams in use wait for what is queued on `st`.
-ssd_status batch_fork(ssd_batch *b, hipStream_t st) {
-  SSD_HIP(hipEventRecord(b->fork, st), "fork event");
+ssd_status batch_fork(ssd_batch *b, const ssd_batch::ForkJoin &fj, hipStream_t st) {
+  SSD_HIP(hipEventRecord(fj.fork, st), "fork event");
   for (int k = 0; k < b->nstreams; ++k)
-    SSD_HIP(hipStreamWaitEvent(b->streams[k], b->fork, 0), "fork wait");
+    SSD_HIP(hipStreamWaitEvent(b->streams[k], fj.fork, 0), "fork wait");
   return SSD_OK;
 }
 
 // Join: `st` waits for everything queued on the batch streams in use.
-ssd_status batch_join(ssd_batch *b, hipStream_t st) {
+ssd_status batch_join(ssd_batch *b, const ssd_batch::ForkJoin &fj, hipStream_t st) {
   for (int k = 0; k < b->nstreams; ++k) {
-    SSD_HIP(hipEventRecord(b->join[k], b->streams[k]), "join event");
-    SSD_HIP(hipStreamWaitEvent(st, b->join[k], 0), "join wait");
+    SSD_HIP(hipEventRecord(fj.join[k], b->streams[k]), "join event");
+    SSD_HIP(hipStreamWaitEvent(st, fj.join[k], 0), "join wait");
   }
   return SSD_OK;
 }
 
 // nsteps steps of every group, each group on its stream, between a fork
-// from and a join to `st`; the face parity starts and ends at `*cur`
-// (updated).
-ssd_status batch_steps(ssd_batch *b, ssd_rk scheme, int nsteps, int *cur, hipStream_t st) {
-  if (ssd_status e = batch_fork(b, st)) return e;
+// from and a join to `st` with the events fj; the face parity starts and
+// ends at `*cur` (updated).
+ssd_status batch_steps(ssd_batch *b, const ssd_batch::ForkJoin &fj, ssd_rk scheme, int nsteps,
+                       int *cur, hipStream_t st) {
+  if (ssd_status e = batch_fork(b, fj, st)) return e;
   int c_end = *cur;
   for (auto &g : b->groups) {
     int c = *cur;
@@ -1282,7 +1327,7 @@ ssd_status batch_steps(ssd_batch *b, ssd_rk scheme, int nsteps, int *cur, hipStr
     c_end = c;
   }
   *cur = c_end;
-  return batch_join(b, st);
+  return batch_join(b, fj, st);
 }
 
 // Deals the groups to n streams, longest measured stage first, each to the
@@ -1353,11 +1398,11 @@ ssd_status batch_tune(ssd_batch *b, hipStream_t st) {
     float ms = 0.0f;
     result = timed(
         [&]() -> ssd_status {
-          if (ssd_status e = batch_fork(b, st)) return e;
+          if (ssd_status e = batch_fork(b, b->eager, st)) return e;
           for (auto &g : b->groups)
             for (int r = 0; r < kRep; ++r)
               if (ssd_status e = group_stage(b, g, S, b->streams[g.stream])) return e;
-          return batch_join(b, st);
+          return batch_join(b, b->eager, st);
         },
         &ms);
     if (!result && ms < best) {
@@ -1382,6 +1427,9 @@ ssd_status ssd_batch_create(ssd_mesh *const *meshes, int32_t n, ssd_batch **out)
   *out = nullptr;
   for (int c = 0; c < n; ++c) {
     if (!meshes[c]) return fail(SSD_ERR_INVALID_ARG, "null mesh handle in the batch");
+    if (meshes[c]->model)
+      return fail(SSD_ERR_INVALID_ARG,
+                  "a mesh with a learned correction attached cannot be batched");
     if (meshes[c]->device != meshes[0]->device)
       return fail(SSD_ERR_INVALID_ARG, "all meshes of a batch must be on one device");
     for (int d = 0; d < c; ++d)
@@ -1463,11 +1511,7 @@ ssd_status ssd_batch_create(ssd_mesh *const *meshes, int32_t n, ssd_batch **out)
     for (auto &s : b->streams)
       if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(SSD_ERR_DEVICE, "batch streams"));
-    if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
-      return bail(fail(SSD_ERR_DEVICE, "batch events"));
-    for (auto &e : b->join)
-      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
-        return bail(fail(SSD_ERR_DEVICE, "batch events"));
+    if (!forkjoin_create(b->eager)) return bail(fail(SSD_ERR_DEVICE, "batch events"));
   } catch (const std::bad_alloc &) {
     return bail(fail(SSD_ERR_NOMEM, "host allocation failed"));
   }
@@ -1496,6 +1540,9 @@ ssd_status ssd_batch_rk_steps(ssd_batch *b, float *const *q, float *const *work,
   for (int c = 0; c < n; ++c) {
     const ssd_mesh *m = b->meshes[c];
     if (!q[c] || !work[c]) return fail(SSD_ERR_INVALID_ARG, "null state or work pointer");
+    if (m->model)
+      return fail(SSD_ERR_INVALID_ARG,
+                  "a mesh with a learned correction attached cannot be stepped in a batch");
     if (!std::isfinite(t[c]) || !std::isfinite(dt[c]) || !(dt[c] > 0.0))
       return fail(SSD_ERR_INVALID_ARG, "need finite t and dt > 0 for every case");
     const long len = 4L * m->N * m->N * m->E;
@@ -1526,29 +1573,37 @@ ssd_status ssd_batch_rk_steps(ssd_batch *b, float *const *q, float *const *work,
     batch_drop_graphs(b);   // captured before the stream assignment was final
   }
   int cur = 0;
-  if (!use_graph) return batch_steps(b, scheme, nsteps, &cur, st);
-  // graphs of two steps and of one step, each starting at face parity 0;
-  // a step has an odd number of stages, so two steps return to parity 0
-  const int si = scheme == SSD_RK3_SSP ? 0 : 1;
-  for (int k = 0; k < 2; ++k) {
-    if (b->graph[si][k]) continue;
-    hipGraph_t gr = nullptr;
-    SSD_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
-    int c0 = 0;
-    ssd_status e = batch_steps(b, scheme, k ? 2 : 1, &c0, b->cap);
-    hipError_t he = hipStreamEndCapture(b->cap, &gr);
-    if (e) {
-      if (gr) (void)hipGraphDestroy(gr);
-      return e;
+  if (!use_graph) {
+    if (ssd_status e = batch_steps(b, b->eager, scheme, nsteps, &cur, st)) return e;
+  } else {
+    // graphs of two steps and of one step, each starting at face parity 0;
+    // a step has an odd number of stages, so two steps return to parity 0
+    const int si = scheme == SSD_RK3_SSP ? 0 : 1;
+    for (int k = 0; k < 2; ++k) {
+      if (b->graph[si][k]) continue;
+      ssd_batch::ForkJoin &fj = b->captured[si][k];
+      forkjoin_destroy(fj);
+      if (!forkjoin_create(fj)) return fail(SSD_ERR_DEVICE, "batch capture events");
+      hipGraph_t gr = nullptr;
+      SSD_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+      int c0 = 0;
+      ssd_status e = batch_steps(b, fj, scheme, k ? 2 : 1, &c0, b->cap);
+      hipError_t he = hipStreamEndCapture(b->cap, &gr);
+      if (e) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return e;
+      }
+      SSD_HIP(he, "end capture");
+      he = hipGraphInstantiate(&b->graph[si][k], gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      SSD_HIP(he, "graph instantiate");
     }
-    SSD_HIP(he, "end capture");
-    he = hipGraphInstantiate(&b->graph[si][k], gr, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(gr);
-    SSD_HIP(he, "graph instantiate");
+    for (int s = 0; s + 1 < nsteps; s += 2)
+      SSD_HIP(hipGraphLaunch(b->graph[si][1], st), "graph launch");
+    if (nsteps % 2) SSD_HIP(hipGraphLaunch(b->graph[si][0], st), "graph launch");
   }
-  for (int s = 0; s + 1 < nsteps; s += 2)
-    SSD_HIP(hipGraphLaunch(b->graph[si][1], st), "graph launch");
-  if (nsteps % 2) SSD_HIP(hipGraphLaunch(b->graph[si][0], st), "graph launch");
+  // both paths leave every mesh at the rotor angle of its last step, with
+  // its mortars stale, as ssd_rk_steps does
   for (int c = 0; c < n; ++c) {
     ssd_mesh *m = b->meshes[c];
     m->theta = m->theta0 + m->omega0 * (t[c] + nsteps * dt[c]);

@@ -21,6 +21,7 @@ SCHEMES = {"rk3": 0, "rk54": 1}   # ssd_rk
 EXPORTS = ["ssd_create_mesh", "ssd_destroy_mesh", "ssd_query", "ssd_set_rotation",
            "ssd_mortar_rebuild", "ssd_residual", "ssd_rk_step", "ssd_rk_steps", "ssd_check",
            "ssd_last_error", "ssd_timing_enable", "ssd_timing_reset", "ssd_timing_read",
+           "ssd_timing_samples",
            "ssd_batch_create", "ssd_batch_destroy", "ssd_batch_rk_steps", "ssd_batch_query",
            "ssd_mlp_create", "ssd_mlp_destroy", "ssd_mlp_dims", "ssd_mlp_set_params",
            "ssd_mlp_get_params", "ssd_mlp_set_normalization", "ssd_mlp_fit_normalization",
@@ -133,6 +134,8 @@ def lib():
             "ssd_timing_enable": (i32, [vp, ctypes.c_int]),
             "ssd_timing_reset": (i32, [vp]),
             "ssd_timing_read": (i32, [vp, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
+            "ssd_timing_samples": (i32, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_float), i64,
+                                         ctypes.POINTER(i64)]),
             "ssd_batch_create": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]),
             "ssd_batch_destroy": (i32, [vp]),
             "ssd_batch_rk_steps": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -318,6 +321,15 @@ class Mesh:
         n = ctypes.c_int64()
         _check(lib().ssd_timing_read(self._h, KERNELS[kernel], ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def timing_samples(self, kernel):
+        """Durations (ms) of the timed launches of one kernel class since
+        the last reset, in launch order."""
+        n = ctypes.c_int64()
+        _check(lib().ssd_timing_samples(self._h, KERNELS[kernel], None, 0, ctypes.byref(n)))
+        buf = (ctypes.c_float * max(1, n.value))()
+        _check(lib().ssd_timing_samples(self._h, KERNELS[kernel], buf, n.value, ctypes.byref(n)))
+        return np.frombuffer(buf, dtype=np.float32, count=n.value).astype(np.float64)
 
 
 class Batch:

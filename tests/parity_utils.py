@@ -9,10 +9,26 @@ Tolerances (FP32 state and fluxes, FP64 metrics and mortar projections):
   state     per variable, ||Q_gpu - Q_oracle||_2 / ||Q_oracle||_2 <= 1e-5,
             with both momentum components measured against the norm of
             the momentum vector.
+  change    ||dQ_gpu - dQ_oracle||_2 / ||dQ_oracle||_2 over all variables,
+            dQ = Q_end - Q_start: the error of the update itself.  Storing
+            Q in FP32 rounds each value by up to 6e-8 |Q|, and the stored
+            stage values add their own roundings, so the bound is
+            CHANGE_TOL + 1.2e-7 ||Q|| / ||dQ|| (one FP32 ulp; a step that
+            moves Q by 2e-5 of its norm allows 7e-3); half the increment, or
+            none, gives 0.5 or 1.
+  element   per element and variable, max |R_gpu - R_oracle| over the
+            element's points divided by the largest S of that element and
+            variable, <= ELEM_TOL = 1e-4.  FP32 rounding of the O(10^2)
+            operations behind one residual value bounds it by about 1e-5; the
+            L2 norm above would dilute an error confined to a few cells (the
+            64 interface cells of a 384-cell mesh by a factor of 2.4).
 """
 import numpy as np
 
 TOL = 1e-5
+ELEM_TOL = 1e-4
+CHANGE_TOL = 1e-3
+FP32_ROUND = 1.2e-7
 
 
 def residual_error(R_gpu, R_ora, scale):
@@ -28,6 +44,34 @@ def state_error(Q_gpu, Q_ora):
     mom = np.sqrt(np.linalg.norm(Q_ora[1]) ** 2 + np.linalg.norm(Q_ora[2]) ** 2)
     den = [np.linalg.norm(Q_ora[0]), mom, mom, np.linalg.norm(Q_ora[3])]
     return np.array([np.linalg.norm(Q_gpu[v] - Q_ora[v]) / den[v] for v in range(4)])
+
+
+def element_max_error(R_gpu, R_ora, scale, cells=None):
+    """Per variable, the largest over the given cells (all by default) of
+    max |R_gpu - R_ora| / max S within the cell."""
+    R_gpu = np.asarray(R_gpu, dtype=np.float64)
+    if cells is None:
+        cells = np.arange(R_ora.shape[-1])
+    d = np.abs(R_gpu[..., cells] - R_ora[..., cells]).max(axis=(1, 2))
+    s = np.abs(scale[..., cells]).max(axis=(1, 2))
+    return (d / s).max(axis=1)
+
+
+def change_error(Q_gpu, Q_ora, Q_start):
+    """(error of the change, its bound): ||dQ_gpu - dQ_ora|| / ||dQ_ora||
+    over all variables, and CHANGE_TOL + the FP32 rounding of Q relative to
+    the change."""
+    Q_gpu = np.asarray(Q_gpu, dtype=np.float64)
+    do = Q_ora - Q_start
+    err = np.linalg.norm((Q_gpu - Q_start) - do) / np.linalg.norm(do)
+    bound = CHANGE_TOL + FP32_ROUND * np.linalg.norm(Q_ora) / np.linalg.norm(do)
+    return err, bound
+
+
+def interface_cells(mesh):
+    """Elements with a sliding face."""
+    from workloads.meshes import FACE_SLIDING
+    return np.nonzero(np.any(mesh["face_kind"] == FACE_SLIDING, axis=1))[0]
 
 
 def to_gpu(Q, device=0):

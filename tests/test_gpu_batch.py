@@ -1,18 +1,24 @@
 """Batched stepping (ssd_batch_*) of meshes with different N, viscosity,
-sizes and rotation rates against stepping each mesh alone with
-ssd_rk_steps: eager launches and graph replays, SSP-RK3 and SSPRK54, an odd
-number of steps (a two-step graph plus a one-step graph).
+sizes and rotation rates:
 
-The batch forms each stage's rotor angle on the device from t + (n + c) dt
-with a device step counter, the single-mesh path on the host from t + n dt +
-c dt; the results agree to rounding (relative 1e-6), not bit for bit.
+* against the FP64 oracle stepping each case on its own (state and the
+  error of the change, as in the single-mesh parity tests);
+* against stepping each mesh alone with ssd_rk_steps: eager launches and
+  graph replays, SSP-RK3 and SSPRK54, an odd number of steps (a two-step
+  graph plus a one-step graph).  The batch forms each stage's rotor angle
+  on the device from t + (n + c) dt with a device step counter, the
+  single-mesh path on the host from t + n dt + c dt; the results agree to
+  rounding (relative 1e-6), not bit for bit;
+* after a batch call every mesh is at its final rotor angle with stale
+  mortars, as after ssd_rk_steps; meshes with a learned correction attached
+  are refused.
 """
 import numpy as np
 import pytest
 
 from oracle.exact import Couette, vortex_state
 from oracle.ssd import SSD
-from tests.parity_utils import from_gpu, state_error, to_gpu
+from tests.parity_utils import TOL, change_error, from_gpu, state_error, to_gpu
 from workloads import cases as C
 from workloads import meshes as M
 
@@ -39,7 +45,12 @@ def _cases():
         case = C.couette_case()
         mesh = M.couette_mesh(nr, 4 * nr, phi_offset=0.23)
         x, y = SSD(mesh, case, N).sp_coords(0.0)
-        out.append((mesh, case, N, Couette(case).state(x, y), 0.1, 2e-3))
+        # the exact steady state, perturbed so that the steps change it
+        Q = Couette(case).state(x, y)
+        for v, (a, b, c) in enumerate(((1.1, 0.7, 0.2), (0.6, 1.3, 1.0), (0.9, 0.5, 2.1),
+                                        (1.4, 0.8, 0.4))):
+            Q[v] *= 1.0 + 0.02 * np.sin(a * x + b * y + c)
+        out.append((mesh, case, N, Q, 0.1, 2e-3))
     case = C.vortex_case(omega=0.8)
     case["vortex"]["period"] = 100.0
     case["vortex"]["center"] = (1.5, 1.0)
@@ -96,4 +107,93 @@ def test_batch_matches_single_meshes(torch_cuda, scheme, graph):
         err = state_error(from_gpu(qs[k], cs[k][2], gm.info["n_elem"]),
                           from_gpu(q, cs[k][2], gm.info["n_elem"]))
         assert np.all(err < 1e-6), (k, err)
+    batch.close()
+
+
+@pytest.mark.parametrize("scheme", ["rk3", "rk54"])
+def test_batch_matches_oracle(torch_cuda, scheme):
+    """Every case of the mixed batch (graph replays) against the oracle's
+    own run of that case."""
+    import torch
+    from paper_1503_02198_amd import Batch, Mesh
+    print(f"case: batch of 6 meshes vs the oracle, {scheme}", flush=True)
+    cs = _cases()
+    meshes = [Mesh(m, c, N, device=0) for m, c, N, _, _, _ in cs]
+    nsteps = 5
+    batch = Batch(meshes)
+    qs = [to_gpu(Q) for _, _, _, Q, _, _ in cs]
+    ws = [torch.empty(gm.info["work_len"], dtype=torch.float32, device="cuda:0") for gm in meshes]
+    batch.rk_steps(qs, ws, [c[4] for c in cs], [c[5] for c in cs], nsteps, scheme=scheme,
+                   graph=True)
+    for gm in meshes:
+        gm.check()
+    for k, (gm, (m, c, N, Q, t0, dt)) in enumerate(zip(meshes, cs)):
+        Qo = SSD(m, c, N).run(Q, t0, dt, nsteps, scheme=scheme)
+        Qg = from_gpu(qs[k], N, gm.info["n_elem"])
+        err = state_error(Qg, Qo)
+        ch, bound = change_error(Qg, Qo, Q)
+        print(k, "N", N, "state error", err, "error of the change", ch, "bound", bound,
+              flush=True)
+        assert np.all(err <= TOL), (k, err)
+        assert ch <= bound, (k, ch, bound)
+    batch.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_leaves_meshes_at_final_angle(torch_cuda, graph):
+    """After a batch call, a mesh with sliding rings refuses a residual until
+    its mortars are rebuilt, and the rebuilt mortars are those of the angle
+    theta0 + omega (t + nsteps dt)."""
+    import torch
+    from paper_1503_02198_amd import Batch, Mesh
+    from paper_1503_02198_amd.ssd import SSDError
+    print(f"case: batch final angle, graph={graph}", flush=True)
+    cs = _cases()[:2]
+    meshes = [Mesh(m, c, N, device=0) for m, c, N, _, _, _ in cs]
+    batch = Batch(meshes)
+    qs = [to_gpu(Q) for _, _, _, Q, _, _ in cs]
+    ws = [torch.empty(gm.info["work_len"], dtype=torch.float32, device="cuda:0") for gm in meshes]
+    nsteps = 3
+    batch.rk_steps(qs, ws, [c[4] for c in cs], [c[5] for c in cs], nsteps, graph=graph)
+    for gm, q, (m, c, N, Q, t0, dt) in zip(meshes, qs, cs):
+        r = torch.empty_like(q)
+        with pytest.raises(SSDError) as ei:
+            gm.residual(q, r)
+        assert ei.value.status == -3
+        gm.mortar_rebuild()
+        gm.residual(q, r)
+        theta = c["theta0"] + c["omega"] * (t0 + nsteps * dt)
+        gm.set_rotation(theta, c["omega"])
+        gm.mortar_rebuild()
+        r2 = torch.empty_like(q)
+        gm.residual(q, r2)
+        torch.cuda.synchronize()
+        assert torch.equal(r, r2)
+    batch.close()
+
+
+def test_batch_refuses_attached_correction(torch_cuda):
+    import torch
+    from paper_1503_02198_amd import MLP, Batch, Mesh
+    from paper_1503_02198_amd.ssd import SSDError
+    print("case: batch with an attached learned correction", flush=True)
+    cs = _cases()[:2]
+    meshes = [Mesh(m, c, N, device=0) for m, c, N, _, _, _ in cs]
+    net = MLP(3)
+    meshes[1].attach(net)
+    with pytest.raises(SSDError) as ei:
+        Batch(meshes)
+    assert ei.value.status == -1
+    meshes[1].attach(None)
+    batch = Batch(meshes)
+    meshes[0].attach(net)
+    qs = [to_gpu(Q) for _, _, _, Q, _, _ in cs]
+    ws = [torch.empty(gm.info["work_len"], dtype=torch.float32, device="cuda:0") for gm in meshes]
+    with pytest.raises(SSDError) as ei:
+        batch.rk_steps(qs, ws, [c[4] for c in cs], [c[5] for c in cs], 1)
+    assert ei.value.status == -1
+    meshes[0].attach(None)
+    batch.rk_steps(qs, ws, [c[4] for c in cs], [c[5] for c in cs], 1)
+    for gm in meshes:
+        gm.check()
     batch.close()

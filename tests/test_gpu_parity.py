@@ -7,7 +7,8 @@ import pytest
 
 from oracle.exact import vortex_state
 from oracle.ssd import SSD
-from tests.parity_utils import TOL, gpu_residual, gpu_run, residual_error, state_error, to_gpu
+from tests.parity_utils import (ELEM_TOL, TOL, change_error, element_max_error, gpu_residual,
+                                gpu_run, interface_cells, residual_error, state_error, to_gpu)
 from workloads import cases as C
 from workloads import meshes as M
 
@@ -43,8 +44,30 @@ def test_residual_vortex(torch_cuda, theta):
     Rg = gpu_residual(gm, Q, theta, case["omega"])
     Ro, diag = ora.residual(Q, theta, case["omega"], diag=True)
     err = residual_error(Rg, Ro, diag["flux_scale"])
-    print("residual error", err)
+    emax = element_max_error(Rg, Ro, diag["flux_scale"], interface_cells(mesh))
+    print("residual error", err, "interface cells, element maximum", emax)
     assert np.all(err <= TOL), err
+    assert np.all(emax <= ELEM_TOL), emax
+
+
+@pytest.mark.parametrize("N", [2, 4, 5, 6])
+def test_residual_vortex_sliding_all_orders(torch_cuda, N):
+    """The inviscid sliding mortar at every other order, at a zero offset,
+    a mid-face offset and just below a whole face width; the interface
+    cells are compared element by element."""
+    mesh, case, ora, Q = _vortex(N=N)
+    gm = _mesh(mesh, case, N)
+    sl = interface_cells(mesh)
+    for theta in (0.0, 0.083, 2 * np.pi / 32 - 1e-3):
+        print(f"case: vortex residual N={N} theta={theta}", flush=True)
+        Rg = gpu_residual(gm, Q, theta, case["omega"])
+        Ro, diag = ora.residual(Q, theta, case["omega"], diag=True)
+        err = residual_error(Rg, Ro, diag["flux_scale"])
+        emax = element_max_error(Rg, Ro, diag["flux_scale"], sl)
+        eall = element_max_error(Rg, Ro, diag["flux_scale"])
+        print("residual error", err, "interface element maximum", emax, "all cells", eall)
+        assert np.all(err <= TOL), err
+        assert np.all(emax <= ELEM_TOL) and np.all(eall <= ELEM_TOL), (emax, eall)
 
 
 @pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
@@ -80,8 +103,10 @@ def test_residual_relabelled_sliding_mesh(torch_cuda, N):
         Rg = gpu_residual(gm, Q, th, 0.5)
         Ro, diag = ora.residual(Q, th, 0.5, diag=True)
         err = residual_error(Rg, Ro, diag["flux_scale"])
-        print("theta", th, "residual error", err)
+        emax = element_max_error(Rg, Ro, diag["flux_scale"], interface_cells(mesh))
+        print("theta", th, "residual error", err, "interface element maximum", emax)
         assert np.all(err <= TOL), err
+        assert np.all(emax <= ELEM_TOL), emax
 
 
 def test_rk3_vortex_100_steps(torch_cuda):
@@ -92,9 +117,15 @@ def test_rk3_vortex_100_steps(torch_cuda):
     Qg = gpu_run(gm, Q, 0.0, 1e-3, 100)
     Qo = ora.run(Q, 0.0, 1e-3, 100)
     err = state_error(Qg, Qo)
-    pert = np.linalg.norm(Qg - Qo) / np.linalg.norm(Qo - Q)
-    print("state error", err, "relative to the change", pert)
+    ch, bound = change_error(Qg, Qo, Q)
+    # interface cells, element by element, against the largest change
+    sl = interface_cells(mesh)
+    dmax = np.abs(Qg[..., sl] - Qo[..., sl]).max() / np.abs(Qo - Q).max()
+    print("state error", err, "error of the change", ch, "bound", bound,
+          "interface cells, largest error / largest change", dmax)
     assert np.all(err <= TOL), err
+    assert ch <= bound, (ch, bound)
+    assert dmax <= 1e-3, dmax
 
 
 def test_rk3_vortex_offset_wraps(torch_cuda):
@@ -105,8 +136,10 @@ def test_rk3_vortex_offset_wraps(torch_cuda):
     Qg = gpu_run(gm, Q, 0.0, 2e-3, 30)
     Qo = ora.run(Q, 0.0, 2e-3, 30)
     err = state_error(Qg, Qo)
-    print("state error", err)
+    ch, bound = change_error(Qg, Qo, Q)
+    print("state error", err, "error of the change", ch, "bound", bound)
     assert np.all(err <= TOL), err
+    assert ch <= bound, (ch, bound)
 
 
 def test_deterministic_and_restartable(torch_cuda):
@@ -238,9 +271,10 @@ def test_ssprk54_vortex_steps(torch_cuda):
     Qg = gpu_run(gm, Q, 0.0, 2e-3, 40, scheme="rk54")
     Qo = ora.run(Q, 0.0, 2e-3, 40, scheme="rk54")
     err = state_error(Qg, Qo)
-    print("state error", err, "relative to the change",
-          np.linalg.norm(Qg - Qo) / np.linalg.norm(Qo - Q), flush=True)
+    ch, bound = change_error(Qg, Qo, Q)
+    print("state error", err, "error of the change", ch, "bound", bound, flush=True)
     assert np.all(err <= TOL), err
+    assert ch <= bound, (ch, bound)
 
 
 def test_ssprk54_rk_steps_equals_repeated(torch_cuda):

@@ -190,6 +190,40 @@ def test_residual_continuous_across_wrap():
     assert np.abs(R1 - R2).max() < 1e-6 * np.abs(R1).max()
 
 
+# ------------------------------------------------------------ exact vortex
+@pytest.mark.parametrize("case_fn", [C.vortex_case, C.paper_vortex_case])
+def test_vortex_state_solves_euler(case_fn):
+    """The exact vortex (Sec. 4.1) with the workload's parameters and with
+    the paper's own (epsilon = 1, Mach 0.3, mean flow at arctan(1/2)): the
+    Euler equations dQ/dt + dF/dx + dG/dy = 0 hold at random points, by
+    fourth-order central differences in x, y and t of the closed form."""
+    case = case_fn()
+    g = case["gamma"]
+    rng = np.random.default_rng(4)
+    x, y = rng.uniform(-2.5, 2.5, (2, 200))
+    t, h = 0.37, 1e-3
+
+    def d(fn, k):
+        e = np.zeros(3)
+        e[k] = h
+        a = lambda s: fn(x + s * e[0], y + s * e[1], t + s * e[2])
+        return (8 * (a(1) - a(-1)) - (a(2) - a(-2))) / (12 * h)
+    Q = lambda xx, yy, tt: vortex_state(xx, yy, tt, case)
+    F = lambda xx, yy, tt: ph.inviscid_flux(Q(xx, yy, tt), g)[0]
+    G = lambda xx, yy, tt: ph.inviscid_flux(Q(xx, yy, tt), g)[1]
+    res = d(Q, 2) + d(F, 0) + d(G, 1)
+    scale = np.abs(d(F, 0)).max(axis=1)
+    assert np.all(np.abs(res).max(axis=1) < 1e-7 * scale), np.abs(res).max(axis=1) / scale
+    # the vortex moves with the mean flow: at the centre after time t the
+    # velocity is the far-field velocity and the density is at its minimum
+    rho_inf, u_inf, v_inf, _ = case["farfield"]
+    xc, yc = np.array(case["vortex"]["center"]) + t * np.array([u_inf, v_inf])
+    q = Q(np.array([xc]), np.array([yc]), t)
+    assert abs(q[1, 0] / q[0, 0] - u_inf) < 1e-12 and abs(q[2, 0] / q[0, 0] - v_inf) < 1e-12
+    ring = Q(xc + 0.3 * np.cos(np.linspace(0, 6, 7)), yc + 0.3 * np.sin(np.linspace(0, 6, 7)), t)
+    assert np.all(ring[0] > q[0, 0])
+
+
 # ------------------------------------------------------------ truncation error
 @pytest.mark.parametrize("N,min_order", [(3, 1.4), (4, 2.2)])
 def test_vortex_truncation_error_decays(N, min_order):

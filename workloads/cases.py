@@ -28,6 +28,19 @@ def vortex_case(omega=0.5, theta0=0.0):
                 vortex=dict(beta=5.0, mach=0.5, center=(0.0, 0.0), period=10.0))
 
 
+def paper_vortex_case(omega=1.0, theta0=0.0, mach=0.3, epsilon=1.0, direction=np.arctan(0.5)):
+    """The paper's own vortex test (Sec. 4.1): U = rho = 1, Mach 0.3, mean
+    flow at angle arctan(1/2), strength epsilon = 1, r_c = 1, period 10,
+    inner disk rotating at omega = 1.  The printed p = 1 would make the
+    Mach number 0.85; p = 1 / (gamma M^2) keeps M = 0.3 (so T = 1 with
+    R = p)."""
+    p = 1.0 / (GAMMA * mach ** 2)
+    return dict(gamma=GAMMA, gas_R=p, mu=0.0, prandtl=0.72, T_wall=1.0,
+                farfield=(1.0, float(np.cos(direction)), float(np.sin(direction)), p),
+                omega=float(omega), theta0=float(theta0),
+                vortex=dict(epsilon=float(epsilon), center=(0.0, 0.0), period=10.0))
+
+
 def couette_case(mach_wall=0.1, reynolds=10.0, prandtl=0.72, omega=1.0, r_in=1.0):
     """Taylor-Couette flow: inner wall speed omega*r_in = 1 at Mach
     `mach_wall`, Re based on r_in and the wall speed, constant viscosity."""
