@@ -207,6 +207,27 @@ ssd_status ssd_rk_steps(ssd_mesh *m, float *q, float *work, double t, double dt,
                         ssd_rk scheme, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * steps as ssd_rk_steps, with the work arrays taken from a fixed array of
+ * SSD_SCRATCH_BYTES per GPU that the library holds until the process ends
+ * (set up by ssd_create_mesh on its device).  The call allocates nothing.
+ * Limits and sharing:
+ *   - the scheme's work arrays (2 state_len floats for SSP-RK3, 3 for
+ *     SSPRK54) must fit in SSD_SCRATCH_BYTES, else SSD_ERR_INVALID_ARG with
+ *     no work enqueued;
+ *   - kernel timing must be off (ssd_timing_enable(m, 0)), else
+ *     SSD_ERR_STATE: the timers may create events;
+ *   - every call on one GPU uses that GPU's one array, which keeps the
+ *     last call's contents (nothing in it needs to start at zero): calls
+ *     that overlap on one GPU (other streams, other threads, other meshes)
+ *     race and must be serialised by the caller.
+ */
+#define SSD_SCRATCH_BYTES (64u << 20)
+ssd_status ssd_rk_steps_noalloc(ssd_mesh *m, float *q, double t, double dt, int32_t nsteps,
+                                ssd_rk scheme, void *stream);
+
+/*
  * Synchronises `stream` and reports SSD_ERR_NUMERIC if any stage since the
  * last check produced a non-finite value, rho <= 0 or p <= 0; clears the
  * flag.
@@ -305,6 +326,7 @@ ssd_status ssd_timing_read(ssd_mesh *m, int kernel, double *total_ms, int64_t *l
  * count.  Synchronises the device.  Errors: SSD_ERR_INVALID_ARG for a bad
  * class, cap < 0, or a null ms with cap > 0. */
 ssd_status ssd_timing_samples(ssd_mesh *m, int kernel, float *ms, int64_t cap, int64_t *launches);
+
 
 /*
  * Learned per-element subgrid correction (an extension of the method; not

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -46,6 +47,32 @@ struct DeviceGuard {
 
 constexpr double PI = 3.14159265358979323846;
 const int FACE_CORNERS[4][2] = {{0, 3}, {3, 6}, {9, 6}, {0, 9}};
+
+// ---------------------------------------------------------------------------
+// Work arrays of ssd_rk_steps_noalloc: one fixed array per GPU, in the code
+// object's device memory, held until the process ends.  In host code
+// `scratch` names a host-side stand-in: kernels and copies get the device
+// address that hipGetSymbolAddress returns for the current device, looked
+// up once per device when the first mesh is created there.
+// ---------------------------------------------------------------------------
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) float scratch[SSD_SCRATCH_BYTES / sizeof(float)];
+float *g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// With `device` current: records the device address of its scratch array.
+ssd_status scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices)
+    return fail(SSD_ERR_DEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return SSD_OK;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(SSD_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch[device] = static_cast<float *>(p);
+  return SSD_OK;
+}
 
 // ---------------------------------------------------------------------------
 // 1-D operators (Sec. 3.1)
@@ -858,6 +885,7 @@ ssd_status ssd_create_mesh(const ssd_mesh_desc *d, int device, ssd_mesh **out) {
   if (device < 0 || device >= ndev) return fail(SSD_ERR_INVALID_ARG, "device out of range");
   DeviceGuard guard(device);
   if (!guard.ok) return fail(SSD_ERR_DEVICE, "hipSetDevice failed");
+  if (ssd_status e = scratch_setup(device)) return e;
   ssd_mesh *m = new (std::nothrow) ssd_mesh();
   if (!m) return fail(SSD_ERR_NOMEM, "host allocation failed");
   m->device = device;
@@ -1046,6 +1074,23 @@ ssd_status ssd_rk_steps(ssd_mesh *m, float *q, float *work, double t, double dt,
 ssd_status ssd_rk_step(ssd_mesh *m, float *q, float *work, double t, double dt, ssd_rk scheme,
                        void *stream) {
   return ssd_rk_steps(m, q, work, t, dt, 1, scheme, stream);
+}
+
+ssd_status ssd_rk_steps_noalloc(ssd_mesh *m, float *q, double t, double dt, int32_t nsteps,
+                                ssd_rk scheme, void *stream) {
+  if (ssd_status s = check_handle(m)) return s;
+  const size_t len = size_t(4) * m->N * m->N * m->E;
+  const size_t nwork = scheme == SSD_RK3_SSP ? 2 : 3;
+  if (nwork * len * sizeof(float) > size_t(SSD_SCRATCH_BYTES))
+    return fail(SSD_ERR_INVALID_ARG,
+                "the mesh needs " + std::to_string(nwork * len * sizeof(float)) +
+                    " bytes of work arrays for this scheme; the scratch array holds " +
+                    std::to_string(size_t(SSD_SCRATCH_BYTES)) + " (use ssd_rk_steps)");
+  // the stage timers create HIP events when their pool runs out
+  if (m->timing) return fail(SSD_ERR_STATE, "turn kernel timing off for ssd_rk_steps_noalloc");
+  float *w = (m->device >= 0 && m->device < kMaxDevices) ? g_scratch[m->device] : nullptr;
+  if (!w) return fail(SSD_ERR_DEVICE, "scratch array of the mesh's device not set up");
+  return ssd_rk_steps(m, q, w, t, dt, nsteps, scheme, stream);
 }
 
 ssd_status ssd_check(ssd_mesh *m, void *stream) {

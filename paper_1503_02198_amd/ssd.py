@@ -19,7 +19,8 @@ STATUS = {0: "SSD_OK", -1: "SSD_ERR_INVALID_ARG", -2: "SSD_ERR_MESH", -3: "SSD_E
 KERNELS = {"stage": 0, "traces": 1, "mortar": 2, "rebuild": 3, "grad": 4}
 SCHEMES = {"rk3": 0, "rk54": 1}   # ssd_rk
 EXPORTS = ["ssd_create_mesh", "ssd_destroy_mesh", "ssd_query", "ssd_set_rotation",
-           "ssd_mortar_rebuild", "ssd_residual", "ssd_rk_step", "ssd_rk_steps", "ssd_check",
+           "ssd_mortar_rebuild", "ssd_residual", "ssd_rk_step", "ssd_rk_steps",
+           "ssd_rk_steps_noalloc", "ssd_check",
            "ssd_last_error", "ssd_timing_enable", "ssd_timing_reset", "ssd_timing_read",
            "ssd_timing_samples",
            "ssd_batch_create", "ssd_batch_destroy", "ssd_batch_rk_steps", "ssd_batch_query",
@@ -129,6 +130,7 @@ def lib():
             "ssd_residual": (i32, [vp, vp, vp, vp]),
             "ssd_rk_step": (i32, [vp, vp, vp, dbl, dbl, ctypes.c_int, vp]),
             "ssd_rk_steps": (i32, [vp, vp, vp, dbl, dbl, i32, ctypes.c_int, vp]),
+            "ssd_rk_steps_noalloc": (i32, [vp, vp, dbl, dbl, i32, ctypes.c_int, vp]),
             "ssd_check": (i32, [vp, vp]),
             "ssd_last_error": (ctypes.c_char_p, []),
             "ssd_timing_enable": (i32, [vp, ctypes.c_int]),
@@ -280,6 +282,13 @@ class Mesh:
                                   self._tensor(work, self.info["work_len"], "work"),
                                   float(t), float(dt), int(nsteps), SCHEMES[scheme],
                                   _stream_ptr(stream, self.device)))
+
+    def rk_steps_noalloc(self, q, t, dt, nsteps, stream=None, scheme="rk3"):
+        """rk_steps with the library's fixed per-GPU work array instead of a
+        caller's work tensor (ssd_rk_steps_noalloc)."""
+        _check(lib().ssd_rk_steps_noalloc(self._h, self._tensor(q, self.info["state_len"], "q"),
+                                          float(t), float(dt), int(nsteps), SCHEMES[scheme],
+                                          _stream_ptr(stream, self.device)))
 
     def check(self, stream=None):
         _check(lib().ssd_check(self._h, _stream_ptr(stream, self.device)))
