@@ -204,8 +204,10 @@ def subgrid_main(args):
     from paper_1503_02198_amd import subgrid as G
     log = lambda m: print("# " + m, file=sys.stderr, flush=True)
     cfg = dict(K=64, n_in=8, n_out=16, runs=4, snapshots=500, window=(0.5, 1.0), epochs=40,
-               batch=4096, lr=2e-3, noise=0.1, eval_window=(0.5, 0.6), seed=20150307,
-               per_step=True)
+               batch=4096, lr=2e-3, noise=0.1, eval_window=(args.eval_t0, args.eval_t1),
+               seed=20150307, per_step=True, rounds=args.aposteriori_rounds,
+               traj_snapshots=250, relax_rate=args.relax_rate, retrain=not args.resume,
+               ft_epochs=args.ft_epochs, ft_lr=1e-3)
     meshes = G.ellipse_pair(cfg["K"], cfg["n_in"], cfg["n_out"])
     rng = np.random.default_rng(cfg["seed"])
     rates = rng.uniform(0.5, 2.0, cfg["runs"])
@@ -217,10 +219,40 @@ def subgrid_main(args):
     losses, train_s = G.train(net, X, T, cfg["epochs"], cfg["batch"], cfg["lr"], seed=7,
                               noise=cfg["noise"])
     log(f"training loss {losses[0]:.4e} -> {losses[-1]:.4e} in {train_s:.2f} s")
+    steps = cfg["epochs"] * (rows // cfg["batch"])
+    rounds = []
+    if cfg["rounds"]:
+        # the network trained on the fine runs alone, evaluated for comparison
+        res0 = G.evaluate(meshes, net, G.convective_omega(rate_eval), *cfg["eval_window"],
+                          weights=(1.0,), per_step=cfg["per_step"])
+        rounds.append({"round": 0, "err": res0["learned"][0]["err"],
+                       "fallback": res0["learned"][0]["fallback"], "training_rows": rows})
+    # a posteriori rounds: rows along the corrected coarse runs, added to the
+    # data, and training continued on all of it
+    for r in range(cfg["rounds"]):
+        Xt, Tt, gs, restarts = G.generate_trajectory(
+            meshes, G.convective_omega(rates), net, cfg["window"][0], cfg["window"][1],
+            cfg["traj_snapshots"], cfg["relax_rate"], per_step=cfg["per_step"], log=log)
+        X, T = torch.cat([X, Xt]), torch.cat([T, Tt])
+        del Xt, Tt
+        rows = X.numel() // 84
+        gen_s += gs
+        if cfg["retrain"]:    # fresh weights and normalisation on all rows so far
+            ls, ts = G.train(net, X, T, cfg["epochs"], cfg["batch"], cfg["lr"], seed=11 + r,
+                             noise=cfg["noise"])
+        else:                 # continue from the current weights
+            ls, ts = G.train(net, X, T, cfg["ft_epochs"], cfg["batch"], cfg["ft_lr"],
+                             seed=11 + r, noise=cfg["noise"], resume=True)
+        train_s += ts
+        steps += (cfg["epochs"] if cfg["retrain"] else cfg["ft_epochs"]) * (rows // cfg["batch"])
+        log(f"round {r + 1}: {rows} rows, loss {ls[0]:.4e} -> {ls[-1]:.4e} in {ts:.2f} s")
+        rounds.append({"round": r + 1, "training_rows": rows, "restarts": restarts,
+                       "loss_last_epoch": ls[-1]})
     res = G.evaluate(meshes, net, G.convective_omega(rate_eval), *cfg["eval_window"],
                      weights=(1.0,), per_step=cfg["per_step"])
     sp = G.speedup_at_equal_error(res)[0]
-    steps = cfg["epochs"] * (rows // cfg["batch"])
+    if rounds:
+        rounds[-1]["err"] = res["learned"][0]["err"]
     print(json.dumps({
         "metric": "learned-coarse vs plain SSD: wall-clock speedup at equal error",
         "value": sp["speedup"], "unit": "x", "n_gpus": 1, "higher_is_better": True,
@@ -236,8 +268,48 @@ def subgrid_main(args):
         "fallback": res["learned"][0]["fallback"],
         "training": {"loss_first_epoch": losses[0], "loss_last_epoch": losses[-1],
                      "steps": steps, "seconds": train_s,
-                     "samples_per_s": steps * cfg["batch"] / train_s},
+                     "samples_per_s": steps * cfg["batch"] / train_s,
+                     "aposteriori_rounds": rounds},
         "data_generation_s": gen_s}), flush=True)
+
+
+def contraction_probe_main(args):
+    """The per-cell contractions (interpolation to the flux points, a
+    pointwise flux, the derivative back) on the stage kernel's layout, as
+    vector fused multiply-adds and on the matrix cores (FP32 MFMA), for the
+    choice between the two: time per launch and agreement of the results."""
+    import torch
+    from paper_1503_02198_amd import Mesh
+    from workloads import cases as C
+    from workloads import meshes as M
+    gm = Mesh(M.box_mesh(2, 2), C.vortex_case(), 4, device=0)   # supplies the N = 4 operators
+    cells, reps = 999424, args.probe_reps
+    g = torch.Generator().manual_seed(20150307)
+    q = (1.0 + 0.1 * torch.rand(64 * cells, generator=g)).to("cuda:0")
+    outs, ms = [], []
+    for variant in (0, 1):
+        out = torch.empty_like(q)
+        for _ in range(3):
+            gm.probe_contraction(variant, cells, reps, q, out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        n = args.probe_launches
+        e0.record()
+        for _ in range(n):
+            gm.probe_contraction(variant, cells, reps, q, out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1) / n)
+        outs.append(out)
+    diff = float(((outs[1] - outs[0]).abs().max() / outs[0].abs().max()).item())
+    # useful flops per launch: per cell, line and variable and round, 5 x 4
+    # multiply-adds to interpolate, 5 products, 4 x 5 to differentiate
+    flops = cells * 4 * 4 * reps * (2 * 20 + 5 + 2 * 20)
+    print(json.dumps({"metric": "contraction probe (N = 4, FP32)", "cells": cells, "reps": reps,
+                      "valu_us": 1e3 * ms[0], "mfma_us": 1e3 * ms[1],
+                      "valu_tflops": flops / (ms[0] * 1e-3) / 1e12,
+                      "mfma_tflops": flops / (ms[1] * 1e-3) / 1e12,
+                      "mfma_over_valu_time": ms[1] / ms[0], "max_rel_diff": diff}), flush=True)
 
 
 def traffic_for(kind_hash, E, N):
@@ -427,8 +499,24 @@ def main():
                     help="the 64-case batch workload instead of the headline run")
     ap.add_argument("--subgrid", action="store_true",
                     help="the learned-correction workload (training data, training, evaluation)")
+    ap.add_argument("--aposteriori-rounds", type=int, default=2,
+                    help="learned-correction workload: rounds of training on rows taken along "
+                         "the corrected coarse runs")
+    ap.add_argument("--relax-rate", type=float, default=0.0,
+                    help="relaxation rate towards the restricted fine state in the a posteriori "
+                         "targets (0: none)")
+    ap.add_argument("--resume", action="store_true",
+                    help="a posteriori rounds continue from the current weights instead of "
+                         "training afresh on all rows")
+    ap.add_argument("--ft-epochs", type=int, default=15)
+    ap.add_argument("--eval-t0", type=float, default=0.5)
+    ap.add_argument("--eval-t1", type=float, default=0.7)
     ap.add_argument("--mlp-kernels", action="store_true",
                     help="throughput of the learned-correction kernels on seeded random rows")
+    ap.add_argument("--contraction-probe", action="store_true",
+                    help="vector-ALU vs matrix-core (FP32 MFMA) per-cell contractions")
+    ap.add_argument("--probe-reps", type=int, default=16)
+    ap.add_argument("--probe-launches", type=int, default=20)
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV",
                                                           "CALIB_FETCH_CSV", "CALIB_WRITE_CSV"))
     args = ap.parse_args()
@@ -455,6 +543,9 @@ def main():
         return
     if args.mlp_kernels:
         mlp_kernels_main(args)
+        return
+    if args.contraction_probe:
+        contraction_probe_main(args)
         return
 
     from paper_1503_02198_amd import Mesh, pack_state, unpack_state

@@ -248,9 +248,15 @@ const char *ssd_last_error(void);
  * group's step counter.  Groups share no data, so each group's
  * whole chain of launches runs on one of up to SSD_BATCH_MAX_STREAMS
  * streams, forked from and joined back to the caller's stream.  On the
- * first call an autotuner times every group's stage alone, then the
- * stage of the whole batch with 1, 2, ... streams (groups dealt to streams
- * longest first by their measured times), and keeps the fastest.  With
+ * first call an autotuner picks, per group, the tile shape of the stage
+ * launch (one or, for N <= 4, two 64-cell tiles per block: the faster by at
+ * least 3 %, remembered for the process by (N, viscous, log2 of the
+ * group's tile count) and reused by later batches), then times the stage of
+ * the whole batch with 1, 2, ... streams (groups dealt to streams longest
+ * first by their measured times) and keeps the most streams within 3 % of
+ * the fastest (the trials are eager launches, whose per-stream fork and
+ * join a replayed graph does not pay); every time is the median of 5
+ * trials.  With
  * use_graph, one and two steps are captured as HIP graphs on the first call
  * for a scheme and replayed; the stage time is read from a device step
  * counter per group, so the graphs do not depend on t.
@@ -272,6 +278,9 @@ typedef struct {
   int32_t n_streams;    /* streams the batch uses (1..SSD_BATCH_MAX_STREAMS)   */
   int32_t tuned;        /* 1 once the autotuner has run                        */
   float stage_us;       /* the group's stage alone, as timed by the autotuner  */
+  int32_t tiles_per_block;   /* 64-cell tiles per block of the stage launch */
+  float stage_us_tpb[2];     /* the stage alone with 1 and 2 tiles per block
+                                (0: not timed; the choice was known)        */
 } ssd_batch_group;
 
 /* n >= 1 distinct meshes, all on one device, none with a learned correction
@@ -326,6 +335,22 @@ ssd_status ssd_timing_read(ssd_mesh *m, int kernel, double *total_ms, int64_t *l
  * count.  Synchronises the device.  Errors: SSD_ERR_INVALID_ARG for a bad
  * class, cap < 0, or a null ms with cap > 0. */
 ssd_status ssd_timing_samples(ssd_mesh *m, int kernel, float *ms, int64_t cap, int64_t *launches);
+/*
+ * Measurement probe for the choice between vector ALUs and matrix cores
+ * for the per-cell contractions of the flux-point method (Sec. 3.1 eqs. Qt,
+ * Ft, Gt), on the stage kernel's data layout (64 cells per wave, one line
+ * per wave): `reps` rounds of interpolation to the flux points of a line
+ * (the mesh's N = 4 operator I), the pointwise flux q^2, and the derivative
+ * back to the solution points (operator D), per cell and variable.
+ * variant 0 runs them as fused multiply-adds per lane, variant 1 on
+ * v_mfma_f32_16x16x4_f32 with 16 cells per matrix.  q and out (device) are
+ * [4][4 lines][4 points][n_cells] floats, cell index fastest; n_cells is a
+ * positive multiple of 64.  Not part of the method: its result is only
+ * compared between the variants.  Errors: SSD_ERR_INVALID_ARG (mesh N != 4,
+ * bad variant, n_cells or reps).
+ */
+ssd_status ssd_probe_contraction(ssd_mesh *m, int32_t variant, int32_t n_cells, int32_t reps,
+                                 const float *q, float *out, void *stream);
 
 
 /*
@@ -446,6 +471,16 @@ ssd_status ssd_restrict(const ssd_mesh *fine, const ssd_mesh *coarse, const int3
 ssd_status ssd_subgrid_targets(const ssd_mesh *fine, const ssd_mesh *coarse,
                                const int32_t *children, const float *Rf, const float *Rc, float *T,
                                void *stream);
+
+/* Relaxation term of training targets taken along a corrected coarse run
+ * (a posteriori training): T [E][4 N^2] (rows as in ssd_subgrid_targets)
+ * += rate (q_ref - q), with q_ref (the restricted fine state) and q (the
+ * coarse run's state) device arrays in the state layout of `coarse`.  With
+ * T = restrict(Rf) - Rc(q) the target is the correction that also pulls q
+ * back to q_ref at the given rate.  Errors: SSD_ERR_INVALID_ARG (null
+ * array, non-finite rate). */
+ssd_status ssd_subgrid_nudge(const ssd_mesh *coarse, const float *q_ref, const float *q, float rate,
+                             float *T, void *stream);
 
 /* Attaches `net` (same N and device) to mesh m with weight w (finite): from
  * then on ssd_rk_step(s) with SSD_RK3_SSP adds w C(Q) to dQ/dt in every

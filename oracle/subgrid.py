@@ -135,6 +135,19 @@ def targets(ssd_f, ssd_c, children, Qf, theta, omega):
     return d.transpose(3, 0, 1, 2).reshape(ssd_c.E, 4 * Nc * Nc), Qc
 
 
+def trajectory_targets(ssd_f, ssd_c, children, Qf, Qc, theta, omega, rate):
+    """Targets along a corrected coarse run (a posteriori training): at the
+    coarse run's state Qc, the correction that makes its dQ/dt the
+    restricted fine dQ/dt and also relaxes Qc towards the restricted fine
+    state at `rate`:  restrict(R_f(Qf)) - R_c(Qc) + rate (restrict(Qf) - Qc),
+    as (Ec, 4 Nc^2) rows.  At Qc = restrict(Qf) it is the a priori target."""
+    Nc = ssd_c.N
+    Rf = ssd_f.residual(Qf, theta, omega)
+    Qr = restrict(Qf, children, Nc)
+    d = restrict(Rf, children, Nc) - ssd_c.residual(Qc, theta, omega) + rate * (Qr - Qc)
+    return d.transpose(3, 0, 1, 2).reshape(ssd_c.E, 4 * Nc * Nc)
+
+
 # ----------------------------------------------------------------------------
 # the MLP
 # ----------------------------------------------------------------------------

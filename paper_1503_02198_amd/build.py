@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libssd.so")
 SOURCES = [os.path.join(HERE, "csrc", f)
            for f in ("ssd_host.hip", "ssd_kernels.hip", "ssd_batch.hip", "ssd_mlp.hip",
-                     "ssd_iface.hip")]
+                     "ssd_iface.hip", "ssd_probe.hip")]
 HEADERS = [os.path.join(ROOT, "include", "ssd.h")] + [
     os.path.join(HERE, "csrc", f) for f in ("ssd_internal.h", "ssd_launch.h", "ssd_device.h", "ssd_tiles.h")]
 

@@ -67,10 +67,18 @@ __global__ __launch_bounds__(MORTAR_BLOCK) void kb_mortar_visc(const BatchCase *
   mortar_visc_chunk<N>(B.M, T, B.ms, fb + nt + nr, B.V.gtr, B.V.mvflux, int(it.y));
 }
 
-template <int N, bool VISC, bool ADD, bool COMB = false>
-__global__ __launch_bounds__(64 * N) void kb_stage(const BatchCase *cases, const uint2 *work,
-                                                   OpTables T, BatchStage S, const double *step) {
-  const uint2 it = batch_item(work, S.reverse != 0);
+// TPB consecutive items of the work table per block (the tile shape the
+// autotuner picks per group); groups of N waves each, see stage_tile.
+template <int N, bool VISC, bool ADD, bool COMB = false, int TPB = 1>
+__global__ __launch_bounds__(64 * N * TPB) void kb_stage(const BatchCase *cases, const uint2 *work,
+                                                         int nwork, OpTables T, BatchStage S,
+                                                         const double *step) {
+  const int b = S.reverse ? int(gridDim.x) - 1 - int(blockIdx.x) : int(blockIdx.x);
+  const int grp = TPB > 1 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) / (64 * N)) : 0;
+  const int idx = b * TPB + grp;
+  const bool active = idx < nwork;
+  const uint2 w = work[active ? idx : b * TPB];
+  const uint2 it = make_uint2(__builtin_amdgcn_readfirstlane(w.x), __builtin_amdgcn_readfirstlane(w.y));
   const BatchCase &B = cases[it.x];
   const Rotation R = batch_rotation(B, step, S.c);
   const ViscBufs V{B.V.G, B.V.gtr, B.V.mvflux};
@@ -81,9 +89,10 @@ __global__ __launch_bounds__(64 * N) void kb_stage(const BatchCase *cases, const
     C.cw3 = S.cw3;
     C.cw4 = S.cw4;
   }
-  stage_tile<N, true, VISC, ADD, COMB>(B.M, T, R, B.buf[S.in], S.qn >= 0 ? B.buf[S.qn] : nullptr,
-                                       B.buf[S.out], B.face[S.cur], B.face[S.cur ^ 1], V, C,
-                                       int(it.y));
+  stage_tile<N, true, VISC, ADD, COMB, TPB>(B.M, T, R, B.buf[S.in],
+                                            S.qn >= 0 ? B.buf[S.qn] : nullptr, B.buf[S.out],
+                                            B.face[S.cur], B.face[S.cur ^ 1], V, C, int(it.y),
+                                            active);
 }
 
 __global__ void k_step_count(double *step) {
@@ -131,11 +140,21 @@ hipError_t launch_batch_mortar_visc(int N, const BatchCase *cases, const uint2 *
 
 hipError_t launch_batch_stage(int N, bool visc, const BatchCase *cases, const uint2 *work,
                               int nwork, const OpTables &T, const BatchStage &S,
-                              const double *step, hipStream_t s) {
+                              const double *step, hipStream_t s, int tpb) {
   if (nwork < 1) return hipSuccess;
-#define SSD_BSTAGE(VV, AV, CV)                                                                  \
-  SSD_DISPATCH_N(N, hipLaunchKernelGGL((kb_stage<NN, VV, AV, CV>), dim3(nwork), dim3(EB * NN), 0, \
-                                       s, cases, work, T, S, step))
+  if (tpb != 1 && !(tpb == 2 && N <= 4)) return hipErrorInvalidValue;
+  const int nblk = (nwork + tpb - 1) / tpb;
+#define SSD_BSTAGE(VV, AV, CV)                                                                 \
+  do {                                                                                         \
+    if (tpb == 1) {                                                                            \
+      SSD_DISPATCH_N(N, hipLaunchKernelGGL((kb_stage<NN, VV, AV, CV, 1>), dim3(nblk),          \
+                                           dim3(EB * NN), 0, s, cases, work, nwork, T, S, step)); \
+    } else {                                                                                   \
+      SSD_DISPATCH_N_SMALL(N, hipLaunchKernelGGL((kb_stage<NN, VV, AV, CV, 2>), dim3(nblk),    \
+                                           dim3(2 * EB * NN), 0, s, cases, work, nwork, T, S,   \
+                                           step));                                             \
+    }                                                                                          \
+  } while (0)
   const bool add = S.add >= 0;
   if (S.comb >= 0) {   // SSPRK54's fourth stage with the increment (never with add)
     if (add || S.qn < 0) return hipErrorInvalidValue;

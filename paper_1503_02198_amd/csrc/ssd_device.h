@@ -112,25 +112,29 @@ __device__ __forceinline__ void rusanov_d(const double ql[4], const double qr[4]
 
 // Gas constants of the viscous terms.
 struct ViscParams {
-  float gamma, R, mu, kcond;   // kcond = mu gamma R / ((gamma - 1) Pr)
+  float gamma, iR, mu, kcond;   // iR = 1 / R; kcond = mu gamma R / ((gamma - 1) Pr)
 };
 
 __device__ __forceinline__ ViscParams visc_params(const DevMesh &M) {
   ViscParams P;
   P.gamma = M.gamma;
-  P.R = M.gas_R;
+  P.iR = rcp(M.gas_R);
   P.mu = M.mu;
-  P.kcond = M.mu * M.gamma * M.gas_R / ((M.gamma - 1.0f) * M.prandtl);
+  P.kcond = M.mu * M.gamma * M.gas_R * rcp((M.gamma - 1.0f) * M.prandtl);
   return P;
 }
 
+// 1 / x: the hardware reciprocal in FP32 (within 1 ulp), a division in FP64.
+__device__ __forceinline__ float recip(float x) { return rcp(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // Normal viscous flux F_vis nx + G_vis ny (Sec. 2.1) from the conservative
 // state and its x, y gradients: tau_ij = mu (u_i,j + u_j,i) - 2/3 mu
-// delta_ij div u, heat flux k grad T with T = p / (rho R).
+// delta_ij div u, heat flux k grad T with T = p / (rho R); iRg = 1 / R.
 template <typename R>
 __device__ __forceinline__ void visc_flux_n(const R q[4], const R gx[4], const R gy[4], R nx, R ny,
-                                            R gamma, R Rg, R mu, R kc, R f[4]) {
-  const R ir = R(1) / q[0];
+                                            R gamma, R iRg, R mu, R kc, R f[4]) {
+  const R ir = recip(q[0]);
   const R u = q[1] * ir, v = q[2] * ir;
   const R p = (gamma - R(1)) * (q[3] - R(0.5) * (q[1] * u + q[2] * v));
   const R ux = (gx[1] - u * gx[0]) * ir, vx = (gx[2] - v * gx[0]) * ir;
@@ -138,8 +142,8 @@ __device__ __forceinline__ void visc_flux_n(const R q[4], const R gx[4], const R
   const R k2 = R(0.5) * (u * u + v * v);
   const R px = (gamma - R(1)) * (gx[3] - u * gx[1] - v * gx[2] + k2 * gx[0]);
   const R py = (gamma - R(1)) * (gy[3] - u * gy[1] - v * gy[2] + k2 * gy[0]);
-  const R Tx = (px - p * ir * gx[0]) * ir / Rg;
-  const R Ty = (py - p * ir * gy[0]) * ir / Rg;
+  const R Tx = (px - p * ir * gx[0]) * (ir * iRg);
+  const R Ty = (py - p * ir * gy[0]) * (ir * iRg);
   const R div = ux + vy;
   const R txx = R(2) * mu * ux - R(2.0 / 3.0) * mu * div;
   const R tyy = R(2) * mu * vy - R(2.0 / 3.0) * mu * div;
@@ -460,12 +464,13 @@ __device__ __forceinline__ void common_solution(const DevMesh &M, int kind, cons
   const float ir = rcp(qo[0]);
   const float u = qo[1] * ir, v = qo[2] * ir;
   const float p = gm1 * (qo[3] - 0.5f * (qo[1] * u + qo[2] * v));
+  const float igm1 = rcp(gm1);
   if (kind == SSD_FACE_WALL_ISOTHERMAL) {
-    const float rb = p / (M.gas_R * M.T_wall);
+    const float rb = p * rcp(M.gas_R * M.T_wall);
     qc[0] = rb;
     qc[1] = rb * G.ug;
     qc[2] = rb * G.vg;
-    qc[3] = p / gm1 + 0.5f * rb * (G.ug * G.ug + G.vg * G.vg);
+    qc[3] = p * igm1 + 0.5f * rb * (G.ug * G.ug + G.vg * G.vg);
     return;
   }
   // slip wall
@@ -476,7 +481,7 @@ __device__ __forceinline__ void common_solution(const DevMesh &M, int kind, cons
   qc[0] = qo[0];
   qc[1] = qo[0] * ub;
   qc[2] = qo[0] * vb;
-  qc[3] = p / gm1 + 0.5f * qo[0] * (ub * ub + vb * vb);
+  qc[3] = p * igm1 + 0.5f * qo[0] * (ub * ub + vb * vb);
 }
 
 }  // namespace ssd

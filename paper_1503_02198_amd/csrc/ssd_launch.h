@@ -76,10 +76,15 @@ hipError_t launch_batch_grad(int N, const BatchCase *cases, const uint2 *work, i
                              hipStream_t s);
 hipError_t launch_batch_mortar_visc(int N, const BatchCase *cases, const uint2 *work, int nwork,
                                     const OpTables &T, int cur, hipStream_t s);
+// tpb: work items (64-cell tiles) per block, 1, or 2 for N <= 4
 hipError_t launch_batch_stage(int N, bool visc, const BatchCase *cases, const uint2 *work,
                               int nwork, const OpTables &T, const BatchStage &S,
-                              const double *step, hipStream_t s);
+                              const double *step, hipStream_t s, int tpb = 1);
 hipError_t launch_step_count(double *step, hipStream_t s);
+
+// the contraction probe (ssd_probe.hip): N = 4 operators of T
+hipError_t launch_probe(int variant, const OpTables &T, int n_cells, int reps, const float *q,
+                        float *out, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // learned per-element subgrid correction (ssd_mlp.hip)
@@ -135,6 +140,9 @@ hipError_t launch_adam(const MlpStore &S, long n, float lr, float b1, float b2, 
                        float bc1, float bc2, hipStream_t s);
 hipError_t launch_mlp_sync(const MlpStore &S, long n, hipStream_t s);
 hipError_t launch_moments(const float *A, long n, int cols, double *acc, hipStream_t s);
+// rows T[e][o] += rate (qa - qb), qa and qb in the cell-blocked state layout
+hipError_t launch_nudge(const float *qa, const float *qb, long E, int planes, float rate, float *T,
+                        hipStream_t s);
 // out = restriction of qf (nested fine state; children null: the same mesh
 // at a lower order) - sub (null: nothing); rows: out[c][o], else the state
 // layout out[o][c]

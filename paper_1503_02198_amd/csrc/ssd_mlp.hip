@@ -563,6 +563,27 @@ __global__ __launch_bounds__(256) void k_restrict(const float *qf, long Ef, cons
 }
 
 // ---------------------------------------------------------------------------
+// relaxation term of trajectory (a posteriori) training targets: rows
+// T[e][o] += rate (qa - qb)[e][o], with qa and qb in the state layout
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_nudge(const float *qa, const float *qb, long E,
+                                               int planes, float rate, float *T) {
+  const long k = long(blockIdx.x) * 256 + threadIdx.x;
+  if (k >= E * planes) return;
+  const long e = k / planes, o = k - e * planes;
+  const long c = cb_index(e, o, planes, E);
+  T[k] += rate * (qa[c] - qb[c]);
+}
+
+hipError_t launch_nudge(const float *qa, const float *qb, long E, int planes, float rate, float *T,
+                        hipStream_t s) {
+  const long n = E * planes;
+  if (n < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_nudge, dim3((n + 255) / 256), dim3(256), 0, s, qa, qb, E, planes, rate, T);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 #define SSD_MLP_DISPATCH(N, CALL)                        \

@@ -130,7 +130,7 @@ __device__ __forceinline__ void common_visc(const DevMesh &M, const ViscParams &
       gy[v] = 0.5f * (gy[v] + b.x[v]);
     }
   }
-  visc_flux_n<float>(qc, gx, gy, G.nx, G.ny, P.gamma, P.R, P.mu, P.kcond, fv);
+  visc_flux_n<float>(qc, gx, gy, G.nx, G.ny, P.gamma, P.iR, P.mu, P.kcond, fv);
 }
 
 // ---------------------------------------------------------------------------
@@ -162,20 +162,29 @@ __device__ __forceinline__ void common_visc(const DevMesh &M, const ViscParams &
 // LDS access of a wave to its own elements touches 64 distinct banks.
 // Global accesses of a wave are contiguous 256-byte rows.
 // ---------------------------------------------------------------------------
-template <int N, bool RK, bool VISC, bool ADD, bool COMB = false>
+//
+// TPB tiles per block (batched stage): the block's waves form TPB groups of
+// N, group g serving its own tile with its own LDS arrays; every group
+// passes the same barriers.  A group with active = false (the block's last
+// tiles past the end of the work table) is handed a valid tile, loads it,
+// and stores nothing.
+template <int N, bool RK, bool VISC, bool ADD, bool COMB = false, int TPB = 1>
 __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, const Rotation &R,
                                            const float *q, const float *qn, float *out,
                                            const float *facein, float *trout, const ViscBufs &V,
-                                           const RKCoef &C, int tile) {
-  __shared__ float S[4][N][N][EB];     // state of the block's elements
-  __shared__ float SR[4][N][N][EB];    // xi part of the residual, then the new state
+                                           const RKCoef &C, int tile, bool active = true) {
+  __shared__ float S_[TPB][4][N][N][EB];    // state of the group's elements
+  __shared__ float SR_[TPB][4][N][N][EB];   // xi part of the residual, then the new state
+  // the wave index and the group are uniform across the wave: say so, so
+  // that offsets derived from them live in SGPRs
+  const int grp = TPB > 1 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) / (EB * N)) : 0;
+  float(&S)[4][N][N][EB] = S_[grp];
+  float(&SR)[4][N][N][EB] = SR_[grp];
   const float *Sf = &S[0][0][0][0];
   const int l = threadIdx.x & (EB - 1);
-  // the wave index is uniform across the wave (blocks are 64 N lanes): say so,
-  // so that offsets derived from it live in SGPRs
-  const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / EB);
+  const int w = __builtin_amdgcn_readfirstlane((int(threadIdx.x) / EB) % N);
   const int e0 = tile * EB + l;
-  const bool valid = e0 < M.E;
+  const bool valid = active && e0 < M.E;
   const int e = valid ? e0 : M.E - 1;
   const float gm1 = M.gamma - 1.0f;
   const uint32_t E4 = uint32_t(M.E) * 4u;
@@ -276,7 +285,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
           for (int i = 0; i < N; ++i) acc += T.I[k][i] * gr[c][i];
           gf[c] = acc;
         }
-        visc_flux_n<float>(qf, gf, gf + 4, G.nx, G.ny, P.gamma, P.R, P.mu, P.kcond, fv);
+        visc_flux_n<float>(qf, gf, gf + 4, G.nx, G.ny, P.gamma, P.iR, P.mu, P.kcond, fv);
 #pragma unroll
         for (int v = 0; v < 4; ++v) f[v] += fv[v];
       }
@@ -398,7 +407,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
         flux_n(qf, G.nx, G.ny, G.vgn, gm1, f);
         if (VISC) {
           float fv[4];
-          visc_flux_n<float>(qf, gf, gf + 4, G.nx, G.ny, P.gamma, P.R, P.mu, P.kcond, fv);
+          visc_flux_n<float>(qf, gf, gf + 4, G.nx, G.ny, P.gamma, P.iR, P.mu, P.kcond, fv);
 #pragma unroll
           for (int v = 0; v < 4; ++v) f[v] += fv[v];
         }
@@ -1006,8 +1015,8 @@ __device__ __forceinline__ void mortar_visc_chunk(const DevMesh &M, const OpTabl
   const int j = right ? t - K : t;
   const int m = ms->m;
   const double sc = M.Rs * M.dphi;
-  const double gam = M.gamma, Rg = M.gas_R, mu = M.mu;
-  const double kc = mu * gam * Rg / ((gam - 1.0) * double(M.prandtl));
+  const double gam = M.gamma, iRg = 1.0 / double(M.gas_R), mu = M.mu;
+  const double kc = mu * gam * double(M.gas_R) / ((gam - 1.0) * double(M.prandtl));
   if (act) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -1023,7 +1032,7 @@ __device__ __forceinline__ void mortar_visc_chunk(const DevMesh &M, const OpTabl
         double q4[4], g8[8], f[4];
         load_slot_point<N>(M, mqc, slot, a, q4);
         load_canon_point<N, 8>(M, gtr, slot, a, g8);
-        visc_flux_n<double>(q4, g8, g8 + 4, cs * sc, sn * sc, gam, Rg, mu, kc, f);
+        visc_flux_n<double>(q4, g8, g8 + 4, cs * sc, sn * sc, gam, iRg, mu, kc, f);
 #pragma unroll
         for (int v = 0; v < 4; ++v) VF[fl][k][side][a][v] = f[v];
       }
@@ -1083,6 +1092,15 @@ __global__ __launch_bounds__(MORTAR_BLOCK) void k_mortar_visc(DevMesh M, OpTable
     case 4: { constexpr int NN = 4; CALL; } break;       \
     case 5: { constexpr int NN = 5; CALL; } break;       \
     case 6: { constexpr int NN = 6; CALL; } break;       \
+    default: return hipErrorInvalidValue;                \
+  }
+
+// The same for the orders that also have two-tile blocks (N <= 4).
+#define SSD_DISPATCH_N_SMALL(N, CALL)                    \
+  switch (N) {                                           \
+    case 2: { constexpr int NN = 2; CALL; } break;       \
+    case 3: { constexpr int NN = 3; CALL; } break;       \
+    case 4: { constexpr int NN = 4; CALL; } break;       \
     default: return hipErrorInvalidValue;                \
   }
 

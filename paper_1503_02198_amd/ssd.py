@@ -22,12 +22,13 @@ EXPORTS = ["ssd_create_mesh", "ssd_destroy_mesh", "ssd_query", "ssd_set_rotation
            "ssd_mortar_rebuild", "ssd_residual", "ssd_rk_step", "ssd_rk_steps",
            "ssd_rk_steps_noalloc", "ssd_check",
            "ssd_last_error", "ssd_timing_enable", "ssd_timing_reset", "ssd_timing_read",
-           "ssd_timing_samples",
+           "ssd_timing_samples", "ssd_probe_contraction",
            "ssd_batch_create", "ssd_batch_destroy", "ssd_batch_rk_steps", "ssd_batch_query",
            "ssd_mlp_create", "ssd_mlp_destroy", "ssd_mlp_dims", "ssd_mlp_set_params",
            "ssd_mlp_get_params", "ssd_mlp_set_normalization", "ssd_mlp_fit_normalization",
            "ssd_mlp_forward", "ssd_mlp_gradient", "ssd_mlp_train_step", "ssd_mlp_loss",
-           "ssd_subgrid_features", "ssd_restrict", "ssd_subgrid_targets", "ssd_subgrid_attach"]
+           "ssd_subgrid_features", "ssd_restrict", "ssd_subgrid_targets", "ssd_subgrid_nudge",
+           "ssd_subgrid_attach"]
 
 
 # -- cell-blocked state layout (include/ssd.h) ------------------------------
@@ -99,7 +100,8 @@ class MeshDesc(ctypes.Structure):
 class BatchGroup(ctypes.Structure):
     _fields_ = [("n_groups", ctypes.c_int32), ("N", ctypes.c_int32), ("viscous", ctypes.c_int32),
                 ("tiles", ctypes.c_int32), ("stream", ctypes.c_int32), ("n_streams", ctypes.c_int32),
-                ("tuned", ctypes.c_int32), ("stage_us", ctypes.c_float)]
+                ("tuned", ctypes.c_int32), ("stage_us", ctypes.c_float),
+                ("tiles_per_block", ctypes.c_int32), ("stage_us_tpb", ctypes.c_float * 2)]
 
 
 class Info(ctypes.Structure):
@@ -138,6 +140,7 @@ def lib():
             "ssd_timing_read": (i32, [vp, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
             "ssd_timing_samples": (i32, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_float), i64,
                                          ctypes.POINTER(i64)]),
+            "ssd_probe_contraction": (i32, [vp, i32, i32, i32, vp, vp, vp]),
             "ssd_batch_create": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]),
             "ssd_batch_destroy": (i32, [vp]),
             "ssd_batch_rk_steps": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -161,6 +164,7 @@ def lib():
             "ssd_subgrid_features": (i32, [vp, vp, vp, vp]),
             "ssd_restrict": (i32, [vp, vp, vp, vp, vp, vp]),
             "ssd_subgrid_targets": (i32, [vp, vp, vp, vp, vp, vp, vp]),
+            "ssd_subgrid_nudge": (i32, [vp, vp, vp, ctypes.c_float, vp, vp]),
             "ssd_subgrid_attach": (i32, [vp, vp, ctypes.c_float, i32]),
         }
         for name, (res, args) in sig.items():
@@ -290,6 +294,13 @@ class Mesh:
                                           float(t), float(dt), int(nsteps), SCHEMES[scheme],
                                           _stream_ptr(stream, self.device)))
 
+    def probe_contraction(self, variant, n_cells, reps, q, out, stream=None):
+        """The VALU (0) or MFMA (1) contraction probe (ssd_probe_contraction)."""
+        n = 64 * n_cells
+        _check(lib().ssd_probe_contraction(self._h, int(variant), int(n_cells), int(reps),
+                                           self._tensor(q, n, "q"), self._tensor(out, n, "out"),
+                                           _stream_ptr(stream, self.device)))
+
     def check(self, stream=None):
         _check(lib().ssd_check(self._h, _stream_ptr(stream, self.device)))
 
@@ -372,7 +383,8 @@ class Batch:
         while True:
             inf = BatchGroup()
             _check(lib().ssd_batch_query(self._h, g, ctypes.byref(inf)))
-            out.append({f: getattr(inf, f) for f, _ in BatchGroup._fields_ if f != "n_groups"})
+            out.append({f: (list(getattr(inf, f)) if f == "stage_us_tpb" else getattr(inf, f))
+                        for f, _ in BatchGroup._fields_ if f != "n_groups"})
             g += 1
             if g >= inf.n_groups:
                 return out
@@ -518,3 +530,12 @@ def subgrid_targets(fine, coarse, children, Rf, Rc, T, stream=None):
                                      coarse._tensor(Rc, coarse.info["state_len"], "Rc"),
                                      coarse._tensor(T, coarse.info["state_len"], "T"),
                                      _stream_ptr(stream, coarse.device)))
+
+
+def subgrid_nudge(coarse, q_ref, q, rate, T, stream=None):
+    """T rows += rate (q_ref - q), both states of the coarse mesh
+    (ssd_subgrid_nudge)."""
+    n = coarse.info["state_len"]
+    _check(lib().ssd_subgrid_nudge(coarse._h, coarse._tensor(q_ref, n, "q_ref"),
+                                   coarse._tensor(q, n, "q"), float(rate),
+                                   coarse._tensor(T, n, "T"), _stream_ptr(stream, coarse.device)))

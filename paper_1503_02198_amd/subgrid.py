@@ -22,7 +22,7 @@ import time
 
 import numpy as np
 
-from .ssd import MLP, Mesh, pack_state, restrict, subgrid_targets, unpack_state
+from .ssd import MLP, Mesh, pack_state, restrict, subgrid_nudge, subgrid_targets, unpack_state
 
 
 def ellipse_pair(K=64, n_in=8, n_out=16, first_in=0.01, first_out=0.02):
@@ -87,21 +87,27 @@ class Pair:
         restrict(self.fine, self.coarse, self.children, qf, qc)
         return qc
 
-    def sample(self, qf, t, X, T):
-        """Features of the restricted state into X and the targets into T
-        (views of Ec rows each)."""
+    def sample(self, qf, t, X, T, qc=None, rate=0.0):
+        """Features into X and targets into T (views of Ec rows each): at the
+        restricted state (qc None), or at the coarse state qc (trajectory
+        targets), with rate > 0 also the relaxation towards the restricted
+        state."""
         import torch
         th, om = self.theta(t), self.case["omega"]
         rf = torch.empty_like(qf)
         self.fine.set_rotation(th, om)
         self.fine.mortar_rebuild()
         self.fine.residual(qf, rf)
-        qc = self.restrict(qf)
+        qr = self.restrict(qf)
+        if qc is None:
+            qc = qr
         rc = torch.empty_like(qc)
         self.coarse.set_rotation(th, om)
         self.coarse.mortar_rebuild()
         self.coarse.residual(qc, rc)
         subgrid_targets(self.fine, self.coarse, self.children, rf, rc, T)
+        if rate:
+            subgrid_nudge(self.coarse, qr, qc, rate, T)
         self.coarse.features(qc, X)
 
 
@@ -166,6 +172,73 @@ def generate(meshes, omegas, t_start, t_end, n_snap, Nc=3, Nf=6, log=None):
     return X, T, time.perf_counter() - t0
 
 
+def generate_trajectory(meshes, omegas, net, t_start, t_end, n_snap, rate=0.0, weight=1.0,
+                        per_step=True, Nc=3, Nf=6, log=None):
+    """Training rows along corrected coarse runs (a posteriori training): the
+    fine runs, one per rotation rate, stepped together as one batch as in
+    `generate`, and beside each the coarse run with `net` attached, started
+    from the restriction of the fine state at t_start.  At n_snap times
+    equally spaced in [t_start, t_end]: the coarse run's features, with the
+    targets restrict(R_f(Q_f)) - R_c(Q_c) + rate (restrict(Q_f) - Q_c), the
+    correction that gives the coarse run the restricted fine dQ/dt at its
+    own state (and, with rate > 0, pulls it back to the restricted fine
+    state).  A coarse run that fails its check (ssd_check) restarts from
+    the restricted fine state.  Returns (X, T) on the GPU, the seconds spent
+    and the number of restarts."""
+    import torch
+    from workloads import cases as C
+    from .ssd import Batch, SSDError
+    Ec = len(meshes[0]["zone"])
+    n_in, n_out = 4 * Nc * Nc + 16 * Nc, 4 * Nc * Nc
+    rows = len(omegas) * n_snap * Ec
+    X = torch.empty(rows * n_in, dtype=torch.float32, device="cuda:0")
+    T = torch.empty(rows * n_out, dtype=torch.float32, device="cuda:0")
+    t0 = time.perf_counter()
+    pairs = [Pair(meshes, C.ellipse_viscous_case(omega=om), Nc, Nf) for om in omegas]
+    dt = min(P.dt_f for P in pairs)
+    batch = Batch([P.fine for P in pairs])
+    qs = [P.uniform(P.fine) for P in pairs]
+    ws = [P.work(P.fine) for P in pairs]
+    n = len(pairs)
+    warm = int(round(t_start / dt))
+    gap = max(1, int(round((t_end - t_start) / (max(n_snap - 1, 1) * dt))))
+    if warm:
+        batch.rk_steps(qs, ws, [0.0] * n, [dt] * n, warm)
+    t = warm * dt
+    qcs = [P.restrict(q) for P, q in zip(pairs, qs)]
+    wcs = [P.work(P.coarse) for P in pairs]
+    k, restarts = 0, 0
+    try:
+        for P in pairs:
+            P.coarse.attach(net, weight, per_step=per_step)
+        for snap in range(n_snap):
+            if snap:
+                batch.rk_steps(qs, ws, [t] * n, [dt] * n, gap)
+                for j, P in enumerate(pairs):
+                    try:
+                        advance(P.coarse, qcs[j], wcs[j], t, P.dt_c, t + gap * dt)
+                        P.coarse.check()
+                    except SSDError:
+                        qcs[j] = P.restrict(qs[j])
+                        restarts += 1
+                t += gap * dt
+            for j, P in enumerate(pairs):
+                P.sample(qs[j], t, X[k * Ec * n_in:(k + 1) * Ec * n_in],
+                         T[k * Ec * n_out:(k + 1) * Ec * n_out], qc=qcs[j], rate=rate)
+                k += 1
+    finally:
+        for P in pairs:
+            P.coarse.attach(None)
+    for P in pairs:
+        P.fine.check()
+    torch.cuda.synchronize()
+    batch.close()
+    if log:
+        log(f"{n} corrected coarse runs beside their fine runs to t = {t:.3f}, {n_snap} snapshots "
+            f"each, {restarts} restarts, {time.perf_counter() - t0:.1f} s")
+    return X, T, time.perf_counter() - t0, restarts
+
+
 def init_params(rng, n_in, n_out, H=MLP.HIDDEN):
     """Glorot-uniform weights and zero biases, drawn from rng."""
     def glorot(o, i):
@@ -175,15 +248,20 @@ def init_params(rng, n_in, n_out, H=MLP.HIDDEN):
                 b2=np.zeros(H, np.float32), W3=glorot(n_out, H), b3=np.zeros(n_out, np.float32))
 
 
-def train(net, X, T, epochs, batch, lr, seed, log=None, min_rel=1e-2, noise=0.0):
+def train(net, X, T, epochs, batch, lr, seed, log=None, min_rel=1e-2, noise=0.0, resume=False):
     """Adam over shuffled minibatches with input noise of standard deviation
     `noise` (normalised units); the learning rate decays as a cosine to a
-    tenth.  Returns the per-epoch mean losses and the seconds spent."""
+    tenth.  resume: continue from the network's weights and normalisation
+    (new Adam moments) instead of fresh weights.  Returns the per-epoch mean
+    losses and the seconds spent."""
     import torch
     rows = X.numel() // net.n_in
     rng = np.random.default_rng(seed)
-    net.set_params(init_params(rng, net.n_in, net.n_out))
-    net.fit_normalization(X, T, min_rel=min_rel)
+    if resume:
+        net.set_params(net.get_params())      # same weights, fresh Adam moments
+    else:
+        net.set_params(init_params(rng, net.n_in, net.n_out))
+        net.fit_normalization(X, T, min_rel=min_rel)
     per = rows // batch
     losses = []
     t0 = time.perf_counter()

@@ -37,7 +37,8 @@ def test_struct_layout_matches_header():
     # ssd_mesh_desc: 2 ints, 6 pointers, 14 doubles (incl. arrays) on LP64
     assert ctypes.sizeof(ssd.MeshDesc) == 8 + 6 * 8 + 14 * 8
     assert ctypes.sizeof(ssd.Info) == 6 * 4 + 2 * 8
-    assert ctypes.sizeof(ssd.BatchGroup) == 8 * 4
+    # ssd_batch_group: 7 int32, a float, an int32 and 2 floats
+    assert ctypes.sizeof(ssd.BatchGroup) == 11 * 4
 
 
 def test_argument_errors_without_device(L):

@@ -167,6 +167,44 @@ def test_targets(torch_cuda, nested):
     assert err <= 1e-5
 
 
+def test_trajectory_targets(torch_cuda, nested):
+    """Targets at a coarse state off the restricted fine state (a corrected
+    run's state): restricted fine dQ/dt minus the coarse residual at that
+    state plus the relaxation rate (restrict(Qf) - Qc), against the oracle."""
+    from paper_1503_02198_amd import Mesh, restrict, subgrid_nudge, subgrid_targets
+    from tests.parity_utils import gpu_residual
+    print("case: trajectory targets, viscous ellipse N 6 -> 3", flush=True)
+    coarse, fine, ch = nested
+    case = C.ellipse_viscous_case(omega=0.9)
+    of, oc = SSD(fine, case, 6), SSD(coarse, case, 3)
+    theta, rate = 0.21, 40.0
+    Qf = _smooth_state(of, case, theta)
+    Qr = S.restrict(Qf, ch, 3)
+    # a coarse state that differs from the restricted one by a smooth field
+    x, y = oc.sp_coords(theta)
+    Qc = Qr * (1.0 + 0.01 * np.sin(0.7 * x + 0.3 * y)[None])
+    T_ora = S.trajectory_targets(of, oc, ch, Qf, Qc, theta, case["omega"], rate)
+    gf, gc = Mesh(fine, case, 6), Mesh(coarse, case, 3)
+    chd = torch_cuda.tensor(ch.ravel(), device="cuda:0")
+    Rf = to_gpu(gpu_residual(gf, Qf, theta, case["omega"]))
+    qr = torch_cuda.empty(gc.info["state_len"], dtype=torch_cuda.float32, device="cuda:0")
+    restrict(gf, gc, chd, to_gpu(Qf), qr)
+    qc = to_gpu(Qc)
+    Rc = to_gpu(gpu_residual(gc, Qc, theta, case["omega"]))
+    T = torch_cuda.empty_like(qc)
+    subgrid_targets(gf, gc, chd, Rf, Rc, T)
+    subgrid_nudge(gc, qr, qc, rate, T)
+    Tg = T.cpu().numpy().reshape(gc.info["n_elem"], -1)
+    scale = np.abs(S.restrict(of.residual(Qf, theta, case["omega"]), ch, 3)).max()
+    relax = rate * np.abs(Qr - Qc).max()
+    err = np.abs(Tg - T_ora).max() / scale
+    print("target error relative to the restricted residual", err, "relaxation term", relax,
+          "residual scale", scale, flush=True)
+    # the relaxation term is far above the tolerance: leaving it out fails
+    assert relax > 100 * 1e-5 * scale
+    assert err <= 1e-5
+
+
 @pytest.mark.parametrize("N,n", [(3, 200), (2, 64), (4, 77)])
 def test_mlp_forward(torch_cuda, N, n):
     print(f"case: network forward N={N} rows={n}", flush=True)
