@@ -83,11 +83,54 @@ struct ViscBufs {
   const float *mvflux;  // viscous mortar flux [slot][point][4]
 };
 
-// Conforming faces export their gradient traces (both sides average the
-// two), sliding faces for the viscous mortar.
-__device__ __forceinline__ bool grad_exported(uint32_t fw) {
+// Orders whose viscous stage passes gradient traces between the block's
+// elements through LDS: the exchange array, [side][8][N][64] floats (16 KB
+// at N = 4), keeps the stage at three blocks per compute unit.
+template <int N>
+__device__ constexpr bool grad_shared() {
+  return N <= 4;
+}
+
+// A conforming face whose neighbour is in the same block, across a face of
+// the same direction (xi face to xi face, eta face to eta face) with the
+// same point order: the neighbour's trace at point p comes from the same
+// wave of the stage kernel (row phase: row p; column phase: column p),
+// which leaves it in the block's exchange array just before it reads it.
+// f: the local face of fw.
+template <int N>
+__device__ __forceinline__ bool grad_in_block(uint32_t fw, int f) {
   const int k = face_kind_of(fw);
-  return k == SSD_FACE_INTERIOR || k == SSD_FACE_PERIODIC || k == SSD_FACE_SLIDING;
+  return grad_shared<N>() && (k == SSD_FACE_INTERIOR || k == SSD_FACE_PERIODIC) &&
+         face_inblock_of(fw) && !face_rev_of(fw) && ((face_nf_of(fw) & 1) == (f & 1));
+}
+
+// Faces whose gradient traces the gradient pass writes: sliding faces (the
+// viscous mortar reads them) and the conforming faces without
+// grad_in_block (both sides average the two).
+template <int N>
+__device__ __forceinline__ bool grad_exported(uint32_t fw, int f) {
+  const int k = face_kind_of(fw);
+  if (k == SSD_FACE_SLIDING) return true;
+  return (k == SSD_FACE_INTERIOR || k == SSD_FACE_PERIODIC) && !grad_in_block<N>(fw, f);
+}
+
+// Gradient traces at the two ends of a line of solution points (flux
+// points 0 and N) into the exchange array at point p: g [8][N] along the
+// line, X [side][8][N][64].
+template <int N>
+__device__ __forceinline__ void share_traces(const OpTables &T, const float (&g)[8][N], float *X,
+                                             int p, int lane) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    float s0 = 0.f, sN = 0.f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      s0 += T.I[0][i] * g[c][i];
+      sN += T.I[N][i] * g[c][i];
+    }
+    X[((0 * 8 + c) * N + p) * EB + lane] = s0;
+    X[((1 * 8 + c) * N + p) * EB + lane] = sN;
+  }
 }
 
 // Common viscous normal flux at one element-boundary flux point (BR1
@@ -95,9 +138,12 @@ __device__ __forceinline__ bool grad_exported(uint32_t fw) {
 // F_vis(Q_b, interior gradient) . n on isothermal walls and the far field,
 // zero on slip walls, the mortar value on sliding faces.  qx: neighbour's
 // state from common_flux; g: own gradient at the point [x0..x3, y0..y3].
+// f: the local face of fw; gbytes: the size of the trace buffer behind
+// rgtr; X: the block's exchange array (grad_shared<N>()), else null.
 template <int N>
 __device__ __forceinline__ void common_visc(const DevMesh &M, const ViscParams &P, rsrc_t rgtr,
-                                            rsrc_t rmv, uint32_t fw, int p, const float qo[4],
+                                            uint32_t gbytes, rsrc_t rmv, const float *X,
+                                            uint32_t fw, int f, int p, const float qo[4],
                                             const float qx[4], const float x[4],
                                             const float g[8], const FPGeo &G, float fv[4]) {
   const int kind = face_kind_of(fw);
@@ -120,14 +166,34 @@ __device__ __forceinline__ void common_visc(const DevMesh &M, const ViscParams &
     gy[v] = g[4 + v];
   }
   if (conforming(kind)) {
+    // grad_in_block lanes point the loads past the end of the trace buffer
+    // (zero, no memory access) and add the trace from the exchange array:
+    // one load per lane, no branch, and either term exactly zero
+    const bool inb = grad_in_block<N>(fw, f);
     const uint32_t nb = uint32_t(face_idx_of(fw)), nf = uint32_t(face_nf_of(fw));
     const uint32_t pp = face_rev_of(fw) ? uint32_t(N - 1 - p) : uint32_t(p);
-    const uint32_t vo = ((nf * uint32_t(M.E) + nb) * N + pp) * 32u;
+    const uint32_t vo = inb ? gbytes : ((nf * uint32_t(M.E) + nb) * N + pp) * 32u;
     const f4 a = bload4(rgtr, vo, 0u), b = bload4(rgtr, vo + 16u, 0u);
+    float gn[8];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      gx[v] = 0.5f * (gx[v] + a.x[v]);
-      gy[v] = 0.5f * (gy[v] + b.x[v]);
+      gn[v] = a.x[v];
+      gn[4 + v] = b.x[v];
+    }
+    if (grad_shared<N>()) {
+      // the neighbour's side of the array: xi = 1 / eta = 1 for faces 1, 2
+      const int side = (nf == 1u || nf == 2u) ? 1 : 0;
+      const float *xs = X + (side * 8 * N + p) * EB + int(nb & uint32_t(EB - 1));
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const float t = xs[c * N * EB];
+        gn[c] += inb ? t : 0.f;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      gx[v] = 0.5f * (gx[v] + gn[v]);
+      gy[v] = 0.5f * (gy[v] + gn[4 + v]);
     }
   }
   visc_flux_n<float>(qc, gx, gy, G.nx, G.ny, P.gamma, P.iR, P.mu, P.kcond, fv);
@@ -175,12 +241,18 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
                                            const RKCoef &C, int tile, bool active = true) {
   __shared__ float S_[TPB][4][N][N][EB];    // state of the group's elements
   __shared__ float SR_[TPB][4][N][N][EB];   // xi part of the residual, then the new state
+  // viscous, grad_shared<N>(): the gradient traces of the current phase's
+  // faces, [side][8][point][lane]; point w is written and read by wave w
+  // alone (in order within the wave), so it needs no barrier
+  constexpr bool GS = VISC && grad_shared<N>();
+  __shared__ float X_[TPB][GS ? 2 * 8 * N * EB : 1];
   // the wave index and the group are uniform across the wave: say so, so
   // that offsets derived from them live in SGPRs
   const int grp = TPB > 1 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) / (EB * N)) : 0;
   float(&S)[4][N][N][EB] = S_[grp];
   float(&SR)[4][N][N][EB] = SR_[grp];
   const float *Sf = &S[0][0][0][0];
+  float *X = GS ? X_[grp] : nullptr;
   const int l = threadIdx.x & (EB - 1);
   const int w = __builtin_amdgcn_readfirstlane((int(threadIdx.x) / EB) % N);
   const int e0 = tile * EB + l;
@@ -305,6 +377,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
       t0[v] = s0;
       tN[v] = sN;
     }
+    if (GS) share_traces<N>(T, gr, X, w, l);
     __syncthreads();   // the block's state is in LDS
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
@@ -327,7 +400,8 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
           for (int i = 0; i < N; ++i) acc += T.I[k][i] * gr[c][i];
           gf[c] = acc;
         }
-        common_visc<N>(M, P, rgtr, rmv, fw, w, side ? tN : t0, qx, side ? x1 : x3, gf, G, fv);
+        common_visc<N>(M, P, rgtr, 2u * tbytes, rmv, X, fw, side ? 1 : 3, w, side ? tN : t0, qx,
+                       side ? x1 : x3, gf, G, fv);
 #pragma unroll
         for (int v = 0; v < 4; ++v) f[v] += fv[v];
       }
@@ -358,6 +432,12 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
 #pragma unroll
         for (int j = 0; j < N; ++j) gc[c][j] = bload(rG, vg, ((c * N + j) * N + w) * rowb);
     }
+    if (GS) {
+      share_traces<N>(T, gc, X, w, l);
+      // keeps the scheduler from hoisting the column loop's work above the
+      // exchange (registers: the viscous N = 4 stage stays at 3 waves/SIMD)
+      __builtin_amdgcn_sched_barrier(0);
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -365,8 +445,11 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
         qc[v][j] = S[v][j][w][l];
         rc[v][j] = SR[v][j][w][l];
       }
+    // viscous stages take the interior flux points first and the two faces
+    // last, so that the face gradient traces are live only at the end
 #pragma unroll
-    for (int k = 0; k <= N; ++k) {
+    for (int kk = 0; kk <= N; ++kk) {
+      const int k = !VISC ? kk : kk < N - 1 ? kk + 1 : kk == N - 1 ? 0 : N;
       float qf[4], f[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -397,7 +480,8 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
         common_flux(M, fw, qf, qx, k == 0 ? x0 : x2, G, f);
         if (VISC) {
           float fv[4];
-          common_visc<N>(M, P, rgtr, rmv, fw, w, qf, qx, k == 0 ? x0 : x2, gf, G, fv);
+          common_visc<N>(M, P, rgtr, 2u * tbytes, rmv, X, fw, k == 0 ? 0 : 2, w, qf, qx,
+                         k == 0 ? x0 : x2, gf, G, fv);
 #pragma unroll
           for (int v = 0; v < 4; ++v) f[v] += fv[v];
         }
@@ -548,8 +632,8 @@ __global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotatio
 //   polynomials through the solution interpolated to the interior flux
 //   points and the common solution at the element's faces (eqs. Ft, Gt
 //   applied to Q); grad Q follows by the chain rule with the SP metrics.
-// Outputs: grad Q at the SPs, G [(c*4+v)][j][i][E]; gradient traces of
-// conforming and sliding faces, gtr [face][E][point][8].
+// Outputs: grad Q at the SPs, G [(c*4+v)][j][i][E]; gradient traces,
+// gtr [face][E][point][8], of the faces grad_exported names.
 // Same block and wave organisation as k_stage.
 // ---------------------------------------------------------------------------
 template <int N>
@@ -725,11 +809,11 @@ __device__ __forceinline__ void grad_tile(const DevMesh &M, const OpTables &T, c
         f2[c] += T.I[N][j] * gcol[c][j];
       }
     }
-    if (grad_exported(fw0)) {
+    if (grad_exported<N>(fw0, 0)) {
       bstore4(f0, rgtr, gvo, 0 * gfs);
       bstore4(f0 + 4, rgtr, gvo + 16u, 0 * gfs);
     }
-    if (grad_exported(fw2)) {
+    if (grad_exported<N>(fw2, 2)) {
       bstore4(f2, rgtr, gvo, 2 * gfs);
       bstore4(f2 + 4, rgtr, gvo + 16u, 2 * gfs);
     }
@@ -742,7 +826,7 @@ __device__ __forceinline__ void grad_tile(const DevMesh &M, const OpTables &T, c
   __syncthreads();
 
   // ---- gradient traces of faces xi = 0, 1 at point w from row w
-  const bool gx1 = grad_exported(fw1), gx3 = grad_exported(fw3);
+  const bool gx1 = grad_exported<N>(fw1, 1), gx3 = grad_exported<N>(fw3, 3);
   if (valid && (gx1 || gx3)) {
     float f1[8], f3[8];
 #pragma unroll
