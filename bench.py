@@ -197,8 +197,10 @@ def mlp_kernels_main(args):
 
 def subgrid_main(args):
     """The learned-correction workload end to end: fine runs for training
-    data, training, then plain SSD runs and the corrected coarse run over one
-    evaluation interval, with the speedup at equal error."""
+    data, training, rounds of training on rows taken along the corrected
+    coarse runs (a posteriori), then plain SSD runs and the corrected coarse
+    run over one evaluation interval, with the speedup at equal error on the
+    plain runs' cost-error front."""
     import torch
     from paper_1503_02198_amd import MLP
     from paper_1503_02198_amd import subgrid as G
@@ -206,7 +208,7 @@ def subgrid_main(args):
     cfg = dict(K=64, n_in=8, n_out=16, runs=4, snapshots=500, window=(0.5, 1.0), epochs=40,
                batch=4096, lr=2e-3, noise=0.1, eval_window=(args.eval_t0, args.eval_t1),
                seed=20150307, per_step=True, rounds=args.aposteriori_rounds,
-               traj_snapshots=250, relax_rate=args.relax_rate, retrain=not args.resume,
+               traj_snapshots=250, relax_rate=args.relax_rate, retrain=args.retrain,
                ft_epochs=args.ft_epochs, ft_lr=1e-3)
     meshes = G.ellipse_pair(cfg["K"], cfg["n_in"], cfg["n_out"])
     rng = np.random.default_rng(cfg["seed"])
@@ -254,16 +256,18 @@ def subgrid_main(args):
     if rounds:
         rounds[-1]["err"] = res["learned"][0]["err"]
     print(json.dumps({
-        "metric": "learned-coarse vs plain SSD: wall-clock speedup at equal error",
-        "value": sp["speedup"], "unit": "x", "n_gpus": 1, "higher_is_better": True,
+        "metric": "learned-coarse vs plain SSD: wall-clock speedup at equal error (interpolated "
+                  "on the plain runs' cost-error front)",
+        "value": sp["speedup_interpolated"], "unit": "x", "n_gpus": 1, "higher_is_better": True,
         "dtype": "f32 state, bf16 network products (f32 accumulate)", "data": "synthetic",
         "config": {"workload": "viscous rotating ellipse (axes 1 x 0.2, isothermal wall, Mach 0.2, "
                                "Re 1000), coarse 64 x (8 + 16) cells N=3, nested fine mesh N=6; "
                                "rotation rates uniform [0.5, 2] in the convective unit",
                    **{k: v for k, v in cfg.items()}, "rates": rates.tolist(),
                    "rate_eval": rate_eval, "training_rows": rows},
-        "speedup_interpolated": sp["speedup_interpolated"],
-        "learned_err": sp["err"], "plain_run_at_equal_error": sp["plain_run"],
+        "speedup_vs_cheapest_plain_run_at_most_that_error": sp["speedup"],
+        "learned_err": sp["err"], "plain_run_at_most_that_error": sp["plain_run"],
+        "plain_run_err": sp["plain_err"],
         "runs": [{k: r[k] for k in ("run", "s", "err", "dof")} for r in res["plain"] + res["learned"]],
         "fallback": res["learned"][0]["fallback"],
         "training": {"loss_first_epoch": losses[0], "loss_last_epoch": losses[-1],
@@ -505,9 +509,9 @@ def main():
     ap.add_argument("--relax-rate", type=float, default=0.0,
                     help="relaxation rate towards the restricted fine state in the a posteriori "
                          "targets (0: none)")
-    ap.add_argument("--resume", action="store_true",
-                    help="a posteriori rounds continue from the current weights instead of "
-                         "training afresh on all rows")
+    ap.add_argument("--retrain", action="store_true",
+                    help="a posteriori rounds train afresh on all rows instead of continuing "
+                         "from the current weights")
     ap.add_argument("--ft-epochs", type=int, default=15)
     ap.add_argument("--eval-t0", type=float, default=0.5)
     ap.add_argument("--eval-t1", type=float, default=0.7)
