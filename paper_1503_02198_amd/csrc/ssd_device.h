@@ -38,6 +38,17 @@ __device__ __forceinline__ void bstore4(const float x[4], rsrc_t r, uint32_t vof
   __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, t), r, voff, soff, 0);
 }
 
+// Streaming forms: the non-temporal cache policy (bit 1 of the policy
+// operand on gfx950), for large arrays a kernel touches once, so that they
+// do not push out of the caches what this or the next kernel reads again.
+constexpr int kNT = 2;
+__device__ __forceinline__ float bload_nt(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, kNT));
+}
+__device__ __forceinline__ void bstore_nt(float x, rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), r, voff, soff, kNT);
+}
+
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // A wave-uniform float as an opaque register value.

@@ -283,7 +283,12 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
   const uint32_t rowb = nbt * 4u;
   const long E = M.E;
 
-  // ---- everything the element needs from memory, issued up front
+  // ---- everything the element needs from memory, issued up front.  The
+  // state arrays (Q_k, Qn and the stage's output, and the RK increments)
+  // are read or written once per launch and are far larger than the
+  // caches: they take the non-temporal policy, so that they do not push out
+  // the face words, geometry and face traces, which every stage reads again,
+  // nor (viscous) the gradient rows the column phase reads a second time.
   const uint32_t fw0 = M.face[cb_index32(uint32_t(e), 0u, 4u, uint32_t(E))];
   const uint32_t fw1 = M.face[cb_index32(uint32_t(e), 1u, 4u, uint32_t(E))];
   const uint32_t fw2 = M.face[cb_index32(uint32_t(e), 2u, 4u, uint32_t(E))];
@@ -292,7 +297,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
 #pragma unroll
   for (int v = 0; v < 4; ++v)
 #pragma unroll
-    for (int i = 0; i < N; ++i) qr[v][i] = bload(rq, vs, ((v * N + w) * N + i) * rowb);
+    for (int i = 0; i < N; ++i) qr[v][i] = bload_nt(rq, vs, ((v * N + w) * N + i) * rowb);
   const ElemGeo g = load_geo(M, e, R);
   float x0[4], x1[4], x2[4], x3[4];
   prefetch_face<N>(M, rtin, fbytes, tbytes, uint32_t(M.E), fw3, w, x3);   // row faces xi = 0, 1 at point w
@@ -307,7 +312,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int j = 0; j < N; ++j) qo[v][j] = bload(rqn, vs, ((v * N + j) * N + w) * rowb);
+      for (int j = 0; j < N; ++j) qo[v][j] = bload_nt(rqn, vs, ((v * N + j) * N + w) * rowb);
   }
   float qa[4][N];   // column w of the added increment (ADD)
   if (RK && ADD) {
@@ -315,7 +320,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int j = 0; j < N; ++j) qa[v][j] = bload(radd, vs, ((v * N + j) * N + w) * rowb);
+      for (int j = 0; j < N; ++j) qa[v][j] = bload_nt(radd, vs, ((v * N + j) * N + w) * rowb);
   }
 
   // ---- row phase
@@ -425,12 +430,12 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
   }
   {
     const LineGeo Lc = line_eta(g, float(T.X[w]));  // bilinear-cell metrics along column w
-    float gc[8][N];   // gradient on column w
+    float gc[8][N];   // gradient on column w (its last read: non-temporal)
     if (VISC) {
 #pragma unroll
       for (int c = 0; c < 8; ++c)
 #pragma unroll
-        for (int j = 0; j < N; ++j) gc[c][j] = bload(rG, vg, ((c * N + j) * N + w) * rowb);
+        for (int j = 0; j < N; ++j) gc[c][j] = bload_nt(rG, vg, ((c * N + j) * N + w) * rowb);
     }
     if (GS) {
       share_traces<N>(T, gc, X, w, l);
@@ -511,7 +516,8 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int j = 0; j < N; ++j) bstore(rc[v][j] * ij[j], rout, vs, ((v * N + j) * N + w) * rowb);
+        for (int j = 0; j < N; ++j)
+          bstore_nt(rc[v][j] * ij[j], rout, vs, ((v * N + j) * N + w) * rowb);
     }
     return;
   }
@@ -523,14 +529,14 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int j = 0; j < N; ++j) qo[v][j] = bload(rqn, vs, ((v * N + j) * N + w) * rowb);
+      for (int j = 0; j < N; ++j) qo[v][j] = bload_nt(rqn, vs, ((v * N + j) * N + w) * rowb);
   }
   float u2[4][N];   // (COMB) column w of U2, loaded late for the same reason
   if (COMB) {
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int j = 0; j < N; ++j) u2[v][j] = bload(rcomb, vs, ((v * N + j) * N + w) * rowb);
+      for (int j = 0; j < N; ++j) u2[v][j] = bload_nt(rcomb, vs, ((v * N + j) * N + w) * rowb);
   }
   bool bad = false;
 #pragma unroll
@@ -556,12 +562,12 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
-      for (int j = 0; j < N; ++j) bstore(qc[v][j], rout, vs, ((v * N + j) * N + w) * rowb);
+      for (int j = 0; j < N; ++j) bstore_nt(qc[v][j], rout, vs, ((v * N + j) * N + w) * rowb);
     if (COMB) {
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int j = 0; j < N; ++j) bstore(u2[v][j], rcomb, vs, ((v * N + j) * N + w) * rowb);
+        for (int j = 0; j < N; ++j) bstore_nt(u2[v][j], rcomb, vs, ((v * N + j) * N + w) * rowb);
     }
     if (bad) M.flag[0] = 1;
   }
