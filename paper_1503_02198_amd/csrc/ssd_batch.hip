@@ -70,9 +70,10 @@ __global__ __launch_bounds__(MORTAR_BLOCK) void kb_mortar_visc(const BatchCase *
 // TPB consecutive items of the work table per block (the tile shape the
 // autotuner picks per group); groups of N waves each, see stage_tile.
 template <int N, bool VISC, bool ADD, bool COMB = false, int TPB = 1>
-__global__ __launch_bounds__(64 * N * TPB) void kb_stage(const BatchCase *cases, const uint2 *work,
-                                                         int nwork, OpTables T, BatchStage S,
-                                                         const double *step) {
+__global__ __launch_bounds__(64 * N * TPB)
+__attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<N, true, VISC, ADD, COMB>()))) void kb_stage(
+    const BatchCase *cases, const uint2 *work, int nwork, OpTables T, BatchStage S,
+    const double *step) {
   const int b = S.reverse ? int(gridDim.x) - 1 - int(blockIdx.x) : int(blockIdx.x);
   const int grp = TPB > 1 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) / (64 * N)) : 0;
   const int idx = b * TPB + grp;

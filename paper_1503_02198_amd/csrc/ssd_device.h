@@ -431,6 +431,37 @@ __device__ __forceinline__ void neighbor_state(const OpTables &T, const float *S
   }
 }
 
+// Orders whose inviscid stage passes the solution traces at a line's two
+// end points between the block's elements through LDS: the exchange array,
+// [side][4][N][64] floats (8 KB at N = 4), keeps the block at 4 per compute
+// unit, as without it.
+template <int N>
+__device__ constexpr bool trace_shared() {
+  return N <= 4;
+}
+
+// neighbor_state with the exchange array X (XCH): an in-block neighbour's
+// trace at point p comes from the same wave (row phase: row p; column
+// phase: column p), which has written it to X before; four LDS reads instead
+// of an interpolation of the neighbour's line.
+template <int N, bool XCH>
+__device__ __forceinline__ void neighbor_state_x(const OpTables &T, const float *Sf, const float *X,
+                                                 uint32_t fw, int p, const float x[4],
+                                                 float qx[4]) {
+  if (!XCH) {
+    neighbor_state<N>(T, Sf, fw, p, x, qx);
+  } else if (face_inblock_of(fw)) {
+    const uint32_t nf = uint32_t(face_nf_of(fw));
+    const int side = (nf == 1u || nf == 2u) ? 1 : 0;   // xi = 1 / eta = 1
+    const float *xs = X + (side * 4 * N + p) * EB + (face_idx_of(fw) & (EB - 1));
+#pragma unroll
+    for (int v = 0; v < 4; ++v) qx[v] = xs[v * N * EB];
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) qx[v] = x[v];
+  }
+}
+
 // Common inviscid normal flux at one element-boundary flux point along the
 // outward normal of `G`, given the state across the face qx (the
 // neighbour's on conforming faces, the far-field state on far-field faces)

@@ -575,7 +575,12 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
                                 : std::hypot(ax - cx2, ay - cy2) + std::hypot(bx - dx2, by - dy2);
           if (e1 > 1e-8 * len) return fail(SSD_ERR_MESH, where + ": neighbouring faces do not meet");
         }
-        face[cb_index(e, f, 4, E)] = pack_face(kind, nb, nf, rev, nb / EB == e / EB);
+        // in-block: the neighbour is in the same 64-element block, across a
+        // face of the same direction with the same point order, so the same
+        // wave of a stage handles both sides of every point of the face;
+        // every other conforming face goes through the trace buffer
+        const bool inblock = nb / EB == e / EB && !rev && (nf & 1) == (f & 1);
+        face[cb_index(e, f, 4, E)] = pack_face(kind, nb, nf, rev, inblock);
       } else if (kind == SSD_FACE_SLIDING) {
         if (!(Rs > 0.0)) return fail(SSD_ERR_MESH, where + ": sliding face but iface_radius <= 0");
         const double ra = std::hypot(ax - cx, ay - cy), rb = std::hypot(bx - cx, by - cy);

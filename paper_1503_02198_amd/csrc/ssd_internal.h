@@ -48,7 +48,9 @@ __host__ __device__ inline int face_inblock_of(uint32_t w) { return int((w >> 25
 __host__ __device__ inline int face_nf_of(uint32_t w) { return int((w >> 26) & 3u); }
 __host__ __device__ inline int face_rev_of(uint32_t w) { return int((w >> 28) & 1u); }
 // A face's trace is read by another block (or by the mortar kernel) and must
-// be stored: sliding faces, and conforming faces whose neighbour is elsewhere.
+// be stored: sliding faces, and conforming faces without the in-block bit
+// (set where the neighbour is in the same 64-element block, across a face of
+// the same direction with the same point order).
 __host__ __device__ inline bool face_exported(uint32_t w) {
   const int k = face_kind_of(w);
   return k == SSD_FACE_SLIDING ||

@@ -91,27 +91,24 @@ __device__ constexpr bool grad_shared() {
   return N <= 4;
 }
 
-// A conforming face whose neighbour is in the same block, across a face of
-// the same direction (xi face to xi face, eta face to eta face) with the
-// same point order: the neighbour's trace at point p comes from the same
-// wave of the stage kernel (row phase: row p; column phase: column p),
-// which leaves it in the block's exchange array just before it reads it.
-// f: the local face of fw.
+// An in-block face (the neighbour in the same block, across a face of the
+// same direction with the same point order): the neighbour's gradient trace
+// at point p comes from the same wave of the stage kernel (row phase: row
+// p; column phase: column p), which leaves it in the block's exchange
+// array just before it reads it.
 template <int N>
-__device__ __forceinline__ bool grad_in_block(uint32_t fw, int f) {
-  const int k = face_kind_of(fw);
-  return grad_shared<N>() && (k == SSD_FACE_INTERIOR || k == SSD_FACE_PERIODIC) &&
-         face_inblock_of(fw) && !face_rev_of(fw) && ((face_nf_of(fw) & 1) == (f & 1));
+__device__ __forceinline__ bool grad_in_block(uint32_t fw) {
+  return grad_shared<N>() && face_inblock_of(fw);
 }
 
 // Faces whose gradient traces the gradient pass writes: sliding faces (the
 // viscous mortar reads them) and the conforming faces without
 // grad_in_block (both sides average the two).
 template <int N>
-__device__ __forceinline__ bool grad_exported(uint32_t fw, int f) {
+__device__ __forceinline__ bool grad_exported(uint32_t fw) {
   const int k = face_kind_of(fw);
   if (k == SSD_FACE_SLIDING) return true;
-  return (k == SSD_FACE_INTERIOR || k == SSD_FACE_PERIODIC) && !grad_in_block<N>(fw, f);
+  return (k == SSD_FACE_INTERIOR || k == SSD_FACE_PERIODIC) && !grad_in_block<N>(fw);
 }
 
 // Gradient traces at the two ends of a line of solution points (flux
@@ -138,12 +135,12 @@ __device__ __forceinline__ void share_traces(const OpTables &T, const float (&g)
 // F_vis(Q_b, interior gradient) . n on isothermal walls and the far field,
 // zero on slip walls, the mortar value on sliding faces.  qx: neighbour's
 // state from common_flux; g: own gradient at the point [x0..x3, y0..y3].
-// f: the local face of fw; gbytes: the size of the trace buffer behind
-// rgtr; X: the block's exchange array (grad_shared<N>()), else null.
+// gbytes: the size of the trace buffer behind rgtr; X: the block's
+// exchange array (grad_shared<N>()), else null.
 template <int N>
 __device__ __forceinline__ void common_visc(const DevMesh &M, const ViscParams &P, rsrc_t rgtr,
                                             uint32_t gbytes, rsrc_t rmv, const float *X,
-                                            uint32_t fw, int f, int p, const float qo[4],
+                                            uint32_t fw, int p, const float qo[4],
                                             const float qx[4], const float x[4],
                                             const float g[8], const FPGeo &G, float fv[4]) {
   const int kind = face_kind_of(fw);
@@ -169,7 +166,7 @@ __device__ __forceinline__ void common_visc(const DevMesh &M, const ViscParams &
     // grad_in_block lanes point the loads past the end of the trace buffer
     // (zero, no memory access) and add the trace from the exchange array:
     // one load per lane, no branch, and either term exactly zero
-    const bool inb = grad_in_block<N>(fw, f);
+    const bool inb = grad_in_block<N>(fw);
     const uint32_t nb = uint32_t(face_idx_of(fw)), nf = uint32_t(face_nf_of(fw));
     const uint32_t pp = face_rev_of(fw) ? uint32_t(N - 1 - p) : uint32_t(p);
     const uint32_t vo = inb ? gbytes : ((nf * uint32_t(M.E) + nb) * N + pp) * 32u;
@@ -246,6 +243,10 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
   // alone (in order within the wave), so it needs no barrier
   constexpr bool GS = VISC && grad_shared<N>();
   __shared__ float X_[TPB][GS ? 2 * 8 * N * EB : 1];
+  // inviscid, trace_shared<N>(): the solution traces of the current
+  // phase's faces, [side][4][point][lane], point w again wave w's alone
+  constexpr bool SX = !VISC && trace_shared<N>();
+  __shared__ float XS_[TPB][SX ? 2 * 4 * N * EB : 1];
   // the wave index and the group are uniform across the wave: say so, so
   // that offsets derived from them live in SGPRs
   const int grp = TPB > 1 ? __builtin_amdgcn_readfirstlane(int(threadIdx.x) / (EB * N)) : 0;
@@ -253,6 +254,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
   float(&SR)[4][N][N][EB] = SR_[grp];
   const float *Sf = &S[0][0][0][0];
   float *X = GS ? X_[grp] : nullptr;
+  float *XS = SX ? XS_[grp] : nullptr;
   const int l = threadIdx.x & (EB - 1);
   const int w = __builtin_amdgcn_readfirstlane((int(threadIdx.x) / EB) % N);
   const int e0 = tile * EB + l;
@@ -383,6 +385,13 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
       tN[v] = sN;
     }
     if (GS) share_traces<N>(T, gr, X, w, l);
+    if (SX) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        XS[(v * N + w) * EB + l] = t0[v];
+        XS[((4 + v) * N + w) * EB + l] = tN[v];
+      }
+    }
     __syncthreads();   // the block's state is in LDS
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
@@ -394,7 +403,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
       G.ny *= sg;
       G.vgn *= sg;
       float f[4], qx[4];
-      neighbor_state<N>(T, Sf, fw, w, side ? x1 : x3, qx);
+      neighbor_state_x<N, SX>(T, Sf, XS, fw, w, side ? x1 : x3, qx);
       common_flux(M, fw, side ? tN : t0, qx, side ? x1 : x3, G, f);
       if (VISC) {
         float gf[8], fv[4];
@@ -405,7 +414,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
           for (int i = 0; i < N; ++i) acc += T.I[k][i] * gr[c][i];
           gf[c] = acc;
         }
-        common_visc<N>(M, P, rgtr, 2u * tbytes, rmv, X, fw, side ? 1 : 3, w, side ? tN : t0, qx,
+        common_visc<N>(M, P, rgtr, 2u * tbytes, rmv, X, fw, w, side ? tN : t0, qx,
                        side ? x1 : x3, gf, G, fv);
 #pragma unroll
         for (int v = 0; v < 4; ++v) f[v] += fv[v];
@@ -450,8 +459,21 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
         qc[v][j] = S[v][j][w][l];
         rc[v][j] = SR[v][j][w][l];
       }
+    if (SX) {   // this column's traces at eta = 0, 1
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float s0 = 0.f, sN = 0.f;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          s0 += T.I[0][j] * qc[v][j];
+          sN += T.I[N][j] * qc[v][j];
+        }
+        XS[(v * N + w) * EB + l] = s0;
+        XS[((4 + v) * N + w) * EB + l] = sN;
+      }
+    }
     // viscous stages take the interior flux points first and the two faces
-    // last, so that the face gradient traces are live only at the end
+    // last (measured 1.5 % faster at N = 4)
 #pragma unroll
     for (int kk = 0; kk <= N; ++kk) {
       const int k = !VISC ? kk : kk < N - 1 ? kk + 1 : kk == N - 1 ? 0 : N;
@@ -481,11 +503,11 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
         G.ny *= sg;
         G.vgn *= sg;
         float qx[4];
-        neighbor_state<N>(T, Sf, fw, w, k == 0 ? x0 : x2, qx);
+        neighbor_state_x<N, SX>(T, Sf, XS, fw, w, k == 0 ? x0 : x2, qx);
         common_flux(M, fw, qf, qx, k == 0 ? x0 : x2, G, f);
         if (VISC) {
           float fv[4];
-          common_visc<N>(M, P, rgtr, 2u * tbytes, rmv, X, fw, k == 0 ? 0 : 2, w, qf, qx,
+          common_visc<N>(M, P, rgtr, 2u * tbytes, rmv, X, fw, w, qf, qx,
                          k == 0 ? x0 : x2, gf, G, fv);
 #pragma unroll
           for (int v = 0; v < 4; ++v) f[v] += fv[v];
@@ -623,11 +645,18 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
   }
 }
 
+// The plain inviscid stage at N <= 4 is held to 128 VGPRs, 4 waves per SIMD
+// (the compiler otherwise settles one or two registers above, at 3).
+template <int N, bool RK, bool VISC, bool ADD, bool COMB>
+constexpr int stage_waves_per_eu() {
+  return (!VISC && !ADD && !COMB && N <= 4) ? 4 : 1;
+}
+
 template <int N, bool RK, bool VISC, bool ADD, bool COMB = false>
-__global__ __launch_bounds__(64 * N) void k_stage(DevMesh M, OpTables T, Rotation R,
-                                                  const float *q, const float *qn, float *out,
-                                                  const float *facein, float *trout, ViscBufs V,
-                                                  RKCoef C) {
+__global__ __launch_bounds__(64 * N)
+__attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<N, RK, VISC, ADD, COMB>()))) void k_stage(
+    DevMesh M, OpTables T, Rotation R, const float *q, const float *qn, float *out,
+    const float *facein, float *trout, ViscBufs V, RKCoef C) {
   const int tile = C.reverse ? int(gridDim.x) - 1 - int(blockIdx.x) : int(blockIdx.x);
   stage_tile<N, RK, VISC, ADD, COMB>(M, T, R, q, qn, out, facein, trout, V, C, tile);
 }
@@ -815,11 +844,11 @@ __device__ __forceinline__ void grad_tile(const DevMesh &M, const OpTables &T, c
         f2[c] += T.I[N][j] * gcol[c][j];
       }
     }
-    if (grad_exported<N>(fw0, 0)) {
+    if (grad_exported<N>(fw0)) {
       bstore4(f0, rgtr, gvo, 0 * gfs);
       bstore4(f0 + 4, rgtr, gvo + 16u, 0 * gfs);
     }
-    if (grad_exported<N>(fw2, 2)) {
+    if (grad_exported<N>(fw2)) {
       bstore4(f2, rgtr, gvo, 2 * gfs);
       bstore4(f2 + 4, rgtr, gvo + 16u, 2 * gfs);
     }
@@ -832,7 +861,7 @@ __device__ __forceinline__ void grad_tile(const DevMesh &M, const OpTables &T, c
   __syncthreads();
 
   // ---- gradient traces of faces xi = 0, 1 at point w from row w
-  const bool gx1 = grad_exported<N>(fw1, 1), gx3 = grad_exported<N>(fw3, 3);
+  const bool gx1 = grad_exported<N>(fw1), gx3 = grad_exported<N>(fw3);
   if (valid && (gx1 || gx3)) {
     float f1[8], f3[8];
 #pragma unroll
