@@ -366,11 +366,11 @@ __device__ __forceinline__ float inv_jacobian(const ElemGeo &g, const DevMesh &M
 // face data
 // ---------------------------------------------------------------------------
 // What a face needs from outside the block, fetched before it is used: the
-// neighbour's trace (a neighbour in another block), the far-field state, or
+// neighbour's trace (a face without the in-block bit), the far-field state, or
 // the interface record (projected mortar flux, or projected common
 // solution) of a sliding face.  Traces and interface records share one face
 // data buffer (rface, `bytes` long), the records from byte `side_base`.
-// Faces whose neighbour is in the same block, and walls, need nothing: their
+// In-block faces, and walls, need nothing: their
 // lanes point the load past the end of the buffer, where a buffer load
 // returns zero without a memory access.  One load per lane, no branch.
 template <int N>
@@ -396,8 +396,8 @@ __device__ __forceinline__ bool conforming(int kind) {
 }
 
 // The neighbour's solution at the face point matching point p of face word
-// fw: interpolated from the block's LDS state Sf [var][j][i][lane] when the
-// neighbour is in the same block, else the prefetched value.
+// fw: interpolated from the block's LDS state Sf [var][j][i][lane] for an
+// in-block face, else the prefetched value.
 template <int N>
 __device__ __forceinline__ void neighbor_state(const OpTables &T, const float *Sf, uint32_t fw,
                                                int p, const float x[4], float qx[4]) {

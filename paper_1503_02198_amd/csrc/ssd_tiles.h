@@ -220,10 +220,13 @@ __device__ __forceinline__ void common_visc(const DevMesh &M, const ViscParams &
 //   pack phase   the face records some other block reads, computed from the
 //                new state in LDS, one face per wave, whole records per
 //                element
-// A neighbour in the same block is read from the block's LDS state, any
-// other through the trace buffer.  LDS arrays are [var][j][i][lane]: every
-// LDS access of a wave to its own elements touches 64 distinct banks.
-// Global accesses of a wave are contiguous 256-byte rows.
+// An in-block neighbour's trace (face word bit: same block, same
+// direction, same point order) comes from the exchange array the same wave
+// filled with its own line's end traces (inviscid, N <= 4), or is
+// interpolated from the block's LDS state; any other neighbour's comes
+// through the trace buffer.  LDS arrays are [var][j][i][lane]: every LDS
+// access of a wave to its own elements touches 64 distinct banks.  Global
+// accesses of a wave are contiguous 256-byte rows.
 // ---------------------------------------------------------------------------
 //
 // TPB tiles per block (batched stage): the block's waves form TPB groups of
