@@ -209,6 +209,7 @@ def subgrid_main(args):
                batch=4096, lr=2e-3, noise=0.1, eval_window=(args.eval_t0, args.eval_t1),
                seed=20150307, per_step=True, rounds=args.aposteriori_rounds,
                traj_snapshots=250, relax_rate=args.relax_rate, retrain=args.retrain,
+               resync=args.resync,
                ft_epochs=args.ft_epochs, ft_lr=1e-3)
     meshes = G.ellipse_pair(cfg["K"], cfg["n_in"], cfg["n_out"])
     rng = np.random.default_rng(cfg["seed"])
@@ -234,7 +235,8 @@ def subgrid_main(args):
     for r in range(cfg["rounds"]):
         Xt, Tt, gs, restarts = G.generate_trajectory(
             meshes, G.convective_omega(rates), net, cfg["window"][0], cfg["window"][1],
-            cfg["traj_snapshots"], cfg["relax_rate"], per_step=cfg["per_step"], log=log)
+            cfg["traj_snapshots"], cfg["relax_rate"], per_step=cfg["per_step"], log=log,
+            resync=cfg["resync"])
         X, T = torch.cat([X, Xt]), torch.cat([T, Tt])
         del Xt, Tt
         rows = X.numel() // 84
@@ -512,6 +514,9 @@ def main():
     ap.add_argument("--retrain", action="store_true",
                     help="a posteriori rounds train afresh on all rows instead of continuing "
                          "from the current weights")
+    ap.add_argument("--resync", type=float, default=0.0,
+                    help="a posteriori rows: restart the corrected coarse runs from the restricted "
+                         "fine state every RESYNC time units (0: only on failure)")
     ap.add_argument("--ft-epochs", type=int, default=15)
     ap.add_argument("--eval-t0", type=float, default=0.5)
     ap.add_argument("--eval-t1", type=float, default=0.7)

@@ -173,7 +173,7 @@ def generate(meshes, omegas, t_start, t_end, n_snap, Nc=3, Nf=6, log=None):
 
 
 def generate_trajectory(meshes, omegas, net, t_start, t_end, n_snap, rate=0.0, weight=1.0,
-                        per_step=True, Nc=3, Nf=6, log=None):
+                        per_step=True, Nc=3, Nf=6, log=None, resync=0.0):
     """Training rows along corrected coarse runs (a posteriori training): the
     fine runs, one per rotation rate, stepped together as one batch as in
     `generate`, and beside each the coarse run with `net` attached, started
@@ -183,8 +183,10 @@ def generate_trajectory(meshes, omegas, net, t_start, t_end, n_snap, rate=0.0, w
     correction that gives the coarse run the restricted fine dQ/dt at its
     own state (and, with rate > 0, pulls it back to the restricted fine
     state).  A coarse run that fails its check (ssd_check) restarts from
-    the restricted fine state.  Returns (X, T) on the GPU, the seconds spent
-    and the number of restarts."""
+    the restricted fine state, and with resync > 0 every coarse run restarts
+    from it each resync time units (the rows then come from coarse states no
+    older than that).  Returns (X, T) on the GPU, the seconds spent and the
+    number of restarts."""
     import torch
     from workloads import cases as C
     from .ssd import Batch, SSDError
@@ -208,6 +210,7 @@ def generate_trajectory(meshes, omegas, net, t_start, t_end, n_snap, rate=0.0, w
     qcs = [P.restrict(q) for P, q in zip(pairs, qs)]
     wcs = [P.work(P.coarse) for P in pairs]
     k, restarts = 0, 0
+    t_sync = t
     try:
         for P in pairs:
             P.coarse.attach(net, weight, per_step=per_step)
@@ -222,6 +225,9 @@ def generate_trajectory(meshes, omegas, net, t_start, t_end, n_snap, rate=0.0, w
                         qcs[j] = P.restrict(qs[j])
                         restarts += 1
                 t += gap * dt
+                if resync > 0.0 and t - t_sync >= resync - 1e-12:
+                    qcs = [P.restrict(q) for P, q in zip(pairs, qs)]
+                    t_sync = t
             for j, P in enumerate(pairs):
                 P.sample(qs[j], t, X[k * Ec * n_in:(k + 1) * Ec * n_in],
                          T[k * Ec * n_out:(k + 1) * Ec * n_out], qc=qcs[j], rate=rate)
