@@ -283,8 +283,8 @@ def train(net, X, T, epochs, batch, lr, seed, log=None, min_rel=1e-2, noise=0.0,
     return losses, time.perf_counter() - t0
 
 
-def evaluate(meshes, net, omega, t0, t1, Nc=3, Nf=6, fine_orders=(5, 4, 3), weights=(1.0,),
-             chunks=10, per_step=True):
+def evaluate(meshes, net, omega, t0, t1, Nc=3, Nf=6, fine_orders=(5, 4, 3), coarse_orders=(4,),
+             weights=(1.0,), chunks=10, per_step=True):
     """Plain SSD runs and the corrected coarse run over [t0, t1], all from the
     state at t0 of a fine run (N = Nf) from the free stream at t = 0.
 
@@ -293,7 +293,8 @@ def evaluate(meshes, net, omega, t0, t1, Nc=3, Nf=6, fine_orders=(5, 4, 3), weig
       * the fine mesh at each N in fine_orders, from the projection of the
         fine state onto that order;
       * the coarse mesh at N = Nc, plain, from the restriction of the fine
-        state;
+        state, and at each N in coarse_orders (higher orders on the coarse
+        mesh, the other plain way to buy accuracy);
       * the coarse mesh with the network attached, once per weight, its
         correction evaluated once per step (per_step) or in every stage;
         checked after each of `chunks` parts of the interval, and if it
@@ -344,6 +345,20 @@ def evaluate(meshes, net, omega, t0, t1, Nc=3, Nf=6, fine_orders=(5, 4, 3), weig
         qc = torch.empty(P.coarse.info["state_len"], dtype=torch.float32, device=qf.device)
         restrict(m, P.coarse, P.children, q, qc)
         runs.append(dict(run=f"fine mesh N={k}", s=s, err=err(qc), dt=dt,
+                         dof=m.info["state_len"]))
+        m.close()
+    coarse_mesh = meshes[0]
+    for k in coarse_orders:
+        m = Mesh(coarse_mesh, case, k, P.device)
+        q = torch.empty(m.info["state_len"], dtype=torch.float32, device=qf.device)
+        restrict(P.fine, m, P.children, q_start, q)
+        w = P.work(m)
+        dt = cfl_dt(coarse_mesh, case, k)
+        s = timed(lambda: advance(m, q, w, t0, dt, t1))
+        m.check()
+        qc = torch.empty(P.coarse.info["state_len"], dtype=torch.float32, device=qf.device)
+        restrict(m, P.coarse, None, q, qc)
+        runs.append(dict(run=f"coarse mesh N={k}", s=s, err=err(qc), dt=dt,
                          dof=m.info["state_len"]))
         m.close()
     wc = P.work(P.coarse)

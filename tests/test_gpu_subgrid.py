@@ -120,8 +120,9 @@ def test_features(torch_cuda, nested):
         _close(Xg, S.features(ora, Q), 1e-6, f"features N={N}")
 
 
-@pytest.mark.parametrize("Nc,Nf,split", [(3, 6, True), (2, 4, True), (3, 5, True),
-                                         (3, 6, False), (5, 6, False), (2, 3, False)])
+@pytest.mark.parametrize("Nc,Nf,split", [(3, 6, True), (2, 4, True), (3, 5, True), (4, 6, True),
+                                         (3, 6, False), (5, 6, False), (2, 3, False),
+                                         (3, 4, False)])
 def test_restrict(torch_cuda, nested, Nc, Nf, split):
     """Nested fine mesh to the coarse one, or one mesh to a lower order."""
     from paper_1503_02198_amd import Mesh, restrict
