@@ -386,9 +386,12 @@ __device__ __forceinline__ void prefetch_face(const DevMesh &M, rsrc_t rface, ui
                        : kind == SSD_FACE_SLIDING ? side_base + (idx * N + uint32_t(p)) * 16u
                                                   : bytes;
   const f4 a = bload4(rface, off, 0u);
-  const bool far = kind == SSD_FACE_FARFIELD;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) x[v] = far ? M.qinf[v] : a.x[v];
+  for (int v = 0; v < 4; ++v) x[v] = a.x[v];
+  if (__builtin_expect(kind == SSD_FACE_FARFIELD, 0)) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) x[v] = M.qinf[v];
+  }
 }
 
 __device__ __forceinline__ bool conforming(int kind) {
@@ -465,10 +468,9 @@ __device__ __forceinline__ void neighbor_state_x(const OpTables &T, const float 
 // Common inviscid normal flux at one element-boundary flux point along the
 // outward normal of `G`, given the state across the face qx (the
 // neighbour's on conforming faces, the far-field state on far-field faces)
-// and the face data x (see prefetch_face).  The Rusanov flux and the wall
-// flux are formed for every lane and the face kind selects between them
-// (values of the unselected forms are discarded), so a wave with mixed face
-// kinds runs one path.
+// and the face data x (see prefetch_face).  The Rusanov flux is formed for
+// every lane; walls and sliding faces replace it in a branch that the waves
+// without such faces (most of them) skip.
 __device__ __forceinline__ void common_flux(const DevMesh &M, uint32_t fw, const float qo[4],
                                             const float qx[4], const float x[4], const FPGeo &G,
                                             float fs[4]) {
@@ -478,9 +480,13 @@ __device__ __forceinline__ void common_flux(const DevMesh &M, uint32_t fw, const
   // walls: no flux relative to the moving wall; pressure from the interior
   const bool wall = kind == SSD_FACE_WALL_ISOTHERMAL || kind == SSD_FACE_WALL_SLIP;
   const bool sliding = kind == SSD_FACE_SLIDING;
-  const float fw4[4] = {0.0f, pr * G.nx, pr * G.ny, pr * G.vgn};
 #pragma unroll
-  for (int v = 0; v < 4; ++v) fs[v] = sliding ? x[v] : (wall ? fw4[v] : fr[v]);
+  for (int v = 0; v < 4; ++v) fs[v] = fr[v];
+  if (__builtin_expect(wall || sliding, 0)) {
+    const float fw4[4] = {0.0f, pr * G.nx, pr * G.ny, pr * G.vgn};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) fs[v] = sliding ? x[v] : fw4[v];
+  }
 }
 
 // Common solution at a face point for the gradient (BR1 reading): the mean
