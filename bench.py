@@ -204,12 +204,13 @@ def subgrid_main(args):
     import torch
     from paper_1503_02198_amd import MLP
     from paper_1503_02198_amd import subgrid as G
+    from workloads import cases as C
     log = lambda m: print("# " + m, file=sys.stderr, flush=True)
     cfg = dict(K=64, n_in=8, n_out=16, runs=4, snapshots=500, window=(0.5, 1.0), epochs=40,
                batch=4096, lr=2e-3, noise=0.1, eval_window=(args.eval_t0, args.eval_t1),
                seed=20150307, per_step=True, rounds=args.aposteriori_rounds,
                traj_snapshots=250, relax_rate=args.relax_rate, retrain=args.retrain,
-               resync=args.resync,
+               resync=args.resync, zero_free_stream=not args.no_zero_free_stream,
                ft_epochs=args.ft_epochs, ft_lr=1e-3)
     meshes = G.ellipse_pair(cfg["K"], cfg["n_in"], cfg["n_out"])
     rng = np.random.default_rng(cfg["seed"])
@@ -221,6 +222,9 @@ def subgrid_main(args):
     net = MLP(3)
     losses, train_s = G.train(net, X, T, cfg["epochs"], cfg["batch"], cfg["lr"], seed=7,
                               noise=cfg["noise"])
+    calib = G.Pair(meshes, C.ellipse_viscous_case(omega=G.convective_omega(rate_eval)))
+    if cfg["zero_free_stream"]:
+        G.zero_at_free_stream(net, calib)
     log(f"training loss {losses[0]:.4e} -> {losses[-1]:.4e} in {train_s:.2f} s")
     steps = cfg["epochs"] * (rows // cfg["batch"])
     rounds = []
@@ -248,6 +252,8 @@ def subgrid_main(args):
             ls, ts = G.train(net, X, T, cfg["ft_epochs"], cfg["batch"], cfg["ft_lr"],
                              seed=11 + r, noise=cfg["noise"], resume=True)
         train_s += ts
+        if cfg["zero_free_stream"]:
+            G.zero_at_free_stream(net, calib)
         steps += (cfg["epochs"] if cfg["retrain"] else cfg["ft_epochs"]) * (rows // cfg["batch"])
         log(f"round {r + 1}: {rows} rows, loss {ls[0]:.4e} -> {ls[-1]:.4e} in {ts:.2f} s")
         rounds.append({"round": r + 1, "training_rows": rows, "restarts": restarts,
@@ -514,9 +520,12 @@ def main():
     ap.add_argument("--retrain", action="store_true",
                     help="a posteriori rounds train afresh on all rows instead of continuing "
                          "from the current weights")
-    ap.add_argument("--resync", type=float, default=0.0,
+    ap.add_argument("--resync", type=float, default=0.2,
                     help="a posteriori rows: restart the corrected coarse runs from the restricted "
                          "fine state every RESYNC time units (0: only on failure)")
+    ap.add_argument("--no-zero-free-stream", action="store_true",
+                    help="learned-correction workload: keep the network's output offset at the "
+                         "free stream (by default it is shifted to zero after each training)")
     ap.add_argument("--ft-epochs", type=int, default=15)
     ap.add_argument("--eval-t0", type=float, default=0.5)
     ap.add_argument("--eval-t1", type=float, default=0.7)

@@ -254,6 +254,34 @@ def init_params(rng, n_in, n_out, H=MLP.HIDDEN):
                 b2=np.zeros(H, np.float32), W3=glorot(n_out, H), b3=np.zeros(n_out, np.float32))
 
 
+def zero_at_free_stream(net, pair):
+    """Shift the network's output bias so that its correction of the
+    uniform free stream of pair's case is zero.  A uniform flow has no
+    subgrid scales (both meshes preserve it), so the corrected scheme then
+    keeps it too; otherwise the fit's small offset there acts as a source in
+    every far-field cell.  Every element of a uniform state has the same
+    features; the output scale of each component is measured as the
+    response to a unit change of its bias.  Resets the Adam moments (as
+    set_params does).  Returns the correction of the free stream before the
+    shift."""
+    import torch
+    q = pair.uniform(pair.coarse)
+    X = torch.empty(pair.Ec * net.n_in, dtype=torch.float32, device=q.device)
+    pair.coarse.features(q, X)
+    x = X[:net.n_in].clone()
+    y = torch.empty(net.n_out, dtype=torch.float32, device=q.device)
+    p = net.get_params()
+    net.forward(x, y)
+    y0 = y.cpu().numpy().astype(np.float64)
+    bumped = dict(p, b3=(p["b3"] + 1.0).astype(np.float32))
+    net.set_params(bumped)
+    net.forward(x, y)
+    scale = y.cpu().numpy().astype(np.float64) - y0
+    p["b3"] = (p["b3"] - y0 / scale).astype(np.float32)
+    net.set_params(p)
+    return y0
+
+
 def train(net, X, T, epochs, batch, lr, seed, log=None, min_rel=1e-2, noise=0.0, resume=False):
     """Adam over shuffled minibatches with input noise of standard deviation
     `noise` (normalised units); the learning rate decays as a cosine to a

@@ -378,9 +378,52 @@ def test_trained_network_reduces_coarse_error(torch_cuda):
     losses, _ = G.train(net, X, T, 30, 1024, 2e-3, seed=7, noise=0.1)
     print("training loss", losses[0], "->", losses[-1], flush=True)
     assert losses[-1] < 0.5 * losses[0]
-    res = G.evaluate(meshes, net, G.convective_omega(1.2), 0.3, 0.31, fine_orders=())
-    plain = [r for r in res["plain"] if r["run"].startswith("coarse")][0]
+    res = G.evaluate(meshes, net, G.convective_omega(1.2), 0.3, 0.31, fine_orders=(),
+                     coarse_orders=())
+    plain = [r for r in res["plain"] if r["run"] == "coarse mesh N=3"][0]
     learned = res["learned"][0]
     print("coarse error plain", plain["err"], "corrected", learned["err"], flush=True)
     assert not learned["fallback"]
     assert learned["err"] < 0.8 * plain["err"]
+
+
+def test_zero_at_free_stream(torch_cuda, nested):
+    """zero_at_free_stream shifts the output bias so that the correction of
+    the uniform free stream vanishes: the network's output there drops from
+    O(1) to rounding, and an SSP-RK3 step from the free stream with the
+    correction taken at the step's start then equals the plain step (later
+    steps see the sliding interface's small free-stream error, to which the
+    network responds)."""
+    import torch
+    from paper_1503_02198_amd import subgrid as G
+    print("case: free-stream calibration of the correction, coarse ellipse N=3", flush=True)
+    case = C.ellipse_viscous_case(omega=0.8)
+    P = G.Pair(nested, case, 3, 6)
+    p, norm = _net(np.random.default_rng(43), 3)
+    norm["sig_y"] = np.full(36, 0.05, np.float32)
+    norm["mu_y"] = np.full(36, 0.01, np.float32)
+    net = _gpu_net(3, p, norm)
+    q = P.uniform(P.coarse)
+    X = torch.empty(P.Ec * net.n_in, dtype=torch.float32, device="cuda:0")
+    P.coarse.features(q, X)
+    y = torch.empty(net.n_out, dtype=torch.float32, device="cuda:0")
+    w = P.work(P.coarse)
+
+    def step_gap():
+        qa, qb = q.clone(), q.clone()
+        P.coarse.attach(net, per_step=True)
+        P.coarse.rk_steps(qa, w, 0.0, 1e-3, 1)
+        P.coarse.attach(None)
+        P.coarse.rk_steps(qb, w, 0.0, 1e-3, 1)
+        return float((qa - qb).abs().max())
+
+    before = step_gap()
+    y0 = G.zero_at_free_stream(net, P)
+    net.forward(X[:net.n_in].clone(), y)
+    after_y = float(y.abs().max())
+    after = step_gap()
+    print("free-stream correction", np.abs(y0).max(), "->", after_y,
+          "; corrected minus plain after one step", before, "->", after, flush=True)
+    assert np.abs(y0).max() > 1e-3
+    assert after_y <= 1e-4 * np.abs(y0).max()
+    assert after <= 1e-3 * before
