@@ -222,8 +222,10 @@ def subgrid_main(args):
     net = MLP(3)
     losses, train_s = G.train(net, X, T, cfg["epochs"], cfg["batch"], cfg["lr"], seed=7,
                               noise=cfg["noise"])
-    calib = G.Pair(meshes, C.ellipse_viscous_case(omega=G.convective_omega(rate_eval)))
-    if cfg["zero_free_stream"]:
+    # the free stream is the same at every rate: any rate's pair serves
+    calib = (G.Pair(meshes, C.ellipse_viscous_case(omega=G.convective_omega(rate_eval)))
+             if cfg["zero_free_stream"] else None)
+    if calib is not None:
         G.zero_at_free_stream(net, calib)
     log(f"training loss {losses[0]:.4e} -> {losses[-1]:.4e} in {train_s:.2f} s")
     steps = cfg["epochs"] * (rows // cfg["batch"])
@@ -252,7 +254,7 @@ def subgrid_main(args):
             ls, ts = G.train(net, X, T, cfg["ft_epochs"], cfg["batch"], cfg["ft_lr"],
                              seed=11 + r, noise=cfg["noise"], resume=True)
         train_s += ts
-        if cfg["zero_free_stream"]:
+        if calib is not None:
             G.zero_at_free_stream(net, calib)
         steps += (cfg["epochs"] if cfg["retrain"] else cfg["ft_epochs"]) * (rows // cfg["batch"])
         log(f"round {r + 1}: {rows} rows, loss {ls[0]:.4e} -> {ls[-1]:.4e} in {ts:.2f} s")
