@@ -326,6 +326,49 @@ def contraction_probe_main(args):
                       "mfma_over_valu_time": ms[1] / ms[0], "max_rel_diff": diff}), flush=True)
 
 
+def stream_probe_main(args):
+    """Bandwidth ceiling of the stage kernel's state traffic: c = 0.75 a +
+    0.25 b over arrays the size of the benchmark's state (63,963,136
+    floats), two read and one written, with 16-byte plain, 16-byte
+    non-temporal, and the stage kernel's own 4-byte non-temporal buffer
+    accesses (variants 0, 1, 2)."""
+    import torch
+    from paper_1503_02198_amd import Mesh
+    from workloads import cases as C
+    from workloads import meshes as M
+    gm = Mesh(M.box_mesh(2, 2), C.vortex_case(), 4, device=0)   # supplies the device handle
+    n = 4 * 16 * 999424
+    g = torch.Generator().manual_seed(20150307)
+    a = torch.rand(n, generator=g).to("cuda:0")
+    b = torch.rand(n, generator=g).to("cuda:0")
+    c = torch.empty_like(a)
+    t_end = time.perf_counter() + args.settle_s   # settle the clocks
+    while time.perf_counter() < t_end:
+        for _ in range(100):
+            gm.probe_stream(2, n, a, b, c)
+        torch.cuda.synchronize()
+    res = {}
+    for variant in (0, 1, 2):
+        for _ in range(5):
+            gm.probe_stream(variant, n, a, b, c)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.probe_launches)]
+        for k in range(args.probe_launches):
+            ev[2 * k].record()
+            gm.probe_stream(variant, n, a, b, c)
+            ev[2 * k + 1].record()
+        torch.cuda.synchronize()
+        us = sorted(1e3 * ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(args.probe_launches))
+        avg = sum(us) / len(us)
+        err = float((c - (0.75 * a + 0.25 * b)).abs().max().item())
+        res[("x4_plain", "x4_nontemporal", "rows_nontemporal")[variant]] = {
+            "avg_us": avg, "median_us": us[len(us) // 2], "TB_s": 12.0 * n / (avg * 1e-6) / 1e12,
+            "max_abs_err": err}
+    print(json.dumps({"metric": "stream probe: two FP32 arrays read, one written",
+                      "floats_per_array": n, "bytes_per_launch": 12 * n, "launches": args.probe_launches,
+                      "variants": res}), flush=True)
+
+
 def traffic_for(kind_hash, E, N):
     """HBM bytes per stage launch from the committed rocprofv3 counter runs,
     or None when the kernels changed since the counters were taken."""
@@ -535,6 +578,8 @@ def main():
                     help="throughput of the learned-correction kernels on seeded random rows")
     ap.add_argument("--contraction-probe", action="store_true",
                     help="vector-ALU vs matrix-core (FP32 MFMA) per-cell contractions")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="bandwidth ceiling of the stage kernel's state traffic")
     ap.add_argument("--probe-reps", type=int, default=16)
     ap.add_argument("--probe-launches", type=int, default=20)
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV",
@@ -566,6 +611,9 @@ def main():
         return
     if args.contraction_probe:
         contraction_probe_main(args)
+        return
+    if args.stream_probe:
+        stream_probe_main(args)
         return
 
     from paper_1503_02198_amd import Mesh, pack_state, unpack_state

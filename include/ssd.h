@@ -351,6 +351,20 @@ ssd_status ssd_timing_samples(ssd_mesh *m, int kernel, float *ms, int64_t cap, i
  */
 ssd_status ssd_probe_contraction(ssd_mesh *m, int32_t variant, int32_t n_cells, int32_t reps,
                                  const float *q, float *out, void *stream);
+/*
+ * Measurement probe for the bandwidth ceiling of the stage kernel's state
+ * traffic: c[i] = 0.75 a[i] + 0.25 b[i] for i < n, two arrays read and one
+ * written, as an SSP-RK stage (Sec. 3.3) reads Q and Qn and writes the new
+ * state.  variant 0: 16-byte accesses per lane, default cache policy;
+ * 1: the same, non-temporal; 2: the stage kernel's own access, 4-byte
+ * non-temporal buffer loads and stores per lane, 256 bytes per wave and
+ * instruction.  a, b, c: device arrays of n floats on the mesh's device,
+ * 16-byte aligned, c overlapping neither a nor b; n a positive multiple of
+ * 1024 with 4 n < 2^32.  Asynchronous on `stream`.  Not part of the method.
+ * Errors: SSD_ERR_INVALID_ARG (bad variant, n or null array).
+ */
+ssd_status ssd_probe_stream(ssd_mesh *m, int32_t variant, int64_t n, const float *a,
+                            const float *b, float *c, void *stream);
 
 
 /*

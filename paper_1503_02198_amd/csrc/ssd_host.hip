@@ -1160,6 +1160,22 @@ ssd_status ssd_probe_contraction(ssd_mesh *m, int32_t variant, int32_t n_cells, 
   return SSD_OK;
 }
 
+ssd_status ssd_probe_stream(ssd_mesh *m, int32_t variant, int64_t n, const float *a,
+                            const float *b, float *c, void *stream) {
+  if (ssd_status s = check_handle(m)) return s;
+  if (variant < 0 || variant > 2 || n < 1024 || n % 1024 != 0 || n > (int64_t(1) << 30) - 1024 ||
+      !a || !b || !c)
+    return fail(SSD_ERR_INVALID_ARG, "need variant 0, 1 or 2, n a positive multiple of 1024 "
+                                     "below 2^30 and device arrays");
+  if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) |
+       reinterpret_cast<uintptr_t>(c)) % 16 != 0)
+    return fail(SSD_ERR_INVALID_ARG, "the stream probe's arrays must be 16-byte aligned");
+  DeviceGuard guard(m->device);
+  SSD_HIP(launch_stream_probe(variant, n, a, b, c, static_cast<hipStream_t>(stream)),
+          "stream probe launch");
+  return SSD_OK;
+}
+
 ssd_status ssd_timing_samples(ssd_mesh *m, int kernel, float *ms, int64_t cap, int64_t *launches) {
   if (ssd_status s = check_handle(m)) return s;
   if (kernel < 0 || kernel >= SSD_KERNEL_COUNT || !launches || cap < 0 || (cap > 0 && !ms))

@@ -85,6 +85,9 @@ hipError_t launch_step_count(double *step, hipStream_t s);
 // the contraction probe (ssd_probe.hip): N = 4 operators of T
 hipError_t launch_probe(int variant, const OpTables &T, int n_cells, int reps, const float *q,
                         float *out, hipStream_t s);
+// the stream probe (ssd_probe.hip): c = 0.75 a + 0.25 b over n floats
+hipError_t launch_stream_probe(int variant, int64_t n, const float *a, const float *b, float *c,
+                               hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // learned per-element subgrid correction (ssd_mlp.hip)

@@ -16,8 +16,14 @@
 // q <- q - 0.01 D f(I q) in registers (Burgers' equation along the line;
 // the values stay of order one), so that the arithmetic, not the 8 bytes per
 // point of memory traffic, sets the time.  N = 4.
+//
+// A second probe measures the bandwidth ceiling of the stage kernel's state
+// traffic: c = 0.75 a + 0.25 b, two arrays read and one written, as an
+// SSP-RK stage reads Q and Qn and writes the new state (see
+// launch_stream_probe for the access variants).
 #include <hip/hip_runtime.h>
 
+#include "ssd_device.h"
 #include "ssd_launch.h"
 
 namespace ssd {
@@ -138,6 +144,64 @@ __global__ __launch_bounds__(64 * PN) void k_probe_mfma(ProbeOps P, const float 
 }  // namespace ssd
 
 namespace ssd {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// 16 bytes per lane and array; one block covers 1024 floats
+template <bool NT>
+__global__ __launch_bounds__(256) void k_stream_x4(const v4f *a, const v4f *b, v4f *c) {
+  const size_t i = size_t(blockIdx.x) * 256 + threadIdx.x;
+  v4f x, y;
+  if (NT) {
+    x = __builtin_nontemporal_load(a + i);
+    y = __builtin_nontemporal_load(b + i);
+  } else {
+    x = a[i];
+    y = b[i];
+  }
+  const v4f z = 0.75f * x + 0.25f * y;
+  if (NT)
+    __builtin_nontemporal_store(z, c + i);
+  else
+    c[i] = z;
+}
+
+// the stage kernel's access: 4-byte non-temporal buffer loads and stores per
+// lane, each wave instruction covering one 256-byte row; a wave takes 4
+// consecutive rows, a block 1024 floats
+__global__ __launch_bounds__(256) void k_stream_rows(const float *a, const float *b, float *c,
+                                                     uint32_t bytes) {
+  const rsrc_t ra = make_rsrc(a, bytes), rb = make_rsrc(b, bytes), rc = make_rsrc(c, bytes);
+  const uint32_t wave = uint32_t(__builtin_amdgcn_readfirstlane(int(threadIdx.x) / 64));
+  const uint32_t base = (blockIdx.x * 1024u + wave * 256u) * 4u;
+  const uint32_t lane = (threadIdx.x & 63u) * 4u;
+  float x[4], y[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    x[k] = bload_nt(ra, lane, base + k * 256u);
+    y[k] = bload_nt(rb, lane, base + k * 256u);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) bstore_nt(0.75f * x[k] + 0.25f * y[k], rc, lane, base + k * 256u);
+}
+
+}  // namespace
+
+// n: a positive multiple of 1024 with 4 n < 2^32 (checked by the caller)
+hipError_t launch_stream_probe(int variant, int64_t n, const float *a, const float *b, float *c,
+                               hipStream_t s) {
+  const dim3 grid(unsigned(n / 1024)), block(256);
+  if (variant == 0)
+    hipLaunchKernelGGL(k_stream_x4<false>, grid, block, 0, s, (const v4f *)a, (const v4f *)b,
+                       (v4f *)c);
+  else if (variant == 1)
+    hipLaunchKernelGGL(k_stream_x4<true>, grid, block, 0, s, (const v4f *)a, (const v4f *)b,
+                       (v4f *)c);
+  else
+    hipLaunchKernelGGL(k_stream_rows, grid, block, 0, s, a, b, c, uint32_t(n * 4));
+  return hipGetLastError();
+}
 
 hipError_t launch_probe(int variant, const OpTables &T, int n_cells, int reps, const float *q,
                         float *out, hipStream_t s) {

@@ -563,21 +563,37 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
 #pragma unroll
       for (int j = 0; j < N; ++j) u2[v][j] = bload_nt(rcomb, vs, ((v * N + j) * N + w) * rowb);
   }
+  // the new value x of variable v at point j: the added increment, the
+  // SSPRK54 combination (stages with Qn only), then the state
+  auto commit = [&](int v, int j, float x, bool qn_stage) {
+    if (ADD) x += C.add_scale * qa[v][j];
+    if (COMB && qn_stage)
+      u2[v][j] = C.cw2 * (u2[v][j] - qo[v][j]) + C.cw3 * (qc[v][j] - qo[v][j]) +
+                 C.cw4 * (x - qo[v][j]);
+    qc[v][j] = x;
+    SR[v][j][w][l] = x;
+  };
+  // a uniform branch, not a per-value select, so that a stage computes
+  // only its own form of the update
+  if (with_qn) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const float gdt = C.gamma * C.dt * ij[j];
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        commit(v, j, qo[v][j] + (C.beta * (qc[v][j] - qo[v][j]) + gdt * rc[v][j]), true);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const float gdt = C.gamma * C.dt * ij[j];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) commit(v, j, qc[v][j] + gdt * rc[v][j], false);
+    }
+  }
   bool bad = false;
 #pragma unroll
   for (int j = 0; j < N; ++j) {
-    const float gdt = C.gamma * C.dt * ij[j];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      float x = with_qn ? qo[v][j] + (C.beta * (qc[v][j] - qo[v][j]) + gdt * rc[v][j])
-                        : qc[v][j] + gdt * rc[v][j];
-      if (ADD) x += C.add_scale * qa[v][j];
-      if (COMB)
-        u2[v][j] = C.cw2 * (u2[v][j] - qo[v][j]) + C.cw3 * (qc[v][j] - qo[v][j]) +
-                   C.cw4 * (x - qo[v][j]);
-      qc[v][j] = x;
-      SR[v][j][w][l] = x;
-    }
     // rho > 0 and p > 0, i.e. 2 rho E > |m|^2; false for any non-finite value
     const float rho = qc[0][j];
     bad |= !(rho > 0.0f) ||

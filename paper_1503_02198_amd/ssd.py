@@ -22,7 +22,7 @@ EXPORTS = ["ssd_create_mesh", "ssd_destroy_mesh", "ssd_query", "ssd_set_rotation
            "ssd_mortar_rebuild", "ssd_residual", "ssd_rk_step", "ssd_rk_steps",
            "ssd_rk_steps_noalloc", "ssd_check",
            "ssd_last_error", "ssd_timing_enable", "ssd_timing_reset", "ssd_timing_read",
-           "ssd_timing_samples", "ssd_probe_contraction",
+           "ssd_timing_samples", "ssd_probe_contraction", "ssd_probe_stream",
            "ssd_batch_create", "ssd_batch_destroy", "ssd_batch_rk_steps", "ssd_batch_query",
            "ssd_mlp_create", "ssd_mlp_destroy", "ssd_mlp_dims", "ssd_mlp_set_params",
            "ssd_mlp_get_params", "ssd_mlp_set_normalization", "ssd_mlp_fit_normalization",
@@ -141,6 +141,7 @@ def lib():
             "ssd_timing_samples": (i32, [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_float), i64,
                                          ctypes.POINTER(i64)]),
             "ssd_probe_contraction": (i32, [vp, i32, i32, i32, vp, vp, vp]),
+            "ssd_probe_stream": (i32, [vp, i32, i64, vp, vp, vp, vp]),
             "ssd_batch_create": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]),
             "ssd_batch_destroy": (i32, [vp]),
             "ssd_batch_rk_steps": (i32, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
@@ -300,6 +301,12 @@ class Mesh:
         _check(lib().ssd_probe_contraction(self._h, int(variant), int(n_cells), int(reps),
                                            self._tensor(q, n, "q"), self._tensor(out, n, "out"),
                                            _stream_ptr(stream, self.device)))
+
+    def probe_stream(self, variant, n, a, b, c, stream=None):
+        """The stream probe c = 0.75 a + 0.25 b over n floats (ssd_probe_stream)."""
+        _check(lib().ssd_probe_stream(self._h, int(variant), int(n), self._tensor(a, n, "a"),
+                                      self._tensor(b, n, "b"), self._tensor(c, n, "c"),
+                                      _stream_ptr(stream, self.device)))
 
     def check(self, stream=None):
         _check(lib().ssd_check(self._h, _stream_ptr(stream, self.device)))
