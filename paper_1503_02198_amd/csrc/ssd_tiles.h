@@ -101,6 +101,11 @@ __device__ __forceinline__ bool grad_in_block(uint32_t fw) {
   return grad_shared<N>() && face_inblock_of(fw);
 }
 
+// Lane stride of the gradient exchange array: one column more than the
+// block's lanes, column EB holding zeros, so that a lane without an
+// in-block neighbour adds zero by its address instead of by a select.
+constexpr int XB = EB + 1;
+
 // Faces whose gradient traces the gradient pass writes: sliding faces (the
 // viscous mortar reads them) and the conforming faces without
 // grad_in_block (both sides average the two).
@@ -113,7 +118,7 @@ __device__ __forceinline__ bool grad_exported(uint32_t fw) {
 
 // Gradient traces at the two ends of a line of solution points (flux
 // points 0 and N) into the exchange array at point p: g [8][N] along the
-// line, X [side][8][N][64].
+// line, X [side][8][N][XB].
 template <int N>
 __device__ __forceinline__ void share_traces(const OpTables &T, const float (&g)[8][N], float *X,
                                              int p, int lane) {
@@ -125,8 +130,8 @@ __device__ __forceinline__ void share_traces(const OpTables &T, const float (&g)
       s0 += T.I[0][i] * g[c][i];
       sN += T.I[N][i] * g[c][i];
     }
-    X[((0 * 8 + c) * N + p) * EB + lane] = s0;
-    X[((1 * 8 + c) * N + p) * EB + lane] = sN;
+    X[((0 * 8 + c) * N + p) * XB + lane] = s0;
+    X[((1 * 8 + c) * N + p) * XB + lane] = sN;
   }
 }
 
@@ -178,14 +183,12 @@ __device__ __forceinline__ void common_visc(const DevMesh &M, const ViscParams &
       gn[4 + v] = b.x[v];
     }
     if (grad_shared<N>()) {
-      // the neighbour's side of the array: xi = 1 / eta = 1 for faces 1, 2
+      // the neighbour's side of the array: xi = 1 / eta = 1 for faces 1, 2;
+      // the zero column for the other lanes
       const int side = (nf == 1u || nf == 2u) ? 1 : 0;
-      const float *xs = X + (side * 8 * N + p) * EB + int(nb & uint32_t(EB - 1));
+      const float *xs = X + (side * 8 * N + p) * XB + (inb ? int(nb & uint32_t(EB - 1)) : EB);
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const float t = xs[c * N * EB];
-        gn[c] += inb ? t : 0.f;
-      }
+      for (int c = 0; c < 8; ++c) gn[c] += xs[c * N * XB];
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -242,10 +245,11 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
   __shared__ float S_[TPB][4][N][N][EB];    // state of the group's elements
   __shared__ float SR_[TPB][4][N][N][EB];   // xi part of the residual, then the new state
   // viscous, grad_shared<N>(): the gradient traces of the current phase's
-  // faces, [side][8][point][lane]; point w is written and read by wave w
-  // alone (in order within the wave), so it needs no barrier
+  // faces, [side][8][point][lane, then a zero column]; point w is written
+  // and read by wave w alone (in order within the wave), so it needs no
+  // barrier
   constexpr bool GS = VISC && grad_shared<N>();
-  __shared__ float X_[TPB][GS ? 2 * 8 * N * EB : 1];
+  __shared__ float X_[TPB][GS ? 2 * 8 * N * XB : 1];
   // inviscid, trace_shared<N>(): the solution traces of the current
   // phase's faces, [side][4][point][lane], point w again wave w's alone
   constexpr bool SX = !VISC && trace_shared<N>();
@@ -387,7 +391,12 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
       t0[v] = s0;
       tN[v] = sN;
     }
-    if (GS) share_traces<N>(T, gr, X, w, l);
+    if (GS) {
+      share_traces<N>(T, gr, X, w, l);
+      // the zero column, 16 N entries, before the barrier below and never
+      // written again
+      if (w == 0 && l < 16 * N) X[l * XB + EB] = 0.f;
+    }
     if (SX) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
