@@ -121,17 +121,18 @@ __device__ __forceinline__ void rusanov_d(const double ql[4], const double qr[4]
   f[3] = 0.5 * (ql[3] * unl + pl * unl + qr[3] * unr + pr * unr) - 0.5 * lam * (qr[3] - ql[3]);
 }
 
-// Gas constants of the viscous terms.
+// Gas constants of the viscous terms: mu, and kT = k (gamma - 1) / R =
+// mu gamma / Pr, the conductivity k = mu gamma R / ((gamma - 1) Pr) times
+// the factor that turns the gradient of the specific internal energy into
+// the gradient of T.
 struct ViscParams {
-  float gamma, iR, mu, kcond;   // iR = 1 / R; kcond = mu gamma R / ((gamma - 1) Pr)
+  float mu, kT;
 };
 
 __device__ __forceinline__ ViscParams visc_params(const DevMesh &M) {
   ViscParams P;
-  P.gamma = M.gamma;
-  P.iR = rcp(M.gas_R);
   P.mu = M.mu;
-  P.kcond = M.mu * M.gamma * M.gas_R * rcp((M.gamma - 1.0f) * M.prandtl);
+  P.kT = M.mu * M.gamma * rcp(M.prandtl);
   return P;
 }
 
@@ -141,28 +142,34 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
 // Normal viscous flux F_vis nx + G_vis ny (Sec. 2.1) from the conservative
 // state and its x, y gradients: tau_ij = mu (u_i,j + u_j,i) - 2/3 mu
-// delta_ij div u, heat flux k grad T with T = p / (rho R); iRg = 1 / R.
+// delta_ij div u and the heat flux k grad T, T = p / (rho R).  In the
+// conservative gradients, with E = rho E / rho and g_c = grad Q_c . n,
+//   rho grad u = grad(rho u) - u grad rho   (likewise v),
+//   k grad T . n = (kT / rho) (g_3 - u g_1 - v g_2 + (|u|^2 - E) g_0),
+// kT = k (gamma - 1) / R; the energy row is -(u (tau n)_x + v (tau n)_y +
+// k grad T . n).
 template <typename R>
 __device__ __forceinline__ void visc_flux_n(const R q[4], const R gx[4], const R gy[4], R nx, R ny,
-                                            R gamma, R iRg, R mu, R kc, R f[4]) {
+                                            R mu, R kT, R f[4]) {
   const R ir = recip(q[0]);
   const R u = q[1] * ir, v = q[2] * ir;
-  const R p = (gamma - R(1)) * (q[3] - R(0.5) * (q[1] * u + q[2] * v));
-  const R ux = (gx[1] - u * gx[0]) * ir, vx = (gx[2] - v * gx[0]) * ir;
-  const R uy = (gy[1] - u * gy[0]) * ir, vy = (gy[2] - v * gy[0]) * ir;
-  const R k2 = R(0.5) * (u * u + v * v);
-  const R px = (gamma - R(1)) * (gx[3] - u * gx[1] - v * gx[2] + k2 * gx[0]);
-  const R py = (gamma - R(1)) * (gy[3] - u * gy[1] - v * gy[2] + k2 * gy[0]);
-  const R Tx = (px - p * ir * gx[0]) * (ir * iRg);
-  const R Ty = (py - p * ir * gy[0]) * (ir * iRg);
-  const R div = ux + vy;
-  const R txx = R(2) * mu * ux - R(2.0 / 3.0) * mu * div;
-  const R tyy = R(2) * mu * vy - R(2.0 / 3.0) * mu * div;
-  const R txy = mu * (uy + vx);
+  const R mir = mu * ir;
+  // mu times the velocity gradients
+  const R ux = (gx[1] - u * gx[0]) * mir, vx = (gx[2] - v * gx[0]) * mir;
+  const R uy = (gy[1] - u * gy[0]) * mir, vy = (gy[2] - v * gy[0]) * mir;
+  const R txy = uy + vx;
+  const R txx = R(2.0 / 3.0) * (R(2) * ux - vy);
+  const R tyy = R(2.0 / 3.0) * (R(2) * vy - ux);
+  const R s1 = txx * nx + txy * ny, s2 = txy * nx + tyy * ny;
+  R g[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) g[c] = gx[c] * nx + gy[c] * ny;
+  const R w = u * u + v * v - q[3] * ir;
+  const R h = g[3] - u * g[1] - v * g[2] + w * g[0];
   f[0] = R(0);
-  f[1] = -(txx * nx + txy * ny);
-  f[2] = -(txy * nx + tyy * ny);
-  f[3] = -((u * txx + v * txy + kc * Tx) * nx + (u * txy + v * tyy + kc * Ty) * ny);
+  f[1] = -s1;
+  f[2] = -s2;
+  f[3] = -(u * s1 + v * s2 + kT * ir * h);
 }
 
 // ---------------------------------------------------------------------------

@@ -200,8 +200,7 @@ __global__ __launch_bounds__(256) void k_gen_vflux(DevMesh M, OpTables T, Mortar
   const double theta = angle_value(Ang);
   const int k = idx / N, a = idx % N;
   const MortarRec r = mortar_at(M, G, theta, k);
-  const double gam = M.gamma, iRg = 1.0 / double(M.gas_R), mu = M.mu;
-  const double kc = mu * gam * double(M.gas_R) / ((gam - 1.0) * double(M.prandtl));
+  const double mu = M.mu, kT = mu * double(M.gamma) / double(M.prandtl);
   double avg[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
@@ -216,7 +215,7 @@ __global__ __launch_bounds__(256) void k_gen_vflux(DevMesh M, OpTables T, Mortar
       double q4[4], g8[8], f[4];
       load_slot_point<N>(M, mqc, slot, b, q4);
       load_canon_point<N, 8>(M, gtr, slot, b, g8);
-      visc_flux_n<double>(q4, g8, g8 + 4, cs * M.Rs, sn * M.Rs, gam, iRg, mu, kc, f);
+      visc_flux_n<double>(q4, g8, g8 + 4, cs * M.Rs, sn * M.Rs, mu, kT, f);
 #pragma unroll
       for (int v = 0; v < 4; ++v) vf[v][b] = f[v];
     }

@@ -196,7 +196,7 @@ __device__ __forceinline__ void common_visc(const DevMesh &M, const ViscParams &
       gy[v] = 0.5f * (gy[v] + gn[4 + v]);
     }
   }
-  visc_flux_n<float>(qc, gx, gy, G.nx, G.ny, P.gamma, P.iR, P.mu, P.kcond, fv);
+  visc_flux_n<float>(qc, gx, gy, G.nx, G.ny, P.mu, P.kT, fv);
 }
 
 // ---------------------------------------------------------------------------
@@ -371,7 +371,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
           for (int i = 0; i < N; ++i) acc += T.I[k][i] * gr[c][i];
           gf[c] = acc;
         }
-        visc_flux_n<float>(qf, gf, gf + 4, G.nx, G.ny, P.gamma, P.iR, P.mu, P.kcond, fv);
+        visc_flux_n<float>(qf, gf, gf + 4, G.nx, G.ny, P.mu, P.kT, fv);
 #pragma unroll
         for (int v = 0; v < 4; ++v) f[v] += fv[v];
       }
@@ -530,7 +530,7 @@ __device__ __forceinline__ void stage_tile(const DevMesh &M, const OpTables &T, 
         flux_n(qf, G.nx, G.ny, G.vgn, gm1, f);
         if (VISC) {
           float fv[4];
-          visc_flux_n<float>(qf, gf, gf + 4, G.nx, G.ny, P.gamma, P.iR, P.mu, P.kcond, fv);
+          visc_flux_n<float>(qf, gf, gf + 4, G.nx, G.ny, P.mu, P.kT, fv);
 #pragma unroll
           for (int v = 0; v < 4; ++v) f[v] += fv[v];
         }
@@ -1162,8 +1162,7 @@ __device__ __forceinline__ void mortar_visc_chunk(const DevMesh &M, const OpTabl
   const int j = right ? t - K : t;
   const int m = ms->m;
   const double sc = M.Rs * M.dphi;
-  const double gam = M.gamma, iRg = 1.0 / double(M.gas_R), mu = M.mu;
-  const double kc = mu * gam * double(M.gas_R) / ((gam - 1.0) * double(M.prandtl));
+  const double mu = M.mu, kT = mu * double(M.gamma) / double(M.prandtl);
   if (act) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -1179,7 +1178,7 @@ __device__ __forceinline__ void mortar_visc_chunk(const DevMesh &M, const OpTabl
         double q4[4], g8[8], f[4];
         load_slot_point<N>(M, mqc, slot, a, q4);
         load_canon_point<N, 8>(M, gtr, slot, a, g8);
-        visc_flux_n<double>(q4, g8, g8 + 4, cs * sc, sn * sc, gam, iRg, mu, kc, f);
+        visc_flux_n<double>(q4, g8, g8 + 4, cs * sc, sn * sc, mu, kT, f);
 #pragma unroll
         for (int v = 0; v < 4; ++v) VF[fl][k][side][a][v] = f[v];
       }
