@@ -695,8 +695,10 @@ __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<N, RK, VISC, ADD, COMB>())
 //   polynomials through the solution interpolated to the interior flux
 //   points and the common solution at the element's faces (eqs. Ft, Gt
 //   applied to Q); grad Q follows by the chain rule with the SP metrics.
-// Outputs: grad Q at the SPs, G [(c*4+v)][j][i][E]; gradient traces,
-// gtr [face][E][point][8], of the faces grad_exported names.
+// Outputs: grad Q at the SPs, G [(c*4+v)][j][i][E], stored with the
+// non-temporal policy (the stage reads it once per phase, after other
+// traffic); gradient traces, gtr [face][E][point][8], of the faces
+// grad_exported names.
 // Same block and wave organisation as k_stage.
 // ---------------------------------------------------------------------------
 template <int N>
@@ -867,7 +869,7 @@ __device__ __forceinline__ void grad_tile(const DevMesh &M, const OpTables &T, c
       f0[c] = f2[c] = 0.f;
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        bstore(gcol[c][j], rG, vg, ((c * N + j) * N + w) * rowb);
+        bstore_nt(gcol[c][j], rG, vg, ((c * N + j) * N + w) * rowb);
         f0[c] += T.I[0][j] * gcol[c][j];
         f2[c] += T.I[N][j] * gcol[c][j];
       }
