@@ -320,7 +320,10 @@ struct ssd_mesh {
   double theta0 = 0.0, omega0 = 0.0;   // motion used by ssd_rk_step
   double theta = 0.0, omega = 0.0;     // angle/rate for ssd_residual
   bool mortar_fresh = false;
-  unsigned stage_launches = 0;        // parity picks the stage kernel's tile order
+  // tiles a reversed stage launch still takes first, in order: the first
+  // sixteenth of the tiles, up to the last of them holding a cubic cell (0:
+  // a plain reversal)
+  int lead_tiles = 0;
   std::vector<void *> allocs;
   float *tr[2] = {nullptr, nullptr};
   ViscIO V{};                          // viscous work buffers (mu > 0)
@@ -492,6 +495,15 @@ ssd_status build(ssd_mesh *m, const ssd_mesh_desc *d) {
   }
   if (C >= (1 << 23)) return fail(SSD_ERR_MESH, "too many cubic elements");
   m->C = C;
+  {
+    // cubic cells cost the stage kernel FP64 metric work: a reversed launch
+    // that took them among its last tiles would end on its slowest ones
+    const long tiles = (long(E) + EB - 1) / EB, head = (tiles + 15) / 16;
+    int last = -1;
+    for (int e = 0; e < E && e / EB < head; ++e)
+      if (cslot[e] >= 0) last = e / EB;
+    m->lead_tiles = last + 1;
+  }
   // |J| > 0 at every solution and flux point
   for (int e = 0; e < E; ++e) {
     const double *xy = d->elem_xy + 24L * e;
@@ -826,11 +838,11 @@ ssd_status residual_pass(ssd_mesh *m, double th, double omega, const float *in, 
               "mortar launch");
   }
   const Rotation rot{std::cos(th), std::sin(th), omega};
-  // tile order: successive tile kernels alternate, so that each starts on
-  // the tiles the one before touched last.  Euler meshes alternate from stage
-  // to stage; on viscous meshes the gradient pass runs forward and the stage
-  // in reverse, every time.
-  const bool parity = (m->stage_launches++ & 1u) != 0;
+  // tile order: on Euler meshes every stage runs forward (tiles in order,
+  // the cubic cells of the meshes built here in the first tiles); on viscous
+  // meshes the gradient pass runs forward and the stage in reverse, so that
+  // it starts on the tiles the gradient pass touched last, after the lead
+  // tiles that hold the cubic cells.
   if (V) {
     {
       LaunchTimer lt(m, SSD_KERNEL_GRAD, st);
@@ -849,7 +861,8 @@ ssd_status residual_pass(ssd_mesh *m, double th, double omega, const float *in, 
     }
   }
   RKCoef Cs = C;
-  Cs.reverse = V ? 1 : int(parity);
+  Cs.reverse = V ? 1 : 0;
+  Cs.lead = m->lead_tiles;
   LaunchTimer lt(m, SSD_KERNEL_STAGE, st, true);
   SSD_HIP(launch_stage(m->D, m->T, rot, in, qn, out, facein, trout, V, Cs, rk, st, lt.start, lt.stop),
           rk ? "stage launch" : "residual launch");

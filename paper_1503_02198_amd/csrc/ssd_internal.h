@@ -162,8 +162,10 @@ struct RKCoef {
   const float *add;        // null: nothing added
   float add_scale = 1.0f;
   // nonzero: tiles taken in reverse block order, so that a launch starts on
-  // the cells the previous launch touched last (still in the memory-side cache)
+  // the cells the previous launch touched last (still in the memory-side
+  // cache), except that tiles 0 .. lead - 1 come first, in order
   int reverse = 0;
+  int lead = 0;
   // SSPRK54, fourth stage: with comb set, the stage also forms the last
   // stage's increment W = cw2 (U2 - Qn) + cw3 (Q - Qn) + cw4 (Q_new - Qn),
   // reading U2 from comb and writing W over it

@@ -685,7 +685,8 @@ __global__ __launch_bounds__(64 * N)
 __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<N, RK, VISC, ADD, COMB>()))) void k_stage(
     DevMesh M, OpTables T, Rotation R, const float *q, const float *qn, float *out,
     const float *facein, float *trout, ViscBufs V, RKCoef C) {
-  const int tile = C.reverse ? int(gridDim.x) - 1 - int(blockIdx.x) : int(blockIdx.x);
+  const int b = int(blockIdx.x);
+  const int tile = !C.reverse ? b : b < C.lead ? b : int(gridDim.x) - 1 - (b - C.lead);
   stage_tile<N, RK, VISC, ADD, COMB>(M, T, R, q, qn, out, facein, trout, V, C, tile);
 }
 

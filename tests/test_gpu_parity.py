@@ -185,29 +185,47 @@ def test_deterministic_and_restartable(torch_cuda):
     assert np.all(state_error(c, a) < 1e-6)
 
 
-def test_tile_order_does_not_change_the_residual(torch_cuda):
-    """Successive stage launches take the 64-cell tiles in opposite orders;
-    blocks share nothing within a launch, so two residual evaluations of the
-    same state (one in each order) agree bit for bit.  A rotating-ellipse
-    mesh of two tiles, the last one ragged (112 cells)."""
+def test_tile_order_does_not_change_the_step(torch_cuda):
+    """Blocks share nothing within a launch, so the order in which a launch
+    takes the 64-cell tiles cannot change its result.  The single-mesh path
+    runs every Euler stage in tile order; the batched path takes successive
+    stages of a group in opposite orders.  With the rotor at rest at angle
+    0 (so that both paths form the same rotation exactly), one SSP-RK3 step
+    by each agrees bit for bit, and so do repeated residual evaluations.  A
+    rotating-ellipse mesh of two tiles, the last one ragged (112 cells)."""
     import torch
-    print("case: tile order (two residual calls, opposite orders)", flush=True)
-    case = C.ellipse_case()
+    from paper_1503_02198_amd import Batch
+    print("case: tile order (single-mesh step in order, batched step alternating)", flush=True)
+    case = C.ellipse_case(omega=0.0)
     mesh = M.ellipse_mesh(K=16, n_in=3, n_out=4, radius=1.5, box_half=4.0, first_in=0.1,
                           first_out=0.2, tile=None)
-    gm = _mesh(mesh, case, 4)
+    gm, gb = _mesh(mesh, case, 4), _mesh(mesh, case, 4)
     Q = C.perturbed_farfield_state(case, 4, gm.info["n_elem"], amplitude=0.05)
     E = gm.info["n_elem"]
     assert E > 64 and E % 64 != 0, E
     q = to_gpu(Q)
     r = [torch.empty_like(q) for _ in range(3)]
-    gm.set_rotation(0.3, case["omega"])
+    gm.set_rotation(0.0, 0.0)
     gm.mortar_rebuild()
     for k in range(3):
         gm.residual(q, r[k])
     torch.cuda.synchronize()
     assert torch.equal(r[0], r[1]) and torch.equal(r[1], r[2])
     assert bool(torch.isfinite(r[0]).all()) and float(r[0].abs().max()) > 0
+    dt = 2e-3
+    qa, qb = to_gpu(Q), to_gpu(Q)
+    wa = torch.empty(gm.info["work_len"], dtype=torch.float32, device="cuda:0")
+    wb = torch.empty(gb.info["work_len"], dtype=torch.float32, device="cuda:0")
+    gm.rk_steps(qa, wa, 0.0, dt, 1)
+    batch = Batch([gb])
+    batch.rk_steps([qb], [wb], [0.0], [dt], 1, graph=False)
+    torch.cuda.synchronize()
+    batch.close()
+    moved = float((qa - q).abs().max())
+    diff = float((qa - qb).abs().max())
+    print("step moved the state by", moved, "; single minus batched", diff, flush=True)
+    assert moved > 1e-4
+    assert torch.equal(qa, qb)
 
 
 def test_error_paths(torch_cuda):
