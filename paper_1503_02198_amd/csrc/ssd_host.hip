@@ -1221,7 +1221,7 @@ struct ssd_batch {
     double *step = nullptr;   // device step counter of the group
     std::vector<int> general; // cases with general rings: their mortars launched per case
     int stream = 0;           // index into ssd_batch::streams
-    unsigned stages = 0;      // stage launches so far: parity picks the tile order
+    unsigned stages = 0;      // stage launches so far: parity picks a viscous group's tile order
     float stage_ms = 0.0f;    // the group's stage alone (autotuner)
     int tpb = 1;              // 64-cell tiles per block of the stage launch (autotuner)
     float tpb_ms[2] = {0.0f, 0.0f};   // the stage alone with 1 and 2 tiles per block
@@ -1312,13 +1312,14 @@ void case_mortar_bufs(const ssd_batch *b, int c, int cur, float **mflux, float *
   *mqc = *mflux + face_record_floats(m->N, m->K);
 }
 
-// One RK stage of group g, launched on stream st (alternating the tile
-// order from stage to stage).  Cases with uniform rings
+// One RK stage of group g, launched on stream st (viscous groups alternate
+// the tile order from stage to stage; inviscid groups take it forward, as the
+// single-mesh Euler stages do).  Cases with uniform rings
 // share the batched mortar launches; each case with general rings launches
 // its own merge, flux and back-projection, its angle read from the step
 // counter on the device.
 ssd_status group_stage(ssd_batch *b, ssd_batch::Group &g, BatchStage S, hipStream_t st) {
-  S.reverse = int(g.stages++ & 1u);
+  S.reverse = g.visc ? int(g.stages++ & 1u) : 0;
   SSD_HIP(launch_batch_mortar(g.N, g.visc, b->dcases, g.mortar_work, g.nmortar, g.T, g.MT, S.cur,
                               S.c, g.step, st),
           "batched mortar launch");
