@@ -41,6 +41,28 @@ def test_struct_layout_matches_header():
     assert ctypes.sizeof(ssd.BatchGroup) == 11 * 4
 
 
+def test_struct_layout_matches_c_compiler(tmp_path):
+    """The binding's structures against sizeof/offsetof from a C compiler
+    reading include/ssd.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "ssd.h"\n'
+                   "int main(void) { printf(\"%zu %zu %zu %zu %zu\\n\", sizeof(ssd_mesh_desc), "
+                   "offsetof(ssd_mesh_desc, face_kind), sizeof(ssd_info), offsetof(ssd_info, work_len), "
+                   "sizeof(ssd_batch_group)); return 0; }\n")
+    exe = tmp_path / "layout"
+    include = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-std=c99", "-I", include, "-o", str(exe), str(src)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got == [ctypes.sizeof(ssd.MeshDesc), ssd.MeshDesc.face_kind.offset, ctypes.sizeof(ssd.Info),
+                   ssd.Info.work_len.offset, ctypes.sizeof(ssd.BatchGroup)]
+
+
 def test_argument_errors_without_device(L):
     h = ctypes.c_void_p()
     assert L.ssd_create_mesh(None, 0, ctypes.byref(h)) == -1
