@@ -59,8 +59,9 @@ struct BatchStage {
   // last stage's increment W = cw2 (U2 - Qn) + cw3 (Q - Qn) + cw4 (Q_new - Qn)
   int comb = -1;
   float cw2 = 0.0f, cw3 = 0.0f, cw4 = 0.0f;
-  // nonzero: the work table is taken in reverse order (successive stages
-  // alternate, so a stage starts on the tiles the previous one touched last)
+  // nonzero: the work table is taken in reverse order (successive stages of
+  // a viscous group alternate, so a stage starts on the tiles the previous
+  // one touched last; inviscid groups run forward)
   int reverse = 0;
 };
 
