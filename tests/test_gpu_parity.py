@@ -185,20 +185,24 @@ def test_deterministic_and_restartable(torch_cuda):
     assert np.all(state_error(c, a) < 1e-6)
 
 
-def test_tile_order_does_not_change_the_step(torch_cuda):
+@pytest.mark.parametrize("viscous", [False, True])
+def test_tile_order_does_not_change_the_step(torch_cuda, viscous):
     """Blocks share nothing within a launch, so the order in which a launch
     takes the 64-cell tiles cannot change its result.  The single-mesh path
-    runs every Euler stage in tile order; the batched path takes successive
-    stages of a group in opposite orders.  With the rotor at rest at angle
-    0 (so that both paths form the same rotation exactly), one SSP-RK3 step
-    by each agrees bit for bit, and so do repeated residual evaluations.  A
-    rotating-ellipse mesh of two tiles, the last one ragged (112 cells)."""
+    runs every Euler stage in tile order and every viscous stage in reverse
+    order after its lead tiles; the batched path takes successive stages of
+    a viscous group in opposite orders and an inviscid group's in order.
+    With the rotor at rest at angle 0 (so that both paths form the same
+    rotation exactly), one SSP-RK3 step by each agrees bit for bit, and so
+    do repeated residual evaluations.  A rotating-ellipse mesh of two tiles,
+    the last one ragged (112 cells); viscous: isothermal wall, Re 1000."""
     import torch
     from paper_1503_02198_amd import Batch
-    print("case: tile order (single-mesh step in order, batched step alternating)", flush=True)
-    case = C.ellipse_case(omega=0.0)
+    print(f"case: tile order (single-mesh step, batched step), viscous={viscous}", flush=True)
+    case = C.ellipse_viscous_case(omega=0.0) if viscous else C.ellipse_case(omega=0.0)
     mesh = M.ellipse_mesh(K=16, n_in=3, n_out=4, radius=1.5, box_half=4.0, first_in=0.1,
-                          first_out=0.2, tile=None)
+                          first_out=0.2, tile=None,
+                          wall=M.FACE_WALL_ISOTHERMAL if viscous else M.FACE_WALL_SLIP)
     gm, gb = _mesh(mesh, case, 4), _mesh(mesh, case, 4)
     Q = C.perturbed_farfield_state(case, 4, gm.info["n_elem"], amplitude=0.05)
     E = gm.info["n_elem"]
