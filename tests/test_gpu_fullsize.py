@@ -1,7 +1,8 @@
 """Parity at the benchmark's full size (999,424-cell rotating-ellipse mesh,
 N = 4, the launch configuration bench.py times): the GPU's residual and one
-SSP-RK3 step are compared with the FP64 oracle on sampled cells, which the
-oracle evaluates on sub-meshes around them (every interface cell included).
+SSP-RK3 or SSPRK54 step, Euler and Navier-Stokes, are compared with the FP64
+oracle on sampled cells, which the oracle evaluates on sub-meshes around
+them (every interface cell included).
 """
 import numpy as np
 import pytest
@@ -151,3 +152,28 @@ def test_fullsize_viscous_residual_sampled(c3_viscous):
     err = residual_error(Rg[..., pick], Ro[..., loc], diag["flux_scale"][..., loc])
     print("sampled viscous residual error", err)
     assert np.all(err <= TOL), err
+
+
+def test_fullsize_viscous_rk3_step_sampled(c3_viscous):
+    """One viscous SSP-RK3 step on the full mesh of `bench.py --viscous`,
+    the launch sequence it times (mortar, gradient pass, viscous mortar,
+    stage, three times), against the oracle on a sub-mesh six neighbour
+    layers deep (two per stage: the BR1 common solution and gradient)."""
+    import torch
+    mesh, case, N, E, Q0, dt, gm = c3_viscous
+    print(f"case: full-size viscous SSP-RK3 step E={E} dt={dt:.3e}", flush=True)
+    q = to_gpu(Q0)
+    work = torch.empty(gm.info["work_len"], dtype=torch.float32, device=q.device)
+    gm.rk_step(q, work, 0.0, dt)
+    gm.check()
+    Qg = from_gpu(q, N, E)
+    pick = _samples(E, np.random.default_rng(9))
+    sub, idx = submesh(mesh, pick, depth=6)
+    ora = SSD(sub, case, N)
+    Qo = ora.ssprk3_step(Q0[..., idx].astype(np.float64), 0.0, dt)
+    loc = np.searchsorted(idx, pick)
+    err = state_error(Qg[..., pick], Qo[..., loc])
+    ch, bound = change_error(Qg[..., pick], Qo[..., loc], Q0[..., pick])
+    print("sampled state error", err, "error of the change", ch, "bound", bound)
+    assert np.all(err <= TOL), err
+    assert ch <= bound, (ch, bound)
