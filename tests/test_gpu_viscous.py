@@ -94,14 +94,18 @@ def test_residual_viscous_box(torch_cuda, N, curved):
     _check_residual(gm, ora, Q, 0.3, 0.8, "box")
 
 
-@pytest.mark.parametrize("N", [3, 4])
-def test_residual_viscous_ellipse(torch_cuda, N):
-    """Slip wall, far field and the sliding interface with viscosity."""
-    print(f"case: viscous ellipse residual N={N}", flush=True)
+@pytest.mark.parametrize("wall", ["slip", "isothermal"])
+@pytest.mark.parametrize("N", [2, 3, 4, 5, 6])
+def test_residual_viscous_ellipse(torch_cuda, N, wall):
+    """Slip or isothermal no-slip wall, far field and the sliding interface
+    with viscosity, at every order (N >= 5 takes every gradient trace
+    through the trace buffer)."""
+    print(f"case: viscous ellipse residual N={N} wall={wall}", flush=True)
     case = C.ellipse_case()
     case["mu"] = 0.02
     mesh = M.ellipse_mesh(K=32, n_in=4, n_out=4, radius=1.5, box_half=4.0, first_in=0.05,
-                          first_out=0.1)
+                          first_out=0.1,
+                          wall=M.FACE_WALL_SLIP if wall == "slip" else M.FACE_WALL_ISOTHERMAL)
     ora = SSD(mesh, case, N)
     E = len(mesh["zone"])
     Q = C.perturbed_farfield_state(case, N, E, amplitude=0.02)
