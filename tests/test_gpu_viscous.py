@@ -8,7 +8,8 @@ import pytest
 
 from oracle.exact import Couette, vortex_state
 from oracle.ssd import SSD
-from tests.parity_utils import TOL, gpu_residual, gpu_run, residual_error, state_error
+from tests.parity_utils import (TOL, change_error, gpu_residual, gpu_run, residual_error,
+                                state_error)
 from workloads import cases as C
 from workloads import meshes as M
 
@@ -173,16 +174,22 @@ def test_rk_steps_viscous_equals_repeated(torch_cuda):
     assert np.all(state_error(b, a) < 1e-6)
 
 
-def test_ssprk54_couette_steps(torch_cuda):
-    """SSPRK54 on the viscous Couette mesh."""
-    print("case: couette SSPRK54 15 steps", flush=True)
+@pytest.mark.parametrize("N", [3, 5, 6])
+def test_ssprk54_couette_steps(torch_cuda, N):
+    """SSPRK54 on the viscous Couette mesh (the fourth stage forms the last
+    stage's increment in the same kernel, at N = 5 and 6 too), asserting
+    the state and the error of the run's change."""
+    print(f"case: couette SSPRK54 15 steps N={N}", flush=True)
     case = C.couette_case()
     mesh = M.couette_mesh(4, 16, phi_offset=0.11)
-    ora = SSD(mesh, case, 3)
+    ora = SSD(mesh, case, N)
     Q = _couette_state(ora, case, 0.0)
-    gm = _mesh(mesh, case, 3)
-    Qg = gpu_run(gm, Q, 0.0, 3e-3, 15, scheme="rk54")
-    Qo = ora.run(Q, 0.0, 3e-3, 15, scheme="rk54")
+    gm = _mesh(mesh, case, N)
+    dt = 3e-3 * (3.0 / N) ** 2
+    Qg = gpu_run(gm, Q, 0.0, dt, 15, scheme="rk54")
+    Qo = ora.run(Q, 0.0, dt, 15, scheme="rk54")
     err = state_error(Qg, Qo)
-    print("state error", err, flush=True)
+    ch, bound = change_error(Qg, Qo, Q)
+    print("state error", err, "error of the change", ch, "bound", bound, flush=True)
     assert np.all(err <= TOL), err
+    assert ch <= bound, (ch, bound)
