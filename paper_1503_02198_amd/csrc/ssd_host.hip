@@ -1607,7 +1607,7 @@ ssd_status ssd_batch_create(ssd_mesh *const *meshes, int32_t n, ssd_batch **out)
         gi = int(b->groups.size()) - 1;
       }
       for (int t = 0; t < (m->E + EB - 1) / EB; ++t) sw[gi].push_back(make_uint2(c, t));
-      const int fpb = 256 / m->N;
+      const int fpb = MORTAR_BLOCK / m->N;   // the mortar kernels' faces per workgroup
       if (m->general)
         b->groups[gi].general.push_back(c);
       else

@@ -18,6 +18,7 @@ constexpr int NMAX = 6;
 //   bit  28      the neighbour's face parameter runs opposite to ours
 //   bits 29..31  SSD_FACE_* kind
 constexpr int EB = 64;   // elements per stage-kernel block
+constexpr int MORTAR_BLOCK = 64;   // threads per mortar workgroup, N per interface face
 
 // Cell-blocked layout of per-cell arrays of `planes` values each (a state:
 // planes = 4 N^2, plane (v N + j) N + i holds Q[v] at solution point

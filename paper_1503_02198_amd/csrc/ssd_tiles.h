@@ -84,7 +84,7 @@ struct ViscBufs {
 };
 
 // Orders whose viscous stage passes gradient traces between the block's
-// elements through LDS: the exchange array, [side][8][N][64] floats (16 KB
+// elements through LDS: the exchange array, [side][8][N][65] floats (16.25 KB
 // at N = 4), keeps the stage at three blocks per compute unit.
 template <int N>
 __device__ constexpr bool grad_shared() {
@@ -1032,7 +1032,6 @@ __device__ __forceinline__ void load_canon(const DevMesh &M, const float *__rest
 // With VISC also the common solution on the face for the gradient pass: the
 // mean of the two sides' projections on each mortar, projected back
 // (Sec. 3.2), mqc[slot][point][var].
-constexpr int MORTAR_BLOCK = 256;
 
 template <int N, bool VISC>
 __device__ __forceinline__ void mortar_chunk(const DevMesh &M, const OpTables &T,
