@@ -7,8 +7,9 @@ import numpy as np
 import pytest
 
 from oracle.ssd import SSD, GeneralInterface
-from tests.parity_utils import (TOL, from_gpu, gpu_residual, gpu_run, residual_error,
-                                state_error, to_gpu)
+from tests.parity_utils import (ELEM_TOL, TOL, change_error, element_max_error, from_gpu,
+                                gpu_residual, gpu_run, interface_cells, residual_error, state_error,
+                                to_gpu)
 from workloads import cases as C
 from workloads import meshes as M
 
@@ -29,7 +30,7 @@ def _mesh(K, K_out, warp):
 
 
 @pytest.mark.parametrize("K,K_out,warp,N", [(16, 24, 0.3, 3), (24, 16, -0.4, 4), (16, 16, 0.5, 2),
-                                            (32, 48, 0.0, 5)])
+                                            (32, 48, 0.0, 5), (16, 24, 0.2, 6)])
 def test_residual(torch_cuda, K, K_out, warp, N):
     from paper_1503_02198_amd import Mesh
     print(f"case: general interface residual K={K} K_out={K_out} warp={warp} N={N}", flush=True)
@@ -43,8 +44,10 @@ def test_residual(torch_cuda, K, K_out, warp, N):
         Rg = gpu_residual(gm, Q, th, case["omega"])
         Ro, diag = ora.residual(Q, th, case["omega"], diag=True)
         err = residual_error(Rg, Ro, diag["flux_scale"])
-        print("theta", th, "residual error", err, flush=True)
+        emax = element_max_error(Rg, Ro, diag["flux_scale"], interface_cells(mesh))
+        print("theta", th, "residual error", err, "interface-cell maximum", emax, flush=True)
         assert np.all(err <= TOL), err
+        assert np.all(emax <= ELEM_TOL), emax
 
 
 def test_rk3_steps(torch_cuda):
@@ -60,11 +63,14 @@ def test_rk3_steps(torch_cuda):
     Qg = gpu_run(gm, Q, 0.4, 1.2e-4, 40)
     Qo = ora.run(Q, 0.4, 1.2e-4, 40)
     err = state_error(Qg, Qo)
-    print("state error", err, flush=True)
+    ch, bound = change_error(Qg, Qo, Q)
+    print("state error", err, "error of the change", ch, "bound", bound, flush=True)
     assert np.all(err <= TOL), err
+    assert ch <= bound, (ch, bound)
 
 
-@pytest.mark.parametrize("K,K_out,warp,N", [(16, 24, 0.3, 3), (24, 16, -0.4, 4)])
+@pytest.mark.parametrize("K,K_out,warp,N", [(16, 24, 0.3, 3), (24, 16, -0.4, 4), (16, 16, 0.5, 2),
+                                            (32, 48, 0.0, 5)])
 def test_viscous_residual(torch_cuda, K, K_out, warp, N):
     """BR1 common solution and viscous flux through the general mortars."""
     from paper_1503_02198_amd import Mesh
